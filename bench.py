@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Benchmark: mixed-precision H-matrix-vector product and BiCGSTAB
+time-to-1e-8 residual on one MI355X, mixed (Method 2-Mixed) vs FP64.
+
+Workload (default): two parallel 1 x 1 plates at gap 0.1, each a 128 x 128
+grid of squares cut into 4 right triangles (N = 131,072 panels), BEM
+collocation, cluster leaf 64, eta = 2, ACA tolerance 1e-5, right-hand side
++1 / -1 on the two plates.  Inputs are synthetic and seeded (the paper's
+6-sphere geometry is not available).
+
+One step = one BiCGSTAB solve from x0 = 0 to relative residual 1e-8 with the
+mixed operator, confirmed with the FP64 true residual: every stage of the
+path (stage-1 z partials, stage-1 reduction with D_m, stage-2 dense + V'
+streaming, the device-side Krylov vector work and the FP64 residual check).
+`value` = algorithmic bytes of all products executed in the timed solves
+divided by their wall time (whole-job GB/s).  Per-kernel durations are
+measured live with HIP events on the product's stream during the timed
+solves; the roofline entry is for the dominant kernel (stage 2).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+WORKLOADS = {
+    "plates-128": dict(leaf=64, eta=2.0, eps=1e-5,
+                       desc="two 1x1 plates, gap 0.1, 128x128 squares x 4 right triangles each, N=131072; "
+                            "leaf 64, eta 2, ACA 1e-5; b = +1/-1"),
+    "sphere-L7+8": dict(leaf=64, eta=2.0, eps=1e-6,
+                        desc="unit icosphere L7 + 8 random icosphere-L2 spheres r~U[0.05,0.2] (seed 0), "
+                             "N=330240; leaf 64, eta 2, ACA 1e-6; b = 1"),
+    "sphere-L4": dict(leaf=32, eta=2.0, eps=1e-6,
+                      desc="unit icosphere L4, N=5120; leaf 32, eta 2, ACA 1e-6; b = 1 (cache-resident)"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="plates-128", choices=sorted(WORKLOADS))
+    ap.add_argument("--variant", default="M2-Mixed")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--poll-every", type=int, default=4)
+    ap.add_argument("--matvec-reps", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-matvecs", type=int, default=5)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): this build has no multi-GPU path; "
+              "how the product would shard across GPUs is described in DESIGN.md.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1911_00093_amd import hmat, meshes
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    variant = hmat.PRECISION_NAMES.index(args.variant)
+    W = WORKLOADS[args.workload]
+
+    # ---------------- setup (untimed): mesh, FP64 H-matrix, conversions
+    t0 = time.time()
+    mesh = meshes.workload(args.workload)
+    bs = hmat.hmat_assemble_bem(mesh.centroids, mesh.areas, leaf=W["leaf"], eta=W["eta"], eps=W["eps"])
+    log(f"[setup] {args.workload}: n={bs.n} blocks={bs.nblocks} assembly {time.time() - t0:.1f}s")
+    t0 = time.time()
+    H64 = hmat.HMatrix(bs, hmat.M1_DOUBLE)
+    Hm = hmat.HMatrix(bs, variant, c=-1)
+    log(f"[setup] builds {time.time() - t0:.1f}s")
+    st64, stm = H64.stats(), Hm.stats()
+    B64, Bm = st64.algorithmic_bytes, stm.algorithmic_bytes
+    b = torch.as_tensor(mesh.rhs()[bs.perm], device=dev)
+    n = bs.n
+    work = torch.empty(hmat.hmat_solver_workspace_bytes(n), dtype=torch.uint8, device=dev)
+
+    def solve(H, tol, x=None):
+        x = torch.zeros(n, dtype=torch.float64, device=dev) if x is None else x.zero_()
+        return hmat.hmat_bicgstab(H, b, x=x, h_fp64=H64, tol=tol, maxiter=2000, poll_every=args.poll_every,
+                                  work=work)
+
+    # reference solution: FP64 to 1e-12
+    xref, iref = solve(H64, 1e-12)
+    xref = xref.clone()
+    log(f"[setup] FP64 reference solve: {iref['iterations']} it, true res {iref['true_rel_res']:.2e}")
+
+    # ---------------- warmup
+    xw = torch.zeros(n, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        solve(Hm, args.tol, xw)
+        solve(H64, args.tol, xw)
+    torch.cuda.synchronize()
+
+    # ---------------- timed region: K mixed solves (live kernel timing on)
+    Hm.set_profiling(True)
+    Hm.kernel_times()  # reset
+    infos = []
+    xs = torch.zeros(n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        xs, info = solve(Hm, args.tol, xs)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t_start
+    kt, kcount = Hm.kernel_times()
+    Hm.set_profiling(False)
+    assert all(i["status"] == 0 for i in infos), infos
+    mv_bytes = sum(i["matvecs"] * Bm + i["matvecs_fp64"] * B64 for i in infos)
+    value = mv_bytes / t_mixed / 1e9
+    ms_per_step = 1e3 * t_mixed / args.steps
+    err_mixed = float(torch.linalg.norm(xs - xref) / torch.linalg.norm(xref))
+
+    # FP64 solves, same protocol (context for "mixed vs FP64")
+    x64 = torch.zeros(n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    infos64 = []
+    for _ in range(args.steps):
+        x64, i64 = solve(H64, args.tol, x64)
+        infos64.append(i64)
+    torch.cuda.synchronize()
+    t_fp64 = time.perf_counter() - t_start
+    err_fp64 = float(torch.linalg.norm(x64 - xref) / torch.linalg.norm(xref))
+
+    # back-to-back products (the paper's matvec-only protocol), per variant
+    matvec_gbs = {}
+    xv = torch.randn(n, dtype=torch.float64, device=dev)
+    yv = torch.empty_like(xv)
+    for name, H in (("M1-Double", H64), (args.variant, Hm)):
+        for _ in range(3):
+            H.matvec(xv, yv)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.matvec_reps):
+            H.matvec(xv, yv, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.matvec_reps
+        matvec_gbs[name] = dict(ms=round(ms, 4), gbs=round(H.stats().algorithmic_bytes / ms / 1e6, 1))
+
+    # STREAM-read ceiling over a buffer larger than the MALL
+    buf = torch.empty(2 << 30, dtype=torch.uint8, device=dev)
+    hmat.hmat_stream_read(buf)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(10):
+        hmat.hmat_stream_read(buf)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    stream_gbs = buf.numel() * 10 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del buf
+
+    # roofline of the dominant kernel (stage 2) from the live event timing
+    k2_bytes = stm.stage2_algorithmic_bytes
+    k1_bytes = stm.stage1_algorithmic_bytes
+    k2_gbs = k2_bytes / (kt[2] / 1e3) / 1e9 if kt[2] > 0 else 0.0
+    k1_gbs = k1_bytes / (kt[0] / 1e3) / 1e9 if kt[0] > 0 else 0.0
+
+    out = {
+        "metric": "H-matvec GB/s and BiCG-STAB time-to-1e-8 residual, mixed vs FP64, 1 GPU",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {W['desc']}",
+            "precision": args.variant,
+            "storage": "fp32 matrix, fp64 D_m / x / y / Krylov",
+            "n": n,
+            "step": "one BiCGSTAB solve x0=0 -> |r|/|b|<1e-8 confirmed by the FP64 true residual",
+            "parallelism": "1 GPU",
+        },
+        "time_to_tol_ms": {"mixed": round(ms_per_step, 3), "fp64": round(1e3 * t_fp64 / args.steps, 3)},
+        "speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
+        "iterations": {"mixed": infos[-1]["iterations"], "fp64": infos64[-1]["iterations"],
+                       "mixed_restarts": infos[-1]["restarts"]},
+        "solution_rel_err_vs_fp64_1e-12": {"mixed": err_mixed, "fp64_1e-8": err_fp64},
+        "true_rel_res": {"mixed": infos[-1]["true_rel_res"], "fp64": infos64[-1]["true_rel_res"]},
+        "bytes_per_matvec": {"mixed": int(Bm), "fp64": int(B64)},
+        "matvec_only": matvec_gbs,
+        "kernel_ms": {"stage1": round(kt[0], 4), "stage1_reduce": round(kt[1], 4), "stage2": round(kt[2], 4),
+                      "products": kcount},
+        "stream_read_gbs": round(stream_gbs, 1),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_stage2",
+            "achieved": round(k2_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(k2_gbs / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "stage1_achieved": round(k1_gbs, 1),
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh, W, variant, args.cpu_matvecs, Bm)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(mesh, W, variant, reps, B):
+    """The oracle as it stands (plain single-threaded C, FP64 arithmetic) on
+    the same workload: its own assembly (untimed; it reproduces the library's
+    blocks bit for bit, so the product moves the same B bytes), then `reps`
+    products with the same precision variant, timed."""
+    import oracle
+
+    t0 = time.time()
+    h = oracle.HMatrix(mesh.centroids, mesh.areas, leaf=W["leaf"], eta=W["eta"], eps=W["eps"])
+    conv = oracle.Converted(h, variant, -1)
+    log(f"[cpu] oracle assembly + conversion {time.time() - t0:.1f}s")
+    x = np.random.default_rng(0).standard_normal(h.n)
+    conv.matvec(x)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        conv.matvec(x)
+    dt = (time.perf_counter() - t0) / reps
+    from paper_1911_00093_amd import hmat
+
+    return {"value": round(B / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} oracle products ({hmat.PRECISION_NAMES[variant]}, build arithmetic) on the full "
+                      f"workload, {dt * 1e3:.0f} ms each, after an untimed oracle assembly",
+            "ms_per_matvec": round(dt * 1e3, 1)}
+
+
+if __name__ == "__main__":
+    main()

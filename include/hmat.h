@@ -1,0 +1,276 @@
+/*
+ * hmat.h -- C ABI of an MI355X (gfx950) library for the mixed-precision
+ * H-matrix-vector product and the BiCGSTAB solve that repeats it.
+ *
+ * Method: Ooi, Iwashita, Fukaya, Ida, Yokota, "Effect of Mixed Precision
+ * Computing on H-Matrix Vector Multiplication in BEM Analysis",
+ * arXiv:1911.00093.  An H-matrix is a partition M of the N x N index set
+ * into blocks I_m x J_m (Sec. 2, Eqs. 1-2); each block is either kept dense
+ * or stored as a low-rank product V_m W_m (Eqs. 3-4).  The product
+ * y = A~ x is the sum of the block products scattered into y (Eqs. 5-8),
+ * a low-rank block being applied in two steps z_m = W_m x_m, y^_m = V_m z_m
+ * (Eqs. 9-10).  The precision variants are those of Sec. 3 / Table 1.
+ *
+ * Conventions used by every entry point:
+ *  - Indices are 0-based and half-open: a block covers rows
+ *    [row0, row0 + nrows) and columns [col0, col0 + ncols).  The paper writes
+ *    them 1-based and inclusive (i_m^(s) .. i_m^(e), Sec. 2); contiguous
+ *    ranges mean the matrix is given in cluster (permuted) order, and every
+ *    vector crossing this ABI is in that order too.
+ *  - "host" pointers point to CPU memory, "device" pointers to memory of the
+ *    current HIP device.  `stream` is a hipStream_t passed as void*
+ *    (NULL = the null stream).
+ *  - Every function returns an hmat_status; on failure a thread-local
+ *    message is available from hmat_last_error().  No function aborts or
+ *    throws across the ABI.
+ *  - The library never allocates device memory for matrices, vectors or
+ *    solver state: the caller passes device buffers sized by hmat_plan() and
+ *    hmat_solver_workspace_bytes().  It allocates small host-side handle
+ *    state only.
+ */
+#ifndef HMAT_H
+#define HMAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef enum {
+    HMAT_OK = 0,
+    HMAT_E_ARG = 1,        /* a null pointer, a size out of range, a bad enum value */
+    HMAT_E_LAYOUT = 2,     /* the blocks do not form a partition (Eqs. 1-2 violated) */
+    HMAT_E_WORKSPACE = 3,  /* a caller buffer is too small or misaligned */
+    HMAT_E_HIP = 4,        /* a HIP runtime call failed */
+    HMAT_E_BREAKDOWN = 5,  /* BiCGSTAB breakdown: rho = 0, r~^T v = 0 or omega = 0 (Alg. 1) */
+    HMAT_E_NOCONV = 6,     /* BiCGSTAB did not reach the tolerance within maxiter */
+    HMAT_E_NONFINITE = 7,  /* a NaN or Inf appeared in the solver's residual */
+    HMAT_E_NOMEM = 8       /* host memory allocation failed */
+} hmat_status;
+
+/* Thread-local description of the last failure in this thread ("" if none). */
+const char *hmat_last_error(void);
+
+/* ------------------------------------------------------------ precision */
+/* Storage and arithmetic types, Table 1 of the paper (Sec. 3.1-3.3), plus one
+ * addition that the paper does not make:
+ *  M1_*  original structure V_m W_m (Sec. 3.1)
+ *  M2_*  extended structure V'_m D_m W'_m, D_m FP64 (Sec. 3.2, Eqs. 11-16)
+ *  M3    per-term split of the M2 structure by the constant c (Sec. 3.3,
+ *        Eqs. 17-20): terms with d_i >= d_max 10^-c FP64, the rest FP32;
+ *        dense blocks FP64
+ *  BF16_SCALED  low-rank factors in bfloat16 with one power-of-two FP32
+ *        scale per factor and block, dense blocks FP32, z in FP64 (not from
+ *        the paper).
+ * Double: FP64 matrix and source vector.  Single: FP32 matrix, source vector
+ * rounded to FP32 before each product (Sec. 3.5).  Mixed: FP32 matrix, FP64
+ * source vector.  The result vector is FP64 in every variant, and every
+ * product and sum is carried out in FP64 after upcasting the stored values;
+ * z_m is rounded to FP32 in M1_SINGLE / M1_MIXED, where Table 1 stores it in
+ * FP32. */
+typedef enum {
+    HMAT_M1_DOUBLE = 0,
+    HMAT_M1_SINGLE = 1,
+    HMAT_M1_MIXED = 2,
+    HMAT_M2_DOUBLE = 3,
+    HMAT_M2_SINGLE = 4,
+    HMAT_M2_MIXED = 5,
+    HMAT_M3 = 6,
+    HMAT_BF16_SCALED = 7
+} hmat_precision;
+
+enum { HMAT_DENSE = 0, HMAT_LOWRANK = 1 };
+
+/* ---------------------------------------------------- block description */
+/* An FP64 H-matrix as produced by a cluster tree and ACA (or any other
+ * source).  All arrays are host memory of length nblocks and are only read
+ * during the call they are passed to.
+ *  data + offset[m] holds, for a dense block, the nrows x ncols block in
+ *  column-major order; for a low-rank block of rank r, V_m (nrows x r,
+ *  column-major) immediately followed by the transpose of W_m (ncols x r,
+ *  column-major).  0 <= r <= min(nrows, ncols) (Eq. 3). */
+typedef struct {
+    int64_t n;                /* matrix order N */
+    int64_t nblocks;
+    const int64_t *row0, *nrows, *col0, *ncols;
+    const int32_t *kind;      /* HMAT_DENSE or HMAT_LOWRANK */
+    const int32_t *rank;      /* ignored for dense blocks */
+    const int64_t *offset;    /* element offset into data */
+    const double *data;
+    int64_t ndata;            /* number of doubles readable at data */
+} hmat_blocks;
+
+typedef struct {
+    int32_t precision;        /* hmat_precision */
+    int32_t c;                /* Method 3 split constant (Eqs. 19-20); the paper uses -1, 1..7 */
+    int32_t nrhs_max;         /* largest nrhs later passed to hmat_matvec, >= 1 */
+    int32_t reserved;         /* must be 0 */
+} hmat_build_opts;
+
+typedef struct {
+    uint64_t device_bytes;    /* size of the device buffer hmat_build needs */
+    uint64_t matrix_bytes;    /* stored matrix values after conversion */
+    uint64_t algorithmic_bytes; /* bytes one product must move at nrhs = 1:
+                                   matrix values + D_m scales + x + y */
+    int64_t nblocks_dense, nblocks_lowrank;
+    int64_t max_rank;
+    int64_t terms_fp64, terms_fp32, terms_bf16; /* low-rank terms per storage type */
+} hmat_plan_info;
+
+typedef struct hmat_s *hmat_t;
+
+/* Validate a block description and size the device buffer for it.
+ * Pure host code; needs no GPU.  Checks that every block lies inside the
+ * matrix, that the blocks are pairwise disjoint and cover all of it
+ * (Eqs. 1-2; else HMAT_E_LAYOUT), that ranks satisfy Eq. 3 and that all data
+ * offsets are in range (else HMAT_E_ARG).  `out` receives the sizes. */
+int hmat_plan(const hmat_blocks *blocks, const hmat_build_opts *opts, hmat_plan_info *out);
+
+/* Convert the FP64 blocks to the requested variant (Sec. 4.1.3: the matrix is
+ * generated in FP64 and converted afterwards; Methods 2 and 3 decompose in
+ * FP64 before rounding) and pack them into the caller's device buffer
+ * `dev_mem` (256-byte aligned, at least plan.device_bytes bytes).  The copy
+ * is enqueued on `stream` and completed before the call returns, so the
+ * host arrays may be freed afterwards.  The handle does not own dev_mem: the
+ * caller keeps it alive until hmat_destroy and frees it afterwards.  The
+ * buffer also holds the per-handle product workspace, so two products with
+ * the same handle must not run concurrently on different streams. */
+int hmat_build(const hmat_blocks *blocks, const hmat_build_opts *opts, void *dev_mem, uint64_t dev_bytes,
+               void *stream, hmat_t *out);
+
+/* y = A~ x (Eq. 5) for nrhs right-hand sides.  x and y are device arrays of
+ * FP64, column-major n x nrhs with leading dimension ld >= n; y is
+ * overwritten and may alias x.  1 <= nrhs <= nrhs_max of the build.
+ * Asynchronous on `stream`; no host synchronisation. */
+int hmat_matvec(hmat_t h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream);
+
+/* Release the host-side handle state (not the caller's device buffer). */
+int hmat_destroy(hmat_t h);
+
+typedef struct {
+    int64_t n, nblocks, nblocks_dense, nblocks_lowrank, max_rank;
+    int64_t row_chunks;       /* stage-2 work units (row ownership) */
+    int64_t column_groups;    /* stage-1 groups of low-rank factors sharing J_m */
+    int64_t stage1_items;     /* stage-1 work units */
+    int64_t z_len;            /* number of z_m entries */
+    uint64_t bytes_dense;     /* stored dense values */
+    uint64_t bytes_v;         /* stored V'_m values */
+    uint64_t bytes_w;         /* stored W'_m values */
+    uint64_t bytes_packed;    /* values incl. row padding as laid out in HBM */
+    uint64_t bytes_index;     /* gather indices and descriptors */
+    uint64_t algorithmic_bytes;        /* per product at nrhs = 1 (see hmat_plan_info) */
+    uint64_t stage1_algorithmic_bytes; /* W' values + x reads + z writes */
+    uint64_t stage2_algorithmic_bytes; /* dense + V' values + x/z reads + y writes */
+    int32_t precision;
+    int32_t c;
+} hmat_stats;
+
+int hmat_get_stats(hmat_t h, hmat_stats *out);
+
+/* ------------------------------------------------------------- solver */
+/* Right preconditioner K for hmat_bicgstab (a fixed linear map; not from the
+ * paper).  HMAT_PRECOND_JACOBI inverts every dense diagonal block of the
+ * handle's FP64 source blocks (Gauss-Jordan with partial pivoting, FP64) and
+ * applies y_tau = A_tautau^{-1} x_tau on each; rows of no diagonal dense
+ * block pass through unchanged. */
+typedef struct hmat_precond_s *hmat_precond_t;
+enum { HMAT_PRECOND_NONE = 0, HMAT_PRECOND_JACOBI = 1 };
+
+/* Device bytes hmat_precond_create needs for `blocks`. */
+int hmat_precond_plan(const hmat_blocks *blocks, int32_t kind, uint64_t *device_bytes);
+int hmat_precond_create(const hmat_blocks *blocks, int32_t kind, void *dev_mem, uint64_t dev_bytes, void *stream,
+                        hmat_precond_t *out);
+/* y = K x for one vector (device FP64, length n); y must not alias x. */
+int hmat_precond_apply(hmat_precond_t p, const double *x, double *y, void *stream);
+int hmat_precond_destroy(hmat_precond_t p);
+
+typedef struct {
+    double tol;               /* relative residual |r|/|b| to reach (Sec. 4.1.3 uses 1e-6) */
+    int64_t maxiter;          /* iterations of Algorithm 1's loop */
+    int32_t poll_every;       /* read the device status every this many iterations (>= 1) */
+    int32_t use_graph;        /* 1: capture one iteration in a HIP graph and replay it */
+    hmat_precond_t precond;   /* NULL: no preconditioner */
+    double *history;          /* host, maxiter + 1 entries, or NULL: |r_i|/|b| per iteration */
+} hmat_solve_opts;
+
+typedef struct {
+    int32_t status;           /* HMAT_OK, HMAT_E_BREAKDOWN, HMAT_E_NOCONV or HMAT_E_NONFINITE */
+    int32_t restarts;         /* restarts after a failed true-residual check */
+    int64_t iterations;
+    int64_t matvecs;          /* products with h_iter */
+    int64_t matvecs_fp64;     /* products with h_fp64 (true residuals) */
+    double rel_res;           /* final recurrence |r|/|b| */
+    double true_rel_res;      /* final |b - A~64 x| / |b| */
+} hmat_solve_info;
+
+/* Device bytes of solver workspace for order n. */
+uint64_t hmat_solver_workspace_bytes(int64_t n);
+
+/* BiCGSTAB (Sec. 3.5, Algorithm 1) with h_iter as the operator and every
+ * vector and scalar in FP64 on the device.  x holds x_0 on entry and the
+ * solution on return (device, length n); b is a device vector.  The
+ * iteration stops when |s|/|b| or |r|/|b| < tol; convergence is then
+ * confirmed with the true residual b - A~ x computed with h_fp64 (Sec. 4.1.3;
+ * h_fp64 may equal h_iter).  If that check fails the iteration restarts from
+ * the current x with r = r~ = the true residual.  b = 0 gives x = 0.
+ * `work` is a device buffer of hmat_solver_workspace_bytes(n) bytes.
+ * Synchronises `stream` before returning; `info` is filled in every case. */
+int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, const hmat_solve_opts *opts,
+                  hmat_solve_info *info, void *work, uint64_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------ assembly */
+/* Setup step (untimed; not the product path): build an FP64 H-matrix for the
+ * BEM collocation problem on a triangle mesh -- cluster tree (bisection of
+ * the centroid box across its longest side), admissible block partition
+ * (min(diam) <= eta dist), dense leaves and partially pivoted ACA to the
+ * relative tolerance eps on the admissible blocks.  The paper only names
+ * ACA (Sec. 1) and leaves generation to the library it extends
+ * (Sec. 4.1.3).  Entries: A_ij = a_j / (4 pi |c_i - c_j|), A_ii = sqrt(a_i/pi)/2.
+ * centroids: host, n x 3 row-major; areas: host, n; original panel order. */
+typedef struct {
+    int64_t leaf;             /* largest leaf cluster */
+    double eta;               /* admissibility constant */
+    double eps;               /* ACA relative tolerance */
+    int32_t threads;          /* host threads (0: all hardware threads) */
+    int32_t reserved;
+} hmat_assemble_opts;
+
+typedef struct hmat_assembly_s *hmat_assembly_t;
+
+int hmat_assemble_bem(int64_t n, const double *centroids, const double *areas, const hmat_assemble_opts *opts,
+                      hmat_assembly_t *out);
+/* Fill `view` with pointers into the assembly (valid until hmat_assembly_free). */
+int hmat_assembly_blocks(hmat_assembly_t a, hmat_blocks *view);
+/* perm[k] = original panel index at cluster position k (length n). */
+const int64_t *hmat_assembly_perm(hmat_assembly_t a);
+int hmat_assembly_free(hmat_assembly_t a);
+
+/* ---------------------------------------------------------- diagnostics */
+/* Kernel timing (not from the paper): while enabled, hmat_matvec records
+ * HIP events on its stream around each of its three kernels (stage 1,
+ * stage-1 reduction, stage 2).  hmat_kernel_times waits for the recorded
+ * events, writes the average duration in milliseconds of each kernel over
+ * the products since the previous call into avg_ms[0..2], the number of
+ * products into *count, and resets the averages.  Enabling adds event
+ * records between the kernels but does not change what they compute. */
+int hmat_set_profiling(hmat_t h, int32_t enable);
+int hmat_kernel_times(hmat_t h, double *avg_ms, int64_t *count);
+
+/* Bandwidth calibration kernels (device pointers, 16-byte aligned, bytes a
+ * multiple of 16), asynchronous on `stream`.  hmat_stream_read reads
+ * `bytes` with the same 16-byte non-temporal loads the product uses (sink:
+ * one device double, written only to keep the loads alive);
+ * hmat_stream_copy copies `bytes` from src to dst. */
+int hmat_stream_read(const void *src, uint64_t bytes, double *sink, void *stream);
+int hmat_stream_copy(void *dst, const void *src, uint64_t bytes, void *stream);
+
+/* Library version string. */
+const char *hmat_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMAT_H */

@@ -1,0 +1,558 @@
+// Host side of hmat_plan / hmat_build: validation of the block partition,
+// precision conversion (Sec. 3 of the paper) and the packed HBM layout.
+//
+// Layout, per storage class (FP64 / FP32 / BF16):
+//  * stage-2 panels: for every row chunk (<= 64 rows owned by one
+//    workgroup) a row-major h x K matrix whose columns are the columns of
+//    every dense block covering those rows followed by one column per
+//    low-rank term (the matching rows of V'_m); each panel column k has a
+//    gather index into src = [x_eff (n) | z (zlen) | 0];
+//  * stage-1 groups: all low-rank terms of one class whose blocks share the
+//    column range J_m, stacked as rows of a row-major R x #J matrix (the
+//    rows of W'_m), so one pass over x_J serves every such block.
+// Rows are padded to 16 bytes so every lane load is one aligned 16-byte load.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <thread>
+#include <tuple>
+
+#include "hmat_impl.h"
+
+namespace hm {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+int fail(int code, const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+const char *last_error() { return g_err.c_str(); }
+
+namespace {
+
+// One stored low-rank term after conversion: value = round_cls(src / div).
+struct Term {
+  int32_t l;      // term index in the FP64 factors
+  int32_t cls;
+  double div_v, div_w;
+  double d;       // scale folded into z (D_m entry, or the BF16 scales)
+  int64_t zidx;   // position in z
+};
+
+struct Group {
+  int cls;
+  int64_t col0, ncols;
+  std::vector<std::pair<int64_t, int32_t>> rows;  // (block, term index into Packed::terms[block])
+  int64_t z0 = 0, zp0 = 0, nch = 0, ld = 0, w_off = 0;
+};
+
+// Column run of a stage-2 panel: `count` consecutive columns from one block.
+struct Run {
+  int64_t block;
+  int32_t first;  // dense: first column of the block; low rank: first term index
+  int32_t count;
+};
+
+struct ChunkPlan {
+  int64_t r0, h;
+  std::vector<Run> runs[NCLS];
+  int64_t K[NCLS] = {0, 0, 0};
+};
+
+inline int64_t pad_to(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+}  // namespace
+
+struct Packed {
+  hmat_blocks b{};
+  int precision = 0, c = 0, nrhs_max = 1;
+  int dense_cls = F64;
+  int x32 = 0, z32 = 0;
+  std::vector<std::vector<Term>> terms;  // per block (empty for dense)
+  std::vector<Group> groups;
+  std::vector<ChunkPlan> chunks;
+  std::vector<int64_t> chunk_order;
+  std::vector<S1Item> items;
+  std::vector<ZInfo> zinfo;
+  std::vector<double> dscale;
+  int64_t zlen = 0, zpart_len = 0;
+  int64_t vals_elems[NCLS] = {0, 0, 0};
+  int64_t gidx_elems[NCLS] = {0, 0, 0};
+  DevLayout lay{};
+  hmat_plan_info info{};
+  hmat_stats stats{};
+  std::vector<int64_t> diag_r0, diag_m;
+};
+
+void packed_free(Packed *p) { delete p; }
+
+// Round a double to the nearest bfloat16 (8 significant bits, ties to even)
+// and return its bit pattern.  Works on the binary64 encoding: the 45 low
+// mantissa bits are rounded away, then the value (exact in binary32) is
+// narrowed.  Magnitudes below the smallest normal bfloat16 are rounded on
+// the subnormal grid 2^-133.
+static uint16_t bf16_bits(double v) {
+  float f;
+  if (v != 0.0 && std::fabs(v) < 0x1p-126) {
+    f = (float)(std::nearbyint(v * 0x1p133) * 0x1p-133);
+  } else {
+    uint64_t u;
+    std::memcpy(&u, &v, 8);
+    uint64_t lsb = (u >> 45) & 1u;
+    u += (uint64_t(1) << 44) - 1 + lsb;
+    u &= ~((uint64_t(1) << 45) - 1);
+    double r;
+    std::memcpy(&r, &u, 8);
+    f = (float)r;
+  }
+  uint32_t w;
+  std::memcpy(&w, &f, 4);
+  return (uint16_t)(w >> 16);
+}
+
+static double max_abs(const double *a, int64_t n, int64_t stride) {
+  double m = 0.0;
+  for (int64_t i = 0; i < n; i++) m = std::max(m, std::fabs(a[i * stride]));
+  return m;
+}
+
+// smallest power of two >= m, m > 0
+static double pow2_at_least(double m) {
+  int e;
+  double f = std::frexp(m, &e);
+  return std::ldexp(1.0, f == 0.5 ? e - 1 : e);
+}
+
+int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *info, Packed **out_keep) {
+  if (!b || !o) return fail(HMAT_E_ARG, "null argument");
+  if (o->precision < HMAT_M1_DOUBLE || o->precision > HMAT_BF16_SCALED)
+    return fail(HMAT_E_ARG, "unknown precision %d", o->precision);
+  if (o->nrhs_max < 1 || o->nrhs_max > 4096) return fail(HMAT_E_ARG, "nrhs_max %d out of range", o->nrhs_max);
+  if (o->reserved != 0) return fail(HMAT_E_ARG, "reserved field must be 0");
+  const int64_t n = b->n;
+  if (n <= 0 || n > (int64_t(1) << 30)) return fail(HMAT_E_ARG, "matrix order %lld out of range", (long long)n);
+  if (b->nblocks <= 0) return fail(HMAT_E_ARG, "no blocks");
+  if (!b->row0 || !b->nrows || !b->col0 || !b->ncols || !b->kind || !b->rank || !b->offset || (!b->data && b->ndata))
+    return fail(HMAT_E_ARG, "null block array");
+  const int64_t nb = b->nblocks;
+  for (int64_t k = 0; k < nb; k++) {
+    int64_t r0 = b->row0[k], m = b->nrows[k], c0 = b->col0[k], nc = b->ncols[k];
+    if (r0 < 0 || m <= 0 || r0 + m > n || c0 < 0 || nc <= 0 || c0 + nc > n)
+      return fail(HMAT_E_ARG, "block %lld outside the matrix", (long long)k);
+    int64_t need;
+    if (b->kind[k] == HMAT_DENSE) {
+      need = m * nc;
+    } else if (b->kind[k] == HMAT_LOWRANK) {
+      int64_t r = b->rank[k];
+      if (r < 0 || r > std::min(m, nc)) return fail(HMAT_E_ARG, "block %lld: rank %lld violates r <= min(#I,#J)", (long long)k, (long long)r);
+      need = r * (m + nc);
+    } else {
+      return fail(HMAT_E_ARG, "block %lld: unknown kind %d", (long long)k, b->kind[k]);
+    }
+    if (b->offset[k] < 0 || b->offset[k] + need > b->ndata)
+      return fail(HMAT_E_ARG, "block %lld: data range outside the data array", (long long)k);
+  }
+
+  auto *P = new Packed();
+  P->b = *b;
+  P->precision = o->precision;
+  P->c = o->c;
+  P->nrhs_max = o->nrhs_max;
+  const int prec = o->precision;
+  P->dense_cls = (prec == HMAT_M1_DOUBLE || prec == HMAT_M2_DOUBLE || prec == HMAT_M3) ? F64 : F32;
+  P->x32 = (prec == HMAT_M1_SINGLE || prec == HMAT_M2_SINGLE);
+  P->z32 = (prec == HMAT_M1_SINGLE || prec == HMAT_M1_MIXED);
+
+  // ---- partition check (Eqs. 1-2): cut the rows at every block boundary;
+  // within each row segment the covering blocks must tile [0, n) exactly.
+  std::vector<int64_t> cuts;
+  cuts.reserve(2 * nb + 2);
+  cuts.push_back(0);
+  cuts.push_back(n);
+  for (int64_t k = 0; k < nb; k++) {
+    cuts.push_back(b->row0[k]);
+    cuts.push_back(b->row0[k] + b->nrows[k]);
+  }
+  std::sort(cuts.begin(), cuts.end());
+  cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
+  const int64_t nseg = (int64_t)cuts.size() - 1;
+  std::vector<std::vector<int64_t>> seg_blocks(nseg);
+  for (int64_t k = 0; k < nb; k++) {
+    int64_t s0 = std::lower_bound(cuts.begin(), cuts.end(), b->row0[k]) - cuts.begin();
+    int64_t s1 = std::lower_bound(cuts.begin(), cuts.end(), b->row0[k] + b->nrows[k]) - cuts.begin();
+    for (int64_t s = s0; s < s1; s++) seg_blocks[s].push_back(k);
+  }
+  for (int64_t s = 0; s < nseg; s++) {
+    auto &v = seg_blocks[s];
+    std::sort(v.begin(), v.end(), [&](int64_t a, int64_t c) {
+      return b->col0[a] != b->col0[c] ? b->col0[a] < b->col0[c] : a < c;
+    });
+    int64_t at = 0;
+    for (int64_t k : v) {
+      if (b->col0[k] != at) {
+        delete P;
+        return fail(HMAT_E_LAYOUT, "rows [%lld,%lld): %s at column %lld (Eqs. 1-2 require a disjoint cover)",
+                    (long long)cuts[s], (long long)cuts[s + 1], b->col0[k] < at ? "blocks overlap" : "gap",
+                    (long long)std::min(at, b->col0[k]));
+      }
+      at += b->ncols[k];
+    }
+    if (at != n) {
+      delete P;
+      return fail(HMAT_E_LAYOUT, "rows [%lld,%lld): columns [%lld,%lld) uncovered", (long long)cuts[s],
+                  (long long)cuts[s + 1], (long long)at, (long long)n);
+    }
+  }
+
+  // ---- conversion decisions per low-rank block
+  P->terms.assign(nb, {});
+  int64_t nterms[NCLS] = {0, 0, 0}, max_rank = 0, ndense = 0, nlr = 0;
+  for (int64_t k = 0; k < nb; k++) {
+    if (b->kind[k] == HMAT_DENSE) {
+      ndense++;
+      if (b->row0[k] == b->col0[k] && b->nrows[k] == b->ncols[k]) {
+        P->diag_r0.push_back(b->row0[k]);
+        P->diag_m.push_back(b->nrows[k]);
+      }
+      continue;
+    }
+    nlr++;
+    const int64_t m = b->nrows[k], nc = b->ncols[k], r = b->rank[k];
+    max_rank = std::max(max_rank, r);
+    const double *U = b->data + b->offset[k];
+    const double *Wt = U + m * r;
+    auto &T = P->terms[k];
+    if (prec <= HMAT_M1_MIXED) {
+      for (int32_t l = 0; l < r; l++) T.push_back({l, prec == HMAT_M1_DOUBLE ? F64 : F32, 1.0, 1.0, 1.0, 0});
+    } else if (prec == HMAT_BF16_SCALED) {
+      double mu = max_abs(U, m * r, 1), mw = max_abs(Wt, nc * r, 1);
+      double sv = mu > 0 ? pow2_at_least(mu) : 1.0, sw = mw > 0 ? pow2_at_least(mw) : 1.0;
+      for (int32_t l = 0; l < r; l++) T.push_back({l, BF16, sv, sw, sv * sw, 0});
+    } else {
+      // Method 2 (Eqs. 13-16): D_V, D_W from the column / row maxima.
+      std::vector<double> dv(r), dw(r);
+      double dmax = 0.0;
+      for (int64_t l = 0; l < r; l++) {
+        dv[l] = max_abs(U + l * m, m, 1);
+        dw[l] = max_abs(Wt + l * nc, nc, 1);
+        dmax = std::max(dmax, dv[l] * dw[l]);
+      }
+      // Method 3 (Eqs. 19-20): FP32 iff d_i < d_max 10^-c; FP64 terms first.
+      const double thr = dmax * std::pow(10.0, -(double)o->c);
+      for (int pass = 0; pass < 2; pass++)
+        for (int32_t l = 0; l < r; l++) {
+          if (!(dv[l] > 0.0 && dw[l] > 0.0)) continue;  // an all-zero term is dropped
+          const double d = dv[l] * dw[l];
+          int cls;
+          if (prec == HMAT_M2_DOUBLE) cls = F64;
+          else if (prec == HMAT_M2_SINGLE || prec == HMAT_M2_MIXED) cls = F32;
+          else cls = d >= thr ? F64 : F32;
+          if ((pass == 0) != (cls == F64)) continue;
+          T.push_back({l, cls, dv[l], dw[l], d, 0});
+        }
+    }
+    for (auto &t : T) nterms[t.cls]++;
+  }
+
+  // ---- stage-1 column groups and z numbering
+  std::map<std::tuple<int, int64_t, int64_t>, int64_t> gmap;
+  for (int64_t k = 0; k < nb; k++) {
+    auto &T = P->terms[k];
+    for (int32_t t = 0; t < (int32_t)T.size(); t++) {
+      auto key = std::make_tuple(T[t].cls, b->col0[k], b->ncols[k]);
+      auto it = gmap.find(key);
+      if (it == gmap.end()) {
+        Group g;
+        g.cls = T[t].cls;
+        g.col0 = b->col0[k];
+        g.ncols = b->ncols[k];
+        it = gmap.emplace(key, (int64_t)P->groups.size()).first;
+        P->groups.push_back(std::move(g));
+      }
+      P->groups[it->second].rows.emplace_back(k, t);
+    }
+  }
+  int64_t z = 0, zp = 0;
+  for (auto &kv : gmap) {  // key order: class, then column range
+    Group &g = P->groups[kv.second];
+    const int64_t R = (int64_t)g.rows.size();
+    const int cls = g.cls;
+    const int64_t CH = (int64_t)s1_slabs(cls) * kWave * vec_of(cls);
+    g.z0 = z;
+    g.zp0 = zp;
+    g.nch = (g.ncols + CH - 1) / CH;
+    g.ld = pad_to(g.ncols, vec_of(cls));
+    g.w_off = P->vals_elems[cls];
+    P->vals_elems[cls] += R * g.ld;
+    for (int64_t k = 0; k < R; k++) {
+      auto [blk, t] = g.rows[k];
+      P->terms[blk][t].zidx = z + k;
+      P->zinfo.push_back({zp + k, (int32_t)g.nch, (int32_t)R});
+      P->dscale.push_back(P->terms[blk][t].d);
+    }
+    for (int64_t ch = 0; ch < g.nch; ch++) {
+      const int64_t c0 = ch * CH, cn = std::min(CH, g.ncols - c0);
+      for (int64_t k0 = 0; k0 < R; k0 += kS1RowsMax) {
+        S1Item it{};
+        it.w_off = g.w_off + k0 * g.ld + c0;
+        it.x0 = g.col0 + c0;
+        it.out_off = zp + ch * R + k0;
+        it.ld = (int32_t)g.ld;
+        it.ncols = (int32_t)cn;
+        it.nrows = (int32_t)std::min<int64_t>(kS1RowsMax, R - k0);
+        it.cls = cls;
+        P->items.push_back(it);
+      }
+    }
+    z += R;
+    zp += g.nch * R;
+  }
+  P->zlen = z;
+  P->zpart_len = zp;
+  if (n + z + 1 >= (int64_t(1) << 31)) {
+    delete P;
+    return fail(HMAT_E_ARG, "n + z exceeds the 32-bit gather index range");
+  }
+  // stage-1 items: largest first so the tail of the launch is short
+  std::stable_sort(P->items.begin(), P->items.end(), [](const S1Item &a, const S1Item &c) {
+    return (int64_t)a.ncols * a.nrows * bytes_of(a.cls) > (int64_t)c.ncols * c.nrows * bytes_of(c.cls);
+  });
+
+  // ---- stage-2 row chunks (segments cut into <= 64 rows)
+  for (int64_t s = 0; s < nseg; s++) {
+    for (int64_t r0 = cuts[s]; r0 < cuts[s + 1]; r0 += kRowChunk) {
+      ChunkPlan cp;
+      cp.r0 = r0;
+      cp.h = std::min<int64_t>(kRowChunk, cuts[s + 1] - r0);
+      for (int64_t k : seg_blocks[s]) {
+        if (b->kind[k] == HMAT_DENSE) {
+          cp.runs[P->dense_cls].push_back({k, 0, (int32_t)b->ncols[k]});
+          cp.K[P->dense_cls] += b->ncols[k];
+        } else {
+          auto &T = P->terms[k];
+          int32_t t = 0;
+          while (t < (int32_t)T.size()) {  // runs of equal class (M3: FP64 terms first)
+            int32_t e = t;
+            while (e < (int32_t)T.size() && T[e].cls == T[t].cls) e++;
+            cp.runs[T[t].cls].push_back({k, t, e - t});
+            cp.K[T[t].cls] += e - t;
+            t = e;
+          }
+        }
+      }
+      P->chunks.push_back(std::move(cp));
+    }
+  }
+  for (auto &cp : P->chunks)
+    for (int c = 0; c < NCLS; c++) {
+      if (!cp.K[c]) continue;
+      const int64_t ld = pad_to(cp.K[c], vec_of(c));
+      P->vals_elems[c] += cp.h * ld;
+      P->gidx_elems[c] += ld;
+    }
+  // chunk order: most bytes first
+  P->chunk_order.resize(P->chunks.size());
+  for (size_t i = 0; i < P->chunks.size(); i++) P->chunk_order[i] = (int64_t)i;
+  auto cbytes = [&](int64_t i) {
+    int64_t s = 0;
+    for (int c = 0; c < NCLS; c++) s += P->chunks[i].h * P->chunks[i].K[c] * bytes_of(c);
+    return s;
+  };
+  std::stable_sort(P->chunk_order.begin(), P->chunk_order.end(),
+                   [&](int64_t a, int64_t c) { return cbytes(a) > cbytes(c); });
+
+  // ---- device layout
+  DevLayout &L = P->lay;
+  uint64_t at = 0;
+  auto take = [&](uint64_t bytes) {
+    uint64_t o2 = at;
+    at += (bytes + 255) / 256 * 256;
+    return o2;
+  };
+  for (int c = 0; c < NCLS; c++) {
+    L.bytes_vals[c] = (uint64_t)P->vals_elems[c] * bytes_of(c);
+    L.off_vals[c] = take(L.bytes_vals[c]);
+  }
+  for (int c = 0; c < NCLS; c++) {
+    L.bytes_gidx[c] = (uint64_t)P->gidx_elems[c] * 4;
+    L.off_gidx[c] = take(L.bytes_gidx[c]);
+  }
+  L.off_chunks = take(P->chunks.size() * sizeof(RowChunk));
+  L.off_items = take(P->items.size() * sizeof(S1Item));
+  L.off_zinfo = take(P->zinfo.size() * sizeof(ZInfo));
+  L.off_dscale = take(P->dscale.size() * sizeof(double));
+  L.off_src = take((uint64_t)P->nrhs_max * (n + P->zlen + 1) * sizeof(double));
+  L.off_zpart = take((uint64_t)P->nrhs_max * std::max<int64_t>(P->zpart_len, 1) * sizeof(double));
+  L.total = at;
+
+  // ---- sizes and statistics
+  uint64_t bd = 0, bv = 0, bw = 0;
+  for (int64_t k = 0; k < nb; k++) {
+    if (b->kind[k] == HMAT_DENSE) {
+      bd += (uint64_t)b->nrows[k] * b->ncols[k] * bytes_of(P->dense_cls);
+    } else {
+      for (auto &t : P->terms[k]) {
+        bv += (uint64_t)b->nrows[k] * bytes_of(t.cls);
+        bw += (uint64_t)b->ncols[k] * bytes_of(t.cls);
+      }
+    }
+  }
+  const bool has_d = prec >= HMAT_M2_DOUBLE;
+  const uint64_t xbytes = (uint64_t)n * (P->x32 ? 4 : 8);
+  hmat_plan_info &I = P->info;
+  I.device_bytes = L.total;
+  I.matrix_bytes = bd + bv + bw;
+  I.algorithmic_bytes = bd + bv + bw + (has_d || prec == HMAT_BF16_SCALED ? (uint64_t)P->zlen * 8 : 0) + xbytes + 8ull * n;
+  I.nblocks_dense = ndense;
+  I.nblocks_lowrank = nlr;
+  I.max_rank = max_rank;
+  I.terms_fp64 = nterms[F64];
+  I.terms_fp32 = nterms[F32];
+  I.terms_bf16 = nterms[BF16];
+  hmat_stats &S = P->stats;
+  S.n = n;
+  S.nblocks = nb;
+  S.nblocks_dense = ndense;
+  S.nblocks_lowrank = nlr;
+  S.max_rank = max_rank;
+  S.row_chunks = (int64_t)P->chunks.size();
+  S.column_groups = (int64_t)P->groups.size();
+  S.stage1_items = (int64_t)P->items.size();
+  S.z_len = P->zlen;
+  S.bytes_dense = bd;
+  S.bytes_v = bv;
+  S.bytes_w = bw;
+  S.bytes_packed = L.bytes_vals[0] + L.bytes_vals[1] + L.bytes_vals[2];
+  S.bytes_index = L.bytes_gidx[0] + L.bytes_gidx[1] + L.bytes_gidx[2] + P->chunks.size() * sizeof(RowChunk) +
+                  P->items.size() * sizeof(S1Item) + P->zinfo.size() * sizeof(ZInfo);
+  S.algorithmic_bytes = I.algorithmic_bytes;
+  S.stage1_algorithmic_bytes = bw + (has_d || prec == HMAT_BF16_SCALED ? (uint64_t)P->zlen * 8 : 0) + xbytes;
+  S.stage2_algorithmic_bytes = bd + bv + 8ull * n;
+  S.precision = prec;
+  S.c = o->c;
+  if (info) *info = I;
+  if (out_keep) *out_keep = P;
+  else delete P;
+  return HMAT_OK;
+}
+
+// Fill the staging image of the device buffer.
+int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
+  const hmat_blocks *b = &P->b;
+  const DevLayout &L = P->lay;
+  const int64_t n = b->n;
+  try {
+    img.assign(L.off_src, 0);  // workspace (src, zpart) needs no initial contents
+  } catch (...) {
+    return fail(HMAT_E_NOMEM, "cannot allocate %llu bytes of host staging", (unsigned long long)L.off_src);
+  }
+  unsigned char *base = img.data();
+  auto put = [&](int cls, int64_t idx, double v) {
+    unsigned char *p = base + L.off_vals[cls];
+    if (cls == F64) {
+      ((double *)p)[idx] = v;
+    } else if (cls == F32) {
+      ((float *)p)[idx] = (float)v;
+    } else {
+      ((uint16_t *)p)[idx] = bf16_bits(v);
+    }
+  };
+  // value of a low-rank term's V' entry / W' entry
+  auto vval = [&](int64_t k, const Term &t, int64_t i) {
+    const double *U = b->data + b->offset[k];
+    return U[i + (int64_t)t.l * b->nrows[k]] / t.div_v;
+  };
+  auto wval = [&](int64_t k, const Term &t, int64_t j) {
+    const double *Wt = b->data + b->offset[k] + b->nrows[k] * (int64_t)b->rank[k];
+    return Wt[j + (int64_t)t.l * b->ncols[k]] / t.div_w;
+  };
+
+  // stage-2 panels and gather indices, in launch order
+  std::vector<RowChunk> rc(P->chunks.size());
+  int64_t voff[NCLS] = {0, 0, 0}, goff[NCLS] = {0, 0, 0};
+  for (auto &g : P->groups) voff[g.cls] = std::max(voff[g.cls], g.w_off + (int64_t)g.rows.size() * g.ld);
+  for (size_t q = 0; q < P->chunk_order.size(); q++) {
+    const ChunkPlan &cp = P->chunks[P->chunk_order[q]];
+    RowChunk &R = rc[q];
+    R.r0 = (int32_t)cp.r0;
+    R.h = (int32_t)cp.h;
+    for (int c = 0; c < NCLS; c++) {
+      R.K[c] = (int32_t)cp.K[c];
+      R.ld[c] = cp.K[c] ? (int32_t)pad_to(cp.K[c], vec_of(c)) : 0;
+      R.panel_off[c] = voff[c];
+      R.gidx_off[c] = goff[c];
+      if (!cp.K[c]) continue;
+      int32_t *gi = (int32_t *)(base + L.off_gidx[c]) + goff[c];
+      int64_t col = 0;
+      for (const Run &run : cp.runs[c]) {
+        const int64_t k = run.block;
+        for (int32_t e = 0; e < run.count; e++, col++) {
+          if (b->kind[k] == HMAT_DENSE) {
+            gi[col] = (int32_t)(b->col0[k] + run.first + e);
+            const double *A = b->data + b->offset[k];
+            for (int64_t i = 0; i < cp.h; i++)
+              put(c, voff[c] + i * R.ld[c] + col, A[(cp.r0 - b->row0[k] + i) + (run.first + e) * b->nrows[k]]);
+          } else {
+            const Term &t = P->terms[k][run.first + e];
+            gi[col] = (int32_t)(n + t.zidx);
+            for (int64_t i = 0; i < cp.h; i++) put(c, voff[c] + i * R.ld[c] + col, vval(k, t, cp.r0 - b->row0[k] + i));
+          }
+        }
+      }
+      for (; col < R.ld[c]; col++) gi[col] = (int32_t)(n + P->zlen);  // padding reads the zero slot
+      voff[c] += cp.h * R.ld[c];
+      goff[c] += R.ld[c];
+    }
+  }
+  // stage-1 W' rows
+  for (auto &g : P->groups)
+    for (size_t r = 0; r < g.rows.size(); r++) {
+      auto [k, ti] = g.rows[r];
+      const Term &t = P->terms[k][ti];
+      for (int64_t j = 0; j < g.ncols; j++) put(g.cls, g.w_off + (int64_t)r * g.ld + j, wval(k, t, j));
+    }
+  std::memcpy(base + L.off_chunks, rc.data(), rc.size() * sizeof(RowChunk));
+  std::memcpy(base + L.off_items, P->items.data(), P->items.size() * sizeof(S1Item));
+  std::memcpy(base + L.off_zinfo, P->zinfo.data(), P->zinfo.size() * sizeof(ZInfo));
+  std::memcpy(base + L.off_dscale, P->dscale.data(), P->dscale.size() * sizeof(double));
+
+  h->n = n;
+  h->precision = P->precision;
+  h->c = P->c;
+  h->nrhs_max = P->nrhs_max;
+  h->x32 = P->x32;
+  h->z32 = P->z32;
+  h->nchunks = (int64_t)P->chunks.size();
+  h->nitems = (int64_t)P->items.size();
+  h->zlen = P->zlen;
+  h->zpart_len = P->zpart_len;
+  h->src_len = n + P->zlen + 1;
+  h->lay = L;
+  h->stats = P->stats;
+  h->diag_r0 = P->diag_r0;
+  h->diag_m = P->diag_m;
+  return HMAT_OK;
+}
+
+}  // namespace hm
+
+extern "C" const char *hmat_last_error(void) { return hm::last_error(); }

@@ -1,0 +1,362 @@
+"""Python binding of ``include/hmat.h`` (ctypes; argument marshalling only).
+
+Every step of the product and of the solver runs in ``libhmat.so``; this
+module only converts numpy arrays and torch device tensors into the plain
+pointers and sizes of the C ABI.  torch provides device memory and streams.
+If the native library is missing, loading fails loudly: there is no
+fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhmat.so")
+
+HMAT_OK, HMAT_E_ARG, HMAT_E_LAYOUT, HMAT_E_WORKSPACE, HMAT_E_HIP, HMAT_E_BREAKDOWN, HMAT_E_NOCONV, \
+    HMAT_E_NONFINITE, HMAT_E_NOMEM = range(9)
+STATUS_NAMES = ["OK", "E_ARG", "E_LAYOUT", "E_WORKSPACE", "E_HIP", "E_BREAKDOWN", "E_NOCONV", "E_NONFINITE", "E_NOMEM"]
+
+M1_DOUBLE, M1_SINGLE, M1_MIXED, M2_DOUBLE, M2_SINGLE, M2_MIXED, M3, BF16_SCALED = range(8)
+PRECISION_NAMES = ["M1-Double", "M1-Single", "M1-Mixed", "M2-Double", "M2-Single", "M2-Mixed", "M3", "BF16-scaled"]
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
+
+EXPORTED = [
+    "hmat_last_error", "hmat_plan", "hmat_build", "hmat_matvec", "hmat_destroy", "hmat_get_stats",
+    "hmat_precond_plan", "hmat_precond_create", "hmat_precond_apply", "hmat_precond_destroy",
+    "hmat_solver_workspace_bytes", "hmat_bicgstab", "hmat_assemble_bem", "hmat_assembly_blocks",
+    "hmat_assembly_perm", "hmat_assembly_free", "hmat_version", "hmat_set_profiling", "hmat_kernel_times",
+    "hmat_stream_read", "hmat_stream_copy",
+]
+
+
+class HmatError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES[code] if 0 <= code < len(STATUS_NAMES) else code}: {msg}")
+        self.code = code
+
+
+class hmat_blocks(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nblocks", C.c_int64),
+                ("row0", C.c_void_p), ("nrows", C.c_void_p), ("col0", C.c_void_p), ("ncols", C.c_void_p),
+                ("kind", C.c_void_p), ("rank", C.c_void_p), ("offset", C.c_void_p),
+                ("data", C.c_void_p), ("ndata", C.c_int64)]
+
+
+class hmat_build_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("c", C.c_int32), ("nrhs_max", C.c_int32), ("reserved", C.c_int32)]
+
+
+class hmat_plan_info(C.Structure):
+    _fields_ = [("device_bytes", C.c_uint64), ("matrix_bytes", C.c_uint64), ("algorithmic_bytes", C.c_uint64),
+                ("nblocks_dense", C.c_int64), ("nblocks_lowrank", C.c_int64), ("max_rank", C.c_int64),
+                ("terms_fp64", C.c_int64), ("terms_fp32", C.c_int64), ("terms_bf16", C.c_int64)]
+
+
+class hmat_stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nblocks", C.c_int64), ("nblocks_dense", C.c_int64),
+                ("nblocks_lowrank", C.c_int64), ("max_rank", C.c_int64), ("row_chunks", C.c_int64),
+                ("column_groups", C.c_int64), ("stage1_items", C.c_int64), ("z_len", C.c_int64),
+                ("bytes_dense", C.c_uint64), ("bytes_v", C.c_uint64), ("bytes_w", C.c_uint64),
+                ("bytes_packed", C.c_uint64), ("bytes_index", C.c_uint64), ("algorithmic_bytes", C.c_uint64),
+                ("stage1_algorithmic_bytes", C.c_uint64), ("stage2_algorithmic_bytes", C.c_uint64),
+                ("precision", C.c_int32), ("c", C.c_int32)]
+
+
+class hmat_solve_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("maxiter", C.c_int64), ("poll_every", C.c_int32), ("use_graph", C.c_int32),
+                ("precond", C.c_void_p), ("history", C.c_void_p)]
+
+
+class hmat_solve_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("restarts", C.c_int32), ("iterations", C.c_int64),
+                ("matvecs", C.c_int64), ("matvecs_fp64", C.c_int64), ("rel_res", C.c_double),
+                ("true_rel_res", C.c_double)]
+
+
+class hmat_assemble_opts(C.Structure):
+    _fields_ = [("leaf", C.c_int64), ("eta", C.c_double), ("eps", C.c_double), ("threads", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhmat.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"native library {LIB_PATH} is missing: run `python -m paper_1911_00093_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+    sig = {
+        "hmat_last_error": (C.c_char_p, []),
+        "hmat_version": (C.c_char_p, []),
+        "hmat_plan": (C.c_int, [P, P, P]),
+        "hmat_build": (C.c_int, [P, P, P, U64, P, P]),
+        "hmat_matvec": (C.c_int, [P, P, P, I64, I64, P]),
+        "hmat_destroy": (C.c_int, [P]),
+        "hmat_get_stats": (C.c_int, [P, P]),
+        "hmat_precond_plan": (C.c_int, [P, I32, P]),
+        "hmat_precond_create": (C.c_int, [P, I32, P, U64, P, P]),
+        "hmat_precond_apply": (C.c_int, [P, P, P, P]),
+        "hmat_precond_destroy": (C.c_int, [P]),
+        "hmat_solver_workspace_bytes": (U64, [I64]),
+        "hmat_bicgstab": (C.c_int, [P, P, P, P, P, P, P, U64, P]),
+        "hmat_assemble_bem": (C.c_int, [I64, P, P, P, P]),
+        "hmat_assembly_blocks": (C.c_int, [P, P]),
+        "hmat_assembly_perm": (C.POINTER(C.c_int64), [P]),
+        "hmat_assembly_free": (C.c_int, [P]),
+        "hmat_set_profiling": (C.c_int, [P, I32]),
+        "hmat_kernel_times": (C.c_int, [P, P, P]),
+        "hmat_stream_read": (C.c_int, [P, U64, P, P]),
+        "hmat_stream_copy": (C.c_int, [P, P, U64, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code != HMAT_OK:
+        raise HmatError(code, lib().hmat_last_error().decode())
+
+
+def _p(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+# ----------------------------------------------------------------- blocks
+@dataclass
+class BlockSet:
+    """An FP64 H-matrix in the ABI's block format (host numpy arrays)."""
+
+    n: int
+    row0: np.ndarray
+    nrows: np.ndarray
+    col0: np.ndarray
+    ncols: np.ndarray
+    kind: np.ndarray
+    rank: np.ndarray
+    offset: np.ndarray
+    data: np.ndarray
+    perm: np.ndarray | None = None
+    _owner: object = None
+
+    @classmethod
+    def from_arrays(cls, n, row0, nrows, col0, ncols, kind, rank, offset, data, perm=None):
+        f = lambda a, t: np.ascontiguousarray(a, dtype=t)
+        return cls(int(n), f(row0, np.int64), f(nrows, np.int64), f(col0, np.int64), f(ncols, np.int64),
+                   f(kind, np.int32), f(rank, np.int32), f(offset, np.int64), f(data, np.float64),
+                   None if perm is None else f(perm, np.int64))
+
+    @property
+    def nblocks(self):
+        return int(self.row0.size)
+
+    def struct(self) -> hmat_blocks:
+        return hmat_blocks(self.n, self.nblocks, self.row0.ctypes.data, self.nrows.ctypes.data,
+                           self.col0.ctypes.data, self.ncols.ctypes.data, self.kind.ctypes.data,
+                           self.rank.ctypes.data, self.offset.ctypes.data, self.data.ctypes.data, self.data.size)
+
+
+class _Assembly:
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def __del__(self):
+        if self.ptr:
+            lib().hmat_assembly_free(self.ptr)
+            self.ptr = None
+
+
+def hmat_assemble_bem(centroids, areas, leaf=64, eta=2.0, eps=1e-5, threads=0) -> BlockSet:
+    """Setup: FP64 H-matrix of the BEM collocation problem (host, multi-threaded)."""
+    cent = np.ascontiguousarray(centroids, dtype=np.float64).reshape(-1, 3)
+    area = np.ascontiguousarray(areas, dtype=np.float64)
+    n = cent.shape[0]
+    o = hmat_assemble_opts(int(leaf), float(eta), float(eps), int(threads), 0)
+    out = C.c_void_p()
+    _check(lib().hmat_assemble_bem(n, _p(cent), _p(area), C.byref(o), C.byref(out)))
+    owner = _Assembly(out)
+    v = hmat_blocks()
+    _check(lib().hmat_assembly_blocks(out, C.byref(v)))
+    nb = v.nblocks
+
+    def view(addr, count, ctype, dtype):
+        if count == 0:
+            return np.zeros(0, dtype)
+        return np.ctypeslib.as_array(C.cast(addr, C.POINTER(ctype)), shape=(count,)).view(dtype)
+
+    perm = np.ctypeslib.as_array(lib().hmat_assembly_perm(out), shape=(n,))
+    return BlockSet(n, view(v.row0, nb, C.c_int64, np.int64), view(v.nrows, nb, C.c_int64, np.int64),
+                    view(v.col0, nb, C.c_int64, np.int64), view(v.ncols, nb, C.c_int64, np.int64),
+                    view(v.kind, nb, C.c_int32, np.int32), view(v.rank, nb, C.c_int32, np.int32),
+                    view(v.offset, nb, C.c_int64, np.int64), view(v.data, v.ndata, C.c_double, np.float64),
+                    perm, owner)
+
+
+def hmat_plan(blocks: BlockSet, precision: int, c: int = 0, nrhs_max: int = 1) -> hmat_plan_info:
+    info = hmat_plan_info()
+    s = blocks.struct()
+    o = hmat_build_opts(int(precision), int(c), int(nrhs_max), 0)
+    _check(lib().hmat_plan(C.byref(s), C.byref(o), C.byref(info)))
+    return info
+
+
+# ----------------------------------------------------------------- device
+class HMatrix:
+    """A packed H-matrix on the device (hmat_build); owns its torch buffer."""
+
+    def __init__(self, blocks: BlockSet, precision: int, c: int = 0, nrhs_max: int = 1, device="cuda", stream=None):
+        import torch
+
+        self.precision, self.c, self.nrhs_max = int(precision), int(c), int(nrhs_max)
+        self.plan = hmat_plan(blocks, precision, c, nrhs_max)
+        self.n = blocks.n
+        self.buf = torch.empty(int(self.plan.device_bytes), dtype=torch.uint8, device=device)
+        s = blocks.struct()
+        o = hmat_build_opts(self.precision, self.c, self.nrhs_max, 0)
+        h = C.c_void_p()
+        _check(lib().hmat_build(C.byref(s), C.byref(o), C.c_void_p(self.buf.data_ptr()), self.buf.numel(),
+                                _stream_ptr(stream), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().hmat_destroy(self.h)
+            self.h = None
+
+    def stats(self) -> hmat_stats:
+        st = hmat_stats()
+        _check(lib().hmat_get_stats(self.h, C.byref(st)))
+        return st
+
+    def matvec(self, x, y=None, stream=None):
+        """y = A~ x for a device FP64 tensor of shape (n,) or (n, nrhs) (column-major: x.T contiguous)."""
+        return hmat_matvec(self, x, y, stream)
+
+    def set_profiling(self, enable=True):
+        _check(lib().hmat_set_profiling(self.h, int(bool(enable))))
+
+    def kernel_times(self):
+        """(avg ms of stage 1, stage-1 reduction, stage 2), number of products."""
+        out = (C.c_double * 3)()
+        cnt = C.c_int64()
+        _check(lib().hmat_kernel_times(self.h, out, C.byref(cnt)))
+        return tuple(out), cnt.value
+
+
+def hmat_matvec(h: HMatrix, x, y=None, stream=None):
+    import torch
+
+    if x.dtype != torch.float64 or not x.is_cuda:
+        raise TypeError("x must be a float64 device tensor")
+    if x.dim() == 1:
+        nrhs, ld = 1, x.shape[0]
+        if not x.is_contiguous():
+            raise ValueError("x must be contiguous")
+    else:  # (n, nrhs) with columns contiguous, i.e. a transposed (nrhs, n) tensor
+        nrhs = x.shape[1]
+        if x.stride(0) != 1:
+            raise ValueError("x must be column-major (x.T contiguous)")
+        ld = x.stride(1)
+    if y is None:
+        y = torch.empty_like(x) if x.dim() == 1 else torch.empty((nrhs, h.n), dtype=torch.float64, device=x.device).T
+    _check(lib().hmat_matvec(h.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nrhs, ld, _stream_ptr(stream)))
+    return y
+
+
+def hmat_get_stats(h: HMatrix) -> hmat_stats:
+    return h.stats()
+
+
+class Precond:
+    """Block-Jacobi right preconditioner (hmat_precond_create)."""
+
+    def __init__(self, blocks: BlockSet, kind: int = PRECOND_JACOBI, device="cuda", stream=None):
+        import torch
+
+        s = blocks.struct()
+        nb = C.c_uint64()
+        _check(lib().hmat_precond_plan(C.byref(s), int(kind), C.byref(nb)))
+        self.buf = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=device)
+        p = C.c_void_p()
+        _check(lib().hmat_precond_create(C.byref(s), int(kind), C.c_void_p(self.buf.data_ptr()), self.buf.numel(),
+                                         _stream_ptr(stream), C.byref(p)))
+        self.p = p
+        self.n = blocks.n
+
+    def __del__(self):
+        if getattr(self, "p", None):
+            lib().hmat_precond_destroy(self.p)
+            self.p = None
+
+    def apply(self, x, y=None, stream=None):
+        import torch
+
+        y = torch.empty_like(x) if y is None else y
+        _check(lib().hmat_precond_apply(self.p, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), _stream_ptr(stream)))
+        return y
+
+
+def hmat_solver_workspace_bytes(n: int) -> int:
+    return int(lib().hmat_solver_workspace_bytes(int(n)))
+
+
+def hmat_bicgstab(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = None, tol=1e-8, maxiter=1000, poll_every=1,
+                  use_graph=False, precond: Precond | None = None, history=False, work=None, stream=None,
+                  raise_on_error=False):
+    """BiCGSTAB (Algorithm 1) on the device; returns (x, info dict)."""
+    import torch
+
+    n = h_iter.n
+    x = torch.zeros(n, dtype=torch.float64, device=b.device) if x is None else x
+    wb = hmat_solver_workspace_bytes(n)
+    if work is None or work.numel() < wb:
+        work = torch.empty(wb, dtype=torch.uint8, device=b.device)
+    hist = np.full(maxiter + 1, np.nan) if history else None
+    o = hmat_solve_opts(float(tol), int(maxiter), int(poll_every), int(bool(use_graph)),
+                        precond.p if precond is not None else None, _p(hist) if hist is not None else None)
+    info = hmat_solve_info()
+    rc = lib().hmat_bicgstab(h_iter.h, (h_fp64 or h_iter).h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                             C.byref(o), C.byref(info), C.c_void_p(work.data_ptr()), work.numel(), _stream_ptr(stream))
+    if rc != HMAT_OK and (raise_on_error or rc not in (HMAT_E_BREAKDOWN, HMAT_E_NOCONV, HMAT_E_NONFINITE)):
+        _check(rc)
+    d = dict(status=info.status, restarts=info.restarts, iterations=info.iterations, matvecs=info.matvecs,
+             matvecs_fp64=info.matvecs_fp64, rel_res=info.rel_res, true_rel_res=info.true_rel_res)
+    if hist is not None:
+        d["history"] = hist[:info.iterations + 1]
+    return x, d
+
+
+def hmat_stream_read(buf, stream=None):
+    """Launch the streaming-read calibration kernel over a uint8 device tensor."""
+    import torch
+
+    sink = torch.zeros(1, dtype=torch.float64, device=buf.device)
+    _check(lib().hmat_stream_read(C.c_void_p(buf.data_ptr()), buf.numel() // 16 * 16, C.c_void_p(sink.data_ptr()),
+                                  _stream_ptr(stream)))
+    return sink
+
+
+def hmat_stream_copy(dst, src, stream=None):
+    nb = min(dst.numel() * dst.element_size(), src.numel() * src.element_size()) // 16 * 16
+    _check(lib().hmat_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nb, _stream_ptr(stream)))

@@ -1,0 +1,138 @@
+"""GPU parity of the H-matrix-vector product (every precision variant)
+against the oracle, through the C ABI, on the same blocks."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1911_00093_amd import hmat
+from tests.conftest import oracle_hmatrix
+from tests.gpu_util import abs_scale, blockset, need_gpu, to_dev, tolerance
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ["sphere-L4", "plates-32", "spheres-mixed", "ellipsoid-12"]
+
+
+@pytest.mark.parametrize("key", KEYS)
+@pytest.mark.parametrize("variant", range(8))
+def test_matvec_parity_small(key, variant):
+    need_gpu()
+    m, h = oracle_hmatrix(key)
+    c = 2
+    H = hmat.HMatrix(blockset(h), variant, c=c)
+    conv = oracle.Converted(h, variant, c)
+    rng = np.random.default_rng(11)
+    for x in (np.ones(h.n), rng.standard_normal(h.n), m.rhs()[h.perm]):
+        y = H.matvec(to_dev(x)).cpu().numpy()
+        yo = conv.matvec(x)
+        scale = abs_scale(h, x).max()
+        err = np.abs(y - yo).max() / scale
+        assert err <= tolerance(variant), (key, variant, err)
+
+
+@pytest.mark.parametrize("variant", [oracle.M1_DOUBLE, oracle.M2_MIXED, oracle.M3, oracle.BF16_SCALED])
+def test_matvec_vs_fp64_error(variant):
+    """FP32-storage variants stay within 1e-6 of the FP64 product on a smooth
+    vector; the BF16 variant is reported (about 1e-3 of the far field)."""
+    need_gpu()
+    m, h = oracle_hmatrix("sphere-L4")
+    H = hmat.HMatrix(blockset(h), variant, c=-1)
+    x = np.ones(h.n)
+    y = H.matvec(to_dev(x)).cpu().numpy()
+    y64 = oracle.Converted(h, oracle.M1_DOUBLE).matvec(x)
+    err = np.linalg.norm(y - y64) / np.linalg.norm(y64)
+    print(f"variant {oracle.VARIANT_NAMES[variant]}: |y - y64|/|y64| = {err:.3e}")
+    assert err < (1e-2 if variant == oracle.BF16_SCALED else 1e-6)
+
+
+def test_multi_rhs_equals_single():
+    need_gpu()
+    import torch
+
+    m, h = oracle_hmatrix("plates-32")
+    H = hmat.HMatrix(blockset(h), oracle.M2_MIXED, nrhs_max=5)
+    X = np.random.default_rng(2).standard_normal((5, h.n))
+    Xd = torch.as_tensor(X).cuda().T  # column-major n x 5
+    Y = H.matvec(Xd).cpu().numpy()
+    for k in range(5):
+        yk = H.matvec(to_dev(X[k])).cpu().numpy()
+        assert np.array_equal(Y[:, k], yk)
+
+
+def test_deterministic_and_aliasing():
+    need_gpu()
+    m, h = oracle_hmatrix("sphere-L4")
+    H = hmat.HMatrix(blockset(h), oracle.M1_MIXED)
+    x = to_dev(np.random.default_rng(3).standard_normal(h.n))
+    y1 = H.matvec(x).cpu().numpy()
+    y2 = H.matvec(x).cpu().numpy()
+    assert np.array_equal(y1, y2)
+    xa = x.clone()
+    H.matvec(xa, xa)  # y may alias x
+    assert np.array_equal(xa.cpu().numpy(), y1)
+
+
+def _one_block(n, kind, rank=0, seed=0):
+    rng = np.random.default_rng(seed)
+    if kind == 0:
+        data = rng.standard_normal(n * n)
+    else:
+        data = rng.standard_normal(rank * 2 * n)
+    return oracle.HMatrix.from_blocks(n, [0], [n], [0], [n], [kind], [rank], [0], data)
+
+
+@pytest.mark.parametrize("n", [1, 3, 63, 64, 65, 200, 1000])
+def test_single_dense_block_ragged(n):
+    """One dense N x N block: one panel per 64 rows, K = N columns with a
+    ragged tail in both directions."""
+    need_gpu()
+    h = _one_block(n, 0, seed=n)
+    x = np.random.default_rng(n + 1).standard_normal(n)
+    for variant in (oracle.M1_DOUBLE, oracle.M1_SINGLE, oracle.M2_MIXED):
+        H = hmat.HMatrix(blockset(h), variant)
+        y = H.matvec(to_dev(x)).cpu().numpy()
+        yo = oracle.Converted(h, variant).matvec(x)
+        assert np.abs(y - yo).max() <= tolerance(variant) * abs_scale(h, x).max()
+
+
+@pytest.mark.parametrize("n,r", [(2, 1), (100, 7), (3000, 40), (5000, 0)])
+def test_single_lowrank_block(n, r):
+    """One low-rank N x N block: stage-1 chunks over all columns, rank 0."""
+    need_gpu()
+    h = _one_block(n, 1, r, seed=r)
+    x = np.random.default_rng(7).standard_normal(n)
+    for variant in (oracle.M1_DOUBLE, oracle.M1_MIXED, oracle.M2_SINGLE, oracle.M3, oracle.BF16_SCALED):
+        H = hmat.HMatrix(blockset(h), variant, c=1)
+        y = H.matvec(to_dev(x)).cpu().numpy()
+        yo = oracle.Converted(h, variant, 1).matvec(x)
+        assert np.abs(y - yo).max() <= tolerance(variant) * max(abs_scale(h, x).max(), 1e-300)
+        if r == 0:
+            assert np.all(y == 0)
+
+
+def test_nonfinite_propagates():
+    need_gpu()
+    m, h = oracle_hmatrix("plates-32")
+    H = hmat.HMatrix(blockset(h), oracle.M1_DOUBLE)
+    x = np.ones(h.n)
+    x[5] = np.nan
+    y = H.matvec(to_dev(x)).cpu().numpy()
+    assert np.isnan(y).any()
+
+
+def test_workspace_too_small():
+    need_gpu()
+    import ctypes as C
+
+    import torch
+
+    m, h = oracle_hmatrix("sphere-L2")
+    bs = blockset(h)
+    info = hmat.hmat_plan(bs, oracle.M1_DOUBLE)
+    buf = torch.empty(int(info.device_bytes) // 2, dtype=torch.uint8, device="cuda")
+    s = bs.struct()
+    o = hmat.hmat_build_opts(0, 0, 1, 0)
+    out = C.c_void_p()
+    rc = hmat.lib().hmat_build(C.byref(s), C.byref(o), C.c_void_p(buf.data_ptr()), buf.numel(), None, C.byref(out))
+    assert rc == hmat.HMAT_E_WORKSPACE

@@ -1,0 +1,151 @@
+"""GPU BiCGSTAB (Algorithm 1) against the oracle's BiCGSTAB, breakdown and
+edge cases, and the block-Jacobi preconditioner."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1911_00093_amd import hmat
+from tests.conftest import oracle_hmatrix
+from tests.gpu_util import blockset, need_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("key", ["sphere-L4", "plates-32"])
+def test_bicgstab_fp64_matches_oracle(key):
+    need_gpu()
+    m, h = oracle_hmatrix(key)
+    b = m.rhs()[h.perm]
+    bs = blockset(h)
+    H = hmat.HMatrix(bs, oracle.M1_DOUBLE)
+    x, info = hmat.hmat_bicgstab(H, to_dev(b), tol=1e-10, maxiter=300, history=True)
+    xo, io = oracle.bicgstab(oracle.Converted(h, oracle.M1_DOUBLE), b, tol=1e-10, maxiter=300)
+    assert info["status"] == 0 and io["status"] == 0
+    assert abs(info["iterations"] - io["iterations"]) <= 1
+    x = x.cpu().numpy()
+    # both solves stop at |r|/|b| < 1e-10, so each is off the exact solution
+    # by up to kappa * 1e-10; compare each with a tight solve instead
+    xt, _ = oracle.bicgstab(oracle.Converted(h, oracle.M1_DOUBLE), b, tol=1e-14, maxiter=500)
+    e_gpu = np.linalg.norm(x - xt) / np.linalg.norm(xt)
+    e_ora = np.linalg.norm(xo - xt) / np.linalg.norm(xt)
+    print(f"{key}: iters gpu {info['iterations']} oracle {io['iterations']}, x err gpu {e_gpu:.2e} oracle {e_ora:.2e}")
+    assert e_gpu <= 10 * e_ora + 1e-12
+    assert info["true_rel_res"] < 1e-10
+    # the recurrence history follows the oracle's over the first iterations.
+    # BiCGSTAB amplifies rounding quickly: the same operator with pairwise
+    # instead of sequential dot products already moves |r_1|/|b| by ~2e-11
+    # and |r_2|/|b| by ~6e-10 on this mesh, so compare at 1e-8 there
+    hg, ho = info["history"][:3], io["history"][:3]
+    assert np.allclose(hg, ho, rtol=1e-8, atol=0)
+
+
+@pytest.mark.parametrize("variant", [oracle.M1_SINGLE, oracle.M1_MIXED, oracle.M2_SINGLE, oracle.M2_MIXED, oracle.M3,
+                                     oracle.BF16_SCALED])
+def test_bicgstab_mixed_true_residual(variant):
+    """Mixed operators: convergence is confirmed with the FP64 true residual
+    (Sec. 4.1.3); the solution error against the FP64 solve is reported."""
+    need_gpu()
+    m, h = oracle_hmatrix("sphere-L4")
+    b = m.rhs()[h.perm]
+    bs = blockset(h)
+    H64 = hmat.HMatrix(bs, oracle.M1_DOUBLE)
+    Hm = hmat.HMatrix(bs, variant, c=-1)
+    x, info = hmat.hmat_bicgstab(Hm, to_dev(b), h_fp64=H64, tol=1e-8, maxiter=500)
+    assert info["status"] == 0, info
+    assert info["true_rel_res"] < 1e-8
+    op64 = oracle.Converted(h, oracle.M1_DOUBLE)
+    x = x.cpu().numpy()
+    assert np.linalg.norm(b - op64.matvec(x)) / np.linalg.norm(b) < 1e-8
+    xo, io = oracle.bicgstab(op64, b, tol=1e-12, maxiter=500)
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    # a residual of 1e-8 leaves an error of up to kappa * 1e-8 in x for any
+    # operator; the FP64 oracle stopped at the same tolerance shows how much
+    x8, _ = oracle.bicgstab(op64, b, tol=1e-8, maxiter=500)
+    err64 = np.linalg.norm(x8 - xo) / np.linalg.norm(xo)
+    print(f"{oracle.VARIANT_NAMES[variant]}: iters {info['iterations']} restarts {info['restarts']} "
+          f"x err vs FP64 {err:.2e} (FP64 at the same tol: {err64:.2e})")
+    assert err < 10 * err64 + 1e-9
+    # the oracle running the same operator converges too
+    xm, im = oracle.bicgstab(oracle.Converted(h, variant, -1), b, op64=op64, tol=1e-8, maxiter=500)
+    assert im["status"] == 0
+
+
+def _dense(A):
+    n = A.shape[0]
+    h = oracle.HMatrix.from_blocks(n, [0], [n], [0], [n], [0], [0], [0], np.asfortranarray(A).ravel(order="F"))
+    return h, hmat.HMatrix(blockset(h), oracle.M1_DOUBLE)
+
+
+def test_bicgstab_breakdowns_and_edges():
+    need_gpu()
+    # omega = 0 (exact): A = [[-2,-2],[-2,0]], b = (1,2)
+    h, H = _dense(np.array([[-2.0, -2.0], [-2.0, 0.0]]))
+    x, info = hmat.hmat_bicgstab(H, to_dev([1.0, 2.0]))
+    assert info["status"] == hmat.HMAT_E_BREAKDOWN
+    # r~^T v = 0: A = diag(1, -1), b = (1, 1)
+    h, H = _dense(np.diag([1.0, -1.0]))
+    x, info = hmat.hmat_bicgstab(H, to_dev([1.0, 1.0]))
+    assert info["status"] == hmat.HMAT_E_BREAKDOWN
+    # identity: one iteration
+    h, H = _dense(np.eye(70))
+    b = np.arange(1.0, 71.0)
+    x, info = hmat.hmat_bicgstab(H, to_dev(b), tol=1e-10)
+    assert info["status"] == 0 and info["iterations"] == 1
+    assert np.array_equal(x.cpu().numpy(), b)
+    # b = 0: x = 0 without iterating
+    x0 = to_dev(np.ones(70))
+    x, info = hmat.hmat_bicgstab(H, to_dev(np.zeros(70)), x=x0)
+    assert info["status"] == 0 and info["iterations"] == 0 and np.all(x.cpu().numpy() == 0)
+    # maxiter reached
+    rng = np.random.default_rng(8)
+    A = np.eye(40) + rng.standard_normal((40, 40))
+    h, H = _dense(A)
+    x, info = hmat.hmat_bicgstab(H, to_dev(rng.standard_normal(40)), tol=1e-14, maxiter=2)
+    assert info["status"] == hmat.HMAT_E_NOCONV and info["iterations"] == 2
+    with pytest.raises(hmat.HmatError):
+        hmat.hmat_bicgstab(H, to_dev(rng.standard_normal(40)), tol=1e-14, maxiter=2, raise_on_error=True)
+
+
+def test_bicgstab_nonfinite():
+    need_gpu()
+    m, h = oracle_hmatrix("plates-32")
+    H = hmat.HMatrix(blockset(h), oracle.M1_DOUBLE)
+    b = m.rhs()[h.perm].copy()
+    b[3] = np.inf
+    x, info = hmat.hmat_bicgstab(H, to_dev(b), maxiter=20)
+    assert info["status"] in (hmat.HMAT_E_NONFINITE, hmat.HMAT_E_BREAKDOWN)
+
+
+def test_bicgstab_poll_every_same_result():
+    need_gpu()
+    m, h = oracle_hmatrix("sphere-L4")
+    b = to_dev(m.rhs()[h.perm])
+    H = hmat.HMatrix(blockset(h), oracle.M2_MIXED)
+    H64 = hmat.HMatrix(blockset(h), oracle.M1_DOUBLE)
+    x1, i1 = hmat.hmat_bicgstab(H, b, h_fp64=H64, poll_every=1)
+    x5, i5 = hmat.hmat_bicgstab(H, b, h_fp64=H64, poll_every=5)
+    assert i1["iterations"] == i5["iterations"]
+    assert np.array_equal(x1.cpu().numpy(), x5.cpu().numpy())
+
+
+def test_jacobi_apply_and_preconditioned_solve():
+    need_gpu()
+    m, h = oracle_hmatrix("sphere-L4")
+    bs = blockset(h)
+    P = hmat.Precond(bs)
+    J = oracle.Jacobi(h)
+    x = np.random.default_rng(4).standard_normal(h.n)
+    y = P.apply(to_dev(x)).cpu().numpy()
+    yo = J.apply(x)
+    assert np.abs(y - yo).max() <= 1e-12 * np.abs(yo).max()
+    b = m.rhs()[h.perm]
+    H = hmat.HMatrix(bs, oracle.M1_DOUBLE)
+    x0, i0 = hmat.hmat_bicgstab(H, to_dev(b), tol=1e-10)
+    x1, i1 = hmat.hmat_bicgstab(H, to_dev(b), tol=1e-10, precond=P)
+    assert i0["status"] == 0 and i1["status"] == 0
+    xo, io = oracle.bicgstab(oracle.Converted(h, oracle.M1_DOUBLE), b, tol=1e-10, precond=J)
+    assert abs(i1["iterations"] - io["iterations"]) <= 1
+    a, c = x0.cpu().numpy(), x1.cpu().numpy()
+    assert np.linalg.norm(a - c) / np.linalg.norm(a) < 1e-7
+    print(f"iterations: none {i0['iterations']}, block-Jacobi {i1['iterations']}")

@@ -1,0 +1,156 @@
+"""Host-side checks of the native library (no GPU needed).
+
+* libhmat.so loads and exports every function include/hmat.h declares;
+* hmat_plan validates the block partition (Eqs. 1-2) and ranks (Eq. 3);
+* the plan's byte counts match the definition of the algorithmic bytes;
+* the library's own setup builder produces the same cluster permutation and
+  block partition as the oracle, bit for bit, and the same factors.
+"""
+
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1911_00093_amd import hmat, meshes
+from tests.conftest import ROOT, oracle_hmatrix
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "hmat.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(hmat_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_symbols_exported():
+    names = header_functions()
+    assert "hmat_matvec" in names and "hmat_bicgstab" in names and "hmat_build" in names
+    L = hmat.lib()
+    for nm in names:
+        assert hasattr(L, nm), nm
+    out = subprocess.run(["nm", "-D", "--defined-only", hmat.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (hmat_\w+)", out))
+    assert set(names) <= exported
+    assert set(hmat.EXPORTED) <= exported
+    assert b"gfx950" in hmat.lib().hmat_version()
+
+
+def blockset_from_oracle(h) -> hmat.BlockSet:
+    return hmat.BlockSet.from_arrays(h.n, h.row0, h.nrows, h.col0, h.ncols, h.kind, h.rank, h.offset, h.data, h.perm)
+
+
+def test_plan_accepts_oracle_partition():
+    m, h = oracle_hmatrix("sphere-L3")
+    bs = blockset_from_oracle(h)
+    for prec in range(8):
+        info = hmat.hmat_plan(bs, prec, c=1)
+        assert info.device_bytes > 0
+        assert info.nblocks_dense + info.nblocks_lowrank == h.nblocks
+
+
+def _tiny_partition():
+    # 4 x 4 matrix: dense 2x2 diagonal blocks + two rank-1 off-diagonal blocks
+    data = np.arange(1, 21, dtype=np.float64)
+    return dict(n=4, row0=[0, 0, 2, 2], nrows=[2, 2, 2, 2], col0=[0, 2, 0, 2], ncols=[2, 2, 2, 2],
+                kind=[0, 1, 1, 0], rank=[0, 1, 1, 0], offset=[0, 4, 8, 12], data=data)
+
+
+def _plan_code(**kw):
+    bs = hmat.BlockSet.from_arrays(**kw)
+    try:
+        hmat.hmat_plan(bs, hmat.M1_DOUBLE)
+        return hmat.HMAT_OK
+    except hmat.HmatError as e:
+        return e.code
+
+
+def test_plan_rejects_overlap_gap_and_bad_rank():
+    assert _plan_code(**_tiny_partition()) == hmat.HMAT_OK
+    d = _tiny_partition()
+    d["col0"] = [0, 1, 0, 2]  # block 1 overlaps block 0
+    assert _plan_code(**d) == hmat.HMAT_E_LAYOUT
+    d = _tiny_partition()
+    d["ncols"] = [2, 1, 2, 2]  # column 3 of rows 0-1 uncovered
+    assert _plan_code(**d) == hmat.HMAT_E_LAYOUT
+    d = _tiny_partition()
+    d["rank"] = [0, 3, 1, 0]  # r > min(#I, #J) (Eq. 3)
+    assert _plan_code(**d) == hmat.HMAT_E_ARG
+    d = _tiny_partition()
+    d["row0"] = [0, 0, 2, 3]  # leaves the matrix
+    assert _plan_code(**d) == hmat.HMAT_E_ARG
+    d = _tiny_partition()
+    d["offset"] = [0, 4, 8, 18]  # data out of range
+    assert _plan_code(**d) == hmat.HMAT_E_ARG
+    d = _tiny_partition()
+    d["kind"] = [0, 1, 2, 0]
+    assert _plan_code(**d) == hmat.HMAT_E_ARG
+
+
+def test_plan_rejects_duplicate_block():
+    d = _tiny_partition()
+    for k in ("row0", "nrows", "col0", "ncols", "kind", "rank", "offset"):
+        d[k] = list(d[k]) + [d[k][0]]
+    assert _plan_code(**d) == hmat.HMAT_E_LAYOUT
+
+
+@pytest.mark.parametrize("prec", range(8))
+def test_plan_algorithmic_bytes(prec):
+    """matrix bytes = sum_dense #I#J s_A + sum_LR r (#I + #J) s_VW (Sec. 3,
+    Table 1 storage types), plus x and y and the FP64 z scales."""
+    m, h = oracle_hmatrix("sphere-L3")
+    bs = blockset_from_oracle(h)
+    info = hmat.hmat_plan(bs, prec, c=2)
+    conv = oracle.Converted(h, prec, 2)
+    sA = 8 if prec in (0, 3, 6) else 4
+    mat = 0
+    zlen = 0
+    for b in range(h.nblocks):
+        if h.kind[b] == 0:
+            mat += h.nrows[b] * h.ncols[b] * sA
+        else:
+            _, V, D, W, P = conv.block(b)
+            sz = np.where(P == 64, 8, np.where(P == 32, 4, 2))
+            mat += int(((h.nrows[b] + h.ncols[b]) * sz).sum())
+            zlen += len(P)
+    assert info.matrix_bytes == mat
+    xs = 4 if prec in (1, 4) else 8
+    extra = zlen * 8 if prec >= 3 else 0
+    assert info.algorithmic_bytes == mat + extra + h.n * xs + h.n * 8
+
+
+@pytest.mark.parametrize("key", ["sphere-L3", "plates-16", "spheres-mixed", "ellipsoid-12"])
+def test_library_assembly_matches_oracle(key):
+    m, h = oracle_hmatrix(key)
+    bs = hmat.hmat_assemble_bem(m.centroids, m.areas, leaf=h.leaf, eta=h.eta, eps=h.eps, threads=4)
+    assert np.array_equal(bs.perm, h.perm)
+    for f in ("row0", "nrows", "col0", "ncols", "kind", "rank"):
+        assert np.array_equal(getattr(bs, f), getattr(h, f)), f
+    # same definitions evaluated in the same order: identical factors
+    for b in range(h.nblocks):
+        sz = h.nrows[b] * h.ncols[b] if h.kind[b] == 0 else h.rank[b] * (h.nrows[b] + h.ncols[b])
+        a = bs.data[bs.offset[b]:bs.offset[b] + sz]
+        o = h.data[h.offset[b]:h.offset[b] + sz]
+        assert np.array_equal(a, o), b
+
+
+def test_library_assembly_threads_deterministic():
+    m = meshes.icosphere(3)
+    a = hmat.hmat_assemble_bem(m.centroids, m.areas, leaf=32, eta=2.0, eps=1e-6, threads=1)
+    b = hmat.hmat_assemble_bem(m.centroids, m.areas, leaf=32, eta=2.0, eps=1e-6, threads=7)
+    assert np.array_equal(a.data, b.data) and np.array_equal(a.offset, b.offset)
+
+
+def test_assemble_rejects_bad_options():
+    m = meshes.icosphere(1)
+    with pytest.raises(hmat.HmatError) as e:
+        hmat.hmat_assemble_bem(m.centroids, m.areas, leaf=0)
+    assert e.value.code == hmat.HMAT_E_ARG
+
+
+def test_solver_workspace_size():
+    assert hmat.hmat_solver_workspace_bytes(0) == 0
+    assert hmat.hmat_solver_workspace_bytes(1000) >= 9 * 1000 * 8
