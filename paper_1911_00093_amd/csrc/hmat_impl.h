@@ -15,40 +15,79 @@ enum Cls : int { F64 = 0, F32 = 1, BF16 = 2, NCLS = 3 };
 
 constexpr int kWave = 64;         // CDNA wavefront
 constexpr int kRowChunk = 64;     // rows owned by one stage-2 workgroup
-constexpr int kS2Waves = 4;       // waves per stage-2 workgroup
-constexpr int kS1RowsMax = 32;    // W' rows handled by one stage-1 wave item
+constexpr int kS2Waves = 8;       // waves per stage-2 workgroup (rows interleaved)
+constexpr int kRowsPerLane = 8;   // row accumulators per lane (stage 1 and stage 2)
+constexpr int kS2Threads = kS2Waves * kWave;
+constexpr int kS2Tile = 2048;     // gathered operands staged in LDS per pass (FP64)
+constexpr int kS1Cols = 1024;     // stage-1 item width (columns) for wide groups
 
 // elements per 16-byte lane load
 constexpr int vec_of(int cls) { return cls == F64 ? 2 : (cls == F32 ? 4 : 8); }
 constexpr int bytes_of(int cls) { return cls == F64 ? 8 : (cls == F32 ? 4 : 2); }
-// stage-1 slabs (64 lanes x VEC columns) per wave item
-constexpr int s1_slabs(int cls) { return cls == F64 ? 4 : (cls == F32 ? 4 : 2); }
+// Stage-1 lanes per W' row: the narrowest of 16 / 32 / 64 lanes whose
+// 16-byte loads span the group's columns, so narrow groups still fill the
+// wave (64 / lpr rows per load instruction).
+constexpr int s1_lpr(int cls, int64_t ncols) {
+  return ncols <= 16 * vec_of(cls) ? 16 : (ncols <= 32 * vec_of(cls) ? 32 : 64);
+}
 
 // Stage 2: one workgroup owns rows [r0, r0 + h) of y and streams its panel:
-// the row-major h x K matrix made of the rows of every dense block and of
-// every V'_m that covers these rows, times the gathered vector
-// g[k] = src[gidx[k]] where src = [x_eff | z | 0].
+// the h x K matrix made of the rows of every dense block and of every V'_m
+// that covers these rows, times the gathered vector g[k] = src[gidx[k]]
+// where src = [x_eff | z | 0].  Row r belongs to wave r % 8.  The panel is
+// stored in the order the waves consume it (see s2_elem): for each wave, for
+// each 64-lane slab of columns, the wave's rows one after another, so every
+// wave reads one contiguous stream.
 struct RowChunk {
   int64_t panel_off[NCLS];  // element offset of the panel in the class value array
   int64_t gidx_off[NCLS];   // offset into the class gather-index array
   int32_t K[NCLS];          // logical panel columns
-  int32_t ld[NCLS];         // row stride (K padded to 16 bytes)
+  int32_t ld[NCLS];         // columns padded to one 16-byte lane load
   int32_t r0, h;
 };
 
 // Stage 1: one wave computes partial z sums of rows [k0, k0 + nrows) of a
 // column group (all low-rank factors W'_m of one class sharing J_m), over
-// columns [x0, x0 + ncols) of x.  Row k's partial goes to
-// zpart[out_off + k] (out_off already includes the chunk offset).
+// columns [x0, x0 + ncols) of x; nrows <= 8 * 64 / lpr.  Row k's partial
+// goes to zpart[out_off + k] (out_off already includes the chunk offset).
+// The item's values are stored contiguously in consumption order (s1_elem).
 struct S1Item {
-  int64_t w_off;   // element offset of (row k0, first column of the chunk)
+  int64_t w_off;   // element offset of the item's block in the class value array
   int64_t x0;      // first global column
   int64_t out_off; // zpart offset of row k0
-  int32_t ld;      // row stride of the group's W' (elements)
   int32_t ncols;
   int32_t nrows;
   int32_t cls;
+  int32_t lpr;     // lanes per row: 16, 32 or 64
 };
+
+// ---- consumption-order layouts (shared by the packer and the kernels)
+// Stage 2, one class of one chunk: h rows, ld columns (ld % VEC == 0).
+constexpr int s2_rows_of_wave(int h, int w) { return h > w ? (h - w + kS2Waves - 1) / kS2Waves : 0; }
+constexpr int64_t s2_wave_base(int h, int ld, int w) {
+  int64_t r = 0;
+  for (int v = 0; v < w; v++) r += s2_rows_of_wave(h, v);
+  return r * ld;
+}
+// lanes of slab s (64 except for the last, ragged slab)
+constexpr int slab_lanes(int cols, int vec, int lanes, int s) {
+  const int slab = lanes * vec, ns = (cols + slab - 1) / slab;
+  return s < ns - 1 ? lanes : (cols - (ns - 1) * slab) / vec;
+}
+constexpr int64_t s2_elem(int h, int ld, int vec, int w, int s, int i, int lane) {
+  return s2_wave_base(h, ld, w) + (int64_t)s * s2_rows_of_wave(h, w) * kWave * vec +
+         (int64_t)i * slab_lanes(ld, vec, kWave, s) * vec + (int64_t)lane * vec;
+}
+// Stage 1, one item: rows padded to a multiple of 64 / lpr, cols = ncols
+// padded to VEC.  Lane (q, u) of row slot i reads row q + (64 / lpr) i.
+constexpr int64_t s1_rows_pad(int nrows, int lpr) {
+  return (int64_t)((nrows + kWave / lpr - 1) / (kWave / lpr)) * (kWave / lpr);
+}
+constexpr int64_t s1_elem(int nrows, int cols, int vec, int lpr, int s, int i, int q, int u) {
+  const int ws = slab_lanes(cols, vec, lpr, s);
+  return (int64_t)s * s1_rows_pad(nrows, lpr) * lpr * vec + (int64_t)i * (kWave / lpr) * ws * vec +
+         (int64_t)q * ws * vec + (int64_t)u * vec;
+}
 
 // Stage-1 reduction: z entry j = round_z(dscale[j] * sum_c zpart[zp[j] + c * stride[j]]).
 struct ZInfo {
@@ -86,6 +125,9 @@ struct hmat_s {
   hm::S1Item *items = nullptr;
   hm::ZInfo *zinfo = nullptr;
   double *dscale = nullptr;
+  int64_t item_begin[hm::NCLS] = {0, 0, 0}, item_end[hm::NCLS] = {0, 0, 0};  // stage-1 items per class
+  int32_t cls_mask = 0;     // classes present in the stage-2 panels
+  int32_t grid1[hm::NCLS] = {0, 0, 0}, grid2 = 0;  // persistent grid sizes
   double *src = nullptr;    // nrhs_max x (n + zlen + 1)
   double *zpart = nullptr;  // nrhs_max x zpart_len
   // kept for the block-Jacobi preconditioner and diagnostics
@@ -106,6 +148,7 @@ void packed_free(Packed *p);
 
 // Kernel launchers (matvec.hip)
 int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream);
+int size_grids(hmat_s *h);
 
 // Kernel timing (diag.hip): mark(h, k, stream) records event k (0..3) of the
 // current product when timing is enabled.

@@ -5,20 +5,23 @@
 // Three launches per product, all deterministic (no atomics: every partial
 // sum has one owner and is reduced in a fixed order):
 //  K1  stage 1: z partials.  One wave per work item = (column group, chunk of
-//      <= 64*VEC*SB columns, <= 32 rows).  The lane's x values stay in
-//      registers while the wave streams the W' rows with 16-byte
-//      non-temporal loads; each row is reduced across the wave.   (Eq. 22)
+//      columns, up to 16 row slots per lane).  Lanes split the columns
+//      (16, 32 or 64 lanes per W' row depending on the group width) and keep
+//      one FP64 accumulator per row slot while they stream the rows with
+//      16-byte non-temporal loads; the accumulators are reduced across the
+//      lanes of each row once, at the end of the item.            (Eq. 22)
 //  K1b stage-1 reduction in chunk order, times D_m (Eq. 23), rounding of z
 //      where Table 1 keeps it in FP32, and the source-vector copy x_eff
 //      (rounded to FP32 in the Single variants, Sec. 3.5) into src.
-//  K2  stage 2: one workgroup owns <= 64 rows of y.  Its four waves split
-//      the panel columns (dense leaves + V'_m rows, Eqs. 21, 24), gather
-//      their operands from src into registers once, stream the panel rows,
-//      reduce per row, and combine in LDS in a fixed order before the single
-//      write of y (Eq. 25).
+//  K2  stage 2: one workgroup owns <= 64 rows of y.  The workgroup gathers
+//      the panel's operands (x for dense columns, z for low-rank columns)
+//      into LDS, then each of its four waves streams its own 16 interleaved
+//      rows over all panel columns (dense leaves + V'_m rows, Eqs. 21, 24),
+//      reduces once and writes its rows of y (Eq. 25).
 // All products and sums are FP64 after upcasting the stored value.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 
 #include "hmat_impl.h"
@@ -29,97 +32,134 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
-// 16-byte streaming load of VEC values, upcast to FP64.
-template <int CLS>
-__device__ __forceinline__ void load16(const void *base, int64_t idx, double (&v)[vec_of(CLS)]) {
-  if constexpr (CLS == F64) {
-    d2v t = __builtin_nontemporal_load((const d2v *)((const double *)base + idx));
-    v[0] = t.x;
-    v[1] = t.y;
-  } else if constexpr (CLS == F32) {
-    f4v t = __builtin_nontemporal_load((const f4v *)((const float *)base + idx));
-    v[0] = (double)t.x;
-    v[1] = (double)t.y;
-    v[2] = (double)t.z;
-    v[3] = (double)t.w;
-  } else {
-    u4v t = __builtin_nontemporal_load((const u4v *)((const unsigned short *)base + idx));
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      unsigned int w = t[q];
-      v[2 * q] = (double)__uint_as_float(w << 16);
-      v[2 * q + 1] = (double)__uint_as_float(w & 0xffff0000u);
-    }
-  }
+// 16-byte streaming load (non-temporal: each matrix value is used once).
+typedef unsigned int raw16 __attribute__((ext_vector_type(4)));
+// base: wave-uniform address; lane_off: the lane's 32-bit byte offset
+__device__ __forceinline__ raw16 ld16(const char *base, uint32_t lane_off) {
+  return __builtin_nontemporal_load((const raw16 *)(base + lane_off));
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
+// acc += dot(values of one 16-byte load, g), every product in FP64
+template <int CLS>
+__device__ __forceinline__ double dot16(raw16 t, const double (&g)[vec_of(CLS)], double acc) {
+  if constexpr (CLS == F64) {
+    double v0, v1;
+    __builtin_memcpy(&v0, &t, 8);
+    __builtin_memcpy(&v1, (const char *)&t + 8, 8);
+    acc = fma(v0, g[0], acc);
+    acc = fma(v1, g[1], acc);
+  } else if constexpr (CLS == F32) {
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-  return v;
+    for (int e = 0; e < 4; e++) acc = fma((double)__uint_as_float(t[e]), g[e], acc);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      acc = fma((double)__uint_as_float(t[q] << 16), g[2 * q], acc);
+      acc = fma((double)__uint_as_float(t[q] & 0xffff0000u), g[2 * q + 1], acc);
+    }
+  }
+  return acc;
+}
+
+// Butterfly reduce-scatter of R = 8 accumulators over the lowest log2(L)
+// lane bits (L = 16, 32 or 64 lanes per row): the three halving steps (lane
+// bits L/2, L/4, L/8) each exchange the half of the accumulators a lane gives
+// away, the remaining bits are plain xor-adds, so 8 row sums cost 8-10
+// shuffles instead of 8 full reductions.  Afterwards the lane whose in-row
+// index u satisfies u % (L / 8) == 0 holds the complete sum of accumulator
+// u / (L / 8).
+__device__ __forceinline__ double reduce_rows(double (&a)[kRowsPerLane], int lane, int L) {
+  static_assert(kRowsPerLane == 8, "three halving steps");
+#pragma unroll
+  for (int step = 0; step < 3; step++) {
+    const int half = kRowsPerLane >> (step + 1);
+    const int bit = L >> (step + 1);
+    const bool upper = (lane & bit) != 0;
+#pragma unroll
+    for (int j = 0; j < half; j++) {
+      const double give = upper ? a[j] : a[j + half];
+      const double keep = upper ? a[j + half] : a[j];
+      a[j] = keep + __shfl_xor(give, bit, kWave);
+    }
+  }
+  for (int bit = L >> 4; bit >= 1; bit >>= 1) a[0] += __shfl_xor(a[0], bit, kWave);
+  return a[0];
 }
 
 // ------------------------------------------------------------------ K1
+// L (lanes per row) is a run-time value so that one code path serves all
+// group widths: lane (q, u) reads row slot q of every 64/L rows, columns
+// u*VEC .. u*VEC+VEC-1 of every slab of L*VEC columns.
 template <int CLS>
 __device__ __forceinline__ void s1_item(const S1Item &it, const void *vals, const double *x, int x32,
                                         double *zpart, int lane) {
   constexpr int VEC = vec_of(CLS);
-  constexpr int SB = s1_slabs(CLS);
-  constexpr int SLAB = kWave * VEC;
-  constexpr int RG = 4;
-  double g[SB][VEC];
+  const int L = it.lpr;
+  const int RPI = kWave / L;  // rows per load instruction
+  const int SLAB = L * VEC;   // columns per load instruction
+  const int q = lane / L, u = lane % L;
+  double acc[kRowsPerLane];
 #pragma unroll
-  for (int sb = 0; sb < SB; sb++)
+  for (int i = 0; i < kRowsPerLane; i++) acc[i] = 0.0;
+  const int cols = (it.ncols + VEC - 1) / VEC * VEC;
+  const int nslab = (cols + SLAB - 1) / SLAB;
+  const int64_t rows_pad = s1_rows_pad(it.nrows, L);
+  const int nslot = (int)(rows_pad / RPI);  // row slots that exist in this item
+#pragma unroll 1
+  for (int s = 0; s < nslab; s++) {
+    const int ws = slab_lanes(cols, VEC, L, s);
+    const bool act = u < ws;
+    const int uc = act ? u : 0;  // inactive lanes read a valid value and weigh it by 0
+    const int col = s * SLAB + uc * VEC;
+    double g[VEC];
 #pragma unroll
     for (int e = 0; e < VEC; e++) {
-      const int col = sb * SLAB + lane * VEC + e;
-      double xv = col < it.ncols ? x[it.x0 + col] : 0.0;
-      g[sb][e] = x32 ? (double)(float)xv : xv;
+      const bool in = act && col + e < it.ncols;
+      const double xv = x[it.x0 + (in ? col + e : 0)];
+      g[e] = in ? (x32 ? (double)(float)xv : xv) : 0.0;
     }
-  for (int rg = 0; rg < it.nrows; rg += RG) {
-    double acc[RG];
+    // consumption order: slab s, then row slot i, then lane group q, then
+    // lane u.  The slot bases are wave-uniform (scalar registers); each lane
+    // adds one 32-bit offset.  All loads are issued before any is used;
+    // slots past the item's rows re-read the last slot and their
+    // accumulators are never written.
+    const char *sbase = (const char *)vals + (it.w_off + (int64_t)s * rows_pad * SLAB) * bytes_of(CLS);
+    const uint32_t loff = (uint32_t)((q * ws + uc) * VEC * bytes_of(CLS));
+    const uint32_t slot_bytes = (uint32_t)(RPI * ws * VEC * bytes_of(CLS));
+    raw16 t[kRowsPerLane];
 #pragma unroll
-    for (int rr = 0; rr < RG; rr++) {
-      acc[rr] = 0.0;
-      const int row = rg + rr;
-      if (row < it.nrows) {
-#pragma unroll
-        for (int sb = 0; sb < SB; sb++) {
-          const int col = sb * SLAB + lane * VEC;
-          if (col < it.ncols) {
-            double v[VEC];
-            load16<CLS>(vals, it.w_off + (int64_t)row * it.ld + col, v);
-#pragma unroll
-            for (int e = 0; e < VEC; e++) acc[rr] = fma(v[e], g[sb][e], acc[rr]);
-          }
-        }
-      }
+    for (int i = 0; i < kRowsPerLane; i++) {
+      const int ic = i < nslot ? i : nslot - 1;
+      t[i] = ld16(sbase + (int64_t)ic * slot_bytes, loff);
     }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int rr = 0; rr < RG; rr++) acc[rr] = wave_sum(acc[rr]);
-    if (lane == 0) {
-#pragma unroll
-      for (int rr = 0; rr < RG; rr++)
-        if (rg + rr < it.nrows) zpart[it.out_off + rg + rr] = acc[rr];
-    }
+    for (int i = 0; i < kRowsPerLane; i++) acc[i] = dot16<CLS>(t[i], g, acc[i]);
+  }
+  const double sum = reduce_rows(acc, lane, L);
+  const int spread = L / kRowsPerLane;
+  if (u % spread == 0) {
+    const int row = q + RPI * (u / spread);
+    if (row < it.nrows) zpart[it.out_off + row] = sum;
   }
 }
 
-__global__ __launch_bounds__(256) void k_stage1(const S1Item *__restrict__ items, int64_t nitems,
-                                                const double *__restrict__ v64, const float *__restrict__ v32,
-                                                const unsigned short *__restrict__ v16, const double *__restrict__ x,
-                                                int64_t ldx, int x32, double *__restrict__ zpart,
-                                                int64_t zpart_len) {
+// Persistent waves over a static round-robin of the size-sorted items:
+// wave g of G takes items g, g + G, g + 2G, ... (no atomics, no waiting).
+template <int CLS>
+__global__ __launch_bounds__(256) void k_stage1(
+    const S1Item *__restrict__ items, int64_t nitems, const void *__restrict__ vals, const double *__restrict__ x,
+    int64_t ldx, int x32, double *__restrict__ zpart, int64_t zpart_len) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t item = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-  if (item >= nitems) return;
   const int64_t rhs = blockIdx.y;
-  const S1Item it = items[item];
   const double *xr = x + rhs * ldx;
   double *zp = zpart + rhs * zpart_len;
-  if (it.cls == F64) s1_item<F64>(it, v64, xr, x32, zp, lane);
-  else if (it.cls == F32) s1_item<F32>(it, v32, xr, x32, zp, lane);
-  else s1_item<BF16>(it, v16, xr, x32, zp, lane);
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  for (int64_t idx = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave; idx < nitems; idx += nwaves) {
+    const S1Item it = items[idx];
+    s1_item<CLS>(it, vals, xr, x32, zp, lane);
+  }
 }
 
 // ----------------------------------------------------------------- K1b
@@ -148,82 +188,148 @@ __global__ __launch_bounds__(256) void k_stage1b(int64_t n, int64_t zlen, const 
 }
 
 // ------------------------------------------------------------------ K2
+// Rows of the chunk are interleaved over the waves: wave w owns rows
+// w, w + 8, ..., so every wave streams all columns of its <= 8 rows.
 template <int CLS>
 __device__ __forceinline__ void s2_class(const RowChunk &ch, const void *vals, const int32_t *gidx,
-                                         const double *src, double *ys, int wave, int lane) {
+                                         const double *src, double *gbuf, double (&acc)[kRowsPerLane], int wave,
+                                         int lane) {
   constexpr int VEC = vec_of(CLS);
   constexpr int SLAB = kWave * VEC;
-  constexpr int RG = 8;
   const int ld = ch.ld[CLS];
-  if (ld == 0) return;
+  if (ld == 0) return;  // uniform over the workgroup
   const int h = ch.h;
-  const int nslab = (ld + SLAB - 1) / SLAB;
   const int32_t *gi = gidx + ch.gidx_off[CLS];
-  const int64_t pbase = ch.panel_off[CLS];
-  for (int s = wave; s < nslab; s += kS2Waves) {
-    const int col = s * SLAB + lane * VEC;
-    const bool act = col < ld;
-    double g[VEC];
+  const int nw = s2_rows_of_wave(h, wave);
+  const int64_t wbase = ch.panel_off[CLS] + s2_wave_base(h, ld, wave);
+  const bool rows = nw > 0;  // waves without rows still help with the gather
+  static_assert(kS2Tile % SLAB == 0, "LDS tiles hold whole slabs");
+  for (int kt0 = 0; kt0 < ld; kt0 += kS2Tile) {
+    const int kn = min(kS2Tile, ld - kt0);
+    __syncthreads();  // the previous tile's operands are no longer read
+    for (int k = threadIdx.x; k < kn; k += kS2Threads) gbuf[k] = src[gi[kt0 + k]];
+    __syncthreads();
+#pragma unroll 1
+    for (int s0 = 0; rows && s0 < kn; s0 += SLAB) {
+      const int s = (kt0 + s0) / SLAB;
+      const int ws = slab_lanes(ld, VEC, kWave, s);
+      const bool act = lane < ws;
+      const int lc = act ? lane : 0;  // inactive lanes read a valid value and weigh it by 0
+      double g[VEC];
 #pragma unroll
-    for (int e = 0; e < VEC; e++) g[e] = act ? src[gi[col + e]] : 0.0;
-    for (int rg = 0; rg < h; rg += RG) {
-      double acc[RG];
+      for (int e = 0; e < VEC; e++) g[e] = act ? gbuf[s0 + lane * VEC + e] : 0.0;
+      // consumption order: this wave's rows of slab s one after another.  The
+      // row bases are wave-uniform; each lane adds one 32-bit offset.  All
+      // loads are issued before any is used; rows past the wave's last row
+      // re-read that row and their accumulators are never written.
+      const char *sbase = (const char *)vals + (wbase + (int64_t)s * nw * SLAB) * bytes_of(CLS);
+      const uint32_t loff = (uint32_t)(lc * VEC * bytes_of(CLS));
+      const uint32_t row_bytes = (uint32_t)(ws * VEC * bytes_of(CLS));
+      raw16 t[kRowsPerLane];
 #pragma unroll
-      for (int rr = 0; rr < RG; rr++) {
-        acc[rr] = 0.0;
-        const int row = rg + rr;
-        if (act && row < h) {
-          double v[VEC];
-          load16<CLS>(vals, pbase + (int64_t)row * ld + col, v);
-#pragma unroll
-          for (int e = 0; e < VEC; e++) acc[rr] = fma(v[e], g[e], acc[rr]);
-        }
+      for (int i = 0; i < kRowsPerLane; i++) {
+        const int ic = i < nw ? i : nw - 1;
+        t[i] = ld16(sbase + (int64_t)ic * row_bytes, loff);
       }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int rr = 0; rr < RG; rr++) acc[rr] = wave_sum(acc[rr]);
-      if (lane == 0) {
-#pragma unroll
-        for (int rr = 0; rr < RG; rr++)
-          if (rg + rr < h) ys[rg + rr] += acc[rr];
-      }
+      for (int i = 0; i < kRowsPerLane; i++) acc[i] = dot16<CLS>(t[i], g, acc[i]);
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_stage2(const RowChunk *__restrict__ chunks,
-                                                const double *__restrict__ v64, const float *__restrict__ v32,
-                                                const unsigned short *__restrict__ v16,
-                                                const int32_t *__restrict__ g64, const int32_t *__restrict__ g32,
-                                                const int32_t *__restrict__ g16, const double *__restrict__ src,
-                                                int64_t src_len, double *__restrict__ y, int64_t ldy) {
-  __shared__ double ys[kS2Waves][kRowChunk];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+template <int MASK>
+__device__ __forceinline__ void s2_body(const RowChunk *__restrict__ chunks, int64_t nchunks,
+                                        const double *__restrict__ v64, const float *__restrict__ v32,
+                                        const unsigned short *__restrict__ v16, const int32_t *__restrict__ g64,
+                                        const int32_t *__restrict__ g32, const int32_t *__restrict__ g16,
+                                        const double *__restrict__ src, int64_t src_len, double *__restrict__ y,
+                                        int64_t ldy) {
+  __shared__ double gbuf[kS2Tile];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   const int64_t rhs = blockIdx.y;
-  const RowChunk ch = chunks[blockIdx.x];
-  ys[wave][lane] = 0.0;
-  __syncthreads();
   const double *s = src + rhs * src_len;
-  s2_class<F64>(ch, v64, g64, s, ys[wave], wave, lane);
-  s2_class<F32>(ch, v32, g32, s, ys[wave], wave, lane);
-  s2_class<BF16>(ch, v16, g16, s, ys[wave], wave, lane);
-  __syncthreads();
-  if (threadIdx.x < ch.h) {
-    const int t = threadIdx.x;
-    y[rhs * ldy + ch.r0 + t] = ((ys[0][t] + ys[1][t]) + ys[2][t]) + ys[3][t];
+  // static round-robin over the size-sorted chunks
+  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const RowChunk ch = chunks[c];
+    double acc[kRowsPerLane];
+#pragma unroll
+    for (int i = 0; i < kRowsPerLane; i++) acc[i] = 0.0;
+    if constexpr ((MASK & 1) != 0) s2_class<F64>(ch, v64, g64, s, gbuf, acc, wave, lane);
+    if constexpr ((MASK & 2) != 0) s2_class<F32>(ch, v32, g32, s, gbuf, acc, wave, lane);
+    if constexpr ((MASK & 4) != 0) s2_class<BF16>(ch, v16, g16, s, gbuf, acc, wave, lane);
+    const double sum = reduce_rows(acc, lane, kWave);
+    if ((lane & 7) == 0) {
+      const int row = wave + kS2Waves * (lane >> 3);
+      if (row < ch.h) y[rhs * ldy + ch.r0 + row] = sum;
+    }
   }
 }
 
-static_assert(kS2Waves * kWave == 256, "stage-2 workgroup is 4 waves");
-static_assert(kRowChunk <= kWave, "one LDS slot per lane");
+#define HM_S2_ARGS                                                                                              \
+  const RowChunk *__restrict__ chunks, int64_t nchunks, const double *__restrict__ v64,                         \
+      const float *__restrict__ v32, const unsigned short *__restrict__ v16, const int32_t *__restrict__ g64,   \
+      const int32_t *__restrict__ g32, const int32_t *__restrict__ g16, const double *__restrict__ src,         \
+      int64_t src_len, double *__restrict__ y, int64_t ldy
+#define HM_S2_PASS chunks, nchunks, v64, v32, v16, g64, g32, g16, src, src_len, y, ldy
+
+// One storage class.
+template <int MASK>
+__global__ __launch_bounds__(kS2Threads) void k_stage2(HM_S2_ARGS) {
+  s2_body<MASK>(HM_S2_PASS);
+}
+// Two or three classes: let the compiler size the registers (no spills).
+template <int MASK>
+__global__ __launch_bounds__(kS2Threads) void k_stage2_multi(HM_S2_ARGS) {
+  s2_body<MASK>(HM_S2_PASS);
+}
+
+static_assert(kRowChunk == kS2Waves * kRowsPerLane, "each wave owns 8 rows of a chunk");
+
+typedef void (*Stage2Fn)(const RowChunk *, int64_t, const double *, const float *, const unsigned short *,
+                         const int32_t *, const int32_t *, const int32_t *, const double *, int64_t, double *,
+                         int64_t);
+static Stage2Fn stage2_fn(int mask) {
+  switch (mask) {
+    case 1: return k_stage2<1>;
+    case 2: return k_stage2<2>;
+    case 3: return k_stage2_multi<3>;
+    case 4: return k_stage2_multi<4>;
+    case 5: return k_stage2_multi<5>;
+    case 6: return k_stage2_multi<6>;
+    default: return k_stage2_multi<7>;
+  }
+}
+typedef void (*Stage1Fn)(const S1Item *, int64_t, const void *, const double *, int64_t, int, double *, int64_t);
+static Stage1Fn stage1_fn(int cls) { return cls == F64 ? k_stage1<F64> : cls == F32 ? k_stage1<F32> : k_stage1<BF16>; }
+
+// Persistent grid sizes: as many workgroups as fit on the device at once
+// (capped by the number of work units).
+int size_grids(hmat_s *h) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return fail(HMAT_E_HIP, "cannot query the device");
+  for (int c = 0; c < NCLS; c++) {
+    const int64_t cnt = h->item_end[c] - h->item_begin[c];
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, stage1_fn(c), 256, 0) != hipSuccess || per < 1) per = 1;
+    h->grid1[c] = (int32_t)std::max<int64_t>(1, std::min<int64_t>((cnt + 3) / 4, (int64_t)per * cus));
+  }
+  int per = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, stage2_fn(h->cls_mask), kS2Threads, 0) != hipSuccess || per < 1) per = 1;
+  h->grid2 = (int32_t)std::max<int64_t>(1, std::min<int64_t>(h->nchunks, (int64_t)per * cus));
+  return HMAT_OK;
+}
 
 int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   const dim3 blk(256);
   prof_mark(h, 0, stream);
-  if (h->nitems > 0) {
-    dim3 grd((unsigned)((h->nitems + 3) / 4), (unsigned)nrhs);
-    hipLaunchKernelGGL(k_stage1, grd, blk, 0, st, h->items, h->nitems, (const double *)h->vals[F64],
-                       (const float *)h->vals[F32], (const unsigned short *)h->vals[BF16], x, ld, h->x32, h->zpart,
+  for (int c = 0; c < NCLS; c++) {
+    const int64_t cnt = h->item_end[c] - h->item_begin[c];
+    if (cnt <= 0) continue;
+    hipLaunchKernelGGL(stage1_fn(c), dim3((unsigned)h->grid1[c], (unsigned)nrhs), blk, 0, st,
+                       h->items + h->item_begin[c], cnt, (const void *)h->vals[c], x, ld, h->x32, h->zpart,
                        h->zpart_len);
   }
   prof_mark(h, 1, stream);
@@ -234,12 +340,10 @@ int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int
                        h->zpart, h->zpart_len, h->src, h->src_len);
   }
   prof_mark(h, 2, stream);
-  {
-    dim3 grd((unsigned)h->nchunks, (unsigned)nrhs);
-    hipLaunchKernelGGL(k_stage2, grd, blk, 0, st, h->chunks, (const double *)h->vals[F64],
-                       (const float *)h->vals[F32], (const unsigned short *)h->vals[BF16], h->gidx[F64],
-                       h->gidx[F32], h->gidx[BF16], h->src, h->src_len, y, ld);
-  }
+  hipLaunchKernelGGL(stage2_fn(h->cls_mask), dim3((unsigned)h->grid2, (unsigned)nrhs), dim3(kS2Threads), 0, st, h->chunks,
+                     h->nchunks, (const double *)h->vals[F64], (const float *)h->vals[F32],
+                     (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16], h->src,
+                     h->src_len, y, ld);
   prof_mark(h, 3, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(HMAT_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
@@ -305,6 +409,10 @@ int hmat_build(const hmat_blocks *blocks, const hmat_build_opts *opts, void *dev
   if (e != hipSuccess) {
     delete h;
     return hm::fail(HMAT_E_HIP, "copy to device failed: %s", hipGetErrorString(e));
+  }
+  if ((rc = hm::size_grids(h)) != HMAT_OK) {
+    delete h;
+    return rc;
   }
   *out = h;
   return HMAT_OK;

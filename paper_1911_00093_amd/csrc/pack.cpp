@@ -12,6 +12,7 @@
 //    rows of W'_m), so one pass over x_J serves every such block.
 // Rows are padded to 16 bytes so every lane load is one aligned 16-byte load.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -62,7 +63,7 @@ struct Group {
   int cls;
   int64_t col0, ncols;
   std::vector<std::pair<int64_t, int32_t>> rows;  // (block, term index into Packed::terms[block])
-  int64_t z0 = 0, zp0 = 0, nch = 0, ld = 0, w_off = 0;
+  int64_t z0 = 0, zp0 = 0, nch = 0;
 };
 
 // Column run of a stage-2 panel: `count` consecutive columns from one block.
@@ -92,6 +93,8 @@ struct Packed {
   std::vector<ChunkPlan> chunks;
   std::vector<int64_t> chunk_order;
   std::vector<S1Item> items;
+  std::vector<int64_t> item_group, item_k0, item_c0;  // source of each item's values
+  std::vector<RowChunk> rc;                            // chunk descriptors in launch order
   std::vector<ZInfo> zinfo;
   std::vector<double> dscale;
   int64_t zlen = 0, zpart_len = 0;
@@ -292,17 +295,21 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
     }
   }
   int64_t z = 0, zp = 0;
+  struct ItemSrc {
+    S1Item it;
+    int64_t group, k0, c0;
+  };
+  std::vector<ItemSrc> isrc;
   for (auto &kv : gmap) {  // key order: class, then column range
     Group &g = P->groups[kv.second];
     const int64_t R = (int64_t)g.rows.size();
     const int cls = g.cls;
-    const int64_t CH = (int64_t)s1_slabs(cls) * kWave * vec_of(cls);
+    const int lpr = s1_lpr(cls, g.ncols);
+    const int64_t CH = std::max<int64_t>((int64_t)lpr * vec_of(cls), kS1Cols);
+    const int64_t RB = (int64_t)kRowsPerLane * (kWave / lpr);  // rows per item
     g.z0 = z;
     g.zp0 = zp;
     g.nch = (g.ncols + CH - 1) / CH;
-    g.ld = pad_to(g.ncols, vec_of(cls));
-    g.w_off = P->vals_elems[cls];
-    P->vals_elems[cls] += R * g.ld;
     for (int64_t k = 0; k < R; k++) {
       auto [blk, t] = g.rows[k];
       P->terms[blk][t].zidx = z + k;
@@ -311,16 +318,15 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
     }
     for (int64_t ch = 0; ch < g.nch; ch++) {
       const int64_t c0 = ch * CH, cn = std::min(CH, g.ncols - c0);
-      for (int64_t k0 = 0; k0 < R; k0 += kS1RowsMax) {
+      for (int64_t k0 = 0; k0 < R; k0 += RB) {
         S1Item it{};
-        it.w_off = g.w_off + k0 * g.ld + c0;
         it.x0 = g.col0 + c0;
         it.out_off = zp + ch * R + k0;
-        it.ld = (int32_t)g.ld;
         it.ncols = (int32_t)cn;
-        it.nrows = (int32_t)std::min<int64_t>(kS1RowsMax, R - k0);
+        it.nrows = (int32_t)std::min<int64_t>(RB, R - k0);
         it.cls = cls;
-        P->items.push_back(it);
+        it.lpr = lpr;
+        isrc.push_back({it, kv.second, k0, c0});
       }
     }
     z += R;
@@ -332,10 +338,22 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
     delete P;
     return fail(HMAT_E_ARG, "n + z exceeds the 32-bit gather index range");
   }
-  // stage-1 items: largest first so the tail of the launch is short
-  std::stable_sort(P->items.begin(), P->items.end(), [](const S1Item &a, const S1Item &c) {
-    return (int64_t)a.ncols * a.nrows * bytes_of(a.cls) > (int64_t)c.ncols * c.nrows * bytes_of(c.cls);
+  // stage-1 items: largest first so the tail of the launch is short; each
+  // item's values are stored in launch order, so consecutive waves read
+  // consecutive memory
+  std::stable_sort(isrc.begin(), isrc.end(), [](const ItemSrc &a, const ItemSrc &c) {
+    if (a.it.cls != c.it.cls) return a.it.cls < c.it.cls;  // one launch per class
+    return (int64_t)a.it.ncols * a.it.nrows * bytes_of(a.it.cls) > (int64_t)c.it.ncols * c.it.nrows * bytes_of(c.it.cls);
   });
+  for (auto &q : isrc) {
+    const int c = q.it.cls;
+    q.it.w_off = P->vals_elems[c];
+    P->vals_elems[c] += s1_rows_pad(q.it.nrows, q.it.lpr) * pad_to(q.it.ncols, vec_of(c));
+    P->items.push_back(q.it);
+    P->item_group.push_back(q.group);
+    P->item_k0.push_back(q.k0);
+    P->item_c0.push_back(q.c0);
+  }
 
   // ---- stage-2 row chunks (segments cut into <= 64 rows)
   for (int64_t s = 0; s < nseg; s++) {
@@ -362,14 +380,7 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
       P->chunks.push_back(std::move(cp));
     }
   }
-  for (auto &cp : P->chunks)
-    for (int c = 0; c < NCLS; c++) {
-      if (!cp.K[c]) continue;
-      const int64_t ld = pad_to(cp.K[c], vec_of(c));
-      P->vals_elems[c] += cp.h * ld;
-      P->gidx_elems[c] += ld;
-    }
-  // chunk order: most bytes first
+  // chunk order: most bytes first; panels stored in that order
   P->chunk_order.resize(P->chunks.size());
   for (size_t i = 0; i < P->chunks.size(); i++) P->chunk_order[i] = (int64_t)i;
   auto cbytes = [&](int64_t i) {
@@ -379,6 +390,21 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   };
   std::stable_sort(P->chunk_order.begin(), P->chunk_order.end(),
                    [&](int64_t a, int64_t c) { return cbytes(a) > cbytes(c); });
+  P->rc.resize(P->chunks.size());
+  for (size_t q = 0; q < P->chunk_order.size(); q++) {
+    const ChunkPlan &cp = P->chunks[P->chunk_order[q]];
+    RowChunk &R = P->rc[q];
+    R.r0 = (int32_t)cp.r0;
+    R.h = (int32_t)cp.h;
+    for (int c = 0; c < NCLS; c++) {
+      R.K[c] = (int32_t)cp.K[c];
+      R.ld[c] = cp.K[c] ? (int32_t)pad_to(cp.K[c], vec_of(c)) : 0;
+      R.panel_off[c] = P->vals_elems[c];
+      R.gidx_off[c] = P->gidx_elems[c];
+      P->vals_elems[c] += (int64_t)cp.h * R.ld[c];
+      P->gidx_elems[c] += R.ld[c];
+    }
+  }
 
   // ---- device layout
   DevLayout &L = P->lay;
@@ -455,6 +481,24 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   return HMAT_OK;
 }
 
+// Run f(i) for i in [0, count) on the host's threads (disjoint outputs).
+template <class F>
+static void parallel_for(int64_t count, F f) {
+  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::atomic<int64_t> next{0};
+  auto work = [&]() {
+    for (;;) {
+      const int64_t i = next.fetch_add(1);
+      if (i >= count) break;
+      f(i);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt && t < count; t++) th.emplace_back(work);
+  work();
+  for (auto &x : th) x.join();
+}
+
 // Fill the staging image of the device buffer.
 int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
   const hmat_blocks *b = &P->b;
@@ -466,71 +510,85 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
     return fail(HMAT_E_NOMEM, "cannot allocate %llu bytes of host staging", (unsigned long long)L.off_src);
   }
   unsigned char *base = img.data();
-  auto put = [&](int cls, int64_t idx, double v) {
+  auto put = [base, &L](int cls, int64_t idx, double v) {
     unsigned char *p = base + L.off_vals[cls];
-    if (cls == F64) {
-      ((double *)p)[idx] = v;
-    } else if (cls == F32) {
-      ((float *)p)[idx] = (float)v;
-    } else {
-      ((uint16_t *)p)[idx] = bf16_bits(v);
-    }
+    if (cls == F64) ((double *)p)[idx] = v;
+    else if (cls == F32) ((float *)p)[idx] = (float)v;
+    else ((uint16_t *)p)[idx] = bf16_bits(v);
   };
-  // value of a low-rank term's V' entry / W' entry
-  auto vval = [&](int64_t k, const Term &t, int64_t i) {
+  // converted value of a low-rank term's V' entry (row i) / W' entry (column j)
+  auto vval = [b](int64_t k, const Term &t, int64_t i) {
     const double *U = b->data + b->offset[k];
     return U[i + (int64_t)t.l * b->nrows[k]] / t.div_v;
   };
-  auto wval = [&](int64_t k, const Term &t, int64_t j) {
+  auto wval = [b](int64_t k, const Term &t, int64_t j) {
     const double *Wt = b->data + b->offset[k] + b->nrows[k] * (int64_t)b->rank[k];
     return Wt[j + (int64_t)t.l * b->ncols[k]] / t.div_w;
   };
 
   // stage-2 panels and gather indices, in launch order
-  std::vector<RowChunk> rc(P->chunks.size());
-  int64_t voff[NCLS] = {0, 0, 0}, goff[NCLS] = {0, 0, 0};
-  for (auto &g : P->groups) voff[g.cls] = std::max(voff[g.cls], g.w_off + (int64_t)g.rows.size() * g.ld);
-  for (size_t q = 0; q < P->chunk_order.size(); q++) {
+  parallel_for((int64_t)P->chunk_order.size(), [&](int64_t q) {
     const ChunkPlan &cp = P->chunks[P->chunk_order[q]];
-    RowChunk &R = rc[q];
-    R.r0 = (int32_t)cp.r0;
-    R.h = (int32_t)cp.h;
+    const RowChunk &R = P->rc[q];
     for (int c = 0; c < NCLS; c++) {
-      R.K[c] = (int32_t)cp.K[c];
-      R.ld[c] = cp.K[c] ? (int32_t)pad_to(cp.K[c], vec_of(c)) : 0;
-      R.panel_off[c] = voff[c];
-      R.gidx_off[c] = goff[c];
       if (!cp.K[c]) continue;
-      int32_t *gi = (int32_t *)(base + L.off_gidx[c]) + goff[c];
-      int64_t col = 0;
-      for (const Run &run : cp.runs[c]) {
-        const int64_t k = run.block;
-        for (int32_t e = 0; e < run.count; e++, col++) {
-          if (b->kind[k] == HMAT_DENSE) {
-            gi[col] = (int32_t)(b->col0[k] + run.first + e);
-            const double *A = b->data + b->offset[k];
-            for (int64_t i = 0; i < cp.h; i++)
-              put(c, voff[c] + i * R.ld[c] + col, A[(cp.r0 - b->row0[k] + i) + (run.first + e) * b->nrows[k]]);
-          } else {
-            const Term &t = P->terms[k][run.first + e];
-            gi[col] = (int32_t)(n + t.zidx);
-            for (int64_t i = 0; i < cp.h; i++) put(c, voff[c] + i * R.ld[c] + col, vval(k, t, cp.r0 - b->row0[k] + i));
+      const int vec = vec_of(c), ld = R.ld[c], hh = (int)cp.h;
+      // column sources: (block, column of a dense block / term of a low-rank block)
+      std::vector<std::pair<int64_t, int32_t>> col(ld, {-1, 0});
+      int32_t *gi = (int32_t *)(base + L.off_gidx[c]) + R.gidx_off[c];
+      int64_t k2 = 0;
+      for (const Run &run : cp.runs[c])
+        for (int32_t e = 0; e < run.count; e++, k2++) {
+          const int64_t k = run.block;
+          col[k2] = {k, run.first + e};
+          gi[k2] = b->kind[k] == HMAT_DENSE ? (int32_t)(b->col0[k] + run.first + e)
+                                            : (int32_t)(n + P->terms[k][run.first + e].zidx);
+        }
+      for (; k2 < ld; k2++) gi[k2] = (int32_t)(n + P->zlen);  // padding reads the zero slot
+      for (int w = 0; w < kS2Waves; w++) {
+        const int nw = s2_rows_of_wave(hh, w);
+        for (int i = 0; i < nw; i++) {
+          const int64_t row = cp.r0 + w + (int64_t)kS2Waves * i;
+          for (int64_t kk = 0; kk < ld; kk++) {
+            const int s = (int)(kk / ((int64_t)kWave * vec)), lane = (int)((kk % ((int64_t)kWave * vec)) / vec);
+            const int64_t at = R.panel_off[c] + s2_elem(hh, ld, vec, w, s, i, lane) + kk % vec;
+            const auto src = col[kk];
+            double v = 0.0;
+            if (src.first >= 0) {
+              const int64_t k = src.first;
+              if (b->kind[k] == HMAT_DENSE)
+                v = b->data[b->offset[k] + (row - b->row0[k]) + (int64_t)src.second * b->nrows[k]];
+              else
+                v = vval(k, P->terms[k][src.second], row - b->row0[k]);
+            }
+            put(c, at, v);
           }
         }
       }
-      for (; col < R.ld[c]; col++) gi[col] = (int32_t)(n + P->zlen);  // padding reads the zero slot
-      voff[c] += cp.h * R.ld[c];
-      goff[c] += R.ld[c];
     }
-  }
-  // stage-1 W' rows
-  for (auto &g : P->groups)
-    for (size_t r = 0; r < g.rows.size(); r++) {
-      auto [k, ti] = g.rows[r];
-      const Term &t = P->terms[k][ti];
-      for (int64_t j = 0; j < g.ncols; j++) put(g.cls, g.w_off + (int64_t)r * g.ld + j, wval(k, t, j));
+  });
+  // stage-1 items: W' rows in consumption order
+  parallel_for((int64_t)P->items.size(), [&](int64_t q) {
+    const S1Item &it = P->items[q];
+    const Group &g = P->groups[P->item_group[q]];
+    const int c = it.cls, vec = vec_of(c), lpr = it.lpr, rpi = kWave / lpr;
+    const int cols = (int)pad_to(it.ncols, vec);
+    const int64_t rows = s1_rows_pad(it.nrows, lpr);
+    for (int64_t r = 0; r < rows; r++) {
+      const int i = (int)(r / rpi), qq = (int)(r % rpi);
+      for (int jj = 0; jj < cols; jj++) {
+        const int s = jj / (lpr * vec), u = (jj % (lpr * vec)) / vec;
+        const int64_t at = it.w_off + s1_elem(it.nrows, cols, vec, lpr, s, i, qq, u) + jj % vec;
+        double v = 0.0;
+        if (r < it.nrows && jj < it.ncols) {
+          auto [k, ti] = g.rows[P->item_k0[q] + r];
+          v = wval(k, P->terms[k][ti], P->item_c0[q] + jj);
+        }
+        put(c, at, v);
+      }
     }
-  std::memcpy(base + L.off_chunks, rc.data(), rc.size() * sizeof(RowChunk));
+  });
+  std::memcpy(base + L.off_chunks, P->rc.data(), P->rc.size() * sizeof(RowChunk));
   std::memcpy(base + L.off_items, P->items.data(), P->items.size() * sizeof(S1Item));
   std::memcpy(base + L.off_zinfo, P->zinfo.data(), P->zinfo.size() * sizeof(ZInfo));
   std::memcpy(base + L.off_dscale, P->dscale.data(), P->dscale.size() * sizeof(double));
@@ -546,6 +604,20 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
   h->zlen = P->zlen;
   h->zpart_len = P->zpart_len;
   h->src_len = n + P->zlen + 1;
+  for (int c = 0; c < NCLS; c++) {
+    h->item_begin[c] = h->item_end[c] = 0;
+    bool seen = false;
+    for (size_t q = 0; q < P->items.size(); q++)
+      if (P->items[q].cls == c) {
+        if (!seen) h->item_begin[c] = (int64_t)q;
+        seen = true;
+        h->item_end[c] = (int64_t)q + 1;
+      }
+  }
+  h->cls_mask = 0;
+  for (auto &R : P->rc)
+    for (int c = 0; c < NCLS; c++)
+      if (R.K[c]) h->cls_mask |= 1 << c;
   h->lay = L;
   h->stats = P->stats;
   h->diag_r0 = P->diag_r0;
