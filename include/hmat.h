@@ -143,8 +143,29 @@ int hmat_build(const hmat_blocks *blocks, const hmat_build_opts *opts, void *dev
 /* y = A~ x (Eq. 5) for nrhs right-hand sides.  x and y are device arrays of
  * FP64, column-major n x nrhs with leading dimension ld >= n; y is
  * overwritten and may alias x.  1 <= nrhs <= nrhs_max of the build.
- * Asynchronous on `stream`; no host synchronisation. */
+ * Asynchronous on `stream`; no host synchronisation.
+ * A handle built with nrhs_max > 1 stores its blocks for the matrix cores
+ * and multiplies 16 right-hand sides per pass with MFMA: FP64 storage with
+ * FP64 operands (same arithmetic as nrhs_max = 1), FP32 / BF16 storage with
+ * the operands x and z rounded to FP32, products accumulated in FP32 over
+ * each 16-byte load's columns (16 for FP32, 32 for BF16) and in FP64 across
+ * them. */
 int hmat_matvec(hmat_t h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream);
+
+/* Independent systems batched into one handle (not from the paper): system
+ * k (a full H-matrix of order n_k, blocks as in hmat_blocks) occupies the
+ * index range [off_k, off_k + n_k) of a block-diagonal operator, off_0 = 0,
+ * off_{k+1} = off_k + n_k; each system's blocks must partition its own
+ * n_k x n_k index set (Eqs. 1-2 per system).  One product then covers the
+ * blocks of every system in the same launches.  `systems` is a host array
+ * of `count` descriptions, only read during the call.  Vectors of a batched
+ * handle are the systems' vectors concatenated in this order. */
+int hmat_plan_batched(const hmat_blocks *systems, int64_t count, const hmat_build_opts *opts, hmat_plan_info *out);
+int hmat_build_batched(const hmat_blocks *systems, int64_t count, const hmat_build_opts *opts, void *dev_mem,
+                       uint64_t dev_bytes, void *stream, hmat_t *out);
+/* System boundaries of a handle: *count systems, offsets[0..count] (host,
+ * capacity >= count + 1; offsets may be NULL to query the count). */
+int hmat_system_offsets(hmat_t h, int64_t *offsets, int64_t capacity, int64_t *count);
 
 /* Release the host-side handle state (not the caller's device buffer). */
 int hmat_destroy(hmat_t h);

@@ -88,6 +88,7 @@ def _load():
         L.ora_conv_data.argtypes = [P]
         L.ora_matvec.argtypes = [P, P, P]
         L.ora_matvec_literal.argtypes = [P, P, P]
+        L.ora_matvec_mr.argtypes = [P, P, P]
         L.ora_rnd_bf16.restype = D
         L.ora_rnd_bf16.argtypes = [D]
         L.ora_invert.restype = C.c_int
@@ -234,11 +235,14 @@ class Converted:
             _load().ora_conv_free(self._p)
             self._p = None
 
-    def matvec(self, x, literal=False) -> np.ndarray:
+    def matvec(self, x, literal=False, matrix_cores=False) -> np.ndarray:
+        """Product in build arithmetic (default), literal Table 1 arithmetic,
+        or the operand rounding of the FP32 matrix cores (multi-RHS pass)."""
         x = _f64(x)
         y = np.empty(self.h.n)
         L = _load()
-        (L.ora_matvec_literal if literal else L.ora_matvec)(self._p, _ptr(x), _ptr(y))
+        f = L.ora_matvec_mr if matrix_cores else (L.ora_matvec_literal if literal else L.ora_matvec)
+        f(self._p, _ptr(x), _ptr(y))
         return y
 
     def block(self, b):

@@ -89,6 +89,34 @@ constexpr int64_t s1_elem(int nrows, int cols, int vec, int lpr, int s, int i, i
          (int64_t)q * ws * vec + (int64_t)u * vec;
 }
 
+// ---- multi-RHS layout (handles built with nrhs_max > 1): MFMA fragments.
+// Products of 16 right-hand sides at once go through the matrix cores:
+// v_mfma_f32_16x16x4f32 for FP32 / BF16 storage (operands rounded to FP32)
+// and v_mfma_f64_16x16x4f64 for FP64 storage.  A row tile is 16 rows; one
+// 16-byte lane load holds VEC values of one row, feeding VEC MFMA k-steps of
+// 4 columns each, so a column block is CB = 4 * VEC columns.  Within a
+// block (tile t, column block kb), lane l holds
+//   A[16 t + l % 16][kb * CB + 4 v + l / 16],  v = 0 .. VEC - 1,
+// so every wave streams its tile as contiguous 1 KB pieces.
+constexpr int kMRhs = 16;          // right-hand sides per pass (MFMA N)
+constexpr int kMRTile = 16;        // rows per MFMA tile (MFMA M)
+constexpr int kMRCols = 512;       // stage-1 item width (columns)
+constexpr int mr_cb(int cls) { return 4 * vec_of(cls); }
+
+struct MRChunk {  // stage 2, multi-RHS: rows [r0, r0 + h), h <= 64
+  int64_t panel_off[NCLS];  // element offset of (tile 0, block 0)
+  int64_t gidx_off[NCLS];
+  int32_t nkb[NCLS];        // column blocks (K padded to CB)
+  int32_t r0, h;
+};
+
+struct MRItem {  // stage 1, multi-RHS: rows [k0, k0 + nrows) (<= 64) of a group
+  int64_t w_off;
+  int64_t x0;
+  int64_t out_off;  // zpart row of k0 (entries are rows x 16 right-hand sides)
+  int32_t ncols, nrows, cls, nkb;
+};
+
 // Stage-1 reduction: z entry j = round_z(dscale[j] * sum_c zpart[zp[j] + c * stride[j]]).
 struct ZInfo {
   int64_t zp;
@@ -101,6 +129,8 @@ struct DevLayout {
   uint64_t off_gidx[NCLS], bytes_gidx[NCLS];
   uint64_t off_chunks, off_items, off_zinfo, off_dscale;
   uint64_t off_src, off_zpart;
+  uint64_t off_mrc, off_mri, off_src64, off_src32;  // multi-RHS layout
+  uint64_t ws_begin;  // everything before this offset is packed at build
   uint64_t total;
 };
 
@@ -128,6 +158,15 @@ struct hmat_s {
   int64_t item_begin[hm::NCLS] = {0, 0, 0}, item_end[hm::NCLS] = {0, 0, 0};  // stage-1 items per class
   int32_t cls_mask = 0;     // classes present in the stage-2 panels
   int32_t grid1[hm::NCLS] = {0, 0, 0}, grid2 = 0;  // persistent grid sizes
+  // multi-RHS (MFMA) layout
+  bool mr = false;
+  int64_t mr_nitems[hm::NCLS] = {0, 0, 0}, mr_item_begin[hm::NCLS] = {0, 0, 0};
+  hm::MRChunk *mrc = nullptr;
+  hm::MRItem *mri = nullptr;
+  double *src64 = nullptr;  // (n + zlen + 1) x 16, right-hand side fastest
+  float *src32 = nullptr;
+  int32_t mr_grid1[hm::NCLS] = {0, 0, 0}, mr_grid2 = 0;
+  std::vector<int64_t> sys_off;  // system boundaries of a batched handle
   double *src = nullptr;    // nrhs_max x (n + zlen + 1)
   double *zpart = nullptr;  // nrhs_max x zpart_len
   // kept for the block-Jacobi preconditioner and diagnostics
@@ -142,13 +181,20 @@ int fail(int code, const char *fmt, ...);
 
 // Host packer (pack.cpp): validation, conversion, layout and packing.
 struct Packed;
-int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *info, Packed **out_keep);
+int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *info, Packed **out_keep,
+                const int64_t *sys_off = nullptr, int64_t nsys = 0);
+// Merge independent systems into one block-diagonal description owned by a
+// Packed object, then plan it (pack.cpp).
+int plan_batched(const hmat_blocks *systems, int64_t count, const hmat_build_opts *o, hmat_plan_info *info,
+                 Packed **out_keep);
 int pack_into(Packed *p, std::vector<unsigned char> &staging, hmat_s *h);
 void packed_free(Packed *p);
 
 // Kernel launchers (matvec.hip)
 int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream);
 int size_grids(hmat_s *h);
+int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream);
+int size_grids_mr(hmat_s *h);
 
 // Kernel timing (diag.hip): mark(h, k, stream) records event k (0..3) of the
 // current product when timing is enabled.

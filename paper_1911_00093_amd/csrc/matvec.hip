@@ -362,6 +362,69 @@ int hmat_plan(const hmat_blocks *blocks, const hmat_build_opts *opts, hmat_plan_
   return hm::plan_blocks(blocks, opts, out, nullptr);
 }
 
+}  // extern "C"
+
+namespace hm {
+// Pack a planned H-matrix into the caller's device buffer and create the handle.
+static int build_planned(Packed *P, const hmat_plan_info &info, void *dev_mem, uint64_t dev_bytes, void *stream,
+                         hmat_t *out) {
+  if (!dev_mem || ((uintptr_t)dev_mem & 255u)) {
+    packed_free(P);
+    return fail(HMAT_E_WORKSPACE, "device buffer missing or not 256-byte aligned");
+  }
+  if (dev_bytes < info.device_bytes) {
+    packed_free(P);
+    return fail(HMAT_E_WORKSPACE, "device buffer holds %llu bytes, %llu needed", (unsigned long long)dev_bytes,
+                (unsigned long long)info.device_bytes);
+  }
+  hmat_s *h = new (std::nothrow) hmat_s();
+  if (!h) {
+    packed_free(P);
+    return fail(HMAT_E_NOMEM, "handle allocation failed");
+  }
+  std::vector<unsigned char> img;
+  int rc = pack_into(P, img, h);
+  packed_free(P);
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  unsigned char *d = (unsigned char *)dev_mem;
+  const DevLayout &L = h->lay;
+  auto at = [d](uint64_t off) { return off == ~0ull ? nullptr : d + off; };
+  h->dev = d;
+  for (int c = 0; c < NCLS; c++) {
+    h->vals[c] = d + L.off_vals[c];
+    h->gidx[c] = (int32_t *)(d + L.off_gidx[c]);
+  }
+  h->chunks = (RowChunk *)(d + L.off_chunks);
+  h->items = (S1Item *)(d + L.off_items);
+  h->zinfo = (ZInfo *)(d + L.off_zinfo);
+  h->dscale = (double *)(d + L.off_dscale);
+  h->mrc = (MRChunk *)(d + L.off_mrc);
+  h->mri = (MRItem *)(d + L.off_mri);
+  h->src = (double *)at(L.off_src);
+  h->src64 = (double *)at(L.off_src64);
+  h->src32 = (float *)at(L.off_src32);
+  h->zpart = (double *)(d + L.off_zpart);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(d, img.data(), img.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(HMAT_E_HIP, "copy to device failed: %s", hipGetErrorString(e));
+  }
+  if ((rc = h->mr ? size_grids_mr(h) : size_grids(h)) != HMAT_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return HMAT_OK;
+}
+}  // namespace hm
+
+extern "C" {
+
 int hmat_build(const hmat_blocks *blocks, const hmat_build_opts *opts, void *dev_mem, uint64_t dev_bytes,
                void *stream, hmat_t *out) {
   if (!out) return hm::fail(HMAT_E_ARG, "null output handle");
@@ -370,51 +433,33 @@ int hmat_build(const hmat_blocks *blocks, const hmat_build_opts *opts, void *dev
   hmat_plan_info info{};
   int rc = hm::plan_blocks(blocks, opts, &info, &P);
   if (rc) return rc;
-  if (!dev_mem || ((uintptr_t)dev_mem & 255u)) {
-    hm::packed_free(P);
-    return hm::fail(HMAT_E_WORKSPACE, "device buffer missing or not 256-byte aligned");
+  return hm::build_planned(P, info, dev_mem, dev_bytes, stream, out);
+}
+
+int hmat_plan_batched(const hmat_blocks *systems, int64_t count, const hmat_build_opts *opts, hmat_plan_info *out) {
+  if (!out) return hm::fail(HMAT_E_ARG, "null output");
+  return hm::plan_batched(systems, count, opts, out, nullptr);
+}
+
+int hmat_build_batched(const hmat_blocks *systems, int64_t count, const hmat_build_opts *opts, void *dev_mem,
+                       uint64_t dev_bytes, void *stream, hmat_t *out) {
+  if (!out) return hm::fail(HMAT_E_ARG, "null output handle");
+  *out = nullptr;
+  hm::Packed *P = nullptr;
+  hmat_plan_info info{};
+  int rc = hm::plan_batched(systems, count, opts, &info, &P);
+  if (rc) return rc;
+  return hm::build_planned(P, info, dev_mem, dev_bytes, stream, out);
+}
+
+int hmat_system_offsets(hmat_t h, int64_t *offsets, int64_t capacity, int64_t *count) {
+  if (!h || !count) return hm::fail(HMAT_E_ARG, "null argument");
+  *count = (int64_t)h->sys_off.size() - 1;
+  if (offsets) {
+    if (capacity < *count + 1) return hm::fail(HMAT_E_ARG, "offsets array holds %lld entries, %lld needed",
+                                               (long long)capacity, (long long)(*count + 1));
+    for (size_t i = 0; i < h->sys_off.size(); i++) offsets[i] = h->sys_off[i];
   }
-  if (dev_bytes < info.device_bytes) {
-    hm::packed_free(P);
-    return hm::fail(HMAT_E_WORKSPACE, "device buffer holds %llu bytes, %llu needed", (unsigned long long)dev_bytes,
-                    (unsigned long long)info.device_bytes);
-  }
-  hmat_s *h = new (std::nothrow) hmat_s();
-  if (!h) {
-    hm::packed_free(P);
-    return hm::fail(HMAT_E_NOMEM, "handle allocation failed");
-  }
-  std::vector<unsigned char> img;
-  rc = hm::pack_into(P, img, h);
-  hm::packed_free(P);
-  if (rc) {
-    delete h;
-    return rc;
-  }
-  unsigned char *d = (unsigned char *)dev_mem;
-  h->dev = d;
-  for (int c = 0; c < hm::NCLS; c++) {
-    h->vals[c] = d + h->lay.off_vals[c];
-    h->gidx[c] = (int32_t *)(d + h->lay.off_gidx[c]);
-  }
-  h->chunks = (hm::RowChunk *)(d + h->lay.off_chunks);
-  h->items = (hm::S1Item *)(d + h->lay.off_items);
-  h->zinfo = (hm::ZInfo *)(d + h->lay.off_zinfo);
-  h->dscale = (double *)(d + h->lay.off_dscale);
-  h->src = (double *)(d + h->lay.off_src);
-  h->zpart = (double *)(d + h->lay.off_zpart);
-  hipStream_t st = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(d, img.data(), img.size(), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) {
-    delete h;
-    return hm::fail(HMAT_E_HIP, "copy to device failed: %s", hipGetErrorString(e));
-  }
-  if ((rc = hm::size_grids(h)) != HMAT_OK) {
-    delete h;
-    return rc;
-  }
-  *out = h;
   return HMAT_OK;
 }
 
@@ -422,7 +467,7 @@ int hmat_matvec(hmat_t h, const double *x, double *y, int64_t nrhs, int64_t ld, 
   if (!h || !x || !y) return hm::fail(HMAT_E_ARG, "null argument");
   if (nrhs < 1 || nrhs > h->nrhs_max) return hm::fail(HMAT_E_ARG, "nrhs %lld outside [1, %d]", (long long)nrhs, h->nrhs_max);
   if (ld < h->n) return hm::fail(HMAT_E_ARG, "ld %lld < n %lld", (long long)ld, (long long)h->n);
-  return hm::launch_matvec(h, x, y, nrhs, ld, stream);
+  return h->mr ? hm::launch_matvec_mr(h, x, y, nrhs, ld, stream) : hm::launch_matvec(h, x, y, nrhs, ld, stream);
 }
 
 int hmat_destroy(hmat_t h) {

@@ -104,6 +104,17 @@ struct Packed {
   hmat_plan_info info{};
   hmat_stats stats{};
   std::vector<int64_t> diag_r0, diag_m;
+  std::vector<int64_t> sys_off;  // system boundaries (one system: {0, n})
+  // batched build: the merged block description owns these
+  std::vector<int64_t> m_row0, m_nrows, m_col0, m_ncols, m_off;
+  std::vector<int32_t> m_kind, m_rank;
+  std::vector<double> m_data;
+  // multi-RHS layout (MFMA fragment order)
+  bool mr = false;
+  std::vector<MRChunk> mrc;
+  std::vector<MRItem> mri;
+  std::vector<int64_t> mri_group, mri_k0, mri_c0;
+  int64_t mr_vals[NCLS] = {0, 0, 0}, mr_gidx[NCLS] = {0, 0, 0};
 };
 
 void packed_free(Packed *p) { delete p; }
@@ -145,7 +156,8 @@ static double pow2_at_least(double m) {
   return std::ldexp(1.0, f == 0.5 ? e - 1 : e);
 }
 
-int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *info, Packed **out_keep) {
+int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *info, Packed **out_keep,
+                const int64_t *sys_off, int64_t nsys) {
   if (!b || !o) return fail(HMAT_E_ARG, "null argument");
   if (o->precision < HMAT_M1_DOUBLE || o->precision > HMAT_BF16_SCALED)
     return fail(HMAT_E_ARG, "unknown precision %d", o->precision);
@@ -184,16 +196,27 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   P->dense_cls = (prec == HMAT_M1_DOUBLE || prec == HMAT_M2_DOUBLE || prec == HMAT_M3) ? F64 : F32;
   P->x32 = (prec == HMAT_M1_SINGLE || prec == HMAT_M2_SINGLE);
   P->z32 = (prec == HMAT_M1_SINGLE || prec == HMAT_M1_MIXED);
+  P->mr = o->nrhs_max > 1;  // multi-RHS handles use the MFMA layout
 
   // ---- partition check (Eqs. 1-2): cut the rows at every block boundary;
-  // within each row segment the covering blocks must tile [0, n) exactly.
-  std::vector<int64_t> cuts;
-  cuts.reserve(2 * nb + 2);
-  cuts.push_back(0);
-  cuts.push_back(n);
+  // within each row segment the covering blocks must tile the columns of
+  // the segment's system exactly ([0, n) unless several independent systems
+  // are batched block-diagonally).
+  std::vector<int64_t> sysb;  // system boundaries
+  if (sys_off && nsys > 0) sysb.assign(sys_off, sys_off + nsys + 1);
+  else sysb = {0, n};
+  auto sys_of = [&](int64_t i) { return (int64_t)(std::upper_bound(sysb.begin(), sysb.end(), i) - sysb.begin()) - 1; };
+  std::vector<int64_t> cuts(sysb.begin(), sysb.end());
+  cuts.reserve(2 * nb + sysb.size());
   for (int64_t k = 0; k < nb; k++) {
     cuts.push_back(b->row0[k]);
     cuts.push_back(b->row0[k] + b->nrows[k]);
+    const int64_t sr = sys_of(b->row0[k]);
+    if (sys_of(b->row0[k] + b->nrows[k] - 1) != sr || sys_of(b->col0[k]) != sr ||
+        sys_of(b->col0[k] + b->ncols[k] - 1) != sr) {
+      delete P;
+      return fail(HMAT_E_LAYOUT, "block %lld crosses a system boundary", (long long)k);
+    }
   }
   std::sort(cuts.begin(), cuts.end());
   cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
@@ -209,7 +232,8 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
     std::sort(v.begin(), v.end(), [&](int64_t a, int64_t c) {
       return b->col0[a] != b->col0[c] ? b->col0[a] < b->col0[c] : a < c;
     });
-    int64_t at = 0;
+    const int64_t sy = sys_of(cuts[s]);
+    int64_t at = sysb[sy];
     for (int64_t k : v) {
       if (b->col0[k] != at) {
         delete P;
@@ -219,12 +243,13 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
       }
       at += b->ncols[k];
     }
-    if (at != n) {
+    if (at != sysb[sy + 1]) {
       delete P;
       return fail(HMAT_E_LAYOUT, "rows [%lld,%lld): columns [%lld,%lld) uncovered", (long long)cuts[s],
-                  (long long)cuts[s + 1], (long long)at, (long long)n);
+                  (long long)cuts[s + 1], (long long)at, (long long)sysb[sy + 1]);
     }
   }
+  P->sys_off = sysb;
 
   // ---- conversion decisions per low-rank block
   P->terms.assign(nb, {});
@@ -305,8 +330,8 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
     const int64_t R = (int64_t)g.rows.size();
     const int cls = g.cls;
     const int lpr = s1_lpr(cls, g.ncols);
-    const int64_t CH = std::max<int64_t>((int64_t)lpr * vec_of(cls), kS1Cols);
-    const int64_t RB = (int64_t)kRowsPerLane * (kWave / lpr);  // rows per item
+    const int64_t CH = P->mr ? kMRCols : std::max<int64_t>((int64_t)lpr * vec_of(cls), kS1Cols);
+    const int64_t RB = P->mr ? kRowChunk : (int64_t)kRowsPerLane * (kWave / lpr);  // rows per item
     g.z0 = z;
     g.zp0 = zp;
     g.nch = (g.ncols + CH - 1) / CH;
@@ -347,12 +372,29 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   });
   for (auto &q : isrc) {
     const int c = q.it.cls;
-    q.it.w_off = P->vals_elems[c];
-    P->vals_elems[c] += s1_rows_pad(q.it.nrows, q.it.lpr) * pad_to(q.it.ncols, vec_of(c));
-    P->items.push_back(q.it);
-    P->item_group.push_back(q.group);
-    P->item_k0.push_back(q.k0);
-    P->item_c0.push_back(q.c0);
+    if (!P->mr) {
+      q.it.w_off = P->vals_elems[c];
+      P->vals_elems[c] += s1_rows_pad(q.it.nrows, q.it.lpr) * pad_to(q.it.ncols, vec_of(c));
+      P->items.push_back(q.it);
+      P->item_group.push_back(q.group);
+      P->item_k0.push_back(q.k0);
+      P->item_c0.push_back(q.c0);
+    } else {
+      // MFMA fragment order: tile-major, then column block, then lane
+      MRItem m{};
+      m.x0 = q.it.x0;
+      m.out_off = q.it.out_off;
+      m.ncols = q.it.ncols;
+      m.nrows = q.it.nrows;
+      m.cls = c;
+      m.nkb = (int32_t)((q.it.ncols + mr_cb(c) - 1) / mr_cb(c));
+      m.w_off = P->vals_elems[c];
+      P->vals_elems[c] += (int64_t)((m.nrows + kMRTile - 1) / kMRTile) * m.nkb * kWave * vec_of(c);
+      P->mri.push_back(m);
+      P->mri_group.push_back(q.group);
+      P->mri_k0.push_back(q.k0);
+      P->mri_c0.push_back(q.c0);
+    }
   }
 
   // ---- stage-2 row chunks (segments cut into <= 64 rows)
@@ -390,8 +432,25 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   };
   std::stable_sort(P->chunk_order.begin(), P->chunk_order.end(),
                    [&](int64_t a, int64_t c) { return cbytes(a) > cbytes(c); });
-  P->rc.resize(P->chunks.size());
-  for (size_t q = 0; q < P->chunk_order.size(); q++) {
+  if (P->mr) {
+    P->mrc.resize(P->chunks.size());
+    for (size_t q = 0; q < P->chunk_order.size(); q++) {
+      const ChunkPlan &cp = P->chunks[P->chunk_order[q]];
+      MRChunk &R = P->mrc[q];
+      R.r0 = (int32_t)cp.r0;
+      R.h = (int32_t)cp.h;
+      const int64_t tiles = (cp.h + kMRTile - 1) / kMRTile;
+      for (int c = 0; c < NCLS; c++) {
+        R.nkb[c] = (int32_t)((cp.K[c] + mr_cb(c) - 1) / mr_cb(c));
+        R.panel_off[c] = P->vals_elems[c];
+        R.gidx_off[c] = P->gidx_elems[c];
+        P->vals_elems[c] += tiles * R.nkb[c] * kWave * vec_of(c);
+        P->gidx_elems[c] += (int64_t)R.nkb[c] * mr_cb(c);
+      }
+    }
+  }
+  if (!P->mr) P->rc.resize(P->chunks.size());
+  for (size_t q = 0; !P->mr && q < P->chunk_order.size(); q++) {
     const ChunkPlan &cp = P->chunks[P->chunk_order[q]];
     RowChunk &R = P->rc[q];
     R.r0 = (int32_t)cp.r0;
@@ -426,8 +485,30 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   L.off_items = take(P->items.size() * sizeof(S1Item));
   L.off_zinfo = take(P->zinfo.size() * sizeof(ZInfo));
   L.off_dscale = take(P->dscale.size() * sizeof(double));
-  L.off_src = take((uint64_t)P->nrhs_max * (n + P->zlen + 1) * sizeof(double));
-  L.off_zpart = take((uint64_t)P->nrhs_max * std::max<int64_t>(P->zpart_len, 1) * sizeof(double));
+  L.off_mrc = take(P->mrc.size() * sizeof(MRChunk));
+  L.off_mri = take(P->mri.size() * sizeof(MRItem));
+  L.ws_begin = at;
+  if (P->mr) {
+    // operands of the 16 right-hand sides, right-hand side fastest
+    bool need64 = false, need32 = false;
+    for (auto &R : P->mrc) {
+      need64 |= R.nkb[F64] > 0;
+      need32 |= R.nkb[F32] > 0 || R.nkb[BF16] > 0;
+    }
+    for (auto &m : P->mri) {
+      need64 |= m.cls == F64;
+      need32 |= m.cls != F64;
+    }
+    const uint64_t ns = (uint64_t)(n + P->zlen + 1) * kMRhs;
+    L.off_src64 = need64 ? take(ns * sizeof(double)) : ~0ull;
+    L.off_src32 = need32 ? take(ns * sizeof(float)) : ~0ull;
+    L.off_src = ~0ull;
+    L.off_zpart = take((uint64_t)std::max<int64_t>(P->zpart_len, 1) * kMRhs * sizeof(double));
+  } else {
+    L.off_src64 = L.off_src32 = ~0ull;
+    L.off_src = take((uint64_t)P->nrhs_max * (n + P->zlen + 1) * sizeof(double));
+    L.off_zpart = take((uint64_t)P->nrhs_max * std::max<int64_t>(P->zpart_len, 1) * sizeof(double));
+  }
   L.total = at;
 
   // ---- sizes and statistics
@@ -481,6 +562,80 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   return HMAT_OK;
 }
 
+// Independent systems (e.g. several meshes) batched into one block-diagonal
+// H-matrix: system k occupies indices [off_k, off_k + n_k) of the merged
+// index space and keeps its own partition; the merged description is owned
+// by the returned plan.
+int plan_batched(const hmat_blocks *sys, int64_t count, const hmat_build_opts *o, hmat_plan_info *info,
+                 Packed **out_keep) {
+  if (!sys || count < 1) return fail(HMAT_E_ARG, "no systems");
+  std::vector<int64_t> off(count + 1, 0);
+  int64_t nbt = 0, ndt = 0;
+  for (int64_t s = 0; s < count; s++) {
+    if (sys[s].n <= 0 || sys[s].nblocks <= 0 || sys[s].ndata < 0) return fail(HMAT_E_ARG, "system %lld is empty", (long long)s);
+    off[s + 1] = off[s] + sys[s].n;
+    nbt += sys[s].nblocks;
+    ndt += sys[s].ndata;
+  }
+  std::vector<int64_t> row0, nrows, col0, ncols, offs;
+  std::vector<int32_t> kind, rank;
+  std::vector<double> data;
+  try {
+    row0.reserve(nbt); nrows.reserve(nbt); col0.reserve(nbt); ncols.reserve(nbt); offs.reserve(nbt);
+    kind.reserve(nbt); rank.reserve(nbt);
+    data.resize(ndt);
+  } catch (...) {
+    return fail(HMAT_E_NOMEM, "cannot merge the systems");
+  }
+  int64_t dat = 0;
+  for (int64_t s = 0; s < count; s++) {
+    const hmat_blocks &B = sys[s];
+    if (!B.row0 || !B.nrows || !B.col0 || !B.ncols || !B.kind || !B.rank || !B.offset || (!B.data && B.ndata))
+      return fail(HMAT_E_ARG, "system %lld: null block array", (long long)s);
+    for (int64_t k = 0; k < B.nblocks; k++) {
+      if (B.row0[k] < 0 || B.nrows[k] <= 0 || B.row0[k] + B.nrows[k] > B.n || B.col0[k] < 0 || B.ncols[k] <= 0 ||
+          B.col0[k] + B.ncols[k] > B.n)
+        return fail(HMAT_E_ARG, "system %lld: block %lld outside the matrix", (long long)s, (long long)k);
+      row0.push_back(B.row0[k] + off[s]);
+      nrows.push_back(B.nrows[k]);
+      col0.push_back(B.col0[k] + off[s]);
+      ncols.push_back(B.ncols[k]);
+      kind.push_back(B.kind[k]);
+      rank.push_back(B.rank[k]);
+      offs.push_back(B.offset[k] + dat);
+    }
+    if (B.ndata) std::memcpy(data.data() + dat, B.data, (size_t)B.ndata * sizeof(double));
+    dat += B.ndata;
+  }
+  hmat_blocks m{};
+  m.n = off[count];
+  m.nblocks = nbt;
+  m.row0 = row0.data();
+  m.nrows = nrows.data();
+  m.col0 = col0.data();
+  m.ncols = ncols.data();
+  m.kind = kind.data();
+  m.rank = rank.data();
+  m.offset = offs.data();
+  m.data = data.data();
+  m.ndata = ndt;
+  Packed *P = nullptr;
+  int rc = plan_blocks(&m, o, info, &P, off.data(), count);
+  if (rc) return rc;
+  // hand the merged arrays to the plan (moving keeps their addresses)
+  P->m_row0 = std::move(row0);
+  P->m_nrows = std::move(nrows);
+  P->m_col0 = std::move(col0);
+  P->m_ncols = std::move(ncols);
+  P->m_off = std::move(offs);
+  P->m_kind = std::move(kind);
+  P->m_rank = std::move(rank);
+  P->m_data = std::move(data);
+  if (out_keep) *out_keep = P;
+  else delete P;
+  return HMAT_OK;
+}
+
 // Run f(i) for i in [0, count) on the host's threads (disjoint outputs).
 template <class F>
 static void parallel_for(int64_t count, F f) {
@@ -505,9 +660,9 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
   const DevLayout &L = P->lay;
   const int64_t n = b->n;
   try {
-    img.assign(L.off_src, 0);  // workspace (src, zpart) needs no initial contents
+    img.assign(L.ws_begin, 0);  // the workspace after it needs no initial contents
   } catch (...) {
-    return fail(HMAT_E_NOMEM, "cannot allocate %llu bytes of host staging", (unsigned long long)L.off_src);
+    return fail(HMAT_E_NOMEM, "cannot allocate %llu bytes of host staging", (unsigned long long)L.ws_begin);
   }
   unsigned char *base = img.data();
   auto put = [base, &L](int cls, int64_t idx, double v) {
@@ -526,8 +681,71 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
     return Wt[j + (int64_t)t.l * b->ncols[k]] / t.div_w;
   };
 
+  // column sources of a chunk's panel of class c: (block, column of a dense
+  // block / term of a low-rank block), and its gather indices
+  auto chunk_columns = [&](const ChunkPlan &cp, int c, int64_t padded, int32_t *gi) {
+    std::vector<std::pair<int64_t, int32_t>> col(padded, {-1, 0});
+    int64_t k2 = 0;
+    for (const Run &run : cp.runs[c])
+      for (int32_t e = 0; e < run.count; e++, k2++) {
+        const int64_t k = run.block;
+        col[k2] = {k, run.first + e};
+        gi[k2] = b->kind[k] == HMAT_DENSE ? (int32_t)(b->col0[k] + run.first + e)
+                                          : (int32_t)(n + P->terms[k][run.first + e].zidx);
+      }
+    for (; k2 < padded; k2++) gi[k2] = (int32_t)(n + P->zlen);  // padding reads the zero slot
+    return col;
+  };
+  auto panel_value = [&](const std::pair<int64_t, int32_t> &src, int64_t row) {
+    if (src.first < 0) return 0.0;
+    const int64_t k = src.first;
+    if (b->kind[k] == HMAT_DENSE) return b->data[b->offset[k] + (row - b->row0[k]) + (int64_t)src.second * b->nrows[k]];
+    return vval(k, P->terms[k][src.second], row - b->row0[k]);
+  };
+  if (P->mr) {
+    // multi-RHS panels: (tile, column block, lane, v) -> A[16 t + l % 16][kb CB + 4 v + l / 16]
+    parallel_for((int64_t)P->chunk_order.size(), [&](int64_t q) {
+      const ChunkPlan &cp = P->chunks[P->chunk_order[q]];
+      const MRChunk &R = P->mrc[q];
+      for (int c = 0; c < NCLS; c++) {
+        if (!R.nkb[c]) continue;
+        const int vec = vec_of(c), cb = mr_cb(c), nkb = R.nkb[c];
+        int32_t *gi = (int32_t *)(base + L.off_gidx[c]) + R.gidx_off[c];
+        auto col = chunk_columns(cp, c, (int64_t)nkb * cb, gi);
+        const int tiles = (int)((cp.h + kMRTile - 1) / kMRTile);
+        for (int t = 0; t < tiles; t++)
+          for (int kb = 0; kb < nkb; kb++)
+            for (int l = 0; l < kWave; l++)
+              for (int v = 0; v < vec; v++) {
+                const int64_t row = t * kMRTile + l % kMRTile;
+                const int64_t kk = (int64_t)kb * cb + 4 * v + l / kMRTile;
+                const double val = row < cp.h ? panel_value(col[kk], cp.r0 + row) : 0.0;
+                put(c, R.panel_off[c] + (((int64_t)t * nkb + kb) * kWave + l) * vec + v, val);
+              }
+      }
+    });
+    parallel_for((int64_t)P->mri.size(), [&](int64_t q) {
+      const MRItem &m = P->mri[q];
+      const Group &g = P->groups[P->mri_group[q]];
+      const int c = m.cls, vec = vec_of(c), cb = mr_cb(c);
+      const int tiles = (m.nrows + kMRTile - 1) / kMRTile;
+      for (int t = 0; t < tiles; t++)
+        for (int kb = 0; kb < m.nkb; kb++)
+          for (int l = 0; l < kWave; l++)
+            for (int v = 0; v < vec; v++) {
+              const int64_t r = t * kMRTile + l % kMRTile;
+              const int64_t jj = (int64_t)kb * cb + 4 * v + l / kMRTile;
+              double val = 0.0;
+              if (r < m.nrows && jj < m.ncols) {
+                auto [k, ti] = g.rows[P->mri_k0[q] + r];
+                val = wval(k, P->terms[k][ti], P->mri_c0[q] + jj);
+              }
+              put(c, m.w_off + (((int64_t)t * m.nkb + kb) * kWave + l) * vec + v, val);
+            }
+    });
+  }
   // stage-2 panels and gather indices, in launch order
-  parallel_for((int64_t)P->chunk_order.size(), [&](int64_t q) {
+  if (!P->mr) parallel_for((int64_t)P->chunk_order.size(), [&](int64_t q) {
     const ChunkPlan &cp = P->chunks[P->chunk_order[q]];
     const RowChunk &R = P->rc[q];
     for (int c = 0; c < NCLS; c++) {
@@ -568,7 +786,7 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
     }
   });
   // stage-1 items: W' rows in consumption order
-  parallel_for((int64_t)P->items.size(), [&](int64_t q) {
+  if (!P->mr) parallel_for((int64_t)P->items.size(), [&](int64_t q) {
     const S1Item &it = P->items[q];
     const Group &g = P->groups[P->item_group[q]];
     const int c = it.cls, vec = vec_of(c), lpr = it.lpr, rpi = kWave / lpr;
@@ -589,6 +807,8 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
     }
   });
   std::memcpy(base + L.off_chunks, P->rc.data(), P->rc.size() * sizeof(RowChunk));
+  std::memcpy(base + L.off_mrc, P->mrc.data(), P->mrc.size() * sizeof(MRChunk));
+  std::memcpy(base + L.off_mri, P->mri.data(), P->mri.size() * sizeof(MRItem));
   std::memcpy(base + L.off_items, P->items.data(), P->items.size() * sizeof(S1Item));
   std::memcpy(base + L.off_zinfo, P->zinfo.data(), P->zinfo.size() * sizeof(ZInfo));
   std::memcpy(base + L.off_dscale, P->dscale.data(), P->dscale.size() * sizeof(double));
@@ -618,6 +838,21 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
   for (auto &R : P->rc)
     for (int c = 0; c < NCLS; c++)
       if (R.K[c]) h->cls_mask |= 1 << c;
+  for (auto &R : P->mrc)
+    for (int c = 0; c < NCLS; c++)
+      if (R.nkb[c]) h->cls_mask |= 1 << c;
+  h->mr = P->mr;
+  h->sys_off = P->sys_off;
+  for (int c = 0; c < NCLS; c++) {
+    h->mr_nitems[c] = h->mr_item_begin[c] = 0;
+    bool seen = false;
+    for (size_t q = 0; q < P->mri.size(); q++)
+      if (P->mri[q].cls == c) {
+        if (!seen) h->mr_item_begin[c] = (int64_t)q;
+        seen = true;
+        h->mr_nitems[c]++;
+      }
+  }
   h->lay = L;
   h->stats = P->stats;
   h->diag_r0 = P->diag_r0;

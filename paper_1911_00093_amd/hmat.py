@@ -31,7 +31,7 @@ EXPORTED = [
     "hmat_precond_plan", "hmat_precond_create", "hmat_precond_apply", "hmat_precond_destroy",
     "hmat_solver_workspace_bytes", "hmat_bicgstab", "hmat_assemble_bem", "hmat_assembly_blocks",
     "hmat_assembly_perm", "hmat_assembly_free", "hmat_version", "hmat_set_profiling", "hmat_kernel_times",
-    "hmat_stream_read", "hmat_stream_copy",
+    "hmat_stream_read", "hmat_stream_copy", "hmat_plan_batched", "hmat_build_batched", "hmat_system_offsets",
 ]
 
 
@@ -118,6 +118,9 @@ def lib():
         "hmat_kernel_times": (C.c_int, [P, P, P]),
         "hmat_stream_read": (C.c_int, [P, U64, P, P]),
         "hmat_stream_copy": (C.c_int, [P, P, U64, P]),
+        "hmat_plan_batched": (C.c_int, [P, I64, P, P]),
+        "hmat_build_batched": (C.c_int, [P, I64, P, P, U64, P, P]),
+        "hmat_system_offsets": (C.c_int, [P, P, I64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -222,22 +225,47 @@ def hmat_plan(blocks: BlockSet, precision: int, c: int = 0, nrhs_max: int = 1) -
 
 
 # ----------------------------------------------------------------- device
-class HMatrix:
-    """A packed H-matrix on the device (hmat_build); owns its torch buffer."""
+def hmat_plan_batched(systems, precision: int, c: int = 0, nrhs_max: int = 1) -> hmat_plan_info:
+    info = hmat_plan_info()
+    arr = (hmat_blocks * len(systems))(*[b.struct() for b in systems])
+    o = hmat_build_opts(int(precision), int(c), int(nrhs_max), 0)
+    _check(lib().hmat_plan_batched(arr, len(systems), C.byref(o), C.byref(info)))
+    return info
 
-    def __init__(self, blocks: BlockSet, precision: int, c: int = 0, nrhs_max: int = 1, device="cuda", stream=None):
+
+class HMatrix:
+    """A packed H-matrix on the device (hmat_build / hmat_build_batched);
+    owns its torch buffer."""
+
+    def __init__(self, blocks, precision: int, c: int = 0, nrhs_max: int = 1, device="cuda", stream=None):
         import torch
 
         self.precision, self.c, self.nrhs_max = int(precision), int(c), int(nrhs_max)
-        self.plan = hmat_plan(blocks, precision, c, nrhs_max)
-        self.n = blocks.n
-        self.buf = torch.empty(int(self.plan.device_bytes), dtype=torch.uint8, device=device)
-        s = blocks.struct()
+        batched = isinstance(blocks, (list, tuple))
         o = hmat_build_opts(self.precision, self.c, self.nrhs_max, 0)
         h = C.c_void_p()
-        _check(lib().hmat_build(C.byref(s), C.byref(o), C.c_void_p(self.buf.data_ptr()), self.buf.numel(),
-                                _stream_ptr(stream), C.byref(h)))
+        if batched:
+            self.plan = hmat_plan_batched(blocks, precision, c, nrhs_max)
+            self.n = sum(b.n for b in blocks)
+            self.buf = torch.empty(int(self.plan.device_bytes), dtype=torch.uint8, device=device)
+            arr = (hmat_blocks * len(blocks))(*[b.struct() for b in blocks])
+            _check(lib().hmat_build_batched(arr, len(blocks), C.byref(o), C.c_void_p(self.buf.data_ptr()),
+                                            self.buf.numel(), _stream_ptr(stream), C.byref(h)))
+        else:
+            self.plan = hmat_plan(blocks, precision, c, nrhs_max)
+            self.n = blocks.n
+            self.buf = torch.empty(int(self.plan.device_bytes), dtype=torch.uint8, device=device)
+            s = blocks.struct()
+            _check(lib().hmat_build(C.byref(s), C.byref(o), C.c_void_p(self.buf.data_ptr()), self.buf.numel(),
+                                    _stream_ptr(stream), C.byref(h)))
         self.h = h
+
+    def system_offsets(self) -> np.ndarray:
+        cnt = C.c_int64()
+        _check(lib().hmat_system_offsets(self.h, None, 0, C.byref(cnt)))
+        off = np.zeros(cnt.value + 1, np.int64)
+        _check(lib().hmat_system_offsets(self.h, _p(off), off.size, C.byref(cnt)))
+        return off
 
     def __del__(self):
         if getattr(self, "h", None):

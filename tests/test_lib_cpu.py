@@ -154,3 +154,26 @@ def test_assemble_rejects_bad_options():
 def test_solver_workspace_size():
     assert hmat.hmat_solver_workspace_bytes(0) == 0
     assert hmat.hmat_solver_workspace_bytes(1000) >= 9 * 1000 * 8
+
+
+def test_plan_batched_systems():
+    """Several independent systems: each must partition its own index set."""
+    b2 = hmat.BlockSet.from_arrays(2, [0], [2], [0], [2], [0], [0], [0], np.ones(4))
+    d = _tiny_partition()
+    b4 = hmat.BlockSet.from_arrays(**d)
+    info = hmat.hmat_plan_batched([b2, b4, b2], 0)
+    assert info.nblocks_dense == 4 and info.nblocks_lowrank == 2
+    bad = _tiny_partition()
+    bad["ncols"] = [2, 1, 2, 2]
+    with pytest.raises(hmat.HmatError) as e:
+        hmat.hmat_plan_batched([b2, hmat.BlockSet.from_arrays(**bad)], 0)
+    assert e.value.code == hmat.HMAT_E_LAYOUT
+
+
+@pytest.mark.parametrize("nrhs_max", [1, 16])
+def test_plan_multirhs_sizes(nrhs_max):
+    m, h = oracle_hmatrix("sphere-L3")
+    bs = blockset_from_oracle(h)
+    a = hmat.hmat_plan(bs, 5, nrhs_max=nrhs_max)
+    assert a.matrix_bytes == hmat.hmat_plan(bs, 5).matrix_bytes
+    assert a.device_bytes > a.matrix_bytes
