@@ -241,6 +241,39 @@ uint64_t hmat_solver_workspace_bytes(int64_t n);
 int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, const hmat_solve_opts *opts,
                   hmat_solve_info *info, void *work, uint64_t work_bytes, void *stream);
 
+/* Outcome of one recurrence of the batched solver. */
+typedef struct {
+    int32_t status;           /* HMAT_OK, HMAT_E_BREAKDOWN, HMAT_E_NOCONV or HMAT_E_NONFINITE */
+    int32_t restarts;
+    int64_t iterations;
+    double rel_res;           /* final |r|/|b| (the true one once converged) */
+    double true_rel_res;      /* |b - A~64 x| / |b| at the end */
+} hmat_batch_result;
+
+/* Device bytes of workspace hmat_bicgstab_batched needs for handle h and nrhs
+ * right-hand sides (0 on bad arguments). */
+uint64_t hmat_bicgstab_batched_workspace_bytes(hmat_t h, int64_t nrhs);
+
+/* BiCGSTAB (Sec. 3.5, Algorithm 1) on every system of a batched handle for
+ * nrhs right-hand sides at once: nsys x nrhs independent recurrences, each
+ * with its own FP64 scalars, the same stopping rule and FP64 true-residual
+ * confirmation (Sec. 4.1.3) as hmat_bicgstab, and the same restart on a
+ * failed check.  A recurrence that converges or breaks down stops while the
+ * others continue; the products still run over all nrhs columns.
+ * b, x: device, n x nrhs with column k at offset k * n (column-major, the
+ * layout of hmat_matvec with ld = n); x holds x_0 on entry.  1 <= nrhs <=
+ * min(16, nrhs_max of both handles).  h_fp64 (may be NULL = h_iter) must
+ * have the same systems.  opts->precond and opts->history must be NULL;
+ * opts->use_graph = 1 captures one iteration in a HIP graph on an internal
+ * stream and replays it on `stream`.  results: host, nsys x nrhs entries,
+ * system-major (entry s * nrhs + k).  summary (may be NULL): status = the
+ * first failing status, iterations and restarts = maxima, matvecs = batched
+ * products.  Returns HMAT_OK when every recurrence converged.  Synchronises
+ * `stream` before returning. */
+int hmat_bicgstab_batched(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, int64_t nrhs,
+                          const hmat_solve_opts *opts, hmat_batch_result *results, hmat_solve_info *summary,
+                          void *work, uint64_t work_bytes, void *stream);
+
 /* ------------------------------------------------------------ assembly */
 /* Setup step (untimed; not the product path): build an FP64 H-matrix for the
  * BEM collocation problem on a triangle mesh -- cluster tree (bisection of

@@ -302,8 +302,10 @@ class Jacobi:
 
 
 def bicgstab(op: Converted, b, op64: Converted | None = None, x0=None, tol=1e-8, maxiter=1000,
-             literal=False, precond: Jacobi | None = None):
-    """BiCGSTAB (Algorithm 1) with the given operator; returns (x, info dict)."""
+             literal=False, precond: Jacobi | None = None, matrix_cores=False):
+    """BiCGSTAB (Algorithm 1) with the given operator; returns (x, info dict).
+    matrix_cores: iterate with the matrix-core rounding of the product
+    (Converted.matvec(matrix_cores=True)); the true residual stays FP64."""
     L = _load()
     b = _f64(b)
     n = b.size
@@ -316,7 +318,8 @@ def bicgstab(op: Converted, b, op64: Converted | None = None, x0=None, tol=1e-8,
     rr = C.c_double()
     tr = C.c_double()
     o64 = op64 if op64 is not None else op
-    st = L.ora_bicgstab(op._p, o64._p, precond._p if precond is not None else None, int(literal), _ptr(b), _ptr(x),
+    st = L.ora_bicgstab(op._p, o64._p, precond._p if precond is not None else None,
+                        2 if matrix_cores else int(bool(literal)), _ptr(b), _ptr(x),
                         float(tol), int(maxiter), C.byref(it), C.byref(nmv), C.byref(nmv64),
                         _ptr(hist), _ptr(shist), C.byref(rr), C.byref(tr))
     k = it.value

@@ -990,6 +990,8 @@ static double ora_dot(int64_t n, const double *a, const double *b)
     return s;
 }
 
+/* literal: 0 the build product, 1 the literal one, 2 the build product
+ * with matrix-core operand rounding (ora_matvec_mr) */
 typedef struct {
     const ora_conv *v;
     int literal;
@@ -997,7 +999,8 @@ typedef struct {
 
 static void ora_apply_op(const ora_opctx *o, const double *x, double *y)
 {
-    if (o->literal) ora_matvec_literal(o->v, x, y);
+    if (o->literal == 2) ora_matvec_mr(o->v, x, y);
+    else if (o->literal) ora_matvec_literal(o->v, x, y);
     else ora_matvec(o->v, x, y);
 }
 

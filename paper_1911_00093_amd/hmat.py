@@ -32,6 +32,7 @@ EXPORTED = [
     "hmat_solver_workspace_bytes", "hmat_bicgstab", "hmat_assemble_bem", "hmat_assembly_blocks",
     "hmat_assembly_perm", "hmat_assembly_free", "hmat_version", "hmat_set_profiling", "hmat_kernel_times",
     "hmat_stream_read", "hmat_stream_copy", "hmat_plan_batched", "hmat_build_batched", "hmat_system_offsets",
+    "hmat_bicgstab_batched_workspace_bytes", "hmat_bicgstab_batched",
 ]
 
 
@@ -79,6 +80,11 @@ class hmat_solve_info(C.Structure):
                 ("true_rel_res", C.c_double)]
 
 
+class hmat_batch_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("restarts", C.c_int32), ("iterations", C.c_int64),
+                ("rel_res", C.c_double), ("true_rel_res", C.c_double)]
+
+
 class hmat_assemble_opts(C.Structure):
     _fields_ = [("leaf", C.c_int64), ("eta", C.c_double), ("eps", C.c_double), ("threads", C.c_int32),
                 ("reserved", C.c_int32)]
@@ -121,6 +127,8 @@ def lib():
         "hmat_plan_batched": (C.c_int, [P, I64, P, P]),
         "hmat_build_batched": (C.c_int, [P, I64, P, P, U64, P, P]),
         "hmat_system_offsets": (C.c_int, [P, P, I64, P]),
+        "hmat_bicgstab_batched_workspace_bytes": (U64, [P, I64]),
+        "hmat_bicgstab_batched": (C.c_int, [P, P, P, P, I64, P, P, P, P, U64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -373,6 +381,46 @@ def hmat_bicgstab(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = None, tol
     if hist is not None:
         d["history"] = hist[:info.iterations + 1]
     return x, d
+
+
+def hmat_bicgstab_batched_workspace_bytes(h: HMatrix, nrhs: int) -> int:
+    return int(lib().hmat_bicgstab_batched_workspace_bytes(h.h, int(nrhs)))
+
+
+def hmat_bicgstab_batched(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = None, tol=1e-8, maxiter=1000,
+                          poll_every=1, use_graph=True, work=None, stream=None, raise_on_error=False):
+    """BiCGSTAB on every system of a batched handle for every column of b at
+    once.  b: device FP64 (n, nrhs), column-major (b.T contiguous).  Returns
+    (x, summary dict, per-recurrence dict of arrays of shape (nsys, nrhs))."""
+    import torch
+
+    n = h_iter.n
+    if b.dim() != 2 or b.stride(0) != 1 or b.stride(1) != n:
+        raise ValueError("b must be (n, nrhs) with b.T contiguous")
+    nrhs = b.shape[1]
+    if x is None:
+        x = torch.zeros((nrhs, n), dtype=torch.float64, device=b.device).T
+    elif x.shape != b.shape or x.stride() != b.stride():
+        raise ValueError("x must have the shape and layout of b")
+    wb = hmat_bicgstab_batched_workspace_bytes(h_iter, nrhs)
+    if wb == 0:
+        raise ValueError("bad handle or nrhs")
+    if work is None or work.numel() < wb:
+        work = torch.empty(wb, dtype=torch.uint8, device=b.device)
+    nsys = h_iter.system_offsets().size - 1
+    res = (hmat_batch_result * (nsys * nrhs))()
+    o = hmat_solve_opts(float(tol), int(maxiter), int(poll_every), int(bool(use_graph)), None, None)
+    info = hmat_solve_info()
+    rc = lib().hmat_bicgstab_batched(h_iter.h, (h_fp64 or h_iter).h, C.c_void_p(b.data_ptr()),
+                                     C.c_void_p(x.data_ptr()), int(nrhs), C.byref(o), res, C.byref(info),
+                                     C.c_void_p(work.data_ptr()), work.numel(), _stream_ptr(stream))
+    if rc != HMAT_OK and (raise_on_error or rc not in (HMAT_E_BREAKDOWN, HMAT_E_NOCONV, HMAT_E_NONFINITE)):
+        _check(rc)
+    summary = dict(status=info.status, restarts=info.restarts, iterations=info.iterations, matvecs=info.matvecs,
+                   matvecs_fp64=info.matvecs_fp64, rel_res=info.rel_res, true_rel_res=info.true_rel_res)
+    per = {f: np.array([getattr(r, f) for r in res]).reshape(nsys, nrhs)
+           for f in ("status", "restarts", "iterations", "rel_res", "true_rel_res")}
+    return x, summary, per
 
 
 def hmat_stream_read(buf, stream=None):

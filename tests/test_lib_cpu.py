@@ -154,6 +154,7 @@ def test_assemble_rejects_bad_options():
 def test_solver_workspace_size():
     assert hmat.hmat_solver_workspace_bytes(0) == 0
     assert hmat.hmat_solver_workspace_bytes(1000) >= 9 * 1000 * 8
+    assert hmat.lib().hmat_bicgstab_batched_workspace_bytes(None, 4) == 0
 
 
 def test_plan_batched_systems():

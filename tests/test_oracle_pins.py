@@ -586,3 +586,27 @@ def test_matrix_core_mode_rounds_z():
     # block (0,1): V = 3, W = 1/3 -> V' = 1, W' = 1, D = 3 * fl64(1/3)
     d = 3.0 * (1.0 / 3.0)
     assert y[0] == float(np.float32(d * float(np.float32(x[1]))))
+
+
+def test_bicgstab_matrix_core_operator_one_step():
+    """The solver's matrix-core mode iterates with the matrix-core product:
+    one step of Algorithm 1 from x_0 = 0 written out with that product
+    (p = r = b, v = A p, alpha = r.r / r.v, s = r - alpha v, t = A s,
+    omega = t.s / t.t, x = alpha p + omega s).  The plain product differs by
+    ~1e-7 here, far above the 1e-12 the comparison allows."""
+    m, h = oracle_hmatrix("sphere-L3")
+    conv = oracle.Converted(h, oracle.M2_MIXED)
+    b = m.rhs()[h.perm]
+    A = lambda v: conv.matvec(v, matrix_cores=True)
+    r = b.copy()
+    v = A(r)
+    alpha = (r @ r) / (r @ v)
+    s = r - alpha * v
+    t = A(s)
+    omega = (t @ s) / (t @ t)
+    x_step = alpha * r + omega * s
+    x, info = oracle.bicgstab(conv, b, tol=1e-30, maxiter=1, matrix_cores=True)
+    assert info["iterations"] == 1
+    assert np.linalg.norm(x - x_step) <= 1e-12 * np.linalg.norm(x_step)
+    xp, _ = oracle.bicgstab(conv, b, tol=1e-30, maxiter=1)
+    assert np.linalg.norm(xp - x_step) > 1e-10 * np.linalg.norm(x_step)
