@@ -288,7 +288,7 @@ def bench_batched(args, W, variant, dev, stream):
     batched BiCGSTAB of every (mesh, right-hand side) pair to 1e-8, each
     confirmed by the FP64 true residual, with the iteration replayed from a
     HIP graph; the products run over all meshes and right-hand sides in one
-    persistent launch per stage on the matrix cores."""
+    persistent launch per stage on the FP64 matrix cores."""
     import torch
 
     from paper_1911_00093_amd import hmat, meshes
@@ -385,7 +385,7 @@ def bench_batched(args, W, variant, dev, stream):
         "config": {
             "workload": f"{args.workload}: {W['desc']}",
             "precision": args.variant,
-            "storage": "fp32 matrix (matrix-core products, fp32 operands), fp64 D_m / x / y / Krylov",
+            "storage": "fp32 matrix widened exactly on the fp64 matrix cores, fp64 D_m / x / y / Krylov",
             "n": n, "systems": nsys, "rhs_per_system": nrhs,
             "step": f"batched BiCGSTAB of all {nsys * nrhs} (mesh, rhs) pairs, x0=0 -> |r|/|b|<{args.tol:g} each, "
                     "confirmed by the FP64 true residual; iteration replayed from a HIP graph",
@@ -421,9 +421,9 @@ def bench_batched(args, W, variant, dev, stream):
 
 def cpu_baseline_batched(ms, W, variant, nrhs, sample=4):
     """The oracle on a sample of the meshes: its own assembly (untimed), then
-    one product with matrix-core rounding per right-hand side (the oracle
-    has no multi-column product), timed; bytes counted as for the device's
-    16-column product of the same meshes."""
+    one product per right-hand side (the oracle has no multi-column
+    product), timed; bytes counted as for the device's 16-column product of
+    the same meshes."""
     import oracle
     from paper_1911_00093_amd import hmat
 
@@ -439,10 +439,10 @@ def cpu_baseline_batched(ms, W, variant, nrhs, sample=4):
     t0 = time.perf_counter()
     for c, x in zip(convs, X):
         for k in range(nrhs):
-            c.matvec(x[k], matrix_cores=True)
+            c.matvec(x[k])
     dt = time.perf_counter() - t0
     return {"value": round(B / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nrhs} single-column oracle products (matrix-core rounding) on each of the first {sample} "
+            "sample": f"{nrhs} single-column oracle products on each of the first {sample} "
                       f"meshes (N = {sum(c.h.n for c in convs)}), {dt * 1e3:.0f} ms in total, after an untimed "
                       f"oracle assembly"}
 

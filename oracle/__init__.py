@@ -88,7 +88,6 @@ def _load():
         L.ora_conv_data.argtypes = [P]
         L.ora_matvec.argtypes = [P, P, P]
         L.ora_matvec_literal.argtypes = [P, P, P]
-        L.ora_matvec_mr.argtypes = [P, P, P]
         L.ora_rnd_bf16.restype = D
         L.ora_rnd_bf16.argtypes = [D]
         L.ora_invert.restype = C.c_int
@@ -235,13 +234,12 @@ class Converted:
             _load().ora_conv_free(self._p)
             self._p = None
 
-    def matvec(self, x, literal=False, matrix_cores=False) -> np.ndarray:
-        """Product in build arithmetic (default), literal Table 1 arithmetic,
-        or the operand rounding of the FP32 matrix cores (multi-RHS pass)."""
+    def matvec(self, x, literal=False) -> np.ndarray:
+        """Product in build arithmetic (default) or literal Table 1 arithmetic."""
         x = _f64(x)
         y = np.empty(self.h.n)
         L = _load()
-        f = L.ora_matvec_mr if matrix_cores else (L.ora_matvec_literal if literal else L.ora_matvec)
+        f = L.ora_matvec_literal if literal else L.ora_matvec
         f(self._p, _ptr(x), _ptr(y))
         return y
 
@@ -302,10 +300,8 @@ class Jacobi:
 
 
 def bicgstab(op: Converted, b, op64: Converted | None = None, x0=None, tol=1e-8, maxiter=1000,
-             literal=False, precond: Jacobi | None = None, matrix_cores=False):
-    """BiCGSTAB (Algorithm 1) with the given operator; returns (x, info dict).
-    matrix_cores: iterate with the matrix-core rounding of the product
-    (Converted.matvec(matrix_cores=True)); the true residual stays FP64."""
+             literal=False, precond: Jacobi | None = None):
+    """BiCGSTAB (Algorithm 1) with the given operator; returns (x, info dict)."""
     L = _load()
     b = _f64(b)
     n = b.size
@@ -319,7 +315,7 @@ def bicgstab(op: Converted, b, op64: Converted | None = None, x0=None, tol=1e-8,
     tr = C.c_double()
     o64 = op64 if op64 is not None else op
     st = L.ora_bicgstab(op._p, o64._p, precond._p if precond is not None else None,
-                        2 if matrix_cores else int(bool(literal)), _ptr(b), _ptr(x),
+                        int(bool(literal)), _ptr(b), _ptr(x),
                         float(tol), int(maxiter), C.byref(it), C.byref(nmv), C.byref(nmv64),
                         _ptr(hist), _ptr(shist), C.byref(rr), C.byref(tr))
     k = it.value

@@ -697,14 +697,12 @@ const double *ora_conv_data(const ora_conv *v) { return v->data; }
  *             y^_m[i] += V'_m[i][j] z_m[j]                      (Eq. 24)
  *   result:   y~[i] += y^_m[i - i_m^(s) + 1]                    (Eq. 25)
  * Method 3 adds the y^_m of its FP64 part and of its FP32 part. */
-static void ora_matvec_impl(const ora_conv *v, const double *x, double *y, int mr)
+void ora_matvec(const ora_conv *v, const double *x, double *y)
 {
     const ora_hmat *h = v->h;
     int64_t n = h->n;
     double *xe = (double *)malloc((size_t)n * sizeof(double));
-    double *x32 = (double *)malloc((size_t)n * sizeof(double));
     for (int64_t i = 0; i < n; i++) xe[i] = v->x32 ? ora_rnd32(x[i]) : x[i];
-    for (int64_t i = 0; i < n; i++) x32[i] = ora_rnd32(x[i]);
     for (int64_t i = 0; i < n; i++) y[i] = 0.0;
     int64_t maxm = 1, maxr = 1;
     for (int64_t b = 0; b < h->nblocks; b++) {
@@ -717,10 +715,9 @@ static void ora_matvec_impl(const ora_conv *v, const double *x, double *y, int m
     for (int64_t bi = 0; bi < h->nblocks; bi++) {
         const ora_block *b = &h->blocks[bi];
         int64_t m = b->nrows, nc = b->ncols;
+        const double *xm = xe + b->col0;
         const double *d = v->data + v->toff_data[bi];
         if (b->kind == 0) {
-            /* matrix-core arithmetic: an FP32-stored value meets an FP32 operand */
-            const double *xm = (mr && v->dense32 ? x32 : xe) + b->col0;
             for (int64_t i = 0; i < m; i++) {
                 double s = 0.0;
                 for (int64_t j = 0; j < nc; j++) s += d[i + j * m] * xm[j];
@@ -733,12 +730,10 @@ static void ora_matvec_impl(const ora_conv *v, const double *x, double *y, int m
             const int8_t *P = v->tprec + v->toff[bi];
             for (int64_t i = 0; i < m; i++) yh[i] = yh2[i] = 0.0;
             for (int64_t l = 0; l < r; l++) {
-                const int lo = mr && P[l] != 64;
-                const double *xm = (lo ? x32 : xe) + b->col0;
                 double s = 0.0;
                 for (int64_t j = 0; j < nc; j++) s += Wt[j + l * nc] * xm[j];
                 s *= D[l];
-                z[l] = (v->z32 || lo) ? ora_rnd32(s) : s;
+                z[l] = v->z32 ? ora_rnd32(s) : s;
             }
             /* Method 3: FP64 terms into yh, FP32 terms into yh2, then added */
             for (int64_t i = 0; i < m; i++) {
@@ -756,21 +751,10 @@ static void ora_matvec_impl(const ora_conv *v, const double *x, double *y, int m
         for (int64_t i = 0; i < m; i++) y[b->row0 + i] += yh[i];
     }
     free(xe);
-    free(x32);
     free(yh);
     free(yh2);
     free(z);
 }
-
-void ora_matvec(const ora_conv *v, const double *x, double *y) { ora_matvec_impl(v, x, y, 0); }
-
-/* The product as the FP32 matrix cores of a multi-right-hand-side pass form
- * it (not from the paper): every FP32- or BF16-stored value is multiplied by
- * an operand rounded to FP32 -- x, or z rounded to FP32 after its FP64
- * sum -- and the product itself is exact (in FP64); FP64-stored values keep
- * FP64 operands.  The matrix cores additionally accumulate in FP32 over
- * short runs of columns, which the tests bound separately. */
-void ora_matvec_mr(const ora_conv *v, const double *x, double *y) { ora_matvec_impl(v, x, y, 1); }
 
 /* Same product with every operation in the type Table 1 gives its operands
  * ("literal" arithmetic): when two operands differ in precision the lower
@@ -990,8 +974,6 @@ static double ora_dot(int64_t n, const double *a, const double *b)
     return s;
 }
 
-/* literal: 0 the build product, 1 the literal one, 2 the build product
- * with matrix-core operand rounding (ora_matvec_mr) */
 typedef struct {
     const ora_conv *v;
     int literal;
@@ -999,8 +981,7 @@ typedef struct {
 
 static void ora_apply_op(const ora_opctx *o, const double *x, double *y)
 {
-    if (o->literal == 2) ora_matvec_mr(o->v, x, y);
-    else if (o->literal) ora_matvec_literal(o->v, x, y);
+    if (o->literal) ora_matvec_literal(o->v, x, y);
     else ora_matvec(o->v, x, y);
 }
 

@@ -90,14 +90,15 @@ constexpr int64_t s1_elem(int nrows, int cols, int vec, int lpr, int s, int i, i
 }
 
 // ---- multi-RHS layout (handles built with nrhs_max > 1): MFMA fragments.
-// Products of 16 right-hand sides at once go through the matrix cores:
-// v_mfma_f32_16x16x4f32 for FP32 / BF16 storage (operands rounded to FP32)
-// and v_mfma_f64_16x16x4f64 for FP64 storage.  A row tile is 16 rows; one
-// 16-byte lane load holds VEC values of one row, feeding VEC MFMA k-steps of
-// 4 columns each, so a column block is CB = 4 * VEC columns.  Within a
-// block (tile t, column block kb), lane l holds
+// Products of 16 right-hand sides at once go through v_mfma_f64_16x16x4f64
+// with every stored value widened exactly to FP64.  A row tile is 16 rows;
+// one 16-byte lane load holds VEC values of one row, feeding VEC MFMA
+// k-steps of 4 columns each, so a column block is CB = 4 * VEC columns.
+// Within a block (tile t, column block kb), lane l holds
 //   A[16 t + l % 16][kb * CB + 4 v + l / 16],  v = 0 .. VEC - 1,
-// so every wave streams its tile as contiguous 1 KB pieces.
+// so every wave streams its tile as contiguous 1 KB pieces.  The stage-2
+// gather indices of a block are stored lane-group-major: entry
+// kb * CB + q * VEC + v is the source of column kb * CB + 4 v + q.
 constexpr int kMRhs = 16;          // right-hand sides per pass (MFMA N)
 constexpr int kMRTile = 16;        // rows per MFMA tile (MFMA M)
 constexpr int kMRCols = 512;       // stage-1 item width (columns)
@@ -114,6 +115,7 @@ struct MRItem {  // stage 1, multi-RHS: rows [k0, k0 + nrows) (<= 64) of a group
   int64_t w_off;
   int64_t x0;
   int64_t out_off;  // zpart row of k0 (entries are rows x 16 right-hand sides)
+  int64_t z_off;    // z index of k0 when the item spans the group's columns, else -1
   int32_t ncols, nrows, cls, nkb;
 };
 
@@ -129,7 +131,7 @@ struct DevLayout {
   uint64_t off_gidx[NCLS], bytes_gidx[NCLS];
   uint64_t off_chunks, off_items, off_zinfo, off_dscale;
   uint64_t off_src, off_zpart;
-  uint64_t off_mrc, off_mri, off_src64, off_src32;  // multi-RHS layout
+  uint64_t off_mrc, off_mri, off_src64;  // multi-RHS layout
   uint64_t ws_begin;  // everything before this offset is packed at build
   uint64_t total;
 };
@@ -164,7 +166,6 @@ struct hmat_s {
   hm::MRChunk *mrc = nullptr;
   hm::MRItem *mri = nullptr;
   double *src64 = nullptr;  // (n + zlen + 1) x 16, right-hand side fastest
-  float *src32 = nullptr;
   int32_t mr_grid1[hm::NCLS] = {0, 0, 0}, mr_grid2 = 0;
   std::vector<int64_t> sys_off;  // system boundaries of a batched handle
   double *src = nullptr;    // nrhs_max x (n + zlen + 1)

@@ -405,7 +405,6 @@ static int build_planned(Packed *P, const hmat_plan_info &info, void *dev_mem, u
   h->mri = (MRItem *)(d + L.off_mri);
   h->src = (double *)at(L.off_src);
   h->src64 = (double *)at(L.off_src64);
-  h->src32 = (float *)at(L.off_src32);
   h->zpart = (double *)(d + L.off_zpart);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync(d, img.data(), img.size(), hipMemcpyHostToDevice, st);

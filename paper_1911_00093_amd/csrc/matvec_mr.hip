@@ -3,22 +3,21 @@
 //
 // Same two-stage, atomic-free structure as the single-vector product
 // (Eqs. 9-10, 21-25), but every block product is a dense contraction over
-// 16 right-hand sides, so it runs on MFMA:
-//  * FP32 and BF16 storage: v_mfma_f32_16x16x4f32 with FP32 operands (BF16
-//    widens exactly to FP32; x and z are rounded to FP32 for the matrix
-//    cores); each 16-byte load's 4*VEC columns are accumulated in FP32, then
-//    added to FP64 accumulators.
-//  * FP64 storage: v_mfma_f64_16x16x4f64 with FP64 operands, FP64
-//    accumulation (the same arithmetic as the single-vector product).
-// Operands live in src64 / src32 with the right-hand side fastest:
-// src[(index) * 16 + rhs], index in [x_eff (n) | z (zlen) | 0].
-//  K0  x -> src (transpose to right-hand side fastest, FP32 copy).
-//  K1  stage 1: a workgroup per item (<= 64 rows of a column group, <= 512
-//      columns); wave t owns row tile t; B operands read straight from src.
-//  K1b z reduction in chunk order, times D_m / scales, FP32 copy.
-//  K2  stage 2: a workgroup per row chunk (<= 64 rows), wave t owns row
-//      tile t; the chunk's operands for 16 right-hand sides are gathered into
-//      LDS once and shared by the four waves; each row of Y written once.
+// 16 right-hand sides and runs on v_mfma_f64_16x16x4f64.  Stored values of
+// every class (FP64, FP32, BF16) widen exactly to FP64 in registers and the
+// operands are the FP64 x_eff / z of the single-vector product, so the
+// arithmetic is that product's (exact products, FP64 sums, Table 1 roundings
+// of x and z): only the summation order differs.
+// Operands live in src64 with the right-hand side fastest:
+// src64[(index) * 16 + rhs], index in [x_eff (n) | z (zlen) | 0].
+//  K0  x -> src64 (transpose to right-hand side fastest, Table 1 rounding).
+//  K1  stage 1: one wave per item (<= 64 rows = 4 row tiles of a column
+//      group, <= 512 columns); B operands read straight from src64.  An item
+//      that covers its rows' whole column range finishes z = D_m sum itself.
+//  K1b the other z entries: reduction in chunk order, times D_m, rounding.
+//  K2  stage 2: one wave per row chunk (<= 64 rows = 4 row tiles); each
+//      column block's B operands are gathered once and feed every tile; each
+//      row of Y written once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,104 +26,114 @@
 
 namespace hm {
 
-typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef unsigned int mr_raw __attribute__((ext_vector_type(4)));
 
-constexpr int kMRThreads = 256;        // 4 waves = 4 row tiles of 16
-constexpr int kMRBatch = 4;            // column blocks loaded before use
-constexpr int kMRGather32 = 512;       // LDS operand tile (columns), FP32 path
-constexpr int kMRGather64 = 256;       // LDS operand tile (columns), FP64 path
+constexpr int kMRThreads = 256;  // 4 independent waves
+constexpr int kMRWaves = kMRThreads / kWave;
+constexpr int kMRMaxTiles = kRowChunk / kMRTile;  // 4
+constexpr int kMRBatch = 2;      // column blocks loaded before use
 
-// value v of a 16-byte load, widened to the MFMA operand type
+// value v of a 16-byte load, widened exactly to FP64
 template <int CLS>
-__device__ __forceinline__ float mr_a32(mr_raw t, int v) {
-  if constexpr (CLS == F32) return __uint_as_float(t[v]);
-  else return __uint_as_float((v & 1) ? (t[v >> 1] & 0xffff0000u) : (t[v >> 1] << 16));  // BF16
-}
-__device__ __forceinline__ double mr_a64(mr_raw t, int v) {
-  double d;
-  __builtin_memcpy(&d, (const char *)&t + 8 * v, 8);
-  return d;
+__device__ __forceinline__ double mr_a(mr_raw t, int v) {
+  if constexpr (CLS == F64) {
+    double d;
+    __builtin_memcpy(&d, (const char *)&t + 8 * v, 8);
+    return d;
+  } else if constexpr (CLS == F32) {
+    return (double)__uint_as_float(t[v]);
+  } else {  // BF16: the upper half of an FP32
+    return (double)__uint_as_float((v & 1) ? (t[v >> 1] & 0xffff0000u) : (t[v >> 1] << 16));
+  }
 }
 
-// Output element e of lane l is row mr_row(l, e), right-hand side l % 16.
-template <bool F64MMA>
-__device__ __forceinline__ int mr_row(int lane, int e) {
-  return F64MMA ? (lane >> 4) + 4 * e : 4 * (lane >> 4) + e;
-}
+// Output element e of lane l of a row tile is row (l / 16) + 4 e, right-hand
+// side l % 16 (v_mfma_f64_16x16x4f64 result layout).
+__device__ __forceinline__ int mr_row(int lane, int e) { return (lane >> 4) + 4 * e; }
 
 // ----------------------------------------------------------------- K0
 __global__ __launch_bounds__(256) void k_mr_prologue(int64_t n, int64_t nrhs, const double *__restrict__ x,
-                                                     int64_t ldx, int x32, double *__restrict__ s64,
-                                                     float *__restrict__ s32) {
+                                                     int64_t ldx, int x32, double *__restrict__ s64) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * kMRhs) return;
   const int64_t i = e / kMRhs, r = e % kMRhs;
   double v = r < nrhs ? x[r * ldx + i] : 0.0;
   if (x32) v = (double)(float)v;
-  if (s64) s64[e] = v;
-  if (s32) s32[e] = (float)v;
+  s64[e] = v;
 }
 
 // ----------------------------------------------------------------- K1
-template <int CLS>
-__global__ __launch_bounds__(kMRThreads) void k_mr_stage1(const MRItem *__restrict__ items, int64_t nitems,
-                                                          const void *__restrict__ vals,
-                                                          const double *__restrict__ s64,
-                                                          const float *__restrict__ s32,
-                                                          double *__restrict__ zpart) {
+// One item with NT row tiles (straight-line code per NT).
+template <int CLS, int NT>
+__device__ __forceinline__ void mr_s1_item(const MRItem &it, const void *vals, int64_t n, int z32,
+                                           const double *dscale, double *s64, double *zpart, int lane) {
   constexpr int VEC = vec_of(CLS), CB = mr_cb(CLS);
-  constexpr bool F64MMA = CLS == F64;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int t = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int kq = lane / kMRTile;  // k within an MFMA step
   const int rj = lane % kMRTile;  // right-hand side
-  for (int64_t q = blockIdx.x; q < nitems; q += gridDim.x) {
-    const MRItem it = items[q];
-    if (t * kMRTile >= it.nrows) continue;  // no barrier in this kernel
-    double acc[4] = {0, 0, 0, 0};
-    v4d c64 = {0, 0, 0, 0};
-    const char *abase = (const char *)vals + (it.w_off + (int64_t)t * it.nkb * kWave * VEC) * bytes_of(CLS);
-    for (int kb0 = 0; kb0 < it.nkb; kb0 += kMRBatch) {
-      mr_raw a[kMRBatch];
+  const int64_t tstride = (int64_t)it.nkb * kWave * VEC * bytes_of(CLS);
+  const char *abase = (const char *)vals + it.w_off * bytes_of(CLS) + (int64_t)lane * VEC * bytes_of(CLS);
+  v4d c[NT];
 #pragma unroll
-      for (int j = 0; j < kMRBatch; j++) {
-        const int kb = min(kb0 + j, it.nkb - 1);  // past the end: re-read, weighed by 0 below
-        a[j] = __builtin_nontemporal_load((const mr_raw *)(abase + ((int64_t)kb * kWave + lane) * VEC * bytes_of(CLS)));
-      }
-      __builtin_amdgcn_sched_barrier(0);
+  for (int t = 0; t < NT; t++) c[t] = v4d{0, 0, 0, 0};
+  for (int kb0 = 0; kb0 < it.nkb; kb0 += kMRBatch) {
+    mr_raw a[NT][kMRBatch];
+    double b[kMRBatch][VEC];
 #pragma unroll
-      for (int j = 0; j < kMRBatch; j++) {
-        const bool live = kb0 + j < it.nkb;
-        v4f c32 = {0, 0, 0, 0};
+    for (int j = 0; j < kMRBatch; j++) {
+      const int kb = min(kb0 + j, it.nkb - 1);  // past the end: re-read, not used
 #pragma unroll
-        for (int v = 0; v < VEC; v++) {
-          const int col = (kb0 + j) * CB + 4 * v + kq;
-          const bool in = live && col < it.ncols;
-          const int64_t si = (it.x0 + (in ? col : 0)) * kMRhs + rj;
-          if constexpr (F64MMA) {
-            const double b = in ? s64[si] : 0.0;
-            c64 = __builtin_amdgcn_mfma_f64_16x16x4f64(mr_a64(a[j], v), b, c64, 0, 0, 0);
-          } else {
-            const float b = in ? s32[si] : 0.0f;
-            c32 = __builtin_amdgcn_mfma_f32_16x16x4f32(mr_a32<CLS>(a[j], v), b, c32, 0, 0, 0);
-          }
-        }
-        if constexpr (!F64MMA) {
+      for (int t = 0; t < NT; t++)
+        a[t][j] = __builtin_nontemporal_load(
+            (const mr_raw *)(abase + t * tstride + (int64_t)kb * kWave * VEC * bytes_of(CLS)));
 #pragma unroll
-          for (int e = 0; e < 4; e++) acc[e] += (double)c32[e];
-        }
+      for (int v = 0; v < VEC; v++) {
+        const int col = kb * CB + 4 * v + kq;
+        b[j][v] = col < it.ncols ? s64[(it.x0 + col) * kMRhs + rj] : 0.0;
       }
     }
-    if constexpr (F64MMA) {
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int e = 0; e < 4; e++) acc[e] = c64[e];
+    for (int j = 0; j < kMRBatch; j++) {
+      if (kb0 + j >= it.nkb) break;  // uniform
+#pragma unroll
+      for (int v = 0; v < VEC; v++)
+#pragma unroll
+        for (int t = 0; t < NT; t++)
+          c[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(mr_a<CLS>(a[t][j], v), b[j][v], c[t], 0, 0, 0);
     }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; t++)
 #pragma unroll
     for (int e = 0; e < 4; e++) {
-      const int row = t * kMRTile + mr_row<F64MMA>(lane, e);
-      if (row < it.nrows) zpart[(it.out_off + row) * kMRhs + rj] = acc[e];
+      const int row = t * kMRTile + mr_row(lane, e);
+      if (row >= it.nrows) continue;
+      if (it.z_off >= 0) {  // whole column range: z = D_m * sum, Table 1 rounding
+        double z = dscale[it.z_off + row] * c[t][e];
+        if (z32) z = (double)(float)z;
+        s64[(n + it.z_off + row) * kMRhs + rj] = z;
+      } else {
+        zpart[(it.out_off + row) * kMRhs + rj] = c[t][e];
+      }
+    }
+}
+
+template <int CLS>
+__global__ __launch_bounds__(kMRThreads) void k_mr_stage1(const MRItem *__restrict__ items, int64_t nitems,
+                                                          const void *__restrict__ vals, int64_t n, int z32,
+                                                          const double *__restrict__ dscale,
+                                                          double *__restrict__ s64, double *__restrict__ zpart) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t w0 = (int64_t)blockIdx.x * kMRWaves + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t nw = (int64_t)gridDim.x * kMRWaves;
+  for (int64_t q = w0; q < nitems; q += nw) {
+    const MRItem it = items[q];
+    switch ((it.nrows + kMRTile - 1) / kMRTile) {
+      case 1: mr_s1_item<CLS, 1>(it, vals, n, z32, dscale, s64, zpart, lane); break;
+      case 2: mr_s1_item<CLS, 2>(it, vals, n, z32, dscale, s64, zpart, lane); break;
+      case 3: mr_s1_item<CLS, 3>(it, vals, n, z32, dscale, s64, zpart, lane); break;
+      default: mr_s1_item<CLS, 4>(it, vals, n, z32, dscale, s64, zpart, lane); break;
     }
   }
 }
@@ -132,77 +141,85 @@ __global__ __launch_bounds__(kMRThreads) void k_mr_stage1(const MRItem *__restri
 // ---------------------------------------------------------------- K1b
 __global__ __launch_bounds__(256) void k_mr_stage1b(int64_t n, int64_t zlen, int z32, const ZInfo *__restrict__ zi,
                                                     const double *__restrict__ dscale,
-                                                    const double *__restrict__ zpart, double *__restrict__ s64,
-                                                    float *__restrict__ s32) {
+                                                    const double *__restrict__ zpart, double *__restrict__ s64) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (zlen + 1) * kMRhs) return;
   const int64_t j = e / kMRhs, r = e % kMRhs;
   double acc = 0.0;
   if (j < zlen) {
     const ZInfo q = zi[j];
+    if (q.nch == 1) return;  // finished by stage 1
     for (int c = 0; c < q.nch; c++) acc += zpart[(q.zp + (int64_t)c * q.stride) * kMRhs + r];
     acc *= dscale[j];
     if (z32) acc = (double)(float)acc;
   }
-  const int64_t o = (n + j) * kMRhs + r;  // j == zlen: the zero slot
-  if (s64) s64[o] = acc;
-  if (s32) s32[o] = (float)acc;
+  s64[(n + j) * kMRhs + r] = acc;  // j == zlen: the zero slot
 }
 
 // ----------------------------------------------------------------- K2
-// One storage class of a chunk: wave t accumulates its tile into acc (FP32
-// path) or c64 (FP64 path).
-template <int CLS>
+// One storage class of a chunk: the wave accumulates its NT row tiles.
+template <int CLS, int NT>
 __device__ __forceinline__ void mr_s2_class(const MRChunk &ch, const void *vals, const int32_t *gidx,
-                                            const double *s64, const float *s32, void *lds, int t, int lane,
-                                            double (&acc)[4], v4d &c64) {
+                                            const double *s64, int lane, v4d (&c)[NT]) {
   constexpr int VEC = vec_of(CLS), CB = mr_cb(CLS);
-  constexpr bool F64MMA = CLS == F64;
-  constexpr int KT = F64MMA ? kMRGather64 : kMRGather32;
   const int nkb = ch.nkb[CLS];
-  if (nkb == 0) return;  // uniform over the workgroup
-  const int kp = nkb * CB;
-  const int32_t *gi = gidx + ch.gidx_off[CLS];
-  const bool rows = t * kMRTile < ch.h;
+  if (nkb == 0) return;  // uniform
   const int kq = lane / kMRTile, rj = lane % kMRTile;
-  const char *abase = (const char *)vals + (ch.panel_off[CLS] + (int64_t)t * nkb * kWave * VEC) * bytes_of(CLS);
-  for (int kt0 = 0; kt0 < kp; kt0 += KT) {
-    const int kn = min(KT, kp - kt0);
-    __syncthreads();  // the previous tile's operands are no longer read
-    for (int e = threadIdx.x; e < kn * kMRhs; e += kMRThreads) {
-      const int64_t si = (int64_t)gi[kt0 + e / kMRhs] * kMRhs + e % kMRhs;
-      if constexpr (F64MMA) ((double *)lds)[e] = s64[si];
-      else ((float *)lds)[e] = s32[si];
+  const int64_t tstride = (int64_t)nkb * kWave * VEC * bytes_of(CLS);
+  const char *abase = (const char *)vals + ch.panel_off[CLS] * bytes_of(CLS) + (int64_t)lane * VEC * bytes_of(CLS);
+  // gather indices of a column block: lane group kq's VEC columns are contiguous
+  const int32_t *gi = gidx + ch.gidx_off[CLS] + kq * VEC;
+  for (int kb0 = 0; kb0 < nkb; kb0 += kMRBatch) {
+    mr_raw a[NT][kMRBatch];
+    int32_t g[kMRBatch][VEC];
+#pragma unroll
+    for (int j = 0; j < kMRBatch; j++) {
+      const int kb = min(kb0 + j, nkb - 1);  // past the end: re-read, not used
+#pragma unroll
+      for (int t = 0; t < NT; t++)
+        a[t][j] = __builtin_nontemporal_load(
+            (const mr_raw *)(abase + t * tstride + (int64_t)kb * kWave * VEC * bytes_of(CLS)));
+#pragma unroll
+      for (int v = 0; v < VEC; v++) g[j][v] = gi[kb * CB + v];
     }
-    __syncthreads();
-    if (!rows) continue;
-    const int kb_begin = kt0 / CB, kb_end = (kt0 + kn) / CB;
-    for (int kb0 = kb_begin; kb0 < kb_end; kb0 += kMRBatch) {
-      mr_raw a[kMRBatch];
+    double b[kMRBatch][VEC];
 #pragma unroll
-      for (int j = 0; j < kMRBatch; j++) {
-        const int kb = min(kb0 + j, kb_end - 1);
-        a[j] = __builtin_nontemporal_load((const mr_raw *)(abase + ((int64_t)kb * kWave + lane) * VEC * bytes_of(CLS)));
-      }
-      __builtin_amdgcn_sched_barrier(0);
+    for (int j = 0; j < kMRBatch; j++)
 #pragma unroll
-      for (int j = 0; j < kMRBatch; j++) {
-        if (kb0 + j >= kb_end) break;  // uniform
-        const int cl = (kb0 + j) * CB - kt0;  // column of this block within the LDS tile
-        v4f c32 = {0, 0, 0, 0};
+      for (int v = 0; v < VEC; v++) b[j][v] = s64[(int64_t)g[j][v] * kMRhs + rj];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int v = 0; v < VEC; v++) {
-          const int e = (cl + 4 * v + kq) * kMRhs + rj;
-          if constexpr (F64MMA) c64 = __builtin_amdgcn_mfma_f64_16x16x4f64(mr_a64(a[j], v), ((const double *)lds)[e], c64, 0, 0, 0);
-          else c32 = __builtin_amdgcn_mfma_f32_16x16x4f32(mr_a32<CLS>(a[j], v), ((const float *)lds)[e], c32, 0, 0, 0);
-        }
-        if constexpr (!F64MMA) {
+    for (int j = 0; j < kMRBatch; j++) {
+      if (kb0 + j >= nkb) break;  // uniform
 #pragma unroll
-          for (int e2 = 0; e2 < 4; e2++) acc[e2] += (double)c32[e2];
-        }
-      }
+      for (int v = 0; v < VEC; v++)
+#pragma unroll
+        for (int t = 0; t < NT; t++)
+          c[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(mr_a<CLS>(a[t][j], v), b[j][v], c[t], 0, 0, 0);
     }
   }
+}
+
+template <int MASK, int NT>
+__device__ __forceinline__ void mr_s2_chunk(const MRChunk &ch, const double *v64, const float *v32,
+                                            const unsigned short *v16, const int32_t *g64, const int32_t *g32,
+                                            const int32_t *g16, const double *s64, double *y, int64_t ldy,
+                                            int64_t nrhs, int lane) {
+  v4d c[NT];
+#pragma unroll
+  for (int t = 0; t < NT; t++) c[t] = v4d{0, 0, 0, 0};
+  if constexpr ((MASK & 1) != 0) mr_s2_class<F64, NT>(ch, v64, g64, s64, lane, c);
+  if constexpr ((MASK & 2) != 0) mr_s2_class<F32, NT>(ch, v32, g32, s64, lane, c);
+  if constexpr ((MASK & 4) != 0) mr_s2_class<BF16, NT>(ch, v16, g16, s64, lane, c);
+  const int rj = lane % kMRhs;
+  if (rj >= nrhs) return;
+#pragma unroll
+  for (int t = 0; t < NT; t++)
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int row = t * kMRTile + mr_row(lane, e);
+      if (row < ch.h) y[rj * ldy + ch.r0 + row] = c[t][e];
+    }
 }
 
 template <int MASK>
@@ -211,49 +228,26 @@ __global__ __launch_bounds__(kMRThreads) void k_mr_stage2(const MRChunk *__restr
                                                           const unsigned short *__restrict__ v16,
                                                           const int32_t *__restrict__ g64, const int32_t *__restrict__ g32,
                                                           const int32_t *__restrict__ g16,
-                                                          const double *__restrict__ s64, const float *__restrict__ s32,
-                                                          double *__restrict__ y, int64_t ldy, int64_t nrhs) {
-  __shared__ double lds[kMRGather64 * kMRhs];  // 32 KB: also holds kMRGather32 x 16 floats
-  static_assert(kMRGather64 * kMRhs * 8 == kMRGather32 * kMRhs * 4, "one LDS buffer for both paths");
+                                                          const double *__restrict__ s64, double *__restrict__ y,
+                                                          int64_t ldy, int64_t nrhs) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int t = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  for (int64_t q = blockIdx.x; q < nchunks; q += gridDim.x) {
+  const int64_t w0 = (int64_t)blockIdx.x * kMRWaves + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t nw = (int64_t)gridDim.x * kMRWaves;
+  for (int64_t q = w0; q < nchunks; q += nw) {
     const MRChunk ch = chunks[q];
-    double acc[4] = {0, 0, 0, 0};
-    v4d c64 = {0, 0, 0, 0};
-    if constexpr ((MASK & 1) != 0) mr_s2_class<F64>(ch, v64, g64, s64, s32, lds, t, lane, acc, c64);
-    if constexpr ((MASK & 2) != 0) mr_s2_class<F32>(ch, v32, g32, s64, s32, lds, t, lane, acc, c64);
-    if constexpr ((MASK & 4) != 0) mr_s2_class<BF16>(ch, v16, g16, s64, s32, lds, t, lane, acc, c64);
-    const int rj = lane % kMRhs;
-    if constexpr ((MASK & 1) != 0 && (MASK & 6) != 0) {
-      // both paths: move the FP64 tile into the FP32 path's row order
-      // through the (now idle) operand buffer
-      __syncthreads();  // every wave is done reading the operand tile
-#pragma unroll
-      for (int e = 0; e < 4; e++) lds[t * kMRTile * kMRhs + mr_row<true>(lane, e) * kMRhs + rj] = c64[e];
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < 4; e++) acc[e] += lds[t * kMRTile * kMRhs + mr_row<false>(lane, e) * kMRhs + rj];
-    }
-    if (t * kMRTile < ch.h && rj < nrhs) {
-#pragma unroll
-      for (int e = 0; e < 4; e++) {
-        if constexpr (MASK == 1) {  // FP64 matrix cores only
-          const int row = t * kMRTile + mr_row<true>(lane, e);
-          if (row < ch.h) y[rj * ldy + ch.r0 + row] = c64[e];
-        } else {
-          const int row = t * kMRTile + mr_row<false>(lane, e);
-          if (row < ch.h) y[rj * ldy + ch.r0 + row] = acc[e];
-        }
-      }
+    switch ((ch.h + kMRTile - 1) / kMRTile) {
+      case 1: mr_s2_chunk<MASK, 1>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
+      case 2: mr_s2_chunk<MASK, 2>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
+      case 3: mr_s2_chunk<MASK, 3>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
+      default: mr_s2_chunk<MASK, 4>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
     }
   }
 }
 
 // ------------------------------------------------------------- launch
 typedef void (*MRStage2Fn)(const MRChunk *, int64_t, const double *, const float *, const unsigned short *,
-                           const int32_t *, const int32_t *, const int32_t *, const double *, const float *, double *,
-                           int64_t, int64_t);
+                           const int32_t *, const int32_t *, const int32_t *, const double *, double *, int64_t,
+                           int64_t);
 static MRStage2Fn mr_stage2_fn(int mask) {
   switch (mask) {
     case 1: return k_mr_stage2<1>;
@@ -265,7 +259,7 @@ static MRStage2Fn mr_stage2_fn(int mask) {
     default: return k_mr_stage2<7>;
   }
 }
-typedef void (*MRStage1Fn)(const MRItem *, int64_t, const void *, const double *, const float *, double *);
+typedef void (*MRStage1Fn)(const MRItem *, int64_t, const void *, int64_t, int, const double *, double *, double *);
 static MRStage1Fn mr_stage1_fn(int cls) {
   return cls == F64 ? k_mr_stage1<F64> : cls == F32 ? k_mr_stage1<F32> : k_mr_stage1<BF16>;
 }
@@ -274,14 +268,15 @@ int size_grids_mr(hmat_s *h) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return fail(HMAT_E_HIP, "cannot query the device");
+  auto waves_to_groups = [](int64_t units) { return (units + kMRWaves - 1) / kMRWaves; };
   for (int c = 0; c < NCLS; c++) {
     int per = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mr_stage1_fn(c), kMRThreads, 0) != hipSuccess || per < 1) per = 1;
-    h->mr_grid1[c] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(h->mr_nitems[c], (int64_t)per * cus));
+    h->mr_grid1[c] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(waves_to_groups(h->mr_nitems[c]), (int64_t)per * cus));
   }
   int per = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mr_stage2_fn(h->cls_mask), kMRThreads, 0) != hipSuccess || per < 1) per = 1;
-  h->mr_grid2 = (int32_t)std::max<int64_t>(1, std::min<int64_t>(h->nchunks, (int64_t)per * cus));
+  h->mr_grid2 = (int32_t)std::max<int64_t>(1, std::min<int64_t>(waves_to_groups(h->nchunks), (int64_t)per * cus));
   return HMAT_OK;
 }
 
@@ -295,25 +290,25 @@ int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, 
     {
       const int64_t tot = h->n * kMRhs;
       hipLaunchKernelGGL(k_mr_prologue, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, h->n, nr, xr, ld,
-                         h->x32, h->src64, h->src32);
+                         h->x32, h->src64);
     }
     for (int c = 0; c < NCLS; c++) {
       if (h->mr_nitems[c] <= 0) continue;
       hipLaunchKernelGGL(mr_stage1_fn(c), dim3((unsigned)h->mr_grid1[c]), dim3(kMRThreads), 0, st,
-                         h->mri + h->mr_item_begin[c], h->mr_nitems[c], (const void *)h->vals[c], h->src64, h->src32,
-                         h->zpart);
+                         h->mri + h->mr_item_begin[c], h->mr_nitems[c], (const void *)h->vals[c], h->n, h->z32,
+                         h->dscale, h->src64, h->zpart);
     }
     prof_mark(h, 1, stream);
     {
       const int64_t tot = (h->zlen + 1) * kMRhs;
       hipLaunchKernelGGL(k_mr_stage1b, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, h->n, h->zlen, h->z32,
-                         h->zinfo, h->dscale, h->zpart, h->src64, h->src32);
+                         h->zinfo, h->dscale, h->zpart, h->src64);
     }
     prof_mark(h, 2, stream);
     hipLaunchKernelGGL(mr_stage2_fn(h->cls_mask), dim3((unsigned)h->mr_grid2), dim3(kMRThreads), 0, st, h->mrc,
                        h->nchunks, (const double *)h->vals[F64], (const float *)h->vals[F32],
                        (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16], h->src64,
-                       h->src32, yr, ld, nr);
+                       yr, ld, nr);
     prof_mark(h, 3, stream);
   }
   hipError_t e = hipGetLastError();

@@ -388,6 +388,8 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
       m.nrows = q.it.nrows;
       m.cls = c;
       m.nkb = (int32_t)((q.it.ncols + mr_cb(c) - 1) / mr_cb(c));
+      const Group &g = P->groups[q.group];
+      m.z_off = g.nch == 1 ? g.z0 + q.k0 : -1;
       m.w_off = P->vals_elems[c];
       P->vals_elems[c] += (int64_t)((m.nrows + kMRTile - 1) / kMRTile) * m.nkb * kWave * vec_of(c);
       P->mri.push_back(m);
@@ -490,22 +492,11 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   L.ws_begin = at;
   if (P->mr) {
     // operands of the 16 right-hand sides, right-hand side fastest
-    bool need64 = false, need32 = false;
-    for (auto &R : P->mrc) {
-      need64 |= R.nkb[F64] > 0;
-      need32 |= R.nkb[F32] > 0 || R.nkb[BF16] > 0;
-    }
-    for (auto &m : P->mri) {
-      need64 |= m.cls == F64;
-      need32 |= m.cls != F64;
-    }
-    const uint64_t ns = (uint64_t)(n + P->zlen + 1) * kMRhs;
-    L.off_src64 = need64 ? take(ns * sizeof(double)) : ~0ull;
-    L.off_src32 = need32 ? take(ns * sizeof(float)) : ~0ull;
+    L.off_src64 = take((uint64_t)(n + P->zlen + 1) * kMRhs * sizeof(double));
     L.off_src = ~0ull;
     L.off_zpart = take((uint64_t)std::max<int64_t>(P->zpart_len, 1) * kMRhs * sizeof(double));
   } else {
-    L.off_src64 = L.off_src32 = ~0ull;
+    L.off_src64 = ~0ull;
     L.off_src = take((uint64_t)P->nrhs_max * (n + P->zlen + 1) * sizeof(double));
     L.off_zpart = take((uint64_t)P->nrhs_max * std::max<int64_t>(P->zpart_len, 1) * sizeof(double));
   }
@@ -712,6 +703,13 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
         const int vec = vec_of(c), cb = mr_cb(c), nkb = R.nkb[c];
         int32_t *gi = (int32_t *)(base + L.off_gidx[c]) + R.gidx_off[c];
         auto col = chunk_columns(cp, c, (int64_t)nkb * cb, gi);
+        // lane-group-major order within each column block
+        std::vector<int32_t> blk(cb);
+        for (int kb = 0; kb < nkb; kb++) {
+          for (int e = 0; e < cb; e++) blk[e] = gi[(int64_t)kb * cb + e];
+          for (int qg = 0; qg < 4; qg++)
+            for (int v = 0; v < vec; v++) gi[(int64_t)kb * cb + qg * vec + v] = blk[4 * v + qg];
+        }
         const int tiles = (int)((cp.h + kMRTile - 1) / kMRTile);
         for (int t = 0; t < tiles; t++)
           for (int kb = 0; kb < nkb; kb++)

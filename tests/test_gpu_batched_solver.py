@@ -47,10 +47,9 @@ def handles(sysl, variant, nrhs_max):
 @pytest.mark.parametrize("nrhs", [1, 4])
 def test_batched_bicgstab_matches_oracle(variant, nrhs):
     """Every recurrence converges like the oracle's solve of the same system
-    with the same operator arithmetic (matrix-core rounding when nrhs_max >
-    1): same status, iteration counts within a few, the FP64 true residual
-    below tol, and the solution as close to a tight FP64 solve as the
-    oracle's."""
+    with the same operator arithmetic: same status, iteration counts within a
+    few, the FP64 true residual below tol, and the solution as close to a
+    tight FP64 solve as the oracle's."""
     need_gpu()
     sysl = systems()
     mr = nrhs > 1
@@ -67,7 +66,7 @@ def test_batched_bicgstab_matches_oracle(variant, nrhs):
         for k in range(nrhs):
             b = B[k, off[s]:off[s + 1]]
             x = X[k, off[s]:off[s + 1]]
-            xo, io = oracle.bicgstab(op, b, op64=op64, tol=tol, maxiter=400, matrix_cores=mr)
+            xo, io = oracle.bicgstab(op, b, op64=op64, tol=tol, maxiter=400)
             assert io["status"] == 0
             # a recurrence that ends just under tol (BiCGSTAB's residual
             # jumps by 10x between steps) moves by a few iterations under a
@@ -91,14 +90,11 @@ def test_batched_bicgstab_matches_oracle(variant, nrhs):
 @pytest.mark.parametrize("nrhs", [1, 4])
 def test_batched_first_iterations_match_oracle(variant, nrhs):
     """Three iterations of every recurrence (tol unreachable): x_3 agrees
-    with the oracle's x_3 for the same system and operator arithmetic.
-    FP64 (also on the FP64 matrix cores): only dot-product and summation
-    order differ (1e-10).  FP32 / BF16 storage: x_3 amplifies product
-    differences strongly on these meshes -- in the oracle alone, products
-    that differ by 1.4e-9 (matrix-core operand rounding on or off, plates-16,
-    b = +-1) move x_3 by 2.4e-6, a factor ~1700 -- and the matrix cores'
-    FP32 sums differ from the oracle's exact ones by up to ~1e-7 of |A||x|
-    per product, so x_3 may differ by ~2e-4: bound 1e-3."""
+    with the oracle's x_3 for the same system and operator arithmetic.  The
+    products (single-vector or FP64 matrix cores) and the solver differ from
+    the oracle only in summation order; x_3 amplifies such differences up to
+    ~1e3-fold on these meshes (products differing by 1.4e-9 moved x_3 by
+    2.4e-6 on plates-16), so the bound is 1e-10."""
     need_gpu()
     sysl = systems()
     mr = nrhs > 1
@@ -108,21 +104,21 @@ def test_batched_first_iterations_match_oracle(variant, nrhs):
     X, summ, per = hmat.hmat_bicgstab_batched(Hi, to_cols(B), h_fp64=H64, tol=1e-30, maxiter=3)
     X = X.cpu().numpy().T
     assert np.all(per["iterations"] == 3) and np.all(per["status"] == hmat.HMAT_E_NOCONV)
-    bound = 1e-10 if variant == oracle.M1_DOUBLE else 1e-3
+    bound = 1e-10
     worst = 0.0
     for s, (m, h) in enumerate(sysl):
         op = oracle.Converted(h, variant, 1)
         for k in range(nrhs):
             b = B[k, off[s]:off[s + 1]]
-            xo, io = oracle.bicgstab(op, b, tol=1e-30, maxiter=3, matrix_cores=mr)
+            xo, io = oracle.bicgstab(op, b, tol=1e-30, maxiter=3)
             assert io["iterations"] == 3
             e = np.linalg.norm(X[k, off[s]:off[s + 1]] - xo) / np.linalg.norm(xo)
             worst = max(worst, e)
             assert e <= bound, (KEYS[s], k, e)
             # the reported recurrence residual is this recurrence's: it
             # tracks b - A~ x_3 up to the rounding of three products
-            rr = np.linalg.norm(b - op.matvec(X[k, off[s]:off[s + 1]], matrix_cores=mr)) / np.linalg.norm(b)
-            gap = 1e-8 if variant == oracle.M1_DOUBLE else 1e-3
+            rr = np.linalg.norm(b - op.matvec(X[k, off[s]:off[s + 1]])) / np.linalg.norm(b)
+            gap = 1e-8
             assert abs(per["rel_res"][s, k] - rr) <= gap * rr + 1e-12, (KEYS[s], k, per["rel_res"][s, k], rr)
     print(f"{oracle.VARIANT_NAMES[variant]} nrhs={nrhs}: worst |x3 - x3_oracle| / |x3_oracle| = {worst:.2e}")
 

@@ -1,27 +1,20 @@
-"""GPU parity of the multi-right-hand-side product on the matrix cores
-(handles built with nrhs_max > 1) and of batched independent systems."""
+"""GPU parity of the multi-right-hand-side product on the FP64 matrix cores
+(handles built with nrhs_max > 1) and of batched independent systems.
+
+Every stored value widens exactly to FP64 and meets the same FP64 operands
+as in the single-vector product, so the oracle's build arithmetic is the
+reference at the single-vector tolerances (only the summation order
+differs)."""
 
 import numpy as np
 import pytest
 
 import oracle
-from paper_1911_00093_amd import hmat, meshes
+from paper_1911_00093_amd import hmat
 from tests.conftest import oracle_hmatrix
-from tests.gpu_util import abs_scale, blockset, need_gpu
+from tests.gpu_util import abs_scale, blockset, need_gpu, tolerance
 
 pytestmark = pytest.mark.gpu
-
-
-def mr_tolerance(variant):
-    """FP64 storage: FP64 matrix cores, same arithmetic as the single-vector
-    product (1e-13).  FP32 / BF16 storage: the oracle forms the exact
-    products of the stored values with FP32-rounded operands; the FP32
-    matrix cores add at most CB + 1 roundings (u = 2^-24) per run of CB = 16
-    (FP32) or 32 (BF16) columns, in stage 1 and again in stage 2, plus one
-    FP32 rounding flip of z: (2 (32 + 1) + 2) u < 4.1e-6 of |A||x|."""
-    if variant in (oracle.M1_DOUBLE, oracle.M2_DOUBLE):
-        return 1e-13
-    return 4.1e-6
 
 
 def to_cols(X):
@@ -40,10 +33,13 @@ def test_multirhs_parity(key, variant):
     X = np.random.default_rng(21).standard_normal((16, h.n))
     X[0] = 1.0
     Y = H.matvec(to_cols(X)).cpu().numpy()
+    worst = 0.0
     for k in range(16):
-        yo = conv.matvec(X[k], matrix_cores=True)
+        yo = conv.matvec(X[k])
         err = np.abs(Y[:, k] - yo).max() / abs_scale(h, X[k]).max()
-        assert err <= mr_tolerance(variant), (key, variant, k, err)
+        worst = max(worst, err)
+        assert err <= tolerance(variant), (key, variant, k, err)
+    print(f"{key} {oracle.VARIANT_NAMES[variant]}: worst error / |A||x| = {worst:.2e}")
 
 
 @pytest.mark.parametrize("nrhs", [1, 5, 16, 21])
@@ -57,22 +53,21 @@ def test_multirhs_counts(nrhs):
     Y = H.matvec(to_cols(X)).cpu().numpy()
     conv = oracle.Converted(h, oracle.M2_MIXED)
     for k in range(nrhs):
-        yo = conv.matvec(X[k], matrix_cores=True)
-        assert np.abs(Y[:, k] - yo).max() <= 4.1e-6 * abs_scale(h, X[k]).max()
+        yo = conv.matvec(X[k])
+        assert np.abs(Y[:, k] - yo).max() <= 1e-13 * abs_scale(h, X[k]).max()
 
 
-def test_multirhs_vs_fp64_accuracy():
-    """The FP32 matrix-core product stays within FP32 accuracy of the FP64
-    product on a smooth vector."""
+def test_multirhs_columns_independent():
+    """Each column of the result depends on its own column of X only, bit
+    for bit, whatever the other columns and the column position."""
     need_gpu()
-    m, h = oracle_hmatrix("sphere-L4")
+    m, h = oracle_hmatrix("spheres-mixed")
     H = hmat.HMatrix(blockset(h), oracle.M2_MIXED, nrhs_max=16)
-    X = np.tile(m.rhs()[h.perm], (16, 1))
+    X = np.random.default_rng(3).standard_normal((16, h.n))
     Y = H.matvec(to_cols(X)).cpu().numpy()
-    y64 = oracle.Converted(h, oracle.M1_DOUBLE).matvec(X[0])
-    err = np.linalg.norm(Y[:, 3] - y64) / np.linalg.norm(y64)
-    print(f"matrix-core M2-Mixed vs FP64: {err:.2e}")
-    assert err < 2e-6
+    Z = np.stack([X[5], X[0] * 3.0, X[11]])
+    Yz = H.matvec(to_cols(Z)).cpu().numpy()
+    assert np.array_equal(Yz[:, 0], Y[:, 5]) and np.array_equal(Yz[:, 2], Y[:, 11])
 
 
 @pytest.mark.parametrize("variant", [oracle.M1_DOUBLE, oracle.M2_MIXED, oracle.M3, oracle.BF16_SCALED])
@@ -92,16 +87,10 @@ def test_batched_systems(variant, nrhs_max):
     X = np.random.default_rng(5).standard_normal((nr, H.n))
     Xd = torch.as_tensor(X).cuda().T if nr > 1 else torch.as_tensor(X[0]).cuda()
     Y = H.matvec(Xd).cpu().numpy().reshape(H.n, -1)
-    if nrhs_max > 1:
-        tol = mr_tolerance(variant)
-    else:
-        tol = 2.0 ** -23 if variant in (oracle.M1_SINGLE, oracle.M1_MIXED) else 1e-13
     for s, h in enumerate(hs):
         conv = oracle.Converted(h, variant, 1)
         for k in range(nr):
             xs = X[k, off[s]:off[s + 1]]
-            yo = conv.matvec(xs, matrix_cores=nrhs_max > 1)
+            yo = conv.matvec(xs)
             err = np.abs(Y[off[s]:off[s + 1], k] - yo).max() / abs_scale(h, xs).max()
-            assert err <= tol, (keys[s], k, err)
-
-
+            assert err <= tolerance(variant), (keys[s], k, err)

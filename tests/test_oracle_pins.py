@@ -551,62 +551,3 @@ def test_preconditioned_solve_same_solution():
     x1, i1 = oracle.bicgstab(op, b, tol=1e-10, precond=oracle.Jacobi(h))
     assert i0["status"] == 0 and i1["status"] == 0
     assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) < 1e-8
-
-
-# --------------------------------------------------------------------------
-# matrix-core operand rounding (multi-right-hand-side pass; not in the paper)
-
-def test_matrix_core_mode_reduces_to_table1_rows():
-    """M1-Single already rounds x and z to FP32 (Table 1), so the matrix-core
-    rounding changes nothing; on a dense-only matrix M2-Mixed with FP32
-    operands is exactly M2-Single (FP32 x, no z)."""
-    m, h = oracle_hmatrix("sphere-L3")
-    x = np.random.default_rng(12).standard_normal(h.n)
-    c1 = oracle.Converted(h, oracle.M1_SINGLE)
-    assert np.array_equal(c1.matvec(x, matrix_cores=True), c1.matvec(x))
-    for v in (oracle.M1_DOUBLE, oracle.M2_DOUBLE):
-        cv = oracle.Converted(h, v)
-        assert np.array_equal(cv.matvec(x, matrix_cores=True), cv.matvec(x))
-    rng = np.random.default_rng(13)
-    A = rng.standard_normal((50, 50))
-    hd = oracle.HMatrix.from_blocks(50, [0], [50], [0], [50], [0], [0], [0], np.asfortranarray(A).ravel(order="F"))
-    xs = rng.standard_normal(50)
-    ym = oracle.Converted(hd, oracle.M2_MIXED).matvec(xs, matrix_cores=True)
-    ys = oracle.Converted(hd, oracle.M2_SINGLE).matvec(xs)
-    assert np.array_equal(ym, ys)
-    assert np.allclose(ym, f32(A) @ f32(xs), rtol=1e-12)
-
-
-def test_matrix_core_mode_rounds_z():
-    """A single rank-1 block: y = V' fl32(D fl32-operand product)."""
-    h = oracle.HMatrix.from_blocks(2, [0, 0, 1, 1], [1, 1, 1, 1], [0, 1, 0, 1], [1, 1, 1, 1], [0, 1, 1, 0],
-                                   [0, 1, 1, 0], [0, 1, 3, 5], [1.0, 3.0, 1.0 / 3.0, 1.0, 1.0, 1.0])
-    x = np.array([0.0, 1.0 + 2.0 ** -40])
-    y = oracle.Converted(h, oracle.M2_MIXED).matvec(x, matrix_cores=True)
-    # block (0,1): V = 3, W = 1/3 -> V' = 1, W' = 1, D = 3 * fl64(1/3)
-    d = 3.0 * (1.0 / 3.0)
-    assert y[0] == float(np.float32(d * float(np.float32(x[1]))))
-
-
-def test_bicgstab_matrix_core_operator_one_step():
-    """The solver's matrix-core mode iterates with the matrix-core product:
-    one step of Algorithm 1 from x_0 = 0 written out with that product
-    (p = r = b, v = A p, alpha = r.r / r.v, s = r - alpha v, t = A s,
-    omega = t.s / t.t, x = alpha p + omega s).  The plain product differs by
-    ~1e-7 here, far above the 1e-12 the comparison allows."""
-    m, h = oracle_hmatrix("sphere-L3")
-    conv = oracle.Converted(h, oracle.M2_MIXED)
-    b = m.rhs()[h.perm]
-    A = lambda v: conv.matvec(v, matrix_cores=True)
-    r = b.copy()
-    v = A(r)
-    alpha = (r @ r) / (r @ v)
-    s = r - alpha * v
-    t = A(s)
-    omega = (t @ s) / (t @ t)
-    x_step = alpha * r + omega * s
-    x, info = oracle.bicgstab(conv, b, tol=1e-30, maxiter=1, matrix_cores=True)
-    assert info["iterations"] == 1
-    assert np.linalg.norm(x - x_step) <= 1e-12 * np.linalg.norm(x_step)
-    xp, _ = oracle.bicgstab(conv, b, tol=1e-30, maxiter=1)
-    assert np.linalg.norm(xp - x_step) > 1e-10 * np.linalg.norm(x_step)
