@@ -145,11 +145,11 @@ int hmat_build(const hmat_blocks *blocks, const hmat_build_opts *opts, void *dev
  * overwritten and may alias x.  1 <= nrhs <= nrhs_max of the build.
  * Asynchronous on `stream`; no host synchronisation.
  * A handle built with nrhs_max > 1 stores its blocks for the matrix cores
- * and multiplies 16 right-hand sides per pass with MFMA: FP64 storage with
- * FP64 operands (same arithmetic as nrhs_max = 1), FP32 / BF16 storage with
- * the operands x and z rounded to FP32, products accumulated in FP32 over
- * each 16-byte load's columns (16 for FP32, 32 for BF16) and in FP64 across
- * them. */
+ * and multiplies 16 right-hand sides per pass on the FP64 matrix cores:
+ * every stored value is widened exactly to FP64 and meets the same FP64
+ * operands as with nrhs_max = 1, so the arithmetic is the same (exact
+ * products, FP64 sums, Table 1 roundings of x and z); only the summation
+ * order differs. */
 int hmat_matvec(hmat_t h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream);
 
 /* Independent systems batched into one handle (not from the paper): system
@@ -197,12 +197,28 @@ int hmat_get_stats(hmat_t h, hmat_stats *out);
  * applies y_tau = A_tautau^{-1} x_tau on each; rows of no diagonal dense
  * block pass through unchanged. */
 typedef struct hmat_precond_s *hmat_precond_t;
-enum { HMAT_PRECOND_NONE = 0, HMAT_PRECOND_JACOBI = 1 };
+enum { HMAT_PRECOND_NONE = 0, HMAT_PRECOND_JACOBI = 1, HMAT_PRECOND_LEARNED = 2 };
 
 /* Device bytes hmat_precond_create needs for `blocks`. */
 int hmat_precond_plan(const hmat_blocks *blocks, int32_t kind, uint64_t *device_bytes);
 int hmat_precond_create(const hmat_blocks *blocks, int32_t kind, void *dev_mem, uint64_t dev_bytes, void *stream,
                         hmat_precond_t *out);
+/* HMAT_PRECOND_LEARNED: on every dense diagonal block tau (m <= 64 rows, in
+ * the order of `blocks`), K_tau = diag(A_tautau)^{-1} + (1/s_tau) U V^T with
+ * s_tau the mean of A_tautau's diagonal and U, V the 64 x 16 factors the MLP
+ * below predicts for that leaf (rows >= m ignored).  uv: device FP32, one
+ * HMAT_MLP_OUT row per diagonal block (U then V, row-major), copied into
+ * dev_mem.  Size dev_mem with hmat_precond_plan(blocks, HMAT_PRECOND_LEARNED).
+ * Fails with HMAT_E_ARG when a diagonal block exceeds 64 rows. */
+int hmat_precond_create_learned(const hmat_blocks *blocks, const float *uv, void *dev_mem, uint64_t dev_bytes,
+                                void *stream, hmat_precond_t *out);
+
+/* The dense diagonal blocks a preconditioner acts on, in its order: block
+ * index, first row, rows (host arrays of capacity entries; may be NULL to
+ * query *count). */
+int hmat_precond_leaves(const hmat_blocks *blocks, int32_t kind, int64_t *block, int64_t *row0, int64_t *rows,
+                        int64_t capacity, int64_t *count);
+
 /* y = K x for one vector (device FP64, length n); y must not alias x. */
 int hmat_precond_apply(hmat_precond_t p, const double *x, double *y, void *stream);
 int hmat_precond_destroy(hmat_precond_t p);
@@ -273,6 +289,55 @@ uint64_t hmat_bicgstab_batched_workspace_bytes(hmat_t h, int64_t nrhs);
 int hmat_bicgstab_batched(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, int64_t nrhs,
                           const hmat_solve_opts *opts, hmat_batch_result *results, hmat_solve_info *summary,
                           void *work, uint64_t work_bytes, void *stream);
+
+/* ------------------------------------- learned leaf map (not in the paper) */
+/* A small MLP predicts, from the geometry of one leaf cluster (at most 64
+ * panels in cluster order), the factors U, V of the learned preconditioner
+ * above.  Input: per panel p the offset of its centroid from the leaf's mean
+ * centroid divided by the diagonal of the leaf's centroid box (3), its unit
+ * normal (3) and its area over the mean area (1), zero beyond the m panels,
+ * then a mask of m ones (64 x 7 + 64 = 512).  Layers: 512 -> 128 -> 128 ->
+ * 2048, ReLU after the first two.  Parameters: one FP32 device array of
+ * HMAT_MLP_PARAMS floats, W1 (512 x 128, row-major), b1, W2 (128 x 128), b2,
+ * W3 (128 x 2048), b3; H = relu(X W + b).  Training minimises the batch mean
+ * of |K_tau - A_tautau^{-1}|_F^2 / |A_tautau^{-1}|_F^2 with Adam. */
+#define HMAT_MLP_LEAF 64
+#define HMAT_MLP_RANK 16
+#define HMAT_MLP_IN 512
+#define HMAT_MLP_HIDDEN 128
+#define HMAT_MLP_OUT 2048
+#define HMAT_MLP_PARAMS (512 * 128 + 128 + 128 * 128 + 128 + 128 * 2048 + 2048)
+
+/* Features of one leaf (host): centroids and normals m x 3 row-major, areas
+ * m (FP64, cluster order, 1 <= m <= 64); out: 512 floats. */
+int hmat_leaf_features(int64_t m, const double *centroids, const double *normals, const double *areas, float *out);
+
+/* Exact inverse of a dense m x m block (host, FP64 Gauss-Jordan with
+ * partial pivoting; column-major in and out).  HMAT_E_ARG if singular. */
+int hmat_dense_inverse(int64_t m, const double *a, double *out);
+
+/* Device workspace of the MLP calls for `batch` samples. */
+uint64_t hmat_mlp_workspace_bytes(int64_t batch);
+
+/* out (device, batch x 2048) = MLP(x) for x (device, batch x 512). */
+int hmat_mlp_forward(const float *params, const float *x, int64_t batch, float *out, void *work,
+                     uint64_t work_bytes, void *stream);
+
+/* Batch mean loss and its gradient for the samples idx[0 .. batch) (device
+ * int32; an entry outside [0, nsamples) counts as an empty sample) of a
+ * training set on the device: x (nsamples x 512), ainv
+ * (nsamples x 64 x 64, row-major, the exact inverse in the leading m x m
+ * corner, FP32), dinv (nsamples x 64: 1 / A_ii), sinv (nsamples: 1 / s_tau),
+ * m (nsamples, int32, clamped to 0..64).  grad: HMAT_MLP_PARAMS floats (overwritten, same
+ * layout as params); loss: one float (overwritten).  Deterministic. */
+int hmat_mlp_loss_grad(const float *params, const float *x, const float *ainv, const float *dinv, const float *sinv,
+                       const int32_t *m, int64_t nsamples, const int32_t *idx, int64_t batch, float *grad, float *loss,
+                       void *work, uint64_t work_bytes, void *stream);
+
+/* One Adam step (Kingma & Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8) of
+ * number t >= 1 with rate lr on params and its moments m1, m2 (device FP32,
+ * HMAT_MLP_PARAMS each). */
+int hmat_mlp_adam(float *params, float *m1, float *m2, const float *grad, int64_t t, float lr, void *stream);
 
 /* ------------------------------------------------------------ assembly */
 /* Setup step (untimed; not the product path): build an FP64 H-matrix for the

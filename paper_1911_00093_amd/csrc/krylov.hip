@@ -354,12 +354,45 @@ __global__ __launch_bounds__(kThreads) void k_jacobi(int64_t nleaf, const JLeaf 
   }
 }
 
+// ---- learned apply: one wave per diagonal leaf (<= 64 rows):
+// y = dinv .* x + sinv * U (V^T x), U and V the leaf's FP32 factors (row-major
+// 64 x 16, U then V), every product and sum in FP64.
+constexpr int kLeafMax = 64, kLeafRank = 16;
+__global__ __launch_bounds__(64) void k_learned(int64_t nleaf, const JLeaf *__restrict__ leaves,
+                                                const double *__restrict__ dinv, const float *__restrict__ uv,
+                                                const double *__restrict__ sinv, const double *__restrict__ x,
+                                                double *__restrict__ y) {
+  __shared__ double prod[kLeafRank][kLeafMax];
+  __shared__ double t[kLeafRank];
+  const JLeaf L = leaves[blockIdx.x];
+  const int i = threadIdx.x;
+  const float *U = uv + L.off * 2 * kLeafMax * kLeafRank, *V = U + kLeafMax * kLeafRank;
+  const double xi = i < L.m ? x[L.r0 + i] : 0.0;
+#pragma unroll
+  for (int k = 0; k < kLeafRank; k++) prod[k][i] = i < L.m ? (double)V[i * kLeafRank + k] * xi : 0.0;
+  __syncthreads();
+  if (i < kLeafRank) {
+    double a = 0.0;
+    for (int j = 0; j < L.m; j++) a += prod[i][j];  // (V^T x)_k in row order
+    t[i] = a;
+  }
+  __syncthreads();
+  if (i < L.m) {
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < kLeafRank; k++) a += (double)U[i * kLeafRank + k] * t[k];
+    y[L.r0 + i] = dinv[L.r0 + i] * xi + sinv[L.off] * a;
+  }
+}
+
 }  // namespace hm
 
 struct hmat_precond_s {
   int64_t n = 0, nleaf = 0;
   hm::JLeaf *leaves = nullptr;
   double *inv = nullptr;
+  double *dinv = nullptr, *sinv = nullptr;  // learned kind
+  float *uv = nullptr;
   std::vector<char> covered;  // rows without a diagonal leaf pass through
   int32_t kind = 0;
   int any_uncovered = 0;
@@ -410,12 +443,109 @@ uint64_t hmat_solver_workspace_bytes(int64_t n) { return n > 0 ? hm::work_bytes(
 
 int hmat_precond_plan(const hmat_blocks *b, int32_t kind, uint64_t *device_bytes) {
   if (!b || !device_bytes) return hm::fail(HMAT_E_ARG, "null argument");
-  if (kind != HMAT_PRECOND_JACOBI) return hm::fail(HMAT_E_ARG, "unknown preconditioner kind %d", kind);
+  if (kind != HMAT_PRECOND_JACOBI && kind != HMAT_PRECOND_LEARNED)
+    return hm::fail(HMAT_E_ARG, "unknown preconditioner kind %d", kind);
   std::vector<int64_t> ids;
   hm::diag_blocks(b, ids);
+  if (kind == HMAT_PRECOND_LEARNED) {
+    for (int64_t k : ids)
+      if (b->nrows[k] > hm::kLeafMax)
+        return hm::fail(HMAT_E_ARG, "diagonal block %lld has %lld > 64 rows", (long long)k, (long long)b->nrows[k]);
+    *device_bytes = hm::align256(ids.size() * sizeof(hm::JLeaf)) + hm::align256((uint64_t)b->n * 8) +
+                    hm::align256(ids.size() * 8) + hm::align256(ids.size() * (uint64_t)HMAT_MLP_OUT * 4);
+    return HMAT_OK;
+  }
   uint64_t vals = 0;
   for (int64_t k : ids) vals += (uint64_t)b->nrows[k] * b->nrows[k];
   *device_bytes = hm::align256(ids.size() * sizeof(hm::JLeaf)) + hm::align256(vals * 8);
+  return HMAT_OK;
+}
+
+int hmat_precond_leaves(const hmat_blocks *b, int32_t kind, int64_t *block, int64_t *row0, int64_t *rows,
+                        int64_t capacity, int64_t *count) {
+  if (!b || !count) return hm::fail(HMAT_E_ARG, "null argument");
+  if (kind != HMAT_PRECOND_JACOBI && kind != HMAT_PRECOND_LEARNED)
+    return hm::fail(HMAT_E_ARG, "unknown preconditioner kind %d", kind);
+  std::vector<int64_t> ids;
+  hm::diag_blocks(b, ids);
+  *count = (int64_t)ids.size();
+  if (!block && !row0 && !rows) return HMAT_OK;
+  if (capacity < (int64_t)ids.size()) return hm::fail(HMAT_E_ARG, "capacity %lld < %lld leaves", (long long)capacity,
+                                                       (long long)ids.size());
+  for (size_t q = 0; q < ids.size(); q++) {
+    if (block) block[q] = ids[q];
+    if (row0) row0[q] = b->row0[ids[q]];
+    if (rows) rows[q] = b->nrows[ids[q]];
+  }
+  return HMAT_OK;
+}
+
+int hmat_dense_inverse(int64_t m, const double *a, double *out) {
+  if (!a || !out || m < 1) return hm::fail(HMAT_E_ARG, "bad argument");
+  if (!hm::invert(m, a, out)) return hm::fail(HMAT_E_ARG, "singular matrix");
+  return HMAT_OK;
+}
+
+int hmat_precond_create_learned(const hmat_blocks *b, const float *uv, void *dev_mem, uint64_t dev_bytes,
+                                void *stream, hmat_precond_t *out) {
+  if (!out) return hm::fail(HMAT_E_ARG, "null output");
+  *out = nullptr;
+  uint64_t need = 0;
+  int rc = hmat_precond_plan(b, HMAT_PRECOND_LEARNED, &need);
+  if (rc) return rc;
+  if (!dev_mem || ((uintptr_t)dev_mem & 255u) || dev_bytes < need)
+    return hm::fail(HMAT_E_WORKSPACE, "preconditioner buffer too small or misaligned (%llu needed)",
+                    (unsigned long long)need);
+  std::vector<int64_t> ids;
+  hm::diag_blocks(b, ids);
+  if (!uv && !ids.empty()) return hm::fail(HMAT_E_ARG, "null factors");
+  std::vector<hm::JLeaf> leaves(ids.size());
+  std::vector<double> dinv(b->n, 1.0), sinv(ids.size());
+  for (size_t q = 0; q < ids.size(); q++) {
+    const int64_t k = ids[q], m = b->nrows[k];
+    leaves[q] = {b->row0[k], (int64_t)q, (int32_t)m, 0};
+    const double *A = b->data + b->offset[k];
+    double s = 0.0;
+    for (int64_t i = 0; i < m; i++) {
+      const double d = A[i + i * m];
+      if (d == 0.0) return hm::fail(HMAT_E_ARG, "zero diagonal entry in block %lld", (long long)k);
+      dinv[b->row0[k] + i] = 1.0 / d;
+      s += d;
+    }
+    sinv[q] = (double)m / s;
+  }
+  auto *P = new hmat_precond_s();
+  P->n = b->n;
+  P->kind = HMAT_PRECOND_LEARNED;
+  P->nleaf = (int64_t)ids.size();
+  P->covered.assign(b->n, 0);
+  for (auto &L : leaves)
+    for (int64_t i = 0; i < L.m; i++) P->covered[L.r0 + i] = 1;
+  for (char c : P->covered)
+    if (!c) P->any_uncovered = 1;
+  unsigned char *d = (unsigned char *)dev_mem;
+  P->leaves = (hm::JLeaf *)d;
+  d += hm::align256(ids.size() * sizeof(hm::JLeaf));
+  P->dinv = (double *)d;
+  d += hm::align256((uint64_t)b->n * 8);
+  P->sinv = (double *)d;
+  d += hm::align256(ids.size() * 8);
+  P->uv = (float *)d;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  if (!ids.empty()) {
+    e = hipMemcpyAsync(P->leaves, leaves.data(), leaves.size() * sizeof(hm::JLeaf), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->sinv, sinv.data(), sinv.size() * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(P->uv, uv, ids.size() * (size_t)HMAT_MLP_OUT * 4, hipMemcpyDeviceToDevice, st);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(P->dinv, dinv.data(), dinv.size() * 8, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete P;
+    return hm::fail(HMAT_E_HIP, "preconditioner upload failed: %s", hipGetErrorString(e));
+  }
+  *out = P;
   return HMAT_OK;
 }
 
@@ -423,6 +553,8 @@ int hmat_precond_create(const hmat_blocks *b, int32_t kind, void *dev_mem, uint6
                         hmat_precond_t *out) {
   if (!out) return hm::fail(HMAT_E_ARG, "null output");
   *out = nullptr;
+  if (kind != HMAT_PRECOND_JACOBI)
+    return hm::fail(HMAT_E_ARG, "kind %d: use hmat_precond_create_learned for the learned map", kind);
   uint64_t need = 0;
   int rc = hmat_precond_plan(b, kind, &need);
   if (rc) return rc;
@@ -472,7 +604,10 @@ int hmat_precond_apply(hmat_precond_t p, const double *x, double *y, void *strea
   if (!p || !x || !y) return hm::fail(HMAT_E_ARG, "null argument");
   hipStream_t st = (hipStream_t)stream;
   if (p->any_uncovered) hipLaunchKernelGGL(hm::k_copy, dim3(hm::kParts), dim3(hm::kThreads), 0, st, p->n, x, y);
-  if (p->nleaf)
+  if (p->nleaf && p->kind == HMAT_PRECOND_LEARNED)
+    hipLaunchKernelGGL(hm::k_learned, dim3((unsigned)p->nleaf), dim3(64), 0, st, p->nleaf, p->leaves, p->dinv, p->uv,
+                       p->sinv, x, y);
+  else if (p->nleaf)
     hipLaunchKernelGGL(hm::k_jacobi, dim3((unsigned)p->nleaf), dim3(hm::kThreads), 0, st, p->nleaf, p->leaves, p->inv,
                        x, y);
   hipError_t e = hipGetLastError();

@@ -24,7 +24,9 @@ STATUS_NAMES = ["OK", "E_ARG", "E_LAYOUT", "E_WORKSPACE", "E_HIP", "E_BREAKDOWN"
 
 M1_DOUBLE, M1_SINGLE, M1_MIXED, M2_DOUBLE, M2_SINGLE, M2_MIXED, M3, BF16_SCALED = range(8)
 PRECISION_NAMES = ["M1-Double", "M1-Single", "M1-Mixed", "M2-Double", "M2-Single", "M2-Mixed", "M3", "BF16-scaled"]
-PRECOND_NONE, PRECOND_JACOBI = 0, 1
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_LEARNED = 0, 1, 2
+MLP_LEAF, MLP_RANK, MLP_IN, MLP_HIDDEN, MLP_OUT = 64, 16, 512, 128, 2048
+MLP_PARAMS = 512 * 128 + 128 + 128 * 128 + 128 + 128 * 2048 + 2048
 
 EXPORTED = [
     "hmat_last_error", "hmat_plan", "hmat_build", "hmat_matvec", "hmat_destroy", "hmat_get_stats",
@@ -32,7 +34,9 @@ EXPORTED = [
     "hmat_solver_workspace_bytes", "hmat_bicgstab", "hmat_assemble_bem", "hmat_assembly_blocks",
     "hmat_assembly_perm", "hmat_assembly_free", "hmat_version", "hmat_set_profiling", "hmat_kernel_times",
     "hmat_stream_read", "hmat_stream_copy", "hmat_plan_batched", "hmat_build_batched", "hmat_system_offsets",
-    "hmat_bicgstab_batched_workspace_bytes", "hmat_bicgstab_batched",
+    "hmat_bicgstab_batched_workspace_bytes", "hmat_bicgstab_batched", "hmat_precond_create_learned",
+    "hmat_precond_leaves", "hmat_leaf_features", "hmat_dense_inverse", "hmat_mlp_workspace_bytes",
+    "hmat_mlp_forward", "hmat_mlp_loss_grad", "hmat_mlp_adam",
 ]
 
 
@@ -129,6 +133,14 @@ def lib():
         "hmat_system_offsets": (C.c_int, [P, P, I64, P]),
         "hmat_bicgstab_batched_workspace_bytes": (U64, [P, I64]),
         "hmat_bicgstab_batched": (C.c_int, [P, P, P, P, I64, P, P, P, P, U64, P]),
+        "hmat_precond_create_learned": (C.c_int, [P, P, P, U64, P, P]),
+        "hmat_precond_leaves": (C.c_int, [P, I32, P, P, P, I64, P]),
+        "hmat_leaf_features": (C.c_int, [I64, P, P, P, P]),
+        "hmat_dense_inverse": (C.c_int, [I64, P, P]),
+        "hmat_mlp_workspace_bytes": (U64, [I64]),
+        "hmat_mlp_forward": (C.c_int, [P, P, I64, P, P, U64, P]),
+        "hmat_mlp_loss_grad": (C.c_int, [P, P, P, P, P, P, I64, P, I64, P, P, P, U64, P]),
+        "hmat_mlp_adam": (C.c_int, [P, P, P, P, I64, C.c_float, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -325,9 +337,11 @@ def hmat_get_stats(h: HMatrix) -> hmat_stats:
 
 
 class Precond:
-    """Block-Jacobi right preconditioner (hmat_precond_create)."""
+    """Right preconditioner: block-Jacobi (hmat_precond_create) or the learned
+    leaf map (hmat_precond_create_learned; uv = device FP32 factors, one
+    MLP_OUT row per diagonal leaf in precond_leaves order)."""
 
-    def __init__(self, blocks: BlockSet, kind: int = PRECOND_JACOBI, device="cuda", stream=None):
+    def __init__(self, blocks: BlockSet, kind: int = PRECOND_JACOBI, uv=None, device="cuda", stream=None):
         import torch
 
         s = blocks.struct()
@@ -335,8 +349,16 @@ class Precond:
         _check(lib().hmat_precond_plan(C.byref(s), int(kind), C.byref(nb)))
         self.buf = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=device)
         p = C.c_void_p()
-        _check(lib().hmat_precond_create(C.byref(s), int(kind), C.c_void_p(self.buf.data_ptr()), self.buf.numel(),
-                                         _stream_ptr(stream), C.byref(p)))
+        if kind == PRECOND_LEARNED:
+            if uv is None or uv.dtype != torch.float32 or not uv.is_contiguous():
+                raise ValueError("uv must be a contiguous float32 device tensor")
+            self.uv = uv
+            _check(lib().hmat_precond_create_learned(C.byref(s), C.c_void_p(uv.data_ptr()),
+                                                     C.c_void_p(self.buf.data_ptr()), self.buf.numel(),
+                                                     _stream_ptr(stream), C.byref(p)))
+        else:
+            _check(lib().hmat_precond_create(C.byref(s), int(kind), C.c_void_p(self.buf.data_ptr()),
+                                             self.buf.numel(), _stream_ptr(stream), C.byref(p)))
         self.p = p
         self.n = blocks.n
 
@@ -351,6 +373,91 @@ class Precond:
         y = torch.empty_like(x) if y is None else y
         _check(lib().hmat_precond_apply(self.p, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), _stream_ptr(stream)))
         return y
+
+
+def precond_leaves(blocks: BlockSet, kind: int = PRECOND_LEARNED):
+    """(block index, first row, rows) of the diagonal leaves a preconditioner acts on."""
+    s = blocks.struct()
+    cnt = C.c_int64()
+    _check(lib().hmat_precond_leaves(C.byref(s), int(kind), None, None, None, 0, C.byref(cnt)))
+    k = cnt.value
+    blk, r0, m = np.zeros(k, np.int64), np.zeros(k, np.int64), np.zeros(k, np.int64)
+    _check(lib().hmat_precond_leaves(C.byref(s), int(kind), _p(blk), _p(r0), _p(m), k, C.byref(cnt)))
+    return blk, r0, m
+
+
+def hmat_leaf_features(centroids, normals, areas) -> np.ndarray:
+    """The 512 MLP inputs of one leaf (host; rows in cluster order)."""
+    c = np.ascontiguousarray(centroids, dtype=np.float64).reshape(-1, 3)
+    nrm = np.ascontiguousarray(normals, dtype=np.float64).reshape(-1, 3)
+    a = np.ascontiguousarray(areas, dtype=np.float64)
+    out = np.zeros(MLP_IN, np.float32)
+    _check(lib().hmat_leaf_features(a.size, _p(c), _p(nrm), _p(a), _p(out)))
+    return out
+
+
+def hmat_dense_inverse(A) -> np.ndarray:
+    """Exact inverse of a dense block (host FP64 Gauss-Jordan with pivoting)."""
+    A = np.asfortranarray(A, dtype=np.float64)
+    m = A.shape[0]
+    out = np.zeros((m, m), order="F")
+    _check(lib().hmat_dense_inverse(m, C.c_void_p(A.ctypes.data), C.c_void_p(out.ctypes.data)))
+    return out
+
+
+class MLP:
+    """The learned leaf map's parameters and Adam moments on the device
+    (hmat_mlp_*); `params` is a float32 device tensor of MLP_PARAMS."""
+
+    def __init__(self, params, device="cuda"):
+        import torch
+
+        p = torch.as_tensor(np.asarray(params, dtype=np.float32)).to(device)
+        if p.numel() != MLP_PARAMS:
+            raise ValueError("wrong parameter count")
+        self.params = p.contiguous()
+        self.m1 = torch.zeros_like(self.params)
+        self.m2 = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.t = 0
+        self.work = None
+
+    def _work(self, batch):
+        import torch
+
+        need = int(lib().hmat_mlp_workspace_bytes(int(batch)))
+        if self.work is None or self.work.numel() < need:
+            self.work = torch.empty(need, dtype=torch.uint8, device=self.params.device)
+        return self.work
+
+    def forward(self, x, out=None, stream=None):
+        """(batch, 2048) float32 = MLP(x) for x (batch, 512) float32 on the device."""
+        import torch
+
+        B = x.shape[0]
+        out = torch.empty((B, MLP_OUT), dtype=torch.float32, device=x.device) if out is None else out
+        w = self._work(B)
+        _check(lib().hmat_mlp_forward(C.c_void_p(self.params.data_ptr()), C.c_void_p(x.data_ptr()), B,
+                                      C.c_void_p(out.data_ptr()), C.c_void_p(w.data_ptr()), w.numel(),
+                                      _stream_ptr(stream)))
+        return out
+
+    def loss_grad(self, data, idx, stream=None):
+        """Batch loss and gradient (into self.grad / self.loss) for the samples
+        idx (int32 device) of `data` (dict of device tensors x, ainv, dinv, sinv, m)."""
+        B = idx.numel()
+        w = self._work(B)
+        ptr = lambda t: C.c_void_p(t.data_ptr())
+        _check(lib().hmat_mlp_loss_grad(ptr(self.params), ptr(data["x"]), ptr(data["ainv"]), ptr(data["dinv"]),
+                                        ptr(data["sinv"]), ptr(data["m"]), int(data["m"].numel()), ptr(idx), B,
+                                        ptr(self.grad), ptr(self.loss), ptr(w), w.numel(), _stream_ptr(stream)))
+
+    def adam(self, lr=1e-3, stream=None):
+        self.t += 1
+        ptr = lambda t: C.c_void_p(t.data_ptr())
+        _check(lib().hmat_mlp_adam(ptr(self.params), ptr(self.m1), ptr(self.m2), ptr(self.grad), self.t,
+                                   C.c_float(lr), _stream_ptr(stream)))
 
 
 def hmat_solver_workspace_bytes(n: int) -> int:

@@ -264,6 +264,33 @@ def random_ellipsoids(count: int = 64, seed: int = 0, fmin: int = 10, fmax: int 
     return out
 
 
+def plate_pairs(count: int, seed: int = 1, nmin: int = 16, nmax: int = 40, gmin: float = 0.05, gmax: float = 0.5):
+    """Pairs of 1 x 1 plates: nsq ~ U{nmin..nmax}, gap ~ U[gmin, gmax], cut
+    into 4 or 2 triangles per square with equal odds."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(count):
+        nsq = int(rng.integers(nmin, nmax + 1))
+        gap = float(rng.uniform(gmin, gmax))
+        four = bool(rng.integers(0, 2))
+        out.append(parallel_plates(nsq, gap, four))
+    return out
+
+
+def learned_training_meshes(seed: int = 1):
+    """Meshes whose diagonal leaves train the learned leaf map, alternating
+    random ellipsoids (the batched family) and plate pairs; an endless
+    generator, each kind drawn from its own seeded stream."""
+    ss = np.random.SeedSequence(seed).spawn(2)
+    k = 0
+    while True:
+        e = random_ellipsoids(1, seed=int(ss[0].generate_state(1)[0]) + k)[0]
+        p = plate_pairs(1, seed=int(ss[1].generate_state(1)[0]) + k)[0]
+        yield e
+        yield p
+        k += 1
+
+
 def random_vector(n: int, seed: int = 0) -> np.ndarray:
     """Seeded N(0, 1) vector."""
     return np.random.Generator(np.random.PCG64(seed)).standard_normal(n)

@@ -178,3 +178,55 @@ def test_plan_multirhs_sizes(nrhs_max):
     a = hmat.hmat_plan(bs, 5, nrhs_max=nrhs_max)
     assert a.matrix_bytes == hmat.hmat_plan(bs, 5).matrix_bytes
     assert a.device_bytes > a.matrix_bytes
+
+
+def test_leaf_features_match_oracle():
+    """The library's leaf features equal the oracle's (FP64 -> FP32 rounding)."""
+    from oracle import learned as OL
+
+    m, h = oracle_hmatrix("sphere-L3")
+    bs = blockset_from_oracle(h)
+    blk, r0, rows = hmat.precond_leaves(bs, hmat.PRECOND_LEARNED)
+    assert blk.size > 0 and np.all(rows <= 64)
+    cent, nrm, area = m.centroids[h.perm], m.normals[h.perm], m.areas[h.perm]
+    for q in range(0, blk.size, 7):
+        a, k = int(r0[q]), int(rows[q])
+        f = hmat.hmat_leaf_features(cent[a:a + k], nrm[a:a + k], area[a:a + k])
+        fo = OL.leaf_features(cent[a:a + k], nrm[a:a + k], area[a:a + k])
+        assert np.array_equal(f, fo.astype(np.float32)) or np.abs(f - fo).max() <= 2e-7 * np.abs(fo).max()
+    with pytest.raises(hmat.HmatError):
+        hmat.hmat_leaf_features(np.zeros((65, 3)), np.zeros((65, 3)), np.ones(65))
+
+
+def test_dense_inverse_matches_oracle():
+    m, h = oracle_hmatrix("sphere-L3")
+    b = next(i for i in range(h.nblocks) if h.kind[i] == 0 and h.row0[i] == h.col0[i])
+    k = int(h.nrows[b])
+    A = h.data[h.offset[b]:h.offset[b] + k * k].reshape(k, k, order="F")
+    Ai = hmat.hmat_dense_inverse(A)
+    assert np.abs(Ai @ A - np.eye(k)).max() < 1e-10
+    assert np.allclose(Ai, oracle.invert(A), rtol=1e-10, atol=1e-12 * np.abs(Ai).max())
+    with pytest.raises(hmat.HmatError):
+        hmat.hmat_dense_inverse(np.zeros((3, 3)))
+
+
+def test_precond_plan_learned():
+    m, h = oracle_hmatrix("plates-16")
+    bs = blockset_from_oracle(h)
+    blk, r0, rows = hmat.precond_leaves(bs, hmat.PRECOND_LEARNED)
+    assert np.all(np.diff(r0) > 0) and rows.sum() == h.n  # diagonal leaves tile the matrix
+    s = bs.struct()
+    import ctypes
+    nb = ctypes.c_uint64()
+    assert hmat.lib().hmat_precond_plan(ctypes.byref(s), hmat.PRECOND_LEARNED, ctypes.byref(nb)) == 0
+    assert nb.value >= blk.size * hmat.MLP_OUT * 4 + h.n * 8
+
+
+def test_seeded_params_layout():
+    from paper_1911_00093_amd import seeded
+
+    p = seeded.init_params(0)
+    assert p.dtype == np.float32 and p.size == hmat.MLP_PARAMS
+    assert np.array_equal(p, seeded.init_params(0))
+    b = list(seeded.batch_order(1000, 256, 2, seed=3))
+    assert len(b) == 6 and all(x.size == 256 for x in b) and len(set(b[0]) & set(b[1])) == 0
