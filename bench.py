@@ -64,6 +64,11 @@ WORKLOADS = {
                              "N=330240; leaf 64, eta 2, ACA 1e-6; b = 1"),
     "sphere-L4": dict(leaf=32, eta=2.0, eps=1e-6,
                       desc="unit icosphere L4, N=5120; leaf 32, eta 2, ACA 1e-6; b = 1 (cache-resident)"),
+    "sphere-L6+plates": dict(leaf=64, eta=2.0, eps=1e-5, learned=True,
+                             desc="unit icosphere L6 (81,920) + two 1x1 plates at gap 0.1 (240x256 squares x 2 "
+                                  "triangles each, offset 3 along x), N=327,680; leaf 64, eta 2, ACA 1e-5; "
+                                  "b = 1 / +1 / -1; preconditioners none, block-Jacobi, learned leaf map "
+                                  "(trained on 20,000 leaves of random ellipsoids and plate pairs, seed 1)"),
     "ellipsoids-64x16": dict(leaf=32, eta=2.0, eps=1e-6, nsys=64, nrhs=16,
                              desc="64 independent geodesic ellipsoids (frequency U{10..44}, N = 20 f^2 in "
                                   "[2000, 38720], semi-axes U[0.5, 2], seed 0), N = 1,089,460 in total; leaf 32, "
@@ -87,6 +92,8 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-matvecs", type=int, default=5)
+    ap.add_argument("--train-leaves", type=int, default=20000)
+    ap.add_argument("--epochs", type=int, default=30)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -108,6 +115,8 @@ def main():
     W = WORKLOADS[args.workload]
     if "nsys" in W:
         return bench_batched(args, W, variant, dev, stream)
+    if W.get("learned"):
+        return bench_learned(args, W, variant, dev, stream)
 
     # ---------------- setup (untimed): mesh, FP64 H-matrix, conversions
     t0 = time.time()
@@ -417,6 +426,125 @@ def bench_batched(args, W, variant, dev, stream):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batched(ms, W, variant, nrhs)
     print(json.dumps(out), flush=True)
+
+
+def bench_learned(args, W, variant, dev, stream):
+    """Preconditioned solves: the learned leaf map is trained on the GPU by
+    the library's own kernels (setup, timed separately), then one step = one
+    mixed BiCGSTAB solve to 1e-8 (FP64 true residual) with each of no
+    preconditioner, block-Jacobi and the learned map."""
+    import torch
+
+    from paper_1911_00093_amd import hmat, learned, meshes
+
+    t0 = time.time()
+    data = learned.training_set(target=args.train_leaves, seed=1, log=log)
+    t_set = time.time() - t0
+    log(f"[setup] training set: {data['m'].size} leaves from {data['meshes']} meshes, {t_set:.1f}s")
+    dd = learned.to_device(data)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net, hist = learned.train(dd, epochs=args.epochs, batch=256, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"[train] {args.epochs} epochs in {t_train:.2f}s, loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+
+    t0 = time.time()
+    mesh = meshes.workload(args.workload)
+    bs = hmat.hmat_assemble_bem(mesh.centroids, mesh.areas, leaf=W["leaf"], eta=W["eta"], eps=W["eps"])
+    log(f"[setup] {args.workload}: n={bs.n} blocks={bs.nblocks} assembly {time.time() - t0:.1f}s")
+    H64 = hmat.HMatrix(bs, hmat.M1_DOUBLE)
+    Hm = hmat.HMatrix(bs, variant, c=-1)
+    Bm, B64 = Hm.stats().algorithmic_bytes, H64.stats().algorithmic_bytes
+    b = torch.as_tensor(mesh.rhs()[bs.perm], device=dev)
+    n = bs.n
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    uv = learned.factors(net, mesh, bs)
+    torch.cuda.synchronize()
+    t_infer = time.perf_counter() - t0
+    pre = {"none": None, "block-jacobi": hmat.Precond(bs, hmat.PRECOND_JACOBI),
+           "learned": hmat.Precond(bs, hmat.PRECOND_LEARNED, uv=uv)}
+    work = torch.empty(hmat.hmat_solver_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    xref, _ = hmat.hmat_bicgstab(H64, b, tol=1e-12, maxiter=4000, work=work)
+    xref = xref.clone()
+    res = {}
+    for name, P in pre.items():
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            hmat.hmat_bicgstab(Hm, b, x=x.zero_(), h_fp64=H64, tol=args.tol, maxiter=4000, precond=P,
+                               poll_every=args.poll_every, work=work)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = []
+        for _ in range(args.steps):
+            x, info = hmat.hmat_bicgstab(Hm, b, x=x.zero_(), h_fp64=H64, tol=args.tol, maxiter=4000, precond=P,
+                                         poll_every=args.poll_every, work=work)
+            infos.append(info)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert all(i["status"] == 0 for i in infos), (name, infos)
+        res[name] = dict(ms=round(1e3 * dt / args.steps, 3), iterations=infos[-1]["iterations"],
+                         restarts=infos[-1]["restarts"],
+                         gbs=round(sum(i["matvecs"] * Bm + i["matvecs_fp64"] * B64 for i in infos) / dt / 1e9, 1),
+                         x_err_vs_fp64_1e12=float(torch.linalg.norm(x - xref) / torch.linalg.norm(xref)))
+        log(f"[solve] {name}: {res[name]}")
+    L = res["learned"]
+    out = {
+        "metric": "H-matvec GB/s and BiCG-STAB time-to-1e-8 residual, mixed vs FP64, 1 GPU",
+        "value": L["gbs"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": L["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {W['desc']}",
+            "precision": args.variant,
+            "n": n,
+            "step": "one mixed BiCGSTAB solve x0=0 -> |r|/|b|<1e-8 (FP64 true residual) with the learned "
+                    "leaf-map preconditioner",
+            "parallelism": "1 GPU",
+        },
+        "preconditioners": res,
+        "training": {"leaves": int(data["m"].size), "meshes": int(data["meshes"]), "epochs": args.epochs,
+                     "batch": 256, "set_build_s": round(t_set, 2), "train_s": round(t_train, 3),
+                     "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "inference_s": round(t_infer, 4)},
+        "speedup_learned_vs_none": round(res["none"]["ms"] / L["ms"], 3),
+        "speedup_learned_vs_jacobi": round(res["block-jacobi"]["ms"] / L["ms"], 3),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_training(data)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_training(data, steps=200, batch=256):
+    """The oracle (FP64 numpy) taking `steps` Adam steps of the same batch
+    size on the same training set."""
+    import oracle.learned as OL
+    from paper_1911_00093_amd import seeded
+
+    from threadpoolctl import threadpool_limits
+
+    p = seeded.init_params(0).astype(np.float64)
+    m1, m2 = np.zeros_like(p), np.zeros_like(p)
+    order = seeded.batch_order(data["m"].size, batch, steps * batch // data["m"].size + 1, seed=0)
+    with threadpool_limits(limits=1):  # one core, like the other oracle baselines
+        t0 = time.perf_counter()
+        for t in range(1, steps + 1):
+            idx = next(order)
+            f = lambda a: np.asarray(a[idx], dtype=np.float64)
+            _, g = OL.loss_and_grad(p, f(data["x"]), f(data["ainv"]), f(data["dinv"]), f(data["sinv"]),
+                                    data["m"][idx])
+            OL.adam_step(p, m1, m2, g, t)
+        dt = time.perf_counter() - t0
+    return {"value": round(steps * batch / dt, 1), "unit": "training samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} oracle Adam steps of batch {batch} (FP64 numpy) on the same training set"}
 
 
 def cpu_baseline_batched(ms, W, variant, nrhs, sample=4):

@@ -100,7 +100,7 @@ def test_training_tracks_oracle_and_reduces_loss():
     need_gpu()
     import torch
 
-    host, dev = sample_data(64, seed=3)
+    host, dev = sample_data(64, key="sphere-L4", seed=3)
     P = seeded.init_params(7)
     net = hmat.MLP(P)
     p, m1, m2 = f64(P), np.zeros(P.size), np.zeros(P.size)
