@@ -104,6 +104,15 @@ constexpr int kMRTile = 16;        // rows per MFMA tile (MFMA M)
 constexpr int kMRCols = 512;       // stage-1 item width (columns)
 constexpr int mr_cb(int cls) { return 4 * vec_of(cls); }
 
+// Work units of a multi-RHS launch cut into one contiguous range per XCD
+// (units [lo[x], lo[x + 1]) run on the workgroups with blockIdx % 8 == x, the
+// round-robin order in which workgroups are dispatched to the XCDs), so
+// neighbouring units share that XCD's L2.
+constexpr int kXcds = 8;
+struct XcdSplit {
+  int64_t lo[kXcds + 1];
+};
+
 struct MRChunk {  // stage 2, multi-RHS: rows [r0, r0 + h), h <= 64
   int64_t panel_off[NCLS];  // element offset of (tile 0, block 0)
   int64_t gidx_off[NCLS];
@@ -167,6 +176,7 @@ struct hmat_s {
   hm::MRItem *mri = nullptr;
   double *src64 = nullptr;  // (n + zlen + 1) x 16, right-hand side fastest
   int32_t mr_grid1[hm::NCLS] = {0, 0, 0}, mr_grid2 = 0;
+  hm::XcdSplit mr_split2{}, mr_split1[hm::NCLS]{};
   std::vector<int64_t> sys_off;  // system boundaries of a batched handle
   double *src = nullptr;    // nrhs_max x (n + zlen + 1)
   double *zpart = nullptr;  // nrhs_max x zpart_len
@@ -190,6 +200,7 @@ int plan_batched(const hmat_blocks *systems, int64_t count, const hmat_build_opt
                  Packed **out_keep);
 int pack_into(Packed *p, std::vector<unsigned char> &staging, hmat_s *h);
 void packed_free(Packed *p);
+XcdSplit xcd_split(const std::vector<double> &cost);
 
 // Kernel launchers (matvec.hip)
 int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream);

@@ -48,6 +48,16 @@ __device__ __forceinline__ double mr_a(mr_raw t, int v) {
   }
 }
 
+// Work unit loop over this workgroup's XCD range: workgroup b serves range
+// b % 8 with its (b / 8)-th group of waves; every unit of every range is
+// taken by exactly one wave whatever the physical placement (grid >= 8).
+#define XCD_UNIT_LOOP(q, sp)                                                                            \
+  const int xcd_ = blockIdx.x % kXcds;                                                                  \
+  const int64_t gx_ = ((int64_t)gridDim.x - xcd_ + kXcds - 1) / kXcds;                                  \
+  const int64_t w0_ = (int64_t)(blockIdx.x / kXcds) * kMRWaves +                                        \
+                      __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);                              \
+  for (int64_t q = (sp).lo[xcd_] + w0_; q < (sp).lo[xcd_ + 1]; q += gx_ * kMRWaves)
+
 // Output element e of lane l of a row tile is row (l / 16) + 4 e, right-hand
 // side l % 16 (v_mfma_f64_16x16x4f64 result layout).
 __device__ __forceinline__ int mr_row(int lane, int e) { return (lane >> 4) + 4 * e; }
@@ -120,14 +130,12 @@ __device__ __forceinline__ void mr_s1_item(const MRItem &it, const void *vals, i
 }
 
 template <int CLS>
-__global__ __launch_bounds__(kMRThreads) void k_mr_stage1(const MRItem *__restrict__ items, int64_t nitems,
+__global__ __launch_bounds__(kMRThreads) void k_mr_stage1(const MRItem *__restrict__ items, XcdSplit sp,
                                                           const void *__restrict__ vals, int64_t n, int z32,
                                                           const double *__restrict__ dscale,
                                                           double *__restrict__ s64, double *__restrict__ zpart) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t w0 = (int64_t)blockIdx.x * kMRWaves + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int64_t nw = (int64_t)gridDim.x * kMRWaves;
-  for (int64_t q = w0; q < nitems; q += nw) {
+  XCD_UNIT_LOOP(q, sp) {
     const MRItem it = items[q];
     switch ((it.nrows + kMRTile - 1) / kMRTile) {
       case 1: mr_s1_item<CLS, 1>(it, vals, n, z32, dscale, s64, zpart, lane); break;
@@ -223,7 +231,7 @@ __device__ __forceinline__ void mr_s2_chunk(const MRChunk &ch, const double *v64
 }
 
 template <int MASK>
-__global__ __launch_bounds__(kMRThreads) void k_mr_stage2(const MRChunk *__restrict__ chunks, int64_t nchunks,
+__global__ __launch_bounds__(kMRThreads) void k_mr_stage2(const MRChunk *__restrict__ chunks, XcdSplit sp,
                                                           const double *__restrict__ v64, const float *__restrict__ v32,
                                                           const unsigned short *__restrict__ v16,
                                                           const int32_t *__restrict__ g64, const int32_t *__restrict__ g32,
@@ -231,9 +239,7 @@ __global__ __launch_bounds__(kMRThreads) void k_mr_stage2(const MRChunk *__restr
                                                           const double *__restrict__ s64, double *__restrict__ y,
                                                           int64_t ldy, int64_t nrhs) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t w0 = (int64_t)blockIdx.x * kMRWaves + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int64_t nw = (int64_t)gridDim.x * kMRWaves;
-  for (int64_t q = w0; q < nchunks; q += nw) {
+  XCD_UNIT_LOOP(q, sp) {
     const MRChunk ch = chunks[q];
     switch ((ch.h + kMRTile - 1) / kMRTile) {
       case 1: mr_s2_chunk<MASK, 1>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
@@ -245,7 +251,7 @@ __global__ __launch_bounds__(kMRThreads) void k_mr_stage2(const MRChunk *__restr
 }
 
 // ------------------------------------------------------------- launch
-typedef void (*MRStage2Fn)(const MRChunk *, int64_t, const double *, const float *, const unsigned short *,
+typedef void (*MRStage2Fn)(const MRChunk *, XcdSplit, const double *, const float *, const unsigned short *,
                            const int32_t *, const int32_t *, const int32_t *, const double *, double *, int64_t,
                            int64_t);
 static MRStage2Fn mr_stage2_fn(int mask) {
@@ -259,7 +265,7 @@ static MRStage2Fn mr_stage2_fn(int mask) {
     default: return k_mr_stage2<7>;
   }
 }
-typedef void (*MRStage1Fn)(const MRItem *, int64_t, const void *, int64_t, int, const double *, double *, double *);
+typedef void (*MRStage1Fn)(const MRItem *, XcdSplit, const void *, int64_t, int, const double *, double *, double *);
 static MRStage1Fn mr_stage1_fn(int cls) {
   return cls == F64 ? k_mr_stage1<F64> : cls == F32 ? k_mr_stage1<F32> : k_mr_stage1<BF16>;
 }
@@ -268,15 +274,19 @@ int size_grids_mr(hmat_s *h) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return fail(HMAT_E_HIP, "cannot query the device");
-  auto waves_to_groups = [](int64_t units) { return (units + kMRWaves - 1) / kMRWaves; };
+  // a multiple of 8 workgroups, at least 8: every XCD range has workgroups
+  auto groups = [&](int64_t units, int per) {
+    const int64_t g = std::min<int64_t>((units + kMRWaves - 1) / kMRWaves, (int64_t)per * cus);
+    return (int32_t)std::max<int64_t>(kXcds, (g + kXcds - 1) / kXcds * kXcds);
+  };
   for (int c = 0; c < NCLS; c++) {
     int per = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mr_stage1_fn(c), kMRThreads, 0) != hipSuccess || per < 1) per = 1;
-    h->mr_grid1[c] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(waves_to_groups(h->mr_nitems[c]), (int64_t)per * cus));
+    h->mr_grid1[c] = groups(h->mr_nitems[c], per);
   }
   int per = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mr_stage2_fn(h->cls_mask), kMRThreads, 0) != hipSuccess || per < 1) per = 1;
-  h->mr_grid2 = (int32_t)std::max<int64_t>(1, std::min<int64_t>(waves_to_groups(h->nchunks), (int64_t)per * cus));
+  h->mr_grid2 = groups(h->nchunks, per);
   return HMAT_OK;
 }
 
@@ -295,7 +305,7 @@ int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, 
     for (int c = 0; c < NCLS; c++) {
       if (h->mr_nitems[c] <= 0) continue;
       hipLaunchKernelGGL(mr_stage1_fn(c), dim3((unsigned)h->mr_grid1[c]), dim3(kMRThreads), 0, st,
-                         h->mri + h->mr_item_begin[c], h->mr_nitems[c], (const void *)h->vals[c], h->n, h->z32,
+                         h->mri + h->mr_item_begin[c], h->mr_split1[c], (const void *)h->vals[c], h->n, h->z32,
                          h->dscale, h->src64, h->zpart);
     }
     prof_mark(h, 1, stream);
@@ -306,7 +316,7 @@ int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, 
     }
     prof_mark(h, 2, stream);
     hipLaunchKernelGGL(mr_stage2_fn(h->cls_mask), dim3((unsigned)h->mr_grid2), dim3(kMRThreads), 0, st, h->mrc,
-                       h->nchunks, (const double *)h->vals[F64], (const float *)h->vals[F32],
+                       h->mr_split2, (const double *)h->vals[F64], (const float *)h->vals[F32],
                        (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16], h->src64,
                        yr, ld, nr);
     prof_mark(h, 3, stream);

@@ -115,9 +115,27 @@ struct Packed {
   std::vector<MRItem> mri;
   std::vector<int64_t> mri_group, mri_k0, mri_c0;
   int64_t mr_vals[NCLS] = {0, 0, 0}, mr_gidx[NCLS] = {0, 0, 0};
+  XcdSplit mr_split2{}, mr_split1[NCLS]{};
 };
 
 void packed_free(Packed *p) { delete p; }
+
+// Cut a sequence of work units into kXcds contiguous ranges of about equal
+// cost: unit q goes to range x when its cumulative cost crosses x / kXcds of
+// the total.
+XcdSplit xcd_split(const std::vector<double> &cost) {
+  XcdSplit s{};
+  double tot = 0.0;
+  for (double c : cost) tot += c;
+  double run = 0.0;
+  int x = 1;
+  for (size_t q = 0; q < cost.size() && x < kXcds; q++) {
+    run += cost[q];
+    while (x < kXcds && run >= tot * x / kXcds) s.lo[x++] = (int64_t)q + 1;
+  }
+  for (; x <= kXcds; x++) s.lo[x] = (int64_t)cost.size();
+  return s;
+}
 
 // Round a double to the nearest bfloat16 (8 significant bits, ties to even)
 // and return its bit pattern.  Works on the binary64 encoding: the 45 low
@@ -365,9 +383,12 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   }
   // stage-1 items: largest first so the tail of the launch is short; each
   // item's values are stored in launch order, so consecutive waves read
-  // consecutive memory
-  std::stable_sort(isrc.begin(), isrc.end(), [](const ItemSrc &a, const ItemSrc &c) {
+  // consecutive memory.  The multi-RHS layout keeps column-group order
+  // instead (items reading the same x columns run side by side; the launch
+  // is balanced by contiguous per-XCD ranges, see xcd_split).
+  std::stable_sort(isrc.begin(), isrc.end(), [&](const ItemSrc &a, const ItemSrc &c) {
     if (a.it.cls != c.it.cls) return a.it.cls < c.it.cls;  // one launch per class
+    if (P->mr) return false;
     return (int64_t)a.it.ncols * a.it.nrows * bytes_of(a.it.cls) > (int64_t)c.it.ncols * c.it.nrows * bytes_of(c.it.cls);
   });
   for (auto &q : isrc) {
@@ -432,8 +453,10 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
     for (int c = 0; c < NCLS; c++) s += P->chunks[i].h * P->chunks[i].K[c] * bytes_of(c);
     return s;
   };
-  std::stable_sort(P->chunk_order.begin(), P->chunk_order.end(),
-                   [&](int64_t a, int64_t c) { return cbytes(a) > cbytes(c); });
+  // (multi-RHS: row order, so chunks sharing z and x operands are neighbours)
+  if (!P->mr)
+    std::stable_sort(P->chunk_order.begin(), P->chunk_order.end(),
+                     [&](int64_t a, int64_t c) { return cbytes(a) > cbytes(c); });
   if (P->mr) {
     P->mrc.resize(P->chunks.size());
     for (size_t q = 0; q < P->chunk_order.size(); q++) {
@@ -449,6 +472,21 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
         P->vals_elems[c] += tiles * R.nkb[c] * kWave * vec_of(c);
         P->gidx_elems[c] += (int64_t)R.nkb[c] * mr_cb(c);
       }
+    }
+    std::vector<double> cost(P->mrc.size());
+    for (size_t q = 0; q < P->mrc.size(); q++) {
+      const MRChunk &R = P->mrc[q];
+      const double tiles = (R.h + kMRTile - 1) / kMRTile;
+      double c = 0.0;
+      for (int k = 0; k < NCLS; k++) c += R.nkb[k] * (tiles * kWave * 16.0 + mr_cb(k) * (kMRhs * 8.0 + 4.0));
+      cost[q] = c;
+    }
+    P->mr_split2 = xcd_split(cost);
+    for (int k = 0; k < NCLS; k++) {
+      std::vector<double> ci;
+      for (const MRItem &m : P->mri)
+        if (m.cls == k) ci.push_back(((m.nrows + kMRTile - 1) / kMRTile) * (double)m.nkb * kWave * 16.0 + m.ncols * kMRhs * 8.0);
+      P->mr_split1[k] = xcd_split(ci);
     }
   }
   if (!P->mr) P->rc.resize(P->chunks.size());
@@ -840,6 +878,8 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
     for (int c = 0; c < NCLS; c++)
       if (R.nkb[c]) h->cls_mask |= 1 << c;
   h->mr = P->mr;
+  h->mr_split2 = P->mr_split2;
+  for (int c = 0; c < NCLS; c++) h->mr_split1[c] = P->mr_split1[c];
   h->sys_off = P->sys_off;
   for (int c = 0; c < NCLS; c++) {
     h->mr_nitems[c] = h->mr_item_begin[c] = 0;
