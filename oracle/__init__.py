@@ -98,6 +98,8 @@ def _load():
         L.ora_jacobi_apply.argtypes = [P, I64, P, P]
         L.ora_bicgstab.restype = C.c_int
         L.ora_bicgstab.argtypes = [P, P, P, C.c_int, P, P, D, I64, P, P, P, P, P, P, P]
+        L.ora_bicgstab_refine.restype = C.c_int
+        L.ora_bicgstab_refine.argtypes = [P, P, P, C.c_int, P, P, D, D, I64, P, P, P, P, P, P, P]
         _lib = L
         return L
 
@@ -300,8 +302,10 @@ class Jacobi:
 
 
 def bicgstab(op: Converted, b, op64: Converted | None = None, x0=None, tol=1e-8, maxiter=1000,
-             literal=False, precond: Jacobi | None = None):
-    """BiCGSTAB (Algorithm 1) with the given operator; returns (x, info dict)."""
+             literal=False, precond: Jacobi | None = None, refine: float = 0.0):
+    """BiCGSTAB (Algorithm 1) with the given operator; returns (x, info dict).
+    refine > 0: also check the FP64 true residual whenever the recurrence
+    residual falls below refine x the last true one (restart if it fails)."""
     L = _load()
     b = _f64(b)
     n = b.size
@@ -314,10 +318,10 @@ def bicgstab(op: Converted, b, op64: Converted | None = None, x0=None, tol=1e-8,
     rr = C.c_double()
     tr = C.c_double()
     o64 = op64 if op64 is not None else op
-    st = L.ora_bicgstab(op._p, o64._p, precond._p if precond is not None else None,
-                        int(bool(literal)), _ptr(b), _ptr(x),
-                        float(tol), int(maxiter), C.byref(it), C.byref(nmv), C.byref(nmv64),
-                        _ptr(hist), _ptr(shist), C.byref(rr), C.byref(tr))
+    st = L.ora_bicgstab_refine(op._p, o64._p, precond._p if precond is not None else None,
+                               int(bool(literal)), _ptr(b), _ptr(x),
+                               float(tol), float(refine), int(maxiter), C.byref(it), C.byref(nmv), C.byref(nmv64),
+                               _ptr(hist), _ptr(shist), C.byref(rr), C.byref(tr))
     k = it.value
     return x, dict(status=st, iterations=k, matvecs=nmv.value, matvecs_fp64=nmv64.value,
                    history=hist[:k + 1].copy(), shistory=shist[:k + 1].copy(),

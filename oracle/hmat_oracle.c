@@ -985,10 +985,15 @@ static void ora_apply_op(const ora_opctx *o, const double *x, double *y)
     else ora_matvec(o->v, x, y);
 }
 
-int ora_bicgstab(const ora_conv *op, const ora_conv *op64, const ora_jacobi *K, int literal, const double *b,
-                 double *x, double tol, int64_t maxiter, int64_t *iters_out,
-                 int64_t *nmatvec_out, int64_t *nmatvec64_out, double *hist, double *shist, double *relres_out,
-                 double *truerel_out)
+/* BiCGSTAB with an optional early true-residual check (not in the paper):
+ * with refine > 0 the FP64 true residual is also taken whenever the
+ * recurrence residual has fallen below refine times the last true residual
+ * (|r_0| at the start); a check that does not meet tol restarts exactly as a
+ * failed convergence check does.  refine = 0 is ora_bicgstab. */
+int ora_bicgstab_refine(const ora_conv *op, const ora_conv *op64, const ora_jacobi *K, int literal, const double *b,
+                        double *x, double tol, double refine, int64_t maxiter, int64_t *iters_out,
+                        int64_t *nmatvec_out, int64_t *nmatvec64_out, double *hist, double *shist,
+                        double *relres_out, double *truerel_out)
 {
     int64_t n = op->n;
     ora_opctx oc = {op, literal}, oc64 = {op64, 0};
@@ -1004,7 +1009,7 @@ int ora_bicgstab(const ora_conv *op, const ora_conv *op64, const ora_jacobi *K, 
     int64_t nmv = 0, nmv64 = 0, it = 0;
     int status = 6;
     double bn = sqrt(ora_dot(n, b, b));
-    double rho = 0, rho_prev = 1, alpha = 1, omega = 1, relres = 0, truerel = 0;
+    double rho = 0, rho_prev = 1, alpha = 1, omega = 1, relres = 0, truerel = 0, rlast = 1;
     int restart = 1;
     if (bn == 0.0) {
         for (int64_t i = 0; i < n; i++) x[i] = 0.0;
@@ -1019,6 +1024,7 @@ int ora_bicgstab(const ora_conv *op, const ora_conv *op64, const ora_jacobi *K, 
     memcpy(rt, r, (size_t)n * sizeof(double));
     relres = sqrt(ora_dot(n, r, r)) / bn;
     if (hist) hist[0] = relres;
+    rlast = relres;
     for (it = 1; it <= maxiter; it++) {
         rho = ora_dot(n, rt, r);
         if (rho == 0.0) {
@@ -1069,7 +1075,7 @@ int ora_bicgstab(const ora_conv *op, const ora_conv *op64, const ora_jacobi *K, 
             for (int64_t i = 0; i < n; i++) x[i] += alpha * ph[i] + omega * sh[i];
             for (int64_t i = 0; i < n; i++) r[i] = s[i] - omega * t[i];
             relres = sqrt(ora_dot(n, r, r)) / bn;
-            conv = relres < tol;
+            conv = relres < tol || (refine > 0.0 && relres < refine * rlast);
         }
         rho_prev = rho;
         if (hist) hist[it] = relres;
@@ -1087,6 +1093,7 @@ int ora_bicgstab(const ora_conv *op, const ora_conv *op64, const ora_jacobi *K, 
             memcpy(r, tmp, (size_t)n * sizeof(double));
             memcpy(rt, tmp, (size_t)n * sizeof(double));
             relres = truerel;
+            rlast = truerel;
             restart = 1;
         }
     }
@@ -1115,4 +1122,13 @@ done:
     free(t);
     free(tmp);
     return status;
+}
+
+int ora_bicgstab(const ora_conv *op, const ora_conv *op64, const ora_jacobi *K, int literal, const double *b,
+                 double *x, double tol, int64_t maxiter, int64_t *iters_out,
+                 int64_t *nmatvec_out, int64_t *nmatvec64_out, double *hist, double *shist, double *relres_out,
+                 double *truerel_out)
+{
+    return ora_bicgstab_refine(op, op64, K, literal, b, x, tol, 0.0, maxiter, iters_out, nmatvec_out, nmatvec64_out,
+                               hist, shist, relres_out, truerel_out);
 }

@@ -551,3 +551,41 @@ def test_preconditioned_solve_same_solution():
     x1, i1 = oracle.bicgstab(op, b, tol=1e-10, precond=oracle.Jacobi(h))
     assert i0["status"] == 0 and i1["status"] == 0
     assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) < 1e-8
+
+
+# --------------------------------------------------------------------------
+# early true-residual checks (solver option, not in the paper)
+
+def test_bicgstab_refine_dense_vs_direct():
+    """With refine > 0 the solve still meets |b - A x| < tol|b| for the FP64
+    operator and lands within kappa * tol of numpy's direct solution; the
+    extra checks show in the FP64 product count."""
+    rng = np.random.default_rng(11)
+    A = np.eye(60) * 4 + rng.standard_normal((60, 60)) * 0.3
+    h = oracle.HMatrix.from_blocks(60, [0], [60], [0], [60], [0], [0], [0], np.asfortranarray(A).ravel(order="F"))
+    op = oracle.Converted(h, oracle.M1_DOUBLE)
+    b = rng.standard_normal(60)
+    x0, i0 = oracle.bicgstab(op, b, tol=1e-12)
+    x1, i1 = oracle.bicgstab(op, b, tol=1e-12, refine=1e-2)
+    xs = np.linalg.solve(A, b)
+    kappa = np.linalg.cond(A)
+    for x, info in ((x0, i0), (x1, i1)):
+        assert info["status"] == 0
+        assert np.linalg.norm(b - A @ x) / np.linalg.norm(b) < 1e-12
+        assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < kappa * 1e-12
+    assert i0["matvecs_fp64"] == 1 and i1["matvecs_fp64"] > 1
+
+
+def test_bicgstab_refine_restores_bf16_iterations():
+    """On the BF16 operator the early checks turn the long inner solves into
+    short refinement steps: fewer iterations, same true-residual guarantee."""
+    m, h = oracle_hmatrix("plates-32")
+    b = m.rhs()[h.perm]
+    op64 = oracle.Converted(h, oracle.M1_DOUBLE)
+    opb = oracle.Converted(h, oracle.BF16_SCALED)
+    xa, ia = oracle.bicgstab(opb, b, op64=op64, tol=1e-8, maxiter=500)
+    xb, ib = oracle.bicgstab(opb, b, op64=op64, tol=1e-8, maxiter=500, refine=1e-2)
+    assert ia["status"] == 0 and ib["status"] == 0
+    for x in (xa, xb):
+        assert np.linalg.norm(b - op64.matvec(x)) / np.linalg.norm(b) < 1e-8
+    assert ib["iterations"] < ia["iterations"]
