@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-matvecs", type=int, default=5)
+    ap.add_argument("--refine", type=float, default=None,
+                    help="early FP64 true-residual check ratio (default 1e-2 for BF16-scaled, else 0)")
     ap.add_argument("--train-leaves", type=int, default=20000)
     ap.add_argument("--epochs", type=int, default=30)
     args = ap.parse_args()
@@ -112,6 +114,8 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     variant = hmat.PRECISION_NAMES.index(args.variant)
+    if args.refine is None:
+        args.refine = 1e-2 if variant == hmat.BF16_SCALED else 0.0
     W = WORKLOADS[args.workload]
     if "nsys" in W:
         return bench_batched(args, W, variant, dev, stream)
@@ -136,7 +140,7 @@ def main():
     def solve(H, tol, x=None):
         x = torch.zeros(n, dtype=torch.float64, device=dev) if x is None else x.zero_()
         return hmat.hmat_bicgstab(H, b, x=x, h_fp64=H64, tol=tol, maxiter=2000, poll_every=args.poll_every,
-                                  work=work)
+                                  work=work, refine=args.refine if H is Hm else 0.0)
 
     # reference solution: FP64 to 1e-12
     xref, iref = solve(H64, 1e-12)
@@ -250,6 +254,7 @@ def main():
             "storage": "fp32 matrix, fp64 D_m / x / y / Krylov",
             "n": n,
             "step": "one BiCGSTAB solve x0=0 -> |r|/|b|<1e-8 confirmed by the FP64 true residual",
+            "refine": args.refine,
             "parallelism": "1 GPU",
         },
         "time_to_tol_ms": {"mixed": round(ms_per_step, 3), "fp64": round(1e3 * t_fp64 / args.steps, 3)},

@@ -230,6 +230,8 @@ typedef struct {
     int32_t use_graph;        /* 1: capture one iteration in a HIP graph and replay it */
     hmat_precond_t precond;   /* NULL: no preconditioner */
     double *history;          /* host, maxiter + 1 entries, or NULL: |r_i|/|b| per iteration */
+    double refine;            /* 0, or also check the FP64 true residual whenever |r|/|b| < refine x the
+                                 last true residual; a failed check restarts (not in the paper) */
 } hmat_solve_opts;
 
 typedef struct {

@@ -32,6 +32,7 @@ constexpr int kThreads = 256;
 struct SolverState {
   double rho, rho_prev, alpha, omega;
   double bnorm, relres, tol;
+  double refine, rlast;  // early true-residual check: relres < refine * rlast (last true residual)
   int32_t flag;     // 0 running, 1 recurrence converged, 2 breakdown, 3 non-finite
   int32_t restart;  // next iteration starts with p = r
   int64_t iter;
@@ -145,6 +146,7 @@ __global__ void k_start(SolverState *st, const double *__restrict__ part, int fi
     if (first) st->bnorm = sqrt(s[2]);
     st->rho = s[0];
     st->relres = st->bnorm > 0 ? sqrt(s[1]) / st->bnorm : 0.0;
+    st->rlast = st->relres;  // r is b - A x here: the last true residual
     st->restart = 1;
     st->flag = (s[0] == 0.0 && st->bnorm > 0) ? 2 : 0;
     if (!isfinite(s[0])) st->flag = 3;
@@ -298,16 +300,17 @@ __global__ void k_finalize(SolverState *__restrict__ st, const double *__restric
     st->relres = sqrt(q[1]) / st->bnorm;
     st->restart = 0;
     if (!isfinite(st->relres)) st->flag = 3;
-    else if (st->relres < st->tol) st->flag = 1;
+    else if (st->relres < st->tol || (st->refine > 0.0 && st->relres < st->refine * st->rlast)) st->flag = 1;
     else if (q[0] == 0.0) st->flag = 2;
   }
   if (st->iter <= kHistMax) hist[st->iter] = st->relres;
 }
 
-__global__ void k_init_state(SolverState *st, double tol, int64_t maxiter) {
+__global__ void k_init_state(SolverState *st, double tol, int64_t maxiter, double refine) {
   if (threadIdx.x == 0) {
     memset(st, 0, sizeof(SolverState));
     st->tol = tol;
+    st->refine = refine;
     st->maxiter = maxiter;
     st->rho_prev = 1.0;
     st->alpha = 1.0;
@@ -627,7 +630,8 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
   if (!h_fp64) h_fp64 = h_iter;
   const int64_t n = h_iter->n;
   if (h_fp64->n != n) return fail(HMAT_E_ARG, "operators differ in order");
-  if (!(o->tol > 0) || o->maxiter < 0 || o->poll_every < 1) return fail(HMAT_E_ARG, "bad solver options");
+  if (!(o->tol > 0) || o->maxiter < 0 || o->poll_every < 1 || !(o->refine >= 0.0 && o->refine < 1.0))
+    return fail(HMAT_E_ARG, "bad solver options");
   if (o->precond && o->precond->n != n) return fail(HMAT_E_ARG, "preconditioner order differs");
   if (((uintptr_t)work & 255u) || work_bytes < hm::work_bytes(n))
     return fail(HMAT_E_WORKSPACE, "solver workspace too small or misaligned (%llu needed)",
@@ -660,7 +664,7 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
     return e;
   };
 
-  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, st, w.st, o->tol, o->maxiter);
+  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, st, w.st, o->tol, o->maxiter, o->refine);
   // r0 = b - A x0 (Algorithm 1)
   if ((rc = mv(h_iter, x, w.tmp))) return rc;
   hipLaunchKernelGGL(k_residual, G, B, 0, st, n, b, w.tmp, w.r, w.rt, w.part, 1);
@@ -695,7 +699,8 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
       continue;
     }
     if (hs.flag == 1) {
-      // convergence of the recurrence: confirm with the FP64 true residual
+      // convergence of the recurrence (or an early check, opts->refine):
+      // confirm with the FP64 true residual
       if ((rc = mv(h_fp64, x, w.tmp))) return rc;
       hipLaunchKernelGGL(k_residual, G, B, 0, st, n, b, w.tmp, w.t, w.rt, w.part, 0);
       hipLaunchKernelGGL(k_true_norm, dim3(1), B, 0, st, w.st, w.part, true_slot);

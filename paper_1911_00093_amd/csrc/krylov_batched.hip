@@ -42,6 +42,7 @@ struct BTile {
 // 2 breakdown, 3 non-finite, 5 done
 struct BState {
   double rho, rho_prev, alpha, omega, bnorm, relres, snorm, truerel;
+  double rlast;  // last true residual (early checks: relres < refine * rlast)
   int32_t flag;
   int32_t restart;  // next iteration starts with p = r
   int32_t mode;     // last step: 0 breakdown, 1 converged on |s|, 2 full step
@@ -172,6 +173,7 @@ __global__ void kb_start(int nsys, int nrhs, const int32_t *__restrict__ sys_tb,
   }
   S.rho = rr;  // r~ = r
   S.relres = S.bnorm > 0 ? sqrt(rr) / S.bnorm : 0.0;
+  S.rlast = S.relres;  // r is b - A x here
   S.restart = 1;
   if (S.bnorm == 0.0) S.flag = 5;  // b = 0: x = 0
   else if (!isfinite(rr)) S.flag = 3;
@@ -332,7 +334,7 @@ __global__ __launch_bounds__(kBThreads) void kb_xupdate(int64_t n, int nrhs, con
 
 // One thread per recurrence: end of an iteration.
 __global__ void kb_finalize(int nsys, int nrhs, const int32_t *__restrict__ sys_tb, BState *__restrict__ st,
-                            const double *__restrict__ bank, double tol) {
+                            const double *__restrict__ bank, double tol, double refine) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= nsys * nrhs) return;
   const int sy = id / nrhs, k = id % nrhs;
@@ -355,7 +357,7 @@ __global__ void kb_finalize(int nsys, int nrhs, const int32_t *__restrict__ sys_
   S.rho = rtr;
   S.relres = sqrt(rr) / S.bnorm;
   if (!isfinite(S.relres)) S.flag = 3;
-  else if (S.relres < tol) S.flag = 1;
+  else if (S.relres < tol || (refine > 0.0 && S.relres < refine * S.rlast)) S.flag = 1;
   else if (rtr == 0.0) S.flag = 2;
 }
 
@@ -440,7 +442,8 @@ int hmat_bicgstab_batched(hmat_t h_iter, hmat_t h_fp64, const double *b, double 
     return fail(HMAT_E_ARG, "nrhs %lld outside [1, min(16, nrhs_max)]", (long long)nrhs);
   if (h_fp64->n != h_iter->n || h_fp64->sys_off != h_iter->sys_off || h_iter->sys_off.size() < 2)
     return fail(HMAT_E_ARG, "the two operators differ in size or systems");
-  if (!(o->tol > 0) || o->maxiter < 0 || o->poll_every < 1) return fail(HMAT_E_ARG, "bad solver options");
+  if (!(o->tol > 0) || o->maxiter < 0 || o->poll_every < 1 || !(o->refine >= 0.0 && o->refine < 1.0))
+    return fail(HMAT_E_ARG, "bad solver options");
   if (o->precond || o->history) return fail(HMAT_E_ARG, "the batched solver takes no preconditioner or history");
   const int64_t n = h_iter->n, nsys = (int64_t)h_iter->sys_off.size() - 1, R = nsys * nrhs;
   std::vector<BTile> tiles;
@@ -478,7 +481,7 @@ int hmat_bicgstab_batched(hmat_t h_iter, hmat_t h_fp64, const double *b, double 
     hipLaunchKernelGGL(kb_dot_t, GT, B, 0, s2, n, nr, w.tiles, w.st, w.t, w.s, w.part);
     hipLaunchKernelGGL(kb_xupdate, GT, B, 0, s2, n, nr, w.tiles, w.st, x, w.r, w.rt, w.p, w.s, w.t, w.part, w.bank,
                        o->tol);
-    hipLaunchKernelGGL(kb_finalize, GR, BR, 0, s2, ns, nr, w.sys_tb, w.st, w.bank, o->tol);
+    hipLaunchKernelGGL(kb_finalize, GR, BR, 0, s2, ns, nr, w.sys_tb, w.st, w.bank, o->tol, o->refine);
     return HMAT_OK;
   };
 

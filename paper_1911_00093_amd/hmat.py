@@ -75,7 +75,7 @@ class hmat_stats(C.Structure):
 
 class hmat_solve_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("maxiter", C.c_int64), ("poll_every", C.c_int32), ("use_graph", C.c_int32),
-                ("precond", C.c_void_p), ("history", C.c_void_p)]
+                ("precond", C.c_void_p), ("history", C.c_void_p), ("refine", C.c_double)]
 
 
 class hmat_solve_info(C.Structure):
@@ -466,7 +466,7 @@ def hmat_solver_workspace_bytes(n: int) -> int:
 
 def hmat_bicgstab(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = None, tol=1e-8, maxiter=1000, poll_every=1,
                   use_graph=False, precond: Precond | None = None, history=False, work=None, stream=None,
-                  raise_on_error=False):
+                  raise_on_error=False, refine=0.0):
     """BiCGSTAB (Algorithm 1) on the device; returns (x, info dict)."""
     import torch
 
@@ -477,7 +477,8 @@ def hmat_bicgstab(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = None, tol
         work = torch.empty(wb, dtype=torch.uint8, device=b.device)
     hist = np.full(maxiter + 1, np.nan) if history else None
     o = hmat_solve_opts(float(tol), int(maxiter), int(poll_every), int(bool(use_graph)),
-                        precond.p if precond is not None else None, _p(hist) if hist is not None else None)
+                        precond.p if precond is not None else None, _p(hist) if hist is not None else None,
+                        float(refine))
     info = hmat_solve_info()
     rc = lib().hmat_bicgstab(h_iter.h, (h_fp64 or h_iter).h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
                              C.byref(o), C.byref(info), C.c_void_p(work.data_ptr()), work.numel(), _stream_ptr(stream))
@@ -495,7 +496,7 @@ def hmat_bicgstab_batched_workspace_bytes(h: HMatrix, nrhs: int) -> int:
 
 
 def hmat_bicgstab_batched(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = None, tol=1e-8, maxiter=1000,
-                          poll_every=1, use_graph=True, work=None, stream=None, raise_on_error=False):
+                          poll_every=1, use_graph=True, work=None, stream=None, raise_on_error=False, refine=0.0):
     """BiCGSTAB on every system of a batched handle for every column of b at
     once.  b: device FP64 (n, nrhs), column-major (b.T contiguous).  Returns
     (x, summary dict, per-recurrence dict of arrays of shape (nsys, nrhs))."""
@@ -516,7 +517,7 @@ def hmat_bicgstab_batched(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = N
         work = torch.empty(wb, dtype=torch.uint8, device=b.device)
     nsys = h_iter.system_offsets().size - 1
     res = (hmat_batch_result * (nsys * nrhs))()
-    o = hmat_solve_opts(float(tol), int(maxiter), int(poll_every), int(bool(use_graph)), None, None)
+    o = hmat_solve_opts(float(tol), int(maxiter), int(poll_every), int(bool(use_graph)), None, None, float(refine))
     info = hmat_solve_info()
     rc = lib().hmat_bicgstab_batched(h_iter.h, (h_fp64 or h_iter).h, C.c_void_p(b.data_ptr()),
                                      C.c_void_p(x.data_ptr()), int(nrhs), C.byref(o), res, C.byref(info),

@@ -183,3 +183,27 @@ def test_batched_edges():
     with pytest.raises(hmat.HmatError) as e:
         hmat.hmat_bicgstab_batched(Hi, to_cols(B), h_fp64=other)
     assert e.value.code == hmat.HMAT_E_ARG
+
+
+def test_batched_refine_bf16():
+    """The batched solver's early checks: every recurrence converges, the
+    true residual meets tol, and iteration counts follow the oracle's solve
+    with the same policy."""
+    need_gpu()
+    sysl = systems()
+    Hi, H64 = handles(sysl, oracle.BF16_SCALED, 16)
+    off = Hi.system_offsets()
+    B = rhs_columns(sysl, 3, seed=13)
+    X, summ, per = hmat.hmat_bicgstab_batched(Hi, to_cols(B), h_fp64=H64, tol=1e-8, maxiter=600, refine=1e-2)
+    X = X.cpu().numpy().T
+    assert summ["status"] == 0, per
+    for s, (m, h) in enumerate(sysl):
+        op64 = oracle.Converted(h, oracle.M1_DOUBLE)
+        for k in range(3):
+            b = B[k, off[s]:off[s + 1]]
+            xo, io = oracle.bicgstab(oracle.Converted(h, oracle.BF16_SCALED, 1), b, op64=op64, tol=1e-8,
+                                     maxiter=600, refine=1e-2)
+            assert io["status"] == 0
+            assert np.linalg.norm(b - op64.matvec(X[k, off[s]:off[s + 1]])) / np.linalg.norm(b) < 1e-8 * 1.001
+            it, ito = per["iterations"][s, k], io["iterations"]
+            assert abs(it - ito) <= max(8, ito // 3), (KEYS[s], k, it, ito)

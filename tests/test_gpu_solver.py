@@ -149,3 +149,29 @@ def test_jacobi_apply_and_preconditioned_solve():
     a, c = x0.cpu().numpy(), x1.cpu().numpy()
     assert np.linalg.norm(a - c) / np.linalg.norm(a) < 1e-7
     print(f"iterations: none {i0['iterations']}, block-Jacobi {i1['iterations']}")
+
+
+def test_bicgstab_refine_bf16_matches_oracle():
+    """Early FP64 true-residual checks (refine) on the BF16 operator: the
+    GPU solve converges with the oracle's policy in about as many
+    iterations, and in fewer than without the checks."""
+    need_gpu()
+    m, h = oracle_hmatrix("plates-32")
+    b = m.rhs()[h.perm]
+    bs = blockset(h)
+    H64 = hmat.HMatrix(bs, oracle.M1_DOUBLE)
+    Hb = hmat.HMatrix(bs, oracle.BF16_SCALED)
+    x0, i0 = hmat.hmat_bicgstab(Hb, to_dev(b), h_fp64=H64, tol=1e-8, maxiter=500)
+    x1, i1 = hmat.hmat_bicgstab(Hb, to_dev(b), h_fp64=H64, tol=1e-8, maxiter=500, refine=1e-2)
+    op64 = oracle.Converted(h, oracle.M1_DOUBLE)
+    xo, io = oracle.bicgstab(oracle.Converted(h, oracle.BF16_SCALED), b, op64=op64, tol=1e-8, maxiter=500,
+                             refine=1e-2)
+    assert i0["status"] == 0 and i1["status"] == 0 and io["status"] == 0
+    x = x1.cpu().numpy()
+    assert np.linalg.norm(b - op64.matvec(x)) / np.linalg.norm(b) < 1e-8
+    assert abs(i1["iterations"] - io["iterations"]) <= max(6, io["iterations"] // 4)
+    assert i1["iterations"] < i0["iterations"]
+    print(f"BF16 iterations: plain {i0['iterations']} ({i0['restarts']} restarts), refine {i1['iterations']} "
+          f"({i1['restarts']} restarts), oracle refine {io['iterations']}")
+    with pytest.raises(hmat.HmatError):
+        hmat.hmat_bicgstab(Hb, to_dev(b), h_fp64=H64, refine=1.5, raise_on_error=True)
