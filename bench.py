@@ -318,6 +318,14 @@ def bench_batched(args, W, variant, dev, stream):
     Hm = hmat.HMatrix(bss, variant, c=-1, nrhs_max=nrhs)
     H64 = hmat.HMatrix(bss, hmat.M1_DOUBLE, nrhs_max=nrhs)
     log(f"[setup] batched builds {time.time() - t0:.1f}s")
+    t0 = time.time()
+    tune = {"fixed_ms": {}, "tuned_ms": {}, "choice": {}}
+    for name, H in (("M1-Double", H64), (args.variant, Hm)):
+        info = H.autotune(reps=5)
+        tune["fixed_ms"][name] = round(info["ms_fixed"], 4)
+        tune["tuned_ms"][name] = round(info["ms_tuned"], 4)
+        tune["choice"][name] = {k: info[k] for k in ("stage1_batch", "stage1_half", "stage2_batch", "stage2_half")}
+    log(f"[setup] autotune {time.time() - t0:.1f}s: {tune}")
     stm, st64 = Hm.stats(), H64.stats()
     Bm, Bm2 = mr_product_bytes(stm, nrhs, variant)
     B64, _ = mr_product_bytes(st64, nrhs, hmat.M1_DOUBLE)
@@ -417,6 +425,7 @@ def bench_batched(args, W, variant, dev, stream):
         "max_true_rel_res": {"mixed": float(per["true_rel_res"].max()), "fp64": float(per64["true_rel_res"].max())},
         "bytes_per_product": {"mixed": int(Bm), "fp64": int(B64)},
         "matvec_only": matvec,
+        "autotune": tune,
         "kernel_ms": {"stage1": round(k[0], 4), "stage1_reduce": round(k[1], 4), "stage2": round(k[2], 4)},
         "roofline": {
             "bound": "hbm",

@@ -152,6 +152,24 @@ int hmat_build(const hmat_blocks *blocks, const hmat_build_opts *opts, void *dev
  * order differs. */
 int hmat_matvec(hmat_t h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream);
 
+/* Tuning of a multi-right-hand-side handle (nrhs_max > 1; not from the
+ * paper): for each stage-1 storage class and for stage 2, times every
+ * choice of column blocks loaded per batch (1, 2, 4) and persistent grid
+ * (full or half occupancy) on this handle's own blocks, and keeps the
+ * fastest for later products.  x: device, n x min(16, nrhs_max) FP64
+ * column-major (ld = n), the timing input; y (same shape) receives products.
+ * reps: timed launches per choice (1 .. 1000).  Results are unchanged by the
+ * choice (same arithmetic, same summation order).  Synchronises `stream`. */
+typedef struct {
+    int32_t stage1_batch[3];  /* per storage class FP64 / FP32 / BF16 (0: no items) */
+    int32_t stage1_half[3];   /* 1: half-occupancy grid */
+    int32_t stage2_batch, stage2_half;
+    double ms_fixed;          /* one product with the default choice (batch 2, full grid) */
+    double ms_tuned;          /* one product with the chosen configuration */
+} hmat_tune_info;
+
+int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps, hmat_tune_info *info, void *stream);
+
 /* Independent systems batched into one handle (not from the paper): system
  * k (a full H-matrix of order n_k, blocks as in hmat_blocks) occupies the
  * index range [off_k, off_k + n_k) of a block-diagonal operator, off_0 = 0,

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 
 #include "hmat_impl.h"
 
@@ -32,7 +33,7 @@ typedef unsigned int mr_raw __attribute__((ext_vector_type(4)));
 constexpr int kMRThreads = 256;  // 4 independent waves
 constexpr int kMRWaves = kMRThreads / kWave;
 constexpr int kMRMaxTiles = kRowChunk / kMRTile;  // 4
-constexpr int kMRBatch = 2;      // column blocks loaded before use
+constexpr int kMRBatchDefault = 2;  // column blocks loaded before use (hmat_autotune picks 1, 2 or 4)
 
 // value v of a 16-byte load, widened exactly to FP64
 template <int CLS>
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(256) void k_mr_prologue(int64_t n, int64_t nrhs, co
 
 // ----------------------------------------------------------------- K1
 // One item with NT row tiles (straight-line code per NT).
-template <int CLS, int NT>
+template <int CLS, int NT, int NB>
 __device__ __forceinline__ void mr_s1_item(const MRItem &it, const void *vals, int64_t n, int z32,
                                            const double *dscale, double *s64, double *zpart, int lane) {
   constexpr int VEC = vec_of(CLS), CB = mr_cb(CLS);
@@ -86,11 +87,11 @@ __device__ __forceinline__ void mr_s1_item(const MRItem &it, const void *vals, i
   v4d c[NT];
 #pragma unroll
   for (int t = 0; t < NT; t++) c[t] = v4d{0, 0, 0, 0};
-  for (int kb0 = 0; kb0 < it.nkb; kb0 += kMRBatch) {
-    mr_raw a[NT][kMRBatch];
-    double b[kMRBatch][VEC];
+  for (int kb0 = 0; kb0 < it.nkb; kb0 += NB) {
+    mr_raw a[NT][NB];
+    double b[NB][VEC];
 #pragma unroll
-    for (int j = 0; j < kMRBatch; j++) {
+    for (int j = 0; j < NB; j++) {
       const int kb = min(kb0 + j, it.nkb - 1);  // past the end: re-read, not used
 #pragma unroll
       for (int t = 0; t < NT; t++)
@@ -104,7 +105,7 @@ __device__ __forceinline__ void mr_s1_item(const MRItem &it, const void *vals, i
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int j = 0; j < kMRBatch; j++) {
+    for (int j = 0; j < NB; j++) {
       if (kb0 + j >= it.nkb) break;  // uniform
 #pragma unroll
       for (int v = 0; v < VEC; v++)
@@ -129,7 +130,7 @@ __device__ __forceinline__ void mr_s1_item(const MRItem &it, const void *vals, i
     }
 }
 
-template <int CLS>
+template <int CLS, int NB>
 __global__ __launch_bounds__(kMRThreads) void k_mr_stage1(const MRItem *__restrict__ items, XcdSplit sp,
                                                           const void *__restrict__ vals, int64_t n, int z32,
                                                           const double *__restrict__ dscale,
@@ -138,10 +139,10 @@ __global__ __launch_bounds__(kMRThreads) void k_mr_stage1(const MRItem *__restri
   XCD_UNIT_LOOP(q, sp) {
     const MRItem it = items[q];
     switch ((it.nrows + kMRTile - 1) / kMRTile) {
-      case 1: mr_s1_item<CLS, 1>(it, vals, n, z32, dscale, s64, zpart, lane); break;
-      case 2: mr_s1_item<CLS, 2>(it, vals, n, z32, dscale, s64, zpart, lane); break;
-      case 3: mr_s1_item<CLS, 3>(it, vals, n, z32, dscale, s64, zpart, lane); break;
-      default: mr_s1_item<CLS, 4>(it, vals, n, z32, dscale, s64, zpart, lane); break;
+      case 1: mr_s1_item<CLS, 1, NB>(it, vals, n, z32, dscale, s64, zpart, lane); break;
+      case 2: mr_s1_item<CLS, 2, NB>(it, vals, n, z32, dscale, s64, zpart, lane); break;
+      case 3: mr_s1_item<CLS, 3, NB>(it, vals, n, z32, dscale, s64, zpart, lane); break;
+      default: mr_s1_item<CLS, 4, NB>(it, vals, n, z32, dscale, s64, zpart, lane); break;
     }
   }
 }
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(256) void k_mr_stage1b(int64_t n, int64_t zlen, int
 
 // ----------------------------------------------------------------- K2
 // One storage class of a chunk: the wave accumulates its NT row tiles.
-template <int CLS, int NT>
+template <int CLS, int NT, int NB>
 __device__ __forceinline__ void mr_s2_class(const MRChunk &ch, const void *vals, const int32_t *gidx,
                                             const double *s64, int lane, v4d (&c)[NT]) {
   constexpr int VEC = vec_of(CLS), CB = mr_cb(CLS);
@@ -177,11 +178,11 @@ __device__ __forceinline__ void mr_s2_class(const MRChunk &ch, const void *vals,
   const char *abase = (const char *)vals + ch.panel_off[CLS] * bytes_of(CLS) + (int64_t)lane * VEC * bytes_of(CLS);
   // gather indices of a column block: lane group kq's VEC columns are contiguous
   const int32_t *gi = gidx + ch.gidx_off[CLS] + kq * VEC;
-  for (int kb0 = 0; kb0 < nkb; kb0 += kMRBatch) {
-    mr_raw a[NT][kMRBatch];
-    int32_t g[kMRBatch][VEC];
+  for (int kb0 = 0; kb0 < nkb; kb0 += NB) {
+    mr_raw a[NT][NB];
+    int32_t g[NB][VEC];
 #pragma unroll
-    for (int j = 0; j < kMRBatch; j++) {
+    for (int j = 0; j < NB; j++) {
       const int kb = min(kb0 + j, nkb - 1);  // past the end: re-read, not used
 #pragma unroll
       for (int t = 0; t < NT; t++)
@@ -190,14 +191,14 @@ __device__ __forceinline__ void mr_s2_class(const MRChunk &ch, const void *vals,
 #pragma unroll
       for (int v = 0; v < VEC; v++) g[j][v] = gi[kb * CB + v];
     }
-    double b[kMRBatch][VEC];
+    double b[NB][VEC];
 #pragma unroll
-    for (int j = 0; j < kMRBatch; j++)
+    for (int j = 0; j < NB; j++)
 #pragma unroll
       for (int v = 0; v < VEC; v++) b[j][v] = s64[(int64_t)g[j][v] * kMRhs + rj];
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int j = 0; j < kMRBatch; j++) {
+    for (int j = 0; j < NB; j++) {
       if (kb0 + j >= nkb) break;  // uniform
 #pragma unroll
       for (int v = 0; v < VEC; v++)
@@ -208,7 +209,7 @@ __device__ __forceinline__ void mr_s2_class(const MRChunk &ch, const void *vals,
   }
 }
 
-template <int MASK, int NT>
+template <int MASK, int NT, int NB>
 __device__ __forceinline__ void mr_s2_chunk(const MRChunk &ch, const double *v64, const float *v32,
                                             const unsigned short *v16, const int32_t *g64, const int32_t *g32,
                                             const int32_t *g16, const double *s64, double *y, int64_t ldy,
@@ -216,9 +217,9 @@ __device__ __forceinline__ void mr_s2_chunk(const MRChunk &ch, const double *v64
   v4d c[NT];
 #pragma unroll
   for (int t = 0; t < NT; t++) c[t] = v4d{0, 0, 0, 0};
-  if constexpr ((MASK & 1) != 0) mr_s2_class<F64, NT>(ch, v64, g64, s64, lane, c);
-  if constexpr ((MASK & 2) != 0) mr_s2_class<F32, NT>(ch, v32, g32, s64, lane, c);
-  if constexpr ((MASK & 4) != 0) mr_s2_class<BF16, NT>(ch, v16, g16, s64, lane, c);
+  if constexpr ((MASK & 1) != 0) mr_s2_class<F64, NT, NB>(ch, v64, g64, s64, lane, c);
+  if constexpr ((MASK & 2) != 0) mr_s2_class<F32, NT, NB>(ch, v32, g32, s64, lane, c);
+  if constexpr ((MASK & 4) != 0) mr_s2_class<BF16, NT, NB>(ch, v16, g16, s64, lane, c);
   const int rj = lane % kMRhs;
   if (rj >= nrhs) return;
 #pragma unroll
@@ -230,7 +231,7 @@ __device__ __forceinline__ void mr_s2_chunk(const MRChunk &ch, const double *v64
     }
 }
 
-template <int MASK>
+template <int MASK, int NB>
 __global__ __launch_bounds__(kMRThreads) void k_mr_stage2(const MRChunk *__restrict__ chunks, XcdSplit sp,
                                                           const double *__restrict__ v64, const float *__restrict__ v32,
                                                           const unsigned short *__restrict__ v16,
@@ -242,10 +243,10 @@ __global__ __launch_bounds__(kMRThreads) void k_mr_stage2(const MRChunk *__restr
   XCD_UNIT_LOOP(q, sp) {
     const MRChunk ch = chunks[q];
     switch ((ch.h + kMRTile - 1) / kMRTile) {
-      case 1: mr_s2_chunk<MASK, 1>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
-      case 2: mr_s2_chunk<MASK, 2>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
-      case 3: mr_s2_chunk<MASK, 3>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
-      default: mr_s2_chunk<MASK, 4>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
+      case 1: mr_s2_chunk<MASK, 1, NB>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
+      case 2: mr_s2_chunk<MASK, 2, NB>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
+      case 3: mr_s2_chunk<MASK, 3, NB>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
+      default: mr_s2_chunk<MASK, 4, NB>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
     }
   }
 }
@@ -254,39 +255,46 @@ __global__ __launch_bounds__(kMRThreads) void k_mr_stage2(const MRChunk *__restr
 typedef void (*MRStage2Fn)(const MRChunk *, XcdSplit, const double *, const float *, const unsigned short *,
                            const int32_t *, const int32_t *, const int32_t *, const double *, double *, int64_t,
                            int64_t);
-static MRStage2Fn mr_stage2_fn(int mask) {
+template <int NB>
+static MRStage2Fn mr_stage2_nb(int mask) {
   switch (mask) {
-    case 1: return k_mr_stage2<1>;
-    case 2: return k_mr_stage2<2>;
-    case 3: return k_mr_stage2<3>;
-    case 4: return k_mr_stage2<4>;
-    case 5: return k_mr_stage2<5>;
-    case 6: return k_mr_stage2<6>;
-    default: return k_mr_stage2<7>;
+    case 1: return k_mr_stage2<1, NB>;
+    case 2: return k_mr_stage2<2, NB>;
+    case 3: return k_mr_stage2<3, NB>;
+    case 4: return k_mr_stage2<4, NB>;
+    case 5: return k_mr_stage2<5, NB>;
+    case 6: return k_mr_stage2<6, NB>;
+    default: return k_mr_stage2<7, NB>;
   }
 }
+static MRStage2Fn mr_stage2_fn(int mask, int nb) {
+  return nb == 1 ? mr_stage2_nb<1>(mask) : nb == 4 ? mr_stage2_nb<4>(mask) : mr_stage2_nb<2>(mask);
+}
 typedef void (*MRStage1Fn)(const MRItem *, XcdSplit, const void *, int64_t, int, const double *, double *, double *);
-static MRStage1Fn mr_stage1_fn(int cls) {
-  return cls == F64 ? k_mr_stage1<F64> : cls == F32 ? k_mr_stage1<F32> : k_mr_stage1<BF16>;
+template <int NB>
+static MRStage1Fn mr_stage1_nb(int cls) {
+  return cls == F64 ? k_mr_stage1<F64, NB> : cls == F32 ? k_mr_stage1<F32, NB> : k_mr_stage1<BF16, NB>;
+}
+static MRStage1Fn mr_stage1_fn(int cls, int nb) {
+  return nb == 1 ? mr_stage1_nb<1>(cls) : nb == 4 ? mr_stage1_nb<4>(cls) : mr_stage1_nb<2>(cls);
 }
 
 int size_grids_mr(hmat_s *h) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return fail(HMAT_E_HIP, "cannot query the device");
-  // a multiple of 8 workgroups, at least 8: every XCD range has workgroups
-  auto groups = [&](int64_t units, int per) {
-    const int64_t g = std::min<int64_t>((units + kMRWaves - 1) / kMRWaves, (int64_t)per * cus);
+  // a multiple of 8 workgroups, at least 8: every XCD range has workgroups;
+  // full occupancy, or half of it when the tuner found that faster
+  auto groups = [&](int64_t units, const void *fn, int half) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kMRThreads, 0) != hipSuccess || per < 1) per = 1;
+    const int64_t slots = std::max<int64_t>(1, (int64_t)per * cus / (half ? 2 : 1));
+    const int64_t g = std::min<int64_t>((units + kMRWaves - 1) / kMRWaves, slots);
     return (int32_t)std::max<int64_t>(kXcds, (g + kXcds - 1) / kXcds * kXcds);
   };
-  for (int c = 0; c < NCLS; c++) {
-    int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mr_stage1_fn(c), kMRThreads, 0) != hipSuccess || per < 1) per = 1;
-    h->mr_grid1[c] = groups(h->mr_nitems[c], per);
-  }
-  int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, mr_stage2_fn(h->cls_mask), kMRThreads, 0) != hipSuccess || per < 1) per = 1;
-  h->mr_grid2 = groups(h->nchunks, per);
+  for (int c = 0; c < NCLS; c++)
+    h->mr_grid1[c] = groups(h->mr_nitems[c], (const void *)mr_stage1_fn(c, h->mr_nb1[c]), h->mr_half1[c]);
+  h->mr_grid2 = groups(h->nchunks, (const void *)mr_stage2_fn(h->cls_mask, h->mr_nb2), h->mr_half2);
   return HMAT_OK;
 }
 
@@ -304,7 +312,7 @@ int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, 
     }
     for (int c = 0; c < NCLS; c++) {
       if (h->mr_nitems[c] <= 0) continue;
-      hipLaunchKernelGGL(mr_stage1_fn(c), dim3((unsigned)h->mr_grid1[c]), dim3(kMRThreads), 0, st,
+      hipLaunchKernelGGL(mr_stage1_fn(c, h->mr_nb1[c]), dim3((unsigned)h->mr_grid1[c]), dim3(kMRThreads), 0, st,
                          h->mri + h->mr_item_begin[c], h->mr_split1[c], (const void *)h->vals[c], h->n, h->z32,
                          h->dscale, h->src64, h->zpart);
     }
@@ -315,7 +323,8 @@ int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, 
                          h->zinfo, h->dscale, h->zpart, h->src64);
     }
     prof_mark(h, 2, stream);
-    hipLaunchKernelGGL(mr_stage2_fn(h->cls_mask), dim3((unsigned)h->mr_grid2), dim3(kMRThreads), 0, st, h->mrc,
+    hipLaunchKernelGGL(mr_stage2_fn(h->cls_mask, h->mr_nb2), dim3((unsigned)h->mr_grid2), dim3(kMRThreads), 0, st,
+                       h->mrc,
                        h->mr_split2, (const double *)h->vals[F64], (const float *)h->vals[F32],
                        (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16], h->src64,
                        yr, ld, nr);
@@ -326,4 +335,97 @@ int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, 
   return HMAT_OK;
 }
 
+// Mean duration in ms of `reps` runs of `launch` on `st` (HIP events).
+template <class F>
+static double time_ms(hipStream_t st, int reps, F launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1.0;
+  launch();  // warm
+  hipEventRecord(a, st);
+  for (int i = 0; i < reps; i++) launch();
+  hipEventRecord(b, st);
+  float ms = -1.0f;
+  if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) ms = -1.0f;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms < 0 ? -1.0 : (double)ms / reps;
+}
+
 }  // namespace hm
+
+extern "C" int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps, hmat_tune_info *info, void *stream) {
+  using namespace hm;
+  if (!h || !x || !y || !info) return fail(HMAT_E_ARG, "null argument");
+  if (!h->mr) return fail(HMAT_E_ARG, "autotuning applies to multi-right-hand-side handles (nrhs_max > 1)");
+  if (reps < 1 || reps > 1000) return fail(HMAT_E_ARG, "reps %d out of range", reps);
+  std::memset(info, 0, sizeof *info);
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = h->n, nr = std::min<int64_t>(kMRhs, h->nrhs_max);
+  Prof *saved = h->prof;  // the tuner's own events only
+  h->prof = nullptr;
+  auto product = [&]() { launch_matvec_mr(h, x, y, nr, n, st); };
+  info->ms_fixed = time_ms(st, reps, product);
+  const int nbs[3] = {1, 2, 4};
+  // stage 1, per storage class: inputs (x in src64) are in place after product()
+  for (int c = 0; c < NCLS; c++) {
+    info->stage1_batch[c] = 0;
+    if (h->mr_nitems[c] <= 0) continue;
+    double best = 1e300;
+    int bnb = 2, bhalf = 0;
+    for (int nb : nbs)
+      for (int half = 0; half < 2; half++) {
+        h->mr_nb1[c] = nb;
+        h->mr_half1[c] = half;
+        if (size_grids_mr(h) != HMAT_OK) break;
+        const double t = time_ms(st, reps, [&]() {
+          hipLaunchKernelGGL(mr_stage1_fn(c, nb), dim3((unsigned)h->mr_grid1[c]), dim3(kMRThreads), 0, st,
+                             h->mri + h->mr_item_begin[c], h->mr_split1[c], (const void *)h->vals[c], h->n, h->z32,
+                             h->dscale, h->src64, h->zpart);
+        });
+        if (t >= 0 && t < best) {
+          best = t;
+          bnb = nb;
+          bhalf = half;
+        }
+      }
+    h->mr_nb1[c] = bnb;
+    h->mr_half1[c] = bhalf;
+    info->stage1_batch[c] = bnb;
+    info->stage1_half[c] = bhalf;
+  }
+  // stage 2 (z complete after one product)
+  product();
+  {
+    double best = 1e300;
+    int bnb = 2, bhalf = 0;
+    for (int nb : nbs)
+      for (int half = 0; half < 2; half++) {
+        h->mr_nb2 = nb;
+        h->mr_half2 = half;
+        if (size_grids_mr(h) != HMAT_OK) break;
+        const double t = time_ms(st, reps, [&]() {
+          hipLaunchKernelGGL(mr_stage2_fn(h->cls_mask, nb), dim3((unsigned)h->mr_grid2), dim3(kMRThreads), 0, st,
+                             h->mrc, h->mr_split2, (const double *)h->vals[F64], (const float *)h->vals[F32],
+                             (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16],
+                             h->src64, y, n, nr);
+        });
+        if (t >= 0 && t < best) {
+          best = t;
+          bnb = nb;
+          bhalf = half;
+        }
+      }
+    h->mr_nb2 = bnb;
+    h->mr_half2 = bhalf;
+    info->stage2_batch = bnb;
+    info->stage2_half = bhalf;
+  }
+  int rc = size_grids_mr(h);
+  if (rc == HMAT_OK) info->ms_tuned = time_ms(st, reps, product);
+  h->prof = saved;
+  if (rc) return rc;
+  const hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(HMAT_E_HIP, "autotuning failed: %s", hipGetErrorString(e));
+  if (info->ms_fixed < 0 || info->ms_tuned < 0) return fail(HMAT_E_HIP, "event timing failed");
+  return HMAT_OK;
+}

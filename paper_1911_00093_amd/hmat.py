@@ -36,7 +36,7 @@ EXPORTED = [
     "hmat_stream_read", "hmat_stream_copy", "hmat_plan_batched", "hmat_build_batched", "hmat_system_offsets",
     "hmat_bicgstab_batched_workspace_bytes", "hmat_bicgstab_batched", "hmat_precond_create_learned",
     "hmat_precond_leaves", "hmat_leaf_features", "hmat_dense_inverse", "hmat_mlp_workspace_bytes",
-    "hmat_mlp_forward", "hmat_mlp_loss_grad", "hmat_mlp_adam",
+    "hmat_mlp_forward", "hmat_mlp_loss_grad", "hmat_mlp_adam", "hmat_autotune",
 ]
 
 
@@ -82,6 +82,11 @@ class hmat_solve_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("restarts", C.c_int32), ("iterations", C.c_int64),
                 ("matvecs", C.c_int64), ("matvecs_fp64", C.c_int64), ("rel_res", C.c_double),
                 ("true_rel_res", C.c_double)]
+
+
+class hmat_tune_info(C.Structure):
+    _fields_ = [("stage1_batch", C.c_int32 * 3), ("stage1_half", C.c_int32 * 3), ("stage2_batch", C.c_int32),
+                ("stage2_half", C.c_int32), ("ms_fixed", C.c_double), ("ms_tuned", C.c_double)]
 
 
 class hmat_batch_result(C.Structure):
@@ -141,6 +146,7 @@ def lib():
         "hmat_mlp_forward": (C.c_int, [P, P, I64, P, P, U64, P]),
         "hmat_mlp_loss_grad": (C.c_int, [P, P, P, P, P, P, I64, P, I64, P, P, P, U64, P]),
         "hmat_mlp_adam": (C.c_int, [P, P, P, P, I64, C.c_float, P]),
+        "hmat_autotune": (C.c_int, [P, P, P, I32, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -300,6 +306,20 @@ class HMatrix:
     def matvec(self, x, y=None, stream=None):
         """y = A~ x for a device FP64 tensor of shape (n,) or (n, nrhs) (column-major: x.T contiguous)."""
         return hmat_matvec(self, x, y, stream)
+
+    def autotune(self, reps=10, stream=None):
+        """Pick the multi-RHS launch configuration (hmat_autotune); returns a dict."""
+        import torch
+
+        nr = min(16, self.nrhs_max)
+        x = torch.randn((nr, self.n), dtype=torch.float64, device=self.buf.device).T
+        y = torch.empty_like(x)
+        info = hmat_tune_info()
+        _check(lib().hmat_autotune(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), int(reps),
+                                   C.byref(info), _stream_ptr(stream)))
+        return dict(stage1_batch=list(info.stage1_batch), stage1_half=list(info.stage1_half),
+                    stage2_batch=info.stage2_batch, stage2_half=info.stage2_half,
+                    ms_fixed=info.ms_fixed, ms_tuned=info.ms_tuned)
 
     def set_profiling(self, enable=True):
         _check(lib().hmat_set_profiling(self.h, int(bool(enable))))

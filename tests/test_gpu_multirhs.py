@@ -94,3 +94,22 @@ def test_batched_systems(variant, nrhs_max):
             yo = conv.matvec(xs)
             err = np.abs(Y[off[s]:off[s + 1], k] - yo).max() / abs_scale(h, xs).max()
             assert err <= tolerance(variant), (keys[s], k, err)
+
+
+def test_autotune_keeps_results():
+    """hmat_autotune changes only launch parameters: the product is the same
+    bit for bit before and after; single-vector handles are refused."""
+    need_gpu()
+    m, h = oracle_hmatrix("spheres-mixed")
+    H = hmat.HMatrix(blockset(h), oracle.M2_MIXED, nrhs_max=16)
+    X = np.random.default_rng(17).standard_normal((16, h.n))
+    Y0 = H.matvec(to_cols(X)).cpu().numpy()
+    info = H.autotune(reps=3)
+    print(info)
+    assert info["stage2_batch"] in (1, 2, 4) and info["ms_fixed"] > 0 and info["ms_tuned"] > 0
+    assert info["stage1_batch"][oracle.M1_DOUBLE] == 0  # no FP64 items in M2-Mixed
+    Y1 = H.matvec(to_cols(X)).cpu().numpy()
+    assert np.array_equal(Y0, Y1)
+    H1 = hmat.HMatrix(blockset(h), oracle.M2_MIXED)
+    with pytest.raises(hmat.HmatError):
+        H1.autotune()
