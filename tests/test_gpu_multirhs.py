@@ -113,3 +113,48 @@ def test_autotune_keeps_results():
     H1 = hmat.HMatrix(blockset(h), oracle.M2_MIXED)
     with pytest.raises(hmat.HmatError):
         H1.autotune()
+
+
+@pytest.mark.parametrize("n", [1, 15, 16, 17, 64, 65, 1000])
+def test_multirhs_single_dense_block_ragged(n):
+    """One dense block of order n (ragged row tiles and column blocks) on
+    the matrix cores, 16 and 5 right-hand sides."""
+    need_gpu()
+    rng = np.random.default_rng(n)
+    A = rng.standard_normal((n, n))
+    h = oracle.HMatrix.from_blocks(n, [0], [n], [0], [n], [0], [0], [0], np.asfortranarray(A).ravel(order="F"))
+    for variant in (oracle.M1_DOUBLE, oracle.M2_MIXED, oracle.BF16_SCALED):
+        H = hmat.HMatrix(blockset(h), variant, nrhs_max=16)
+        conv = oracle.Converted(h, variant)
+        for nr in (16, 5):
+            X = rng.standard_normal((nr, n))
+            Y = H.matvec(to_cols(X)).cpu().numpy()
+            for k in range(nr):
+                yo = conv.matvec(X[k])
+                assert np.abs(Y[:, k] - yo).max() <= tolerance(variant) * abs_scale(h, X[k]).max(), (variant, nr, k)
+
+
+@pytest.mark.parametrize("n,r", [(2, 1), (100, 7), (3000, 40), (5000, 0), (700, 70)])
+def test_multirhs_single_lowrank_block(n, r):
+    """An off-diagonal low-rank block between two dense diagonal blocks: the
+    z of a group up to 512 columns wide is finished in stage 1, wider groups
+    (3000 columns) go through the partial sums; rank 0 contributes nothing."""
+    need_gpu()
+    rng = np.random.default_rng(n + r)
+    m = n // 2
+    D1, D2 = rng.standard_normal((m, m)), rng.standard_normal((n - m, n - m))
+    V, W = rng.standard_normal((m, r)), rng.standard_normal((r, n - m))
+    V2, W2 = rng.standard_normal((n - m, r)), rng.standard_normal((r, m))
+    data = np.concatenate([D1.ravel(order="F"), V.ravel(order="F"), W.T.ravel(order="F"),
+                           V2.ravel(order="F"), W2.T.ravel(order="F"), D2.ravel(order="F")])
+    offs = np.cumsum([0, m * m, (m + n - m) * r, (n - m + m) * r])
+    h = oracle.HMatrix.from_blocks(n, [0, 0, m, m], [m, m, n - m, n - m], [0, m, 0, m], [m, n - m, m, n - m],
+                                   [0, 1, 1, 0], [0, r, r, 0], offs, data)
+    for variant in (oracle.M1_DOUBLE, oracle.M2_MIXED, oracle.M1_SINGLE):
+        H = hmat.HMatrix(blockset(h), variant, nrhs_max=16)
+        conv = oracle.Converted(h, variant)
+        X = rng.standard_normal((16, n))
+        Y = H.matvec(to_cols(X)).cpu().numpy()
+        for k in range(16):
+            yo = conv.matvec(X[k])
+            assert np.abs(Y[:, k] - yo).max() <= tolerance(variant) * abs_scale(h, X[k]).max(), (variant, k)
