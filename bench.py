@@ -95,7 +95,7 @@ def main():
     ap.add_argument("--refine", type=float, default=None,
                     help="early FP64 true-residual check ratio (default 1e-2 for BF16-scaled, else 0)")
     ap.add_argument("--train-leaves", type=int, default=20000)
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--epochs", type=int, default=100)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -458,7 +458,7 @@ def bench_learned(args, W, variant, dev, stream):
     dd = learned.to_device(data)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    net, hist = learned.train(dd, epochs=args.epochs, batch=256, lr=1e-3, seed=0)
+    net, hist = learned.train(dd, epochs=args.epochs, batch=256, seed=0)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"[train] {args.epochs} epochs in {t_train:.2f}s, loss {hist[0]:.4f} -> {hist[-1]:.4f}")
@@ -477,6 +477,7 @@ def bench_learned(args, W, variant, dev, stream):
     uv = learned.factors(net, mesh, bs)
     torch.cuda.synchronize()
     t_infer = time.perf_counter() - t0
+    eval_loss = learned.mean_loss(net, learned.to_device(learned.leaf_inputs(mesh, bs, with_inverse=True)))
     pre = {"none": None, "block-jacobi": hmat.Precond(bs, hmat.PRECOND_JACOBI),
            "learned": hmat.Precond(bs, hmat.PRECOND_LEARNED, uv=uv)}
     work = torch.empty(hmat.hmat_solver_workspace_bytes(n), dtype=torch.uint8, device=dev)
@@ -527,8 +528,9 @@ def bench_learned(args, W, variant, dev, stream):
         },
         "preconditioners": res,
         "training": {"leaves": int(data["m"].size), "meshes": int(data["meshes"]), "epochs": args.epochs,
-                     "batch": 256, "set_build_s": round(t_set, 2), "train_s": round(t_train, 3),
-                     "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "inference_s": round(t_infer, 4)},
+                     "batch": 256, "lr": "cosine 2e-3 -> 2e-4", "set_build_s": round(t_set, 2), "train_s": round(t_train, 3),
+                     "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1], "inference_s": round(t_infer, 4),
+                     "loss_on_evaluation_leaves": eval_loss},
         "speedup_learned_vs_none": round(res["none"]["ms"] / L["ms"], 3),
         "speedup_learned_vs_jacobi": round(res["block-jacobi"]["ms"] / L["ms"], 3),
     }

@@ -209,10 +209,11 @@ class BlockSet:
 class _Assembly:
     def __init__(self, ptr):
         self.ptr = ptr
+        self._free = lib().hmat_assembly_free  # kept: module globals may be gone at exit
 
     def __del__(self):
         if self.ptr:
-            lib().hmat_assembly_free(self.ptr)
+            self._free(self.ptr)
             self.ptr = None
 
 
@@ -285,6 +286,7 @@ class HMatrix:
             _check(lib().hmat_build(C.byref(s), C.byref(o), C.c_void_p(self.buf.data_ptr()), self.buf.numel(),
                                     _stream_ptr(stream), C.byref(h)))
         self.h = h
+        self._destroy = lib().hmat_destroy  # kept: module globals may be gone at exit
 
     def system_offsets(self) -> np.ndarray:
         cnt = C.c_int64()
@@ -295,7 +297,7 @@ class HMatrix:
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().hmat_destroy(self.h)
+            self._destroy(self.h)
             self.h = None
 
     def stats(self) -> hmat_stats:
@@ -381,10 +383,11 @@ class Precond:
                                              self.buf.numel(), _stream_ptr(stream), C.byref(p)))
         self.p = p
         self.n = blocks.n
+        self._destroy = lib().hmat_precond_destroy  # kept: module globals may be gone at exit
 
     def __del__(self):
         if getattr(self, "p", None):
-            lib().hmat_precond_destroy(self.p)
+            self._destroy(self.p)
             self.p = None
 
     def apply(self, x, y=None, stream=None):

@@ -10,8 +10,6 @@ parameters, batch order) come from `seeded`.
 
 from __future__ import annotations
 
-import time
-
 import numpy as np
 
 from . import hmat, meshes, seeded
@@ -72,23 +70,27 @@ def to_device(data, device="cuda"):
             for key in ("x", "dinv", "sinv", "m", "ainv")}
 
 
-def train(data_dev, params0=None, epochs: int = 30, batch: int = 256, lr: float = 1e-3, seed: int = 0,
-          log=None):
-    """Adam on the batch mean loss; returns the trained hmat.MLP and the
-    mean loss of every epoch (read once per epoch)."""
+def train(data_dev, params0=None, epochs: int = 100, batch: int = 256, lr: float = 2e-3, lr_final: float = 2e-4,
+          seed: int = 0, log=None):
+    """Adam on the batch mean loss with a cosine decay of the rate from lr
+    to lr_final; returns the trained hmat.MLP and the mean loss of every
+    epoch (read once per epoch)."""
+    import math
+
     import torch
 
     n = int(data_dev["m"].numel())
     net = hmat.MLP(seeded.init_params(seed) if params0 is None else params0, device=data_dev["x"].device)
     history = []
     steps_per_epoch = max(1, n // batch)
+    total = steps_per_epoch * epochs
     acc = torch.zeros(1, dtype=torch.float32, device=data_dev["x"].device)
     step = 0
     for idx in seeded.batch_order(n, batch, epochs, seed):
         idx_d = torch.as_tensor(idx).to(data_dev["x"].device)
         net.loss_grad(data_dev, idx_d)
         acc += net.loss
-        net.adam(lr)
+        net.adam(lr_final + (lr - lr_final) * 0.5 * (1.0 + math.cos(math.pi * step / total)))
         step += 1
         if step % steps_per_epoch == 0:
             history.append(float(acc.item()) / steps_per_epoch)
@@ -96,6 +98,19 @@ def train(data_dev, params0=None, epochs: int = 30, batch: int = 256, lr: float 
             if log:
                 log(f"[train] epoch {len(history)}: loss {history[-1]:.4f}")
     return net, history
+
+
+def mean_loss(net: hmat.MLP, data_dev, batch: int = 1024) -> float:
+    """Mean loss of the network over every sample of a device data set."""
+    import torch
+
+    n = int(data_dev["m"].numel())
+    tot = 0.0
+    for s in range(0, n, batch):
+        idx = torch.arange(s, min(n, s + batch), dtype=torch.int32, device=data_dev["x"].device)
+        net.loss_grad(data_dev, idx)
+        tot += float(net.loss.item()) * idx.numel()
+    return tot / n
 
 
 def factors(net: hmat.MLP, mesh, bs: hmat.BlockSet, chunk: int = 8192):
