@@ -652,10 +652,11 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
   double *ph = pre ? w.ph : w.p;
   double *sh = pre ? w.sh : w.s;
 
-  auto mv = [&](hmat_t h, const double *in, double *outv) {
+  // products outside the iteration: r_0 with h_iter, true residuals with h_fp64
+  auto mv = [&](hmat_t h, const double *in, double *outv, bool fp64) {
     int r2 = launch_matvec(h, in, outv, 1, n, st);
-    if (h == h_iter) nmv++;
-    else nmv64++;
+    if (fp64) nmv64++;
+    else nmv++;
     return r2;
   };
   auto poll = [&]() {
@@ -666,7 +667,7 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
 
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, st, w.st, o->tol, o->maxiter, o->refine);
   // r0 = b - A x0 (Algorithm 1)
-  if ((rc = mv(h_iter, x, w.tmp))) return rc;
+  if ((rc = mv(h_iter, x, w.tmp, false))) return rc;
   hipLaunchKernelGGL(k_residual, G, B, 0, st, n, b, w.tmp, w.r, w.rt, w.part, 1);
   hipLaunchKernelGGL(k_start, dim3(1), B, 0, st, w.st, w.part, 1);
   if (poll() != hipSuccess) return fail(HMAT_E_HIP, "solver start failed");
@@ -678,21 +679,62 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
     return HMAT_OK;
   }
   if (o->history) o->history[0] = hs.relres;
+  // one iteration of Algorithm 1 (K = precond, identity when none)
+  auto iteration = [&](hipStream_t s2) -> int {
+    hipLaunchKernelGGL(k_pupdate, G, B, 0, s2, n, w.st, w.r, w.p, w.v);
+    if (pre) hmat_precond_apply(o->precond, w.p, w.ph, s2);
+    int r2 = launch_matvec(h_iter, ph, w.v, 1, n, s2);
+    if (r2) return r2;
+    hipLaunchKernelGGL(k_dot_rtv, G, B, 0, s2, n, w.st, w.rt, w.v, w.part);
+    hipLaunchKernelGGL(k_supdate, G, B, 0, s2, n, w.st, w.r, w.v, w.s, w.part);
+    if (pre) hmat_precond_apply(o->precond, w.s, w.sh, s2);
+    if ((r2 = launch_matvec(h_iter, sh, w.t, 1, n, s2))) return r2;
+    hipLaunchKernelGGL(k_dot_t, G, B, 0, s2, n, w.st, w.t, w.s, w.part);
+    hipLaunchKernelGGL(k_xupdate, G, B, 0, s2, n, w.st, x, w.r, w.rt, ph, w.s, sh, w.t, w.part, bank);
+    hipLaunchKernelGGL(k_finalize, dim3(1), B, 0, s2, w.st, bank, w.hist);
+    return HMAT_OK;
+  };
+  // use_graph: the iteration captured once on an internal stream (default
+  // priority, no memset nodes) and replayed on `st`; kernel timing events
+  // are not recorded inside the graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap = nullptr;
+  struct GraphGuard {
+    hipGraph_t &g;
+    hipGraphExec_t &e;
+    hipStream_t &c;
+    ~GraphGuard() {
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
+      if (c) (void)hipStreamDestroy(c);
+    }
+  } guard{graph, gexec, cap};
+  if (o->use_graph) {
+    Prof *saved = h_iter->prof;
+    h_iter->prof = nullptr;
+    hipError_t e = hipStreamCreate(&cap);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      rc = iteration(cap);
+      e = hipStreamEndCapture(cap, &graph);
+      if (!rc && e == hipSuccess) e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+    }
+    h_iter->prof = saved;
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(HMAT_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  }
   int64_t launched = 0;
   for (;;) {
     if (hs.flag == 0 && launched < o->maxiter) {
       const int64_t todo = std::min<int64_t>(o->poll_every, o->maxiter - launched);
       for (int64_t q = 0; q < todo; q++) {
-        hipLaunchKernelGGL(k_pupdate, G, B, 0, st, n, w.st, w.r, w.p, w.v);
-        if (pre) hmat_precond_apply(o->precond, w.p, w.ph, st);
-        if ((rc = mv(h_iter, ph, w.v))) return rc;
-        hipLaunchKernelGGL(k_dot_rtv, G, B, 0, st, n, w.st, w.rt, w.v, w.part);
-        hipLaunchKernelGGL(k_supdate, G, B, 0, st, n, w.st, w.r, w.v, w.s, w.part);
-        if (pre) hmat_precond_apply(o->precond, w.s, w.sh, st);
-        if ((rc = mv(h_iter, sh, w.t))) return rc;
-        hipLaunchKernelGGL(k_dot_t, G, B, 0, st, n, w.st, w.t, w.s, w.part);
-        hipLaunchKernelGGL(k_xupdate, G, B, 0, st, n, w.st, x, w.r, w.rt, ph, w.s, sh, w.t, w.part, bank);
-        hipLaunchKernelGGL(k_finalize, dim3(1), B, 0, st, w.st, bank, w.hist);
+        if (gexec) {
+          if (hipGraphLaunch(gexec, st) != hipSuccess) return fail(HMAT_E_HIP, "graph launch failed");
+        } else if ((rc = iteration(st))) {
+          return rc;
+        }
+        nmv += 2;
       }
       launched += todo;
       if (poll() != hipSuccess) return fail(HMAT_E_HIP, "solver iteration failed: %s", hipGetErrorString(hipGetLastError()));
@@ -701,7 +743,7 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
     if (hs.flag == 1) {
       // convergence of the recurrence (or an early check, opts->refine):
       // confirm with the FP64 true residual
-      if ((rc = mv(h_fp64, x, w.tmp))) return rc;
+      if ((rc = mv(h_fp64, x, w.tmp, true))) return rc;
       hipLaunchKernelGGL(k_residual, G, B, 0, st, n, b, w.tmp, w.t, w.rt, w.part, 0);
       hipLaunchKernelGGL(k_true_norm, dim3(1), B, 0, st, w.st, w.part, true_slot);
       double tr = 0;
@@ -726,7 +768,7 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
     info->status = hs.flag == 2 ? HMAT_E_BREAKDOWN : hs.flag == 3 ? HMAT_E_NONFINITE : HMAT_E_NOCONV;
     // report the true residual of the returned x
     if (hs.flag != 3) {
-      if ((rc = mv(h_fp64, x, w.tmp))) return rc;
+      if ((rc = mv(h_fp64, x, w.tmp, true))) return rc;
       hipLaunchKernelGGL(k_residual, G, B, 0, st, n, b, w.tmp, w.t, w.rt, w.part, 0);
       hipLaunchKernelGGL(k_true_norm, dim3(1), B, 0, st, w.st, w.part, true_slot);
       hipMemcpyAsync(&truerel, true_slot, 8, hipMemcpyDeviceToHost, st);

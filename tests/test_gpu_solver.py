@@ -175,3 +175,27 @@ def test_bicgstab_refine_bf16_matches_oracle():
           f"({i1['restarts']} restarts), oracle refine {io['iterations']}")
     with pytest.raises(hmat.HmatError):
         hmat.hmat_bicgstab(Hb, to_dev(b), h_fp64=H64, refine=1.5, raise_on_error=True)
+
+
+@pytest.mark.parametrize("pre", [False, True])
+def test_bicgstab_graph_replay_identical(pre):
+    """use_graph replays one captured iteration: same iterations, same x bit
+    for bit as direct launches, with and without a preconditioner; the FP64
+    true-residual products are counted apart from the iteration's."""
+    need_gpu()
+    m, h = oracle_hmatrix("sphere-L4")
+    bs = blockset(h)
+    H = hmat.HMatrix(bs, oracle.M2_MIXED)
+    H64 = hmat.HMatrix(bs, oracle.M1_DOUBLE)
+    P = hmat.Precond(bs) if pre else None
+    b = to_dev(m.rhs()[h.perm])
+    xa, ia = hmat.hmat_bicgstab(H, b, h_fp64=H64, precond=P, poll_every=3)
+    xb, ib = hmat.hmat_bicgstab(H, b, h_fp64=H64, precond=P, poll_every=3, use_graph=True)
+    assert ia["status"] == 0 and ib["status"] == 0
+    assert ia["iterations"] == ib["iterations"] and np.array_equal(xa.cpu().numpy(), xb.cpu().numpy())
+    # r_0 plus two per launched iteration (launches past convergence inside a
+    # polling window are no-ops but counted), the same with and without graph
+    assert ib["matvecs"] == ia["matvecs"] and ia["matvecs"] >= 2 * ia["iterations"] + 1
+    assert ib["matvecs_fp64"] == ia["matvecs_fp64"] >= 1
+    x64, i64 = hmat.hmat_bicgstab(H64, b, poll_every=3, use_graph=True)
+    assert i64["status"] == 0 and i64["matvecs_fp64"] >= 1 and i64["matvecs"] >= 2 * i64["iterations"] + 1
