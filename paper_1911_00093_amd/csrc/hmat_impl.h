@@ -103,6 +103,18 @@ constexpr int kMRhs = 16;          // right-hand sides per pass (MFMA N)
 constexpr int kMRTile = 16;        // rows per MFMA tile (MFMA M)
 constexpr int kMRCols = 512;       // stage-1 item width (columns)
 constexpr int mr_cb(int cls) { return 4 * vec_of(cls); }
+// Rows stored for row tile t of a unit of `rows` rows: 16, or the rest in
+// the last tile.  A tile with tr rows stores, per column block, only the
+// 4 * tr lanes whose row l % 16 is below tr (lane group l / 16 after lane
+// group, tr lanes each), so row padding never reaches memory: the matrix
+// cores see zeros for the missing rows.  A unit holds nkb * 4 * VEC * rows
+// values.
+constexpr int mr_tile_rows(int rows, int t) { return rows - kMRTile * t < kMRTile ? rows - kMRTile * t : kMRTile; }
+constexpr int64_t mr_elem(int rows, int nkb, int vec, int t, int kb, int lane, int v) {
+  return (int64_t)t * nkb * kWave * vec +
+         ((int64_t)kb * 4 * mr_tile_rows(rows, t) + (lane / kMRTile) * mr_tile_rows(rows, t) + lane % kMRTile) * vec +
+         v;
+}
 
 // Work units of a multi-RHS launch cut into one contiguous range per XCD
 // (units [lo[x], lo[x + 1]) run on the workgroups with blockIdx % 8 == x, the

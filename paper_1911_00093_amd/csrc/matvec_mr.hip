@@ -82,8 +82,19 @@ __device__ __forceinline__ void mr_s1_item(const MRItem &it, const void *vals, i
   constexpr int VEC = vec_of(CLS), CB = mr_cb(CLS);
   const int kq = lane / kMRTile;  // k within an MFMA step
   const int rj = lane % kMRTile;  // right-hand side
-  const int64_t tstride = (int64_t)it.nkb * kWave * VEC * bytes_of(CLS);
-  const char *abase = (const char *)vals + it.w_off * bytes_of(CLS) + (int64_t)lane * VEC * bytes_of(CLS);
+  // tile t: rows tr (16, or the rest in the last tile), stored lanes only
+  // (layout: mr_elem); lanes of missing rows feed zeros to the matrix cores
+  const char *tbase[NT];
+  int32_t lstride[NT], loff[NT];
+  bool act[NT];
+#pragma unroll
+  for (int t = 0; t < NT; t++) {
+    const int tr = mr_tile_rows(it.nrows, t);
+    tbase[t] = (const char *)vals + (it.w_off + (int64_t)t * it.nkb * kWave * VEC) * bytes_of(CLS);
+    lstride[t] = 4 * tr * VEC * bytes_of(CLS);
+    loff[t] = ((lane / kMRTile) * tr + lane % kMRTile) * VEC * bytes_of(CLS);
+    act[t] = lane % kMRTile < tr;
+  }
   v4d c[NT];
 #pragma unroll
   for (int t = 0; t < NT; t++) c[t] = v4d{0, 0, 0, 0};
@@ -95,8 +106,8 @@ __device__ __forceinline__ void mr_s1_item(const MRItem &it, const void *vals, i
       const int kb = min(kb0 + j, it.nkb - 1);  // past the end: re-read, not used
 #pragma unroll
       for (int t = 0; t < NT; t++)
-        a[t][j] = __builtin_nontemporal_load(
-            (const mr_raw *)(abase + t * tstride + (int64_t)kb * kWave * VEC * bytes_of(CLS)));
+        a[t][j] = act[t] ? __builtin_nontemporal_load((const mr_raw *)(tbase[t] + (int64_t)kb * lstride[t] + loff[t]))
+                         : mr_raw{0u, 0u, 0u, 0u};
 #pragma unroll
       for (int v = 0; v < VEC; v++) {
         const int col = kb * CB + 4 * v + kq;
@@ -174,28 +185,45 @@ __device__ __forceinline__ void mr_s2_class(const MRChunk &ch, const void *vals,
   const int nkb = ch.nkb[CLS];
   if (nkb == 0) return;  // uniform
   const int kq = lane / kMRTile, rj = lane % kMRTile;
-  const int64_t tstride = (int64_t)nkb * kWave * VEC * bytes_of(CLS);
-  const char *abase = (const char *)vals + ch.panel_off[CLS] * bytes_of(CLS) + (int64_t)lane * VEC * bytes_of(CLS);
+  // tile t: rows tr (16, or the rest in the last tile), stored lanes only
+  // (layout: mr_elem); lanes of missing rows feed zeros to the matrix cores
+  const char *tbase[NT];
+  int32_t lstride[NT], loff[NT];
+  bool act[NT];
+#pragma unroll
+  for (int t = 0; t < NT; t++) {
+    const int tr = mr_tile_rows(ch.h, t);
+    tbase[t] = (const char *)vals + (ch.panel_off[CLS] + (int64_t)t * nkb * kWave * VEC) * bytes_of(CLS);
+    lstride[t] = 4 * tr * VEC * bytes_of(CLS);
+    loff[t] = ((lane / kMRTile) * tr + lane % kMRTile) * VEC * bytes_of(CLS);
+    act[t] = lane % kMRTile < tr;
+  }
   // gather indices of a column block: lane group kq's VEC columns are contiguous
   const int32_t *gi = gidx + ch.gidx_off[CLS] + kq * VEC;
+  // the gather indices of the next batch are loaded while this batch's
+  // values and operands are in flight (two dependent loads per operand)
+  int32_t gn[NB][VEC];
+#pragma unroll
+  for (int j = 0; j < NB; j++)
+#pragma unroll
+    for (int v = 0; v < VEC; v++) gn[j][v] = gi[min(j, nkb - 1) * CB + v];
   for (int kb0 = 0; kb0 < nkb; kb0 += NB) {
     mr_raw a[NT][NB];
-    int32_t g[NB][VEC];
+    double b[NB][VEC];
 #pragma unroll
     for (int j = 0; j < NB; j++) {
       const int kb = min(kb0 + j, nkb - 1);  // past the end: re-read, not used
 #pragma unroll
       for (int t = 0; t < NT; t++)
-        a[t][j] = __builtin_nontemporal_load(
-            (const mr_raw *)(abase + t * tstride + (int64_t)kb * kWave * VEC * bytes_of(CLS)));
+        a[t][j] = act[t] ? __builtin_nontemporal_load((const mr_raw *)(tbase[t] + (int64_t)kb * lstride[t] + loff[t]))
+                         : mr_raw{0u, 0u, 0u, 0u};
 #pragma unroll
-      for (int v = 0; v < VEC; v++) g[j][v] = gi[kb * CB + v];
+      for (int v = 0; v < VEC; v++) b[j][v] = s64[(int64_t)gn[j][v] * kMRhs + rj];
     }
-    double b[NB][VEC];
 #pragma unroll
     for (int j = 0; j < NB; j++)
 #pragma unroll
-      for (int v = 0; v < VEC; v++) b[j][v] = s64[(int64_t)g[j][v] * kMRhs + rj];
+      for (int v = 0; v < VEC; v++) gn[j][v] = gi[min(kb0 + NB + j, nkb - 1) * CB + v];
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < NB; j++) {

@@ -412,7 +412,7 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
       const Group &g = P->groups[q.group];
       m.z_off = g.nch == 1 ? g.z0 + q.k0 : -1;
       m.w_off = P->vals_elems[c];
-      P->vals_elems[c] += (int64_t)((m.nrows + kMRTile - 1) / kMRTile) * m.nkb * kWave * vec_of(c);
+      P->vals_elems[c] += (int64_t)m.nkb * 4 * vec_of(c) * m.nrows;
       P->mri.push_back(m);
       P->mri_group.push_back(q.group);
       P->mri_k0.push_back(q.k0);
@@ -464,28 +464,26 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
       MRChunk &R = P->mrc[q];
       R.r0 = (int32_t)cp.r0;
       R.h = (int32_t)cp.h;
-      const int64_t tiles = (cp.h + kMRTile - 1) / kMRTile;
       for (int c = 0; c < NCLS; c++) {
         R.nkb[c] = (int32_t)((cp.K[c] + mr_cb(c) - 1) / mr_cb(c));
         R.panel_off[c] = P->vals_elems[c];
         R.gidx_off[c] = P->gidx_elems[c];
-        P->vals_elems[c] += tiles * R.nkb[c] * kWave * vec_of(c);
+        P->vals_elems[c] += (int64_t)R.nkb[c] * 4 * vec_of(c) * cp.h;
         P->gidx_elems[c] += (int64_t)R.nkb[c] * mr_cb(c);
       }
     }
     std::vector<double> cost(P->mrc.size());
     for (size_t q = 0; q < P->mrc.size(); q++) {
       const MRChunk &R = P->mrc[q];
-      const double tiles = (R.h + kMRTile - 1) / kMRTile;
-      double c = 0.0;
-      for (int k = 0; k < NCLS; k++) c += R.nkb[k] * (tiles * kWave * 16.0 + mr_cb(k) * (kMRhs * 8.0 + 4.0));
+      double c = 0.0;  // stored values (16 B per stored lane and block) + gathered operands
+      for (int k = 0; k < NCLS; k++) c += R.nkb[k] * (4.0 * R.h * 16.0 + mr_cb(k) * (kMRhs * 8.0 + 4.0));
       cost[q] = c;
     }
     P->mr_split2 = xcd_split(cost);
     for (int k = 0; k < NCLS; k++) {
       std::vector<double> ci;
       for (const MRItem &m : P->mri)
-        if (m.cls == k) ci.push_back(((m.nrows + kMRTile - 1) / kMRTile) * (double)m.nkb * kWave * 16.0 + m.ncols * kMRhs * 8.0);
+        if (m.cls == k) ci.push_back(4.0 * m.nrows * (double)m.nkb * 16.0 + m.ncols * kMRhs * 8.0);
       P->mr_split1[k] = xcd_split(ci);
     }
   }
@@ -748,16 +746,17 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
           for (int qg = 0; qg < 4; qg++)
             for (int v = 0; v < vec; v++) gi[(int64_t)kb * cb + qg * vec + v] = blk[4 * v + qg];
         }
-        const int tiles = (int)((cp.h + kMRTile - 1) / kMRTile);
+        const int hh = (int)cp.h, tiles = (hh + kMRTile - 1) / kMRTile;
         for (int t = 0; t < tiles; t++)
           for (int kb = 0; kb < nkb; kb++)
-            for (int l = 0; l < kWave; l++)
+            for (int l = 0; l < kWave; l++) {
+              if (l % kMRTile >= mr_tile_rows(hh, t)) continue;  // row beyond the chunk: not stored
               for (int v = 0; v < vec; v++) {
                 const int64_t row = t * kMRTile + l % kMRTile;
                 const int64_t kk = (int64_t)kb * cb + 4 * v + l / kMRTile;
-                const double val = row < cp.h ? panel_value(col[kk], cp.r0 + row) : 0.0;
-                put(c, R.panel_off[c] + (((int64_t)t * nkb + kb) * kWave + l) * vec + v, val);
+                put(c, R.panel_off[c] + mr_elem(hh, nkb, vec, t, kb, l, v), panel_value(col[kk], cp.r0 + row));
               }
+            }
       }
     });
     parallel_for((int64_t)P->mri.size(), [&](int64_t q) {
@@ -767,17 +766,19 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
       const int tiles = (m.nrows + kMRTile - 1) / kMRTile;
       for (int t = 0; t < tiles; t++)
         for (int kb = 0; kb < m.nkb; kb++)
-          for (int l = 0; l < kWave; l++)
+          for (int l = 0; l < kWave; l++) {
+            if (l % kMRTile >= mr_tile_rows(m.nrows, t)) continue;  // row beyond the item: not stored
             for (int v = 0; v < vec; v++) {
               const int64_t r = t * kMRTile + l % kMRTile;
               const int64_t jj = (int64_t)kb * cb + 4 * v + l / kMRTile;
               double val = 0.0;
-              if (r < m.nrows && jj < m.ncols) {
+              if (jj < m.ncols) {
                 auto [k, ti] = g.rows[P->mri_k0[q] + r];
                 val = wval(k, P->terms[k][ti], P->mri_c0[q] + jj);
               }
-              put(c, m.w_off + (((int64_t)t * m.nkb + kb) * kWave + l) * vec + v, val);
+              put(c, m.w_off + mr_elem(m.nrows, m.nkb, vec, t, kb, l, v), val);
             }
+          }
     });
   }
   // stage-2 panels and gather indices, in launch order
