@@ -405,6 +405,15 @@ int hmat_kernel_times(hmat_t h, double *avg_ms, int64_t *count);
 int hmat_stream_read(const void *src, uint64_t bytes, double *sink, void *stream);
 int hmat_stream_copy(void *dst, const void *src, uint64_t bytes, void *stream);
 
+/* Vectors between the original panel order and the cluster (permuted)
+ * order every other entry point uses: y[k] = x[perm[k]], or with inverse != 0
+ * y[perm[k]] = x[k], for each of nrhs columns (column j at offset j * n).
+ * perm: device int64, a permutation of 0..n-1 (the one hmat_assembly_perm
+ * returns, copied to the device); x, y: device FP64, must not alias.
+ * Asynchronous on `stream`. */
+int hmat_permute(int64_t n, const int64_t *perm, const double *x, double *y, int64_t nrhs, int32_t inverse,
+                 void *stream);
+
 /* Library version string. */
 const char *hmat_version(void);
 

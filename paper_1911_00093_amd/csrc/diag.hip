@@ -4,6 +4,8 @@
 // copy of known size for scaling hardware byte counters).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <array>
 #include <vector>
 
@@ -69,6 +71,19 @@ __global__ __launch_bounds__(256) void k_stream_read(const uint4 *__restrict__ a
   if (acc == 0x9e3779b9u) sink[0] = (double)acc;  // keeps the loads alive
 }
 
+// y[k] = x[perm[k]] (original -> cluster order) or, inverse, y[perm[k]] = x[k];
+// column j of n x nrhs at offset j * n.  perm entries must lie in [0, n):
+// the host passes the permutation the assembly returned.
+__global__ __launch_bounds__(256) void k_permute(int64_t n, int64_t nrhs, const int64_t *__restrict__ perm,
+                                                 const double *__restrict__ x, double *__restrict__ y, int inverse) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * nrhs; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / n, k = e % n, p = perm[k];
+    if (p < 0 || p >= n) continue;  // not a permutation entry: left untouched
+    if (inverse) y[j * n + p] = x[e];
+    else y[e] = x[j * n + p];
+  }
+}
+
 __global__ __launch_bounds__(256) void k_stream_copy(const uint4 *__restrict__ a, uint4 *__restrict__ b, int64_t n16) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
     b[i] = a[i];
@@ -108,6 +123,18 @@ int hmat_stream_read(const void *src, uint64_t bytes, double *sink, void *stream
   const int64_t n16 = (int64_t)(bytes / 16);
   hipLaunchKernelGGL(hm::k_stream_read, dim3(256 * 16), dim3(256), 0, (hipStream_t)stream, (const uint4 *)src, n16, sink);
   hipError_t e = hipGetLastError();
+  return e == hipSuccess ? HMAT_OK : hm::fail(HMAT_E_HIP, "launch failed: %s", hipGetErrorString(e));
+}
+
+int hmat_permute(int64_t n, const int64_t *perm, const double *x, double *y, int64_t nrhs, int32_t inverse,
+                 void *stream) {
+  if (!perm || !x || !y) return hm::fail(HMAT_E_ARG, "null argument");
+  if (n < 1 || nrhs < 1) return hm::fail(HMAT_E_ARG, "n %lld or nrhs %lld out of range", (long long)n, (long long)nrhs);
+  if (x == y) return hm::fail(HMAT_E_ARG, "y must not alias x");
+  const int64_t tot = n * nrhs;
+  hipLaunchKernelGGL(hm::k_permute, dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 65536)), dim3(256), 0,
+                     (hipStream_t)stream, n, nrhs, perm, x, y, inverse);
+  const hipError_t e = hipGetLastError();
   return e == hipSuccess ? HMAT_OK : hm::fail(HMAT_E_HIP, "launch failed: %s", hipGetErrorString(e));
 }
 

@@ -36,7 +36,7 @@ EXPORTED = [
     "hmat_stream_read", "hmat_stream_copy", "hmat_plan_batched", "hmat_build_batched", "hmat_system_offsets",
     "hmat_bicgstab_batched_workspace_bytes", "hmat_bicgstab_batched", "hmat_precond_create_learned",
     "hmat_precond_leaves", "hmat_leaf_features", "hmat_dense_inverse", "hmat_mlp_workspace_bytes",
-    "hmat_mlp_forward", "hmat_mlp_loss_grad", "hmat_mlp_adam", "hmat_autotune",
+    "hmat_mlp_forward", "hmat_mlp_loss_grad", "hmat_mlp_adam", "hmat_autotune", "hmat_permute",
 ]
 
 
@@ -147,6 +147,7 @@ def lib():
         "hmat_mlp_loss_grad": (C.c_int, [P, P, P, P, P, P, I64, P, I64, P, P, P, U64, P]),
         "hmat_mlp_adam": (C.c_int, [P, P, P, P, I64, C.c_float, P]),
         "hmat_autotune": (C.c_int, [P, P, P, I32, P, P]),
+        "hmat_permute": (C.c_int, [I64, P, P, P, I64, I32, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -552,6 +553,21 @@ def hmat_bicgstab_batched(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = N
     per = {f: np.array([getattr(r, f) for r in res]).reshape(nsys, nrhs)
            for f in ("status", "restarts", "iterations", "rel_res", "true_rel_res")}
     return x, summary, per
+
+
+def hmat_permute(perm, x, inverse=False, stream=None):
+    """Device vector(s) from original to cluster order (y[k] = x[perm[k]]) or
+    back (inverse).  perm: device int64 tensor; x: (n,) or column-major (n, nrhs)."""
+    import torch
+
+    n = perm.numel()
+    nrhs = 1 if x.dim() == 1 else x.shape[1]
+    if x.dtype != torch.float64 or x.shape[0] != n or (x.dim() == 2 and (x.stride(0) != 1 or x.stride(1) != n)):
+        raise ValueError("x must be float64 (n,) or (n, nrhs) column-major")
+    y = torch.empty_like(x) if x.dim() == 1 else torch.empty((nrhs, n), dtype=torch.float64, device=x.device).T
+    _check(lib().hmat_permute(n, C.c_void_p(perm.data_ptr()), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                              nrhs, int(bool(inverse)), _stream_ptr(stream)))
+    return y
 
 
 def hmat_stream_read(buf, stream=None):

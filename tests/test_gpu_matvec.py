@@ -136,3 +136,31 @@ def test_workspace_too_small():
     out = C.c_void_p()
     rc = hmat.lib().hmat_build(C.byref(s), C.byref(o), C.c_void_p(buf.data_ptr()), buf.numel(), None, C.byref(out))
     assert rc == hmat.HMAT_E_WORKSPACE
+
+
+def test_permute_roundtrip():
+    """hmat_permute: y = x[perm] into cluster order and back, 1 and 3 columns;
+    with the assembly's permutation, the product in original order equals
+    the dense matrix of the original panels applied directly."""
+    need_gpu()
+    import torch
+
+    m, h = oracle_hmatrix("sphere-L3")
+    perm = torch.as_tensor(np.ascontiguousarray(h.perm, dtype=np.int64)).cuda()
+    X = np.random.default_rng(3).standard_normal((3, h.n))
+    xd = torch.as_tensor(X).cuda().T
+    y = hmat.hmat_permute(perm, xd)
+    assert np.array_equal(y.cpu().numpy(), X.T[h.perm])
+    back = hmat.hmat_permute(perm, y, inverse=True)
+    assert np.array_equal(back.cpu().numpy(), X.T)
+    x1 = to_dev(X[0])
+    H = hmat.HMatrix(blockset(h), oracle.M1_DOUBLE)
+    yo = hmat.hmat_permute(perm, H.matvec(hmat.hmat_permute(perm, x1)), inverse=True).cpu().numpy()
+    c, a = m.centroids, m.areas  # computed once (properties of the mesh)
+    dist = np.linalg.norm(c[:, None, :] - c[None, :, :], axis=2)
+    np.fill_diagonal(dist, 1.0)
+    A = a[None, :] / (4 * np.pi * dist)
+    np.fill_diagonal(A, np.sqrt(a / np.pi) / 2)
+    ex = A @ X[0]
+    assert np.linalg.norm(yo - ex) / np.linalg.norm(ex) < 1e-5  # ACA 1e-6 blocks
+    assert hmat.lib().hmat_permute(h.n, None, None, None, 1, 0, None) == hmat.HMAT_E_ARG
