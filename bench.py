@@ -99,7 +99,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): this build has no multi-GPU path; "
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): the library has no multi-GPU path; "
               "how the product would shard across GPUs is described in DESIGN.md.", file=sys.stderr)
         sys.exit(2)
 

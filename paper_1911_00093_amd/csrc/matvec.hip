@@ -15,7 +15,7 @@
 //      (rounded to FP32 in the Single variants, Sec. 3.5) into src.
 //  K2  stage 2: one workgroup owns <= 64 rows of y.  The workgroup gathers
 //      the panel's operands (x for dense columns, z for low-rank columns)
-//      into LDS, then each of its four waves streams its own 16 interleaved
+//      into LDS, then each of its eight waves streams its own 8 interleaved
 //      rows over all panel columns (dense leaves + V'_m rows, Eqs. 21, 24),
 //      reduces once and writes its rows of y (Eq. 25).
 // All products and sums are FP64 after upcasting the stored value.
