@@ -99,8 +99,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): the library has no multi-GPU path; "
-              "how the product would shard across GPUs is described in DESIGN.md.", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}): the library has no multi-GPU path "
+              "(independent systems would shard with no exchange; one system by row chunks with an all-gather "
+              "of x per product).", file=sys.stderr)
         sys.exit(2)
 
     import torch
