@@ -92,6 +92,7 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-matvecs", type=int, default=5)
+    ap.add_argument("--eps", type=float, default=None, help="ACA tolerance (default: the workload's)")
     ap.add_argument("--refine", type=float, default=None,
                     help="early FP64 true-residual check ratio (default 1e-2 for BF16-scaled, else 0)")
     ap.add_argument("--train-leaves", type=int, default=20000)
@@ -117,7 +118,10 @@ def main():
     variant = hmat.PRECISION_NAMES.index(args.variant)
     if args.refine is None:
         args.refine = 1e-2 if variant == hmat.BF16_SCALED else 0.0
-    W = WORKLOADS[args.workload]
+    W = dict(WORKLOADS[args.workload])
+    if args.eps is not None:
+        W["eps"] = args.eps
+        W["desc"] = W["desc"].replace("ACA 1e-6", f"ACA {args.eps:g}").replace("ACA 1e-5", f"ACA {args.eps:g}")
     if "nsys" in W:
         return bench_batched(args, W, variant, dev, stream)
     if W.get("learned"):
