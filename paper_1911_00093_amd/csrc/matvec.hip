@@ -15,9 +15,10 @@
 //      (rounded to FP32 in the Single variants, Sec. 3.5) into src.
 //  K2  stage 2: one workgroup owns <= 64 rows of y.  The workgroup gathers
 //      the panel's operands (x for dense columns, z for low-rank columns)
-//      into LDS, then each of its eight waves streams its own 8 interleaved
-//      rows over all panel columns (dense leaves + V'_m rows, Eqs. 21, 24),
-//      reduces once and writes its rows of y (Eq. 25).
+//      into LDS (double-buffered across tiles and chunks when one storage
+//      class is present), then each of its eight waves streams its own 8
+//      interleaved rows over all panel columns (dense leaves + V'_m rows,
+//      Eqs. 21, 24), reduces once and writes its rows of y (Eq. 25).
 // All products and sums are FP64 after upcasting the stored value.
 #include <hip/hip_runtime.h>
 
@@ -111,13 +112,12 @@ __device__ __forceinline__ void s1_item(const S1Item &it, const void *vals, cons
     const bool act = u < ws;
     const int uc = act ? u : 0;  // inactive lanes read a valid value and weigh it by 0
     const int col = s * SLAB + uc * VEC;
-    double g[VEC];
+    // x: unconditional loads of valid columns (clamped), so that they issue
+    // together with the value loads; the weights of columns past the item
+    // and of inactive lanes are zeroed by a bit mask after the loads.
+    double xv[VEC];
 #pragma unroll
-    for (int e = 0; e < VEC; e++) {
-      const bool in = act && col + e < it.ncols;
-      const double xv = x[it.x0 + (in ? col + e : 0)];
-      g[e] = in ? (x32 ? (double)(float)xv : xv) : 0.0;
-    }
+    for (int e = 0; e < VEC; e++) xv[e] = x[it.x0 + min(col + e, it.ncols - 1)];
     // consumption order: slab s, then row slot i, then lane group q, then
     // lane u.  The slot bases are wave-uniform (scalar registers); each lane
     // adds one 32-bit offset.  All loads are issued before any is used;
@@ -133,6 +133,13 @@ __device__ __forceinline__ void s1_item(const S1Item &it, const void *vals, cons
       t[i] = ld16(sbase + (int64_t)ic * slot_bytes, loff);
     }
     __builtin_amdgcn_sched_barrier(0);
+    double g[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; e++) {
+      const double xs = x32 ? (double)(float)xv[e] : xv[e];
+      const uint64_t keep = (act && col + e < it.ncols) ? ~0ull : 0ull;
+      g[e] = __longlong_as_double((long long)((uint64_t)__double_as_longlong(xs) & keep));
+    }
 #pragma unroll
     for (int i = 0; i < kRowsPerLane; i++) acc[i] = dot16<CLS>(t[i], g, acc[i]);
   }
@@ -190,51 +197,177 @@ __global__ __launch_bounds__(256) void k_stage1b(int64_t n, int64_t zlen, const 
 // ------------------------------------------------------------------ K2
 // Rows of the chunk are interleaved over the waves: wave w owns rows
 // w, w + 8, ..., so every wave streams all columns of its <= 8 rows.
+// s2_slabs: the wave streams its rows over slabs [sb, se) (column offsets
+// within the tile, multiples of the slab width) of the tile of one class
+// panel that starts at column kt0; gt holds the tile's gathered operands.
+// (panel_off, ld, h: the chunk's panel offset and padded width in this
+// class, and its row count).
+template <int CLS>
+__device__ __forceinline__ void s2_slabs(int64_t panel_off, int ld, int h, const void *vals, const double *gt,
+                                         int kt0, int sb, int se, double (&acc)[kRowsPerLane], int wave, int lane) {
+  constexpr int VEC = vec_of(CLS);
+  constexpr int SLAB = kWave * VEC;
+  const int nw = s2_rows_of_wave(h, wave);
+  if (nw == 0) return;  // uniform over the wave
+  const int64_t wbase = panel_off + s2_wave_base(h, ld, wave);
+#pragma unroll 1
+  for (int s0 = sb; s0 < se; s0 += SLAB) {
+    const int s = (kt0 + s0) / SLAB;
+    const int ws = slab_lanes(ld, VEC, kWave, s);
+    const bool act = lane < ws;
+    const int lc = act ? lane : 0;  // inactive lanes read a valid value and weigh it by 0
+    double g[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; e++) g[e] = act ? gt[s0 + lane * VEC + e] : 0.0;
+    // consumption order: this wave's rows of slab s one after another.  The
+    // row bases are wave-uniform; each lane adds one 32-bit offset.  All
+    // loads are issued before any is used; rows past the wave's last row
+    // re-read that row and their accumulators are never written.
+    const char *sbase = (const char *)vals + (wbase + (int64_t)s * nw * SLAB) * bytes_of(CLS);
+    const uint32_t loff = (uint32_t)(lc * VEC * bytes_of(CLS));
+    const uint32_t row_bytes = (uint32_t)(ws * VEC * bytes_of(CLS));
+    raw16 t[kRowsPerLane];
+#pragma unroll
+    for (int i = 0; i < kRowsPerLane; i++) {
+      const int ic = i < nw ? i : nw - 1;
+      t[i] = ld16(sbase + (int64_t)ic * row_bytes, loff);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < kRowsPerLane; i++) acc[i] = dot16<CLS>(t[i], g, acc[i]);
+  }
+}
+
+// The workgroup gathers g[k] = src[gi[k]], k < kn <= kS2Tile, into LDS.  The
+// index loads are unconditional (indices past kn repeat the last one), so
+// that each thread's loads issue together.
+__device__ __forceinline__ void s2_gather(const int32_t *gi, int kn, const double *src, double *g) {
+  constexpr int PER = kS2Tile / kS2Threads;
+  if (kn <= 0) return;  // uniform
+  int32_t k[PER];
+  double v[PER];
+#pragma unroll
+  for (int j = 0; j < PER; j++) k[j] = gi[min((int)threadIdx.x + j * kS2Threads, kn - 1)];
+#pragma unroll
+  for (int j = 0; j < PER; j++) v[j] = src[k[j]];
+#pragma unroll
+  for (int j = 0; j < PER; j++)
+    if ((int)threadIdx.x + j * kS2Threads < kn) g[threadIdx.x + j * kS2Threads] = v[j];
+}
+
+// One storage class of a chunk (chunks with several classes): each tile of
+// operands is gathered into LDS, then streamed.
 template <int CLS>
 __device__ __forceinline__ void s2_class(const RowChunk &ch, const void *vals, const int32_t *gidx,
                                          const double *src, double *gbuf, double (&acc)[kRowsPerLane], int wave,
                                          int lane) {
-  constexpr int VEC = vec_of(CLS);
-  constexpr int SLAB = kWave * VEC;
   const int ld = ch.ld[CLS];
   if (ld == 0) return;  // uniform over the workgroup
-  const int h = ch.h;
   const int32_t *gi = gidx + ch.gidx_off[CLS];
-  const int nw = s2_rows_of_wave(h, wave);
-  const int64_t wbase = ch.panel_off[CLS] + s2_wave_base(h, ld, wave);
-  const bool rows = nw > 0;  // waves without rows still help with the gather
-  static_assert(kS2Tile % SLAB == 0, "LDS tiles hold whole slabs");
+  static_assert(kS2Tile % (kWave * vec_of(CLS)) == 0, "LDS tiles hold whole slabs");
   for (int kt0 = 0; kt0 < ld; kt0 += kS2Tile) {
     const int kn = min(kS2Tile, ld - kt0);
     __syncthreads();  // the previous tile's operands are no longer read
-    for (int k = threadIdx.x; k < kn; k += kS2Threads) gbuf[k] = src[gi[kt0 + k]];
+    s2_gather(gi + kt0, kn, src, gbuf);
     __syncthreads();
-#pragma unroll 1
-    for (int s0 = 0; rows && s0 < kn; s0 += SLAB) {
-      const int s = (kt0 + s0) / SLAB;
-      const int ws = slab_lanes(ld, VEC, kWave, s);
-      const bool act = lane < ws;
-      const int lc = act ? lane : 0;  // inactive lanes read a valid value and weigh it by 0
-      double g[VEC];
+    s2_slabs<CLS>(ch.panel_off[CLS], ld, ch.h, vals, gbuf, kt0, 0, kn, acc, wave, lane);
+  }
+}
+
+// Chunk rows to y: one reduction per row, each row written once.
+__device__ __forceinline__ void s2_write(int r0, int h, double (&acc)[kRowsPerLane], double *y, int wave, int lane) {
+  const double sum = reduce_rows(acc, lane, kWave);
+  if ((lane & 7) == 0) {
+    const int row = wave + kS2Waves * (lane >> 3);
+    if (row < h) y[r0 + row] = sum;
+  }
+}
+
+// One storage class in every chunk: the workgroup walks the tiles of its
+// chunks (round-robin over the size-sorted chunks) with two LDS operand
+// buffers.  While the waves stream one tile, every thread loads its share
+// of the next tile's gather indices, then (after the first slab) the
+// operands themselves, and stores them into the other buffer at the end, so
+// the two dependent gather loads overlap the value stream and a tile costs
+// one barrier.  Same products and summation order as s2_class.
+// The fields of one chunk that a single-class walk needs.
+struct S2Cur {
+  int64_t panel_off, gidx_off;
+  int ld, r0, h;
+};
+template <int CLS>
+__device__ __forceinline__ S2Cur s2_cur(const RowChunk *chunks, int64_t c) {
+  const RowChunk &ch = chunks[c];
+  return S2Cur{ch.panel_off[CLS], ch.gidx_off[CLS], ch.ld[CLS], ch.r0, ch.h};
+}
+
+template <int CLS>
+__device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, int64_t nchunks,
+                                          const void *__restrict__ vals, const int32_t *__restrict__ gidx,
+                                          const double *__restrict__ src, double *__restrict__ y) {
+  constexpr int SLAB = kWave * vec_of(CLS);
+  constexpr int PER = kS2Tile / kS2Threads;  // gathered operands per thread and tile
+  static_assert(kS2Tile % kS2Threads == 0 && kS2Tile % SLAB == 0, "whole slabs, equal shares");
+  __shared__ double gbuf[2][kS2Tile];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
+  int64_t c = blockIdx.x;
+  if (c >= nchunks) return;  // uniform over the workgroup
+  S2Cur ch = s2_cur<CLS>(chunks, c);
+  int kt0 = 0;
+  s2_gather(gidx + ch.gidx_off, min(kS2Tile, ch.ld), src, gbuf[0]);
+  __syncthreads();
+  double acc[kRowsPerLane];
 #pragma unroll
-      for (int e = 0; e < VEC; e++) g[e] = act ? gbuf[s0 + lane * VEC + e] : 0.0;
-      // consumption order: this wave's rows of slab s one after another.  The
-      // row bases are wave-uniform; each lane adds one 32-bit offset.  All
-      // loads are issued before any is used; rows past the wave's last row
-      // re-read that row and their accumulators are never written.
-      const char *sbase = (const char *)vals + (wbase + (int64_t)s * nw * SLAB) * bytes_of(CLS);
-      const uint32_t loff = (uint32_t)(lc * VEC * bytes_of(CLS));
-      const uint32_t row_bytes = (uint32_t)(ws * VEC * bytes_of(CLS));
-      raw16 t[kRowsPerLane];
-#pragma unroll
-      for (int i = 0; i < kRowsPerLane; i++) {
-        const int ic = i < nw ? i : nw - 1;
-        t[i] = ld16(sbase + (int64_t)ic * row_bytes, loff);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int i = 0; i < kRowsPerLane; i++) acc[i] = dot16<CLS>(t[i], g, acc[i]);
+  for (int i = 0; i < kRowsPerLane; i++) acc[i] = 0.0;
+  int buf = 0;
+  for (;;) {
+    // the tile after this one: the next of this chunk, else the first of the
+    // workgroup's next chunk
+    int64_t nc = c;
+    int nkt = kt0 + kS2Tile;
+    if (nkt >= ch.ld) {
+      nc = c + gridDim.x;
+      nkt = 0;
     }
+    const bool more = nc < nchunks;
+    const bool same = nc == c;
+    const S2Cur nx = (more && !same) ? s2_cur<CLS>(chunks, nc) : ch;
+    const int nkn = more ? min(kS2Tile, nx.ld - nkt) : 0;
+    // indices past the tile repeat its last one (unconditional loads; the
+    // operands they fetch are not stored)
+    int32_t gn[PER];
+#pragma unroll
+    for (int j = 0; j < PER; j++) gn[j] = 0;
+    if (nkn > 0) {  // uniform
+#pragma unroll
+      for (int j = 0; j < PER; j++)
+        gn[j] = gidx[nx.gidx_off + nkt + min((int)threadIdx.x + j * kS2Threads, nkn - 1)];
+    }
+    const int kn = min(kS2Tile, ch.ld - kt0);
+    const double *gt = gbuf[buf];
+    const int first = min(kn, SLAB);
+    s2_slabs<CLS>(ch.panel_off, ch.ld, ch.h, vals, gt, kt0, 0, first, acc, wave, lane);
+    double pre[PER];
+#pragma unroll
+    for (int j = 0; j < PER; j++) pre[j] = src[gn[j]];
+    s2_slabs<CLS>(ch.panel_off, ch.ld, ch.h, vals, gt, kt0, first, kn, acc, wave, lane);
+    if (!same) {  // the chunk is complete
+      s2_write(ch.r0, ch.h, acc, y, wave, lane);
+#pragma unroll
+      for (int i = 0; i < kRowsPerLane; i++) acc[i] = 0.0;
+    }
+    double *gw = gbuf[buf ^ 1];
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      const int k = threadIdx.x + j * kS2Threads;
+      if (k < nkn) gw[k] = pre[j];
+    }
+    if (!more) break;  // uniform
+    __syncthreads();   // this tile is consumed, the next one is stored
+    buf ^= 1;
+    c = nc;
+    kt0 = nkt;
+    ch = nx;
   }
 }
 
@@ -258,11 +391,7 @@ __device__ __forceinline__ void s2_body(const RowChunk *__restrict__ chunks, int
     if constexpr ((MASK & 1) != 0) s2_class<F64>(ch, v64, g64, s, gbuf, acc, wave, lane);
     if constexpr ((MASK & 2) != 0) s2_class<F32>(ch, v32, g32, s, gbuf, acc, wave, lane);
     if constexpr ((MASK & 4) != 0) s2_class<BF16>(ch, v16, g16, s, gbuf, acc, wave, lane);
-    const double sum = reduce_rows(acc, lane, kWave);
-    if ((lane & 7) == 0) {
-      const int row = wave + kS2Waves * (lane >> 3);
-      if (row < ch.h) y[rhs * ldy + ch.r0 + row] = sum;
-    }
+    s2_write(ch.r0, ch.h, acc, y + rhs * ldy, wave, lane);
   }
 }
 
@@ -273,10 +402,14 @@ __device__ __forceinline__ void s2_body(const RowChunk *__restrict__ chunks, int
       int64_t src_len, double *__restrict__ y, int64_t ldy
 #define HM_S2_PASS chunks, nchunks, v64, v32, v16, g64, g32, g16, src, src_len, y, ldy
 
-// One storage class.
+// One storage class: double-buffered operand tiles.
 template <int MASK>
-__global__ __launch_bounds__(kS2Threads) void k_stage2(HM_S2_ARGS) {
-  s2_body<MASK>(HM_S2_PASS);
+__global__ __launch_bounds__(kS2Threads, 4) void k_stage2(HM_S2_ARGS) {
+  static_assert(MASK == 1 || MASK == 2 || MASK == 4, "one class");
+  constexpr int CLS = MASK == 1 ? F64 : MASK == 2 ? F32 : BF16;
+  const void *vals = CLS == F64 ? (const void *)v64 : CLS == F32 ? (const void *)v32 : (const void *)v16;
+  const int32_t *gidx = CLS == F64 ? g64 : CLS == F32 ? g32 : g16;
+  s2_single<CLS>(chunks, nchunks, vals, gidx, src + blockIdx.y * src_len, y + blockIdx.y * ldy);
 }
 // Two or three classes: let the compiler size the registers (no spills).
 template <int MASK>
@@ -294,7 +427,7 @@ static Stage2Fn stage2_fn(int mask) {
     case 1: return k_stage2<1>;
     case 2: return k_stage2<2>;
     case 3: return k_stage2_multi<3>;
-    case 4: return k_stage2_multi<4>;
+    case 4: return k_stage2<4>;
     case 5: return k_stage2_multi<5>;
     case 6: return k_stage2_multi<6>;
     default: return k_stage2_multi<7>;

@@ -83,17 +83,19 @@ __device__ __forceinline__ void mr_s1_item(const MRItem &it, const void *vals, i
   const int kq = lane / kMRTile;  // k within an MFMA step
   const int rj = lane % kMRTile;  // right-hand side
   // tile t: rows tr (16, or the rest in the last tile), stored lanes only
-  // (layout: mr_elem); lanes of missing rows feed zeros to the matrix cores
+  // (layout: mr_elem).  Every load is unconditional, from a valid address, so
+  // that all loads of a batch issue before the first is waited for: lanes of
+  // missing rows re-read the tile's last row (the matrix-core rows they feed
+  // are never written), columns past the item read its last x column (their
+  // stored values are zero).
   const char *tbase[NT];
   int32_t lstride[NT], loff[NT];
-  bool act[NT];
 #pragma unroll
   for (int t = 0; t < NT; t++) {
     const int tr = mr_tile_rows(it.nrows, t);
     tbase[t] = (const char *)vals + (it.w_off + (int64_t)t * it.nkb * kWave * VEC) * bytes_of(CLS);
     lstride[t] = 4 * tr * VEC * bytes_of(CLS);
-    loff[t] = ((lane / kMRTile) * tr + lane % kMRTile) * VEC * bytes_of(CLS);
-    act[t] = lane % kMRTile < tr;
+    loff[t] = ((lane / kMRTile) * tr + min(lane % kMRTile, tr - 1)) * VEC * bytes_of(CLS);
   }
   v4d c[NT];
 #pragma unroll
@@ -103,26 +105,26 @@ __device__ __forceinline__ void mr_s1_item(const MRItem &it, const void *vals, i
     double b[NB][VEC];
 #pragma unroll
     for (int j = 0; j < NB; j++) {
-      const int kb = min(kb0 + j, it.nkb - 1);  // past the end: re-read, not used
+      const int kb = min(kb0 + j, it.nkb - 1);  // past the end: re-read, weighted by 0
 #pragma unroll
       for (int t = 0; t < NT; t++)
-        a[t][j] = act[t] ? __builtin_nontemporal_load((const mr_raw *)(tbase[t] + (int64_t)kb * lstride[t] + loff[t]))
-                         : mr_raw{0u, 0u, 0u, 0u};
+        a[t][j] = __builtin_nontemporal_load((const mr_raw *)(tbase[t] + (int64_t)kb * lstride[t] + loff[t]));
 #pragma unroll
       for (int v = 0; v < VEC; v++) {
-        const int col = kb * CB + 4 * v + kq;
-        b[j][v] = col < it.ncols ? s64[(it.x0 + col) * kMRhs + rj] : 0.0;
+        const int col = min(kb * CB + 4 * v + kq, it.ncols - 1);
+        b[j][v] = s64[(it.x0 + col) * kMRhs + rj];
       }
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < NB; j++) {
-      if (kb0 + j >= it.nkb) break;  // uniform
+      const double w = (j == 0 || kb0 + j < it.nkb) ? 1.0 : 0.0;  // uniform; exact
 #pragma unroll
       for (int v = 0; v < VEC; v++)
 #pragma unroll
         for (int t = 0; t < NT; t++)
-          c[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(mr_a<CLS>(a[t][j], v), b[j][v], c[t], 0, 0, 0);
+          c[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(mr_a<CLS>(a[t][j], v), j == 0 ? b[j][v] : b[j][v] * w, c[t],
+                                                      0, 0, 0);
     }
   }
 #pragma unroll
@@ -186,17 +188,16 @@ __device__ __forceinline__ void mr_s2_class(const MRChunk &ch, const void *vals,
   if (nkb == 0) return;  // uniform
   const int kq = lane / kMRTile, rj = lane % kMRTile;
   // tile t: rows tr (16, or the rest in the last tile), stored lanes only
-  // (layout: mr_elem); lanes of missing rows feed zeros to the matrix cores
+  // (layout: mr_elem).  Loads are unconditional, as in stage 1: lanes of
+  // missing rows re-read the tile's last row, whose results are not written.
   const char *tbase[NT];
   int32_t lstride[NT], loff[NT];
-  bool act[NT];
 #pragma unroll
   for (int t = 0; t < NT; t++) {
     const int tr = mr_tile_rows(ch.h, t);
     tbase[t] = (const char *)vals + (ch.panel_off[CLS] + (int64_t)t * nkb * kWave * VEC) * bytes_of(CLS);
     lstride[t] = 4 * tr * VEC * bytes_of(CLS);
-    loff[t] = ((lane / kMRTile) * tr + lane % kMRTile) * VEC * bytes_of(CLS);
-    act[t] = lane % kMRTile < tr;
+    loff[t] = ((lane / kMRTile) * tr + min(lane % kMRTile, tr - 1)) * VEC * bytes_of(CLS);
   }
   // gather indices of a column block: lane group kq's VEC columns are contiguous
   const int32_t *gi = gidx + ch.gidx_off[CLS] + kq * VEC;
@@ -212,11 +213,10 @@ __device__ __forceinline__ void mr_s2_class(const MRChunk &ch, const void *vals,
     double b[NB][VEC];
 #pragma unroll
     for (int j = 0; j < NB; j++) {
-      const int kb = min(kb0 + j, nkb - 1);  // past the end: re-read, not used
+      const int kb = min(kb0 + j, nkb - 1);  // past the end: re-read, weighted by 0
 #pragma unroll
       for (int t = 0; t < NT; t++)
-        a[t][j] = act[t] ? __builtin_nontemporal_load((const mr_raw *)(tbase[t] + (int64_t)kb * lstride[t] + loff[t]))
-                         : mr_raw{0u, 0u, 0u, 0u};
+        a[t][j] = __builtin_nontemporal_load((const mr_raw *)(tbase[t] + (int64_t)kb * lstride[t] + loff[t]));
 #pragma unroll
       for (int v = 0; v < VEC; v++) b[j][v] = s64[(int64_t)gn[j][v] * kMRhs + rj];
     }
@@ -227,12 +227,13 @@ __device__ __forceinline__ void mr_s2_class(const MRChunk &ch, const void *vals,
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < NB; j++) {
-      if (kb0 + j >= nkb) break;  // uniform
+      const double w = (j == 0 || kb0 + j < nkb) ? 1.0 : 0.0;  // uniform; exact
 #pragma unroll
       for (int v = 0; v < VEC; v++)
 #pragma unroll
         for (int t = 0; t < NT; t++)
-          c[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(mr_a<CLS>(a[t][j], v), b[j][v], c[t], 0, 0, 0);
+          c[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(mr_a<CLS>(a[t][j], v), j == 0 ? b[j][v] : b[j][v] * w, c[t],
+                                                      0, 0, 0);
     }
   }
 }
