@@ -370,9 +370,20 @@ __global__ __launch_bounds__(64) void k_learned(int64_t nleaf, const JLeaf *__re
   const JLeaf L = leaves[blockIdx.x];
   const int i = threadIdx.x;
   const float *U = uv + L.off * 2 * kLeafMax * kLeafRank, *V = U + kLeafMax * kLeafRank;
-  const double xi = i < L.m ? x[L.r0 + i] : 0.0;
+  // unconditional loads from a valid row (rows past the leaf re-read its
+  // last one); their contributions are zeroed by a bit mask, so the loads
+  // of a lane issue together instead of one guarded load at a time
+  const bool in = i < L.m;
+  const int ic = min(i, L.m - 1);
+  const uint64_t keep = in ? ~0ull : 0ull;
+  const double xr = x[L.r0 + ic];
+  float vr[kLeafRank];
 #pragma unroll
-  for (int k = 0; k < kLeafRank; k++) prod[k][i] = i < L.m ? (double)V[i * kLeafRank + k] * xi : 0.0;
+  for (int k = 0; k < kLeafRank; k++) vr[k] = V[ic * kLeafRank + k];
+  const double xi = __longlong_as_double((long long)((uint64_t)__double_as_longlong(xr) & keep));
+#pragma unroll
+  for (int k = 0; k < kLeafRank; k++)
+    prod[k][i] = __longlong_as_double((long long)((uint64_t)__double_as_longlong((double)vr[k] * xi) & keep));
   __syncthreads();
   if (i < kLeafRank) {
     double a = 0.0;
@@ -673,7 +684,7 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
   if (poll() != hipSuccess) return fail(HMAT_E_HIP, "solver start failed");
   if (hs.bnorm == 0.0) {  // b = 0: x = 0
     hipLaunchKernelGGL(k_zero, G, B, 0, st, n, x);
-    hipStreamSynchronize(st);
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(HMAT_E_HIP, "zero solution failed");
     info->status = HMAT_OK;
     info->matvecs = nmv;
     return HMAT_OK;
@@ -747,8 +758,9 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
       hipLaunchKernelGGL(k_residual, G, B, 0, st, n, b, w.tmp, w.t, w.rt, w.part, 0);
       hipLaunchKernelGGL(k_true_norm, dim3(1), B, 0, st, w.st, w.part, true_slot);
       double tr = 0;
-      hipMemcpyAsync(&tr, true_slot, 8, hipMemcpyDeviceToHost, st);
-      if (hipStreamSynchronize(st) != hipSuccess) return fail(HMAT_E_HIP, "true residual failed");
+      if (hipMemcpyAsync(&tr, true_slot, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return fail(HMAT_E_HIP, "true residual failed");
       truerel = tr;
       if (tr < o->tol) {
         info->status = HMAT_OK;
@@ -771,8 +783,9 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
       if ((rc = mv(h_fp64, x, w.tmp, true))) return rc;
       hipLaunchKernelGGL(k_residual, G, B, 0, st, n, b, w.tmp, w.t, w.rt, w.part, 0);
       hipLaunchKernelGGL(k_true_norm, dim3(1), B, 0, st, w.st, w.part, true_slot);
-      hipMemcpyAsync(&truerel, true_slot, 8, hipMemcpyDeviceToHost, st);
-      hipStreamSynchronize(st);
+      if (hipMemcpyAsync(&truerel, true_slot, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return fail(HMAT_E_HIP, "true residual failed");
     } else {
       truerel = NAN;
     }
@@ -780,7 +793,8 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
   }
   if (o->history && hs.iter > 0) {
     const int64_t cnt = std::min<int64_t>(hs.iter, hist_cap);
-    hipMemcpyAsync(o->history + 1, w.hist + 1, cnt * 8, hipMemcpyDeviceToHost, st);
+    if (hipMemcpyAsync(o->history + 1, w.hist + 1, cnt * 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+      return fail(HMAT_E_HIP, "history copy failed");
   }
   hipError_t e = hipStreamSynchronize(st);
   info->iterations = hs.iter;

@@ -48,13 +48,20 @@ __global__ __launch_bounds__(kGThreads) void k_gemm(int M, int N, int K, const f
       int kk, mm;
       if (TA) { kk = e / kGT; mm = e % kGT; }   // A stored K x M: m fastest
       else { mm = e / kGK; kk = e % kGK; }      // A stored M x K: k fastest
+      // loads are unconditional, from clamped (valid) indices, and elements
+      // outside the matrix are zeroed by a bit mask afterwards: guarded loads
+      // would each sit in a branch that waits for it
       const int gm = m0 + mm, gk = k0 + kk;
-      As[kk][mm] = (gm < M && gk < K) ? (TA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]) : 0.0f;
+      const int cm = min(gm, M - 1), ck = min(gk, K - 1);
+      const float av = TA ? A[(int64_t)ck * lda + cm] : A[(int64_t)cm * lda + ck];
+      As[kk][mm] = __uint_as_float(__float_as_uint(av) & ((gm < M && gk < K) ? ~0u : 0u));
       int kb, nn;
       if (TB) { nn = e / kGK; kb = e % kGK; }   // B stored N x K: k fastest
       else { kb = e / kGT; nn = e % kGT; }      // B stored K x N: n fastest
       const int gn = n0 + nn, gk2 = k0 + kb;
-      Bs[kb][nn] = (gn < N && gk2 < K) ? (TB ? B[(int64_t)gn * ldb + gk2] : B[(int64_t)gk2 * ldb + gn]) : 0.0f;
+      const int cn = min(gn, N - 1), ck2 = min(gk2, K - 1);
+      const float bv = TB ? B[(int64_t)cn * ldb + ck2] : B[(int64_t)ck2 * ldb + cn];
+      Bs[kb][nn] = __uint_as_float(__float_as_uint(bv) & ((gn < N && gk2 < K) ? ~0u : 0u));
     }
     __syncthreads();
 #pragma unroll

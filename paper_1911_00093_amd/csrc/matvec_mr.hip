@@ -32,8 +32,6 @@ typedef unsigned int mr_raw __attribute__((ext_vector_type(4)));
 
 constexpr int kMRThreads = 256;  // 4 independent waves
 constexpr int kMRWaves = kMRThreads / kWave;
-constexpr int kMRMaxTiles = kRowChunk / kMRTile;  // 4
-constexpr int kMRBatchDefault = 2;  // column blocks loaded before use (hmat_autotune picks 1, 2 or 4)
 
 // value v of a 16-byte load, widened exactly to FP64
 template <int CLS>
@@ -370,11 +368,13 @@ static double time_ms(hipStream_t st, int reps, F launch) {
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1.0;
   launch();  // warm
-  hipEventRecord(a, st);
-  for (int i = 0; i < reps; i++) launch();
-  hipEventRecord(b, st);
   float ms = -1.0f;
-  if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) ms = -1.0f;
+  if (hipEventRecord(a, st) == hipSuccess) {
+    for (int i = 0; i < reps; i++) launch();
+    if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess)
+      ms = -1.0f;
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   return ms < 0 ? -1.0 : (double)ms / reps;

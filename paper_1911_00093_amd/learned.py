@@ -85,9 +85,11 @@ def train(data_dev, params0=None, epochs: int = 100, batch: int = 256, lr: float
     steps_per_epoch = max(1, n // batch)
     total = steps_per_epoch * epochs
     acc = torch.zeros(1, dtype=torch.float32, device=data_dev["x"].device)
+    # every step's sample indices go to the device at once: a copy per step
+    # from pageable memory would wait for the previous step's kernels
+    order = torch.as_tensor(np.stack(list(seeded.batch_order(n, batch, epochs, seed)))).to(data_dev["x"].device)
     step = 0
-    for idx in seeded.batch_order(n, batch, epochs, seed):
-        idx_d = torch.as_tensor(idx).to(data_dev["x"].device)
+    for idx_d in order:
         net.loss_grad(data_dev, idx_d)
         acc += net.loss
         net.adam(lr_final + (lr - lr_final) * 0.5 * (1.0 + math.cos(math.pi * step / total)))
