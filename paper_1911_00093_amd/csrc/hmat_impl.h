@@ -217,9 +217,14 @@ void packed_free(Packed *p);
 XcdSplit xcd_split(const std::vector<double> &cost);
 
 // Kernel launchers (matvec.hip)
-int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream);
+// skip: optional device flag read by every product kernel at its start; a
+// nonzero value makes the product a no-op (a solver whose recurrence has
+// stopped inside a batch of queued iterations).
+int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream,
+                  const int32_t *skip = nullptr);
 int size_grids(hmat_s *h);
-int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream);
+int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream,
+                     const int32_t *skip = nullptr);
 int size_grids_mr(hmat_s *h);
 
 // Kernel timing (diag.hip): mark(h, k, stream) records event k (0..3) of the

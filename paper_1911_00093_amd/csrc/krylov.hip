@@ -37,6 +37,7 @@ struct SolverState {
   int32_t restart;  // next iteration starts with p = r
   int64_t iter;
   int64_t maxiter;
+  int64_t runs;     // iterations that ran (their two products included)
 };
 
 // workspace: vectors, two banks of partial sums, residual history, status
@@ -282,6 +283,7 @@ __global__ void k_finalize(SolverState *__restrict__ st, const double *__restric
   double q[2];
   sum_parts<2>(aux, sl, q, lds);
   if (threadIdx.x != 0) return;
+  st->runs += 1;  // the flag was 0 for the whole iteration: its products ran
   const int mode = (int)aux[kParts * 4 + 0];
   const double omega = aux[kParts * 4 + 1];
   const double snorm = aux[kParts * 4 + 2];
@@ -663,9 +665,16 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
   double *ph = pre ? w.ph : w.p;
   double *sh = pre ? w.sh : w.s;
 
-  // products outside the iteration: r_0 with h_iter, true residuals with h_fp64
+  // products of the iteration are skipped on the device once the recurrence
+  // has stopped (the rest of a poll window); they are counted from
+  // SolverState::runs.  Products outside it: r_0 with h_iter, true residuals
+  // with h_fp64.
+  const int32_t *stopped = &w.st->flag;
+  auto product = [&](hmat_t h, const double *in, double *outv, hipStream_t s2, const int32_t *skip) {
+    return h->mr ? launch_matvec_mr(h, in, outv, 1, n, s2, skip) : launch_matvec(h, in, outv, 1, n, s2, skip);
+  };
   auto mv = [&](hmat_t h, const double *in, double *outv, bool fp64) {
-    int r2 = launch_matvec(h, in, outv, 1, n, st);
+    int r2 = product(h, in, outv, st, nullptr);
     if (fp64) nmv64++;
     else nmv++;
     return r2;
@@ -694,12 +703,12 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
   auto iteration = [&](hipStream_t s2) -> int {
     hipLaunchKernelGGL(k_pupdate, G, B, 0, s2, n, w.st, w.r, w.p, w.v);
     if (pre) hmat_precond_apply(o->precond, w.p, w.ph, s2);
-    int r2 = launch_matvec(h_iter, ph, w.v, 1, n, s2);
+    int r2 = product(h_iter, ph, w.v, s2, stopped);
     if (r2) return r2;
     hipLaunchKernelGGL(k_dot_rtv, G, B, 0, s2, n, w.st, w.rt, w.v, w.part);
     hipLaunchKernelGGL(k_supdate, G, B, 0, s2, n, w.st, w.r, w.v, w.s, w.part);
     if (pre) hmat_precond_apply(o->precond, w.s, w.sh, s2);
-    if ((r2 = launch_matvec(h_iter, sh, w.t, 1, n, s2))) return r2;
+    if ((r2 = product(h_iter, sh, w.t, s2, stopped))) return r2;
     hipLaunchKernelGGL(k_dot_t, G, B, 0, s2, n, w.st, w.t, w.s, w.part);
     hipLaunchKernelGGL(k_xupdate, G, B, 0, s2, n, w.st, x, w.r, w.rt, ph, w.s, sh, w.t, w.part, bank);
     hipLaunchKernelGGL(k_finalize, dim3(1), B, 0, s2, w.st, bank, w.hist);
@@ -745,7 +754,6 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
         } else if ((rc = iteration(st))) {
           return rc;
         }
-        nmv += 2;
       }
       launched += todo;
       if (poll() != hipSuccess) return fail(HMAT_E_HIP, "solver iteration failed: %s", hipGetErrorString(hipGetLastError()));
@@ -799,7 +807,7 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
   hipError_t e = hipStreamSynchronize(st);
   info->iterations = hs.iter;
   info->restarts = restarts;
-  info->matvecs = nmv;
+  info->matvecs = nmv + 2 * hs.runs;
   info->matvecs_fp64 = nmv64;
   info->rel_res = hs.relres;
   info->true_rel_res = truerel;

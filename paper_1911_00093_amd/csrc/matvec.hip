@@ -156,7 +156,8 @@ __device__ __forceinline__ void s1_item(const S1Item &it, const void *vals, cons
 template <int CLS>
 __global__ __launch_bounds__(256) void k_stage1(
     const S1Item *__restrict__ items, int64_t nitems, const void *__restrict__ vals, const double *__restrict__ x,
-    int64_t ldx, int x32, double *__restrict__ zpart, int64_t zpart_len) {
+    int64_t ldx, int x32, double *__restrict__ zpart, int64_t zpart_len, const int32_t *__restrict__ skip) {
+  if (skip && *skip) return;  // the caller's recurrence has stopped: nothing to compute
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t rhs = blockIdx.y;
   const double *xr = x + rhs * ldx;
@@ -174,7 +175,9 @@ __global__ __launch_bounds__(256) void k_stage1b(int64_t n, int64_t zlen, const 
                                                  int64_t ldx, int x32, int z32, const ZInfo *__restrict__ zi,
                                                  const double *__restrict__ dscale,
                                                  const double *__restrict__ zpart, int64_t zpart_len,
-                                                 double *__restrict__ src, int64_t src_len) {
+                                                 double *__restrict__ src, int64_t src_len,
+                                                 const int32_t *__restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t rhs = blockIdx.y;
   double *s = src + rhs * src_len;
@@ -184,10 +187,22 @@ __global__ __launch_bounds__(256) void k_stage1b(int64_t n, int64_t zlen, const 
   } else if (i < n + zlen) {
     const int64_t j = i - n;
     const ZInfo q = zi[j];
+    const double d = dscale[j];
     const double *zp = zpart + rhs * zpart_len + q.zp;
+    // partials in chunk order, eight loads in flight at a time (indices past
+    // the last chunk repeat it and are not added)
     double acc = 0.0;
-    for (int c = 0; c < q.nch; c++) acc += zp[(int64_t)c * q.stride];
-    acc *= dscale[j];
+    for (int c0 = 0; c0 < q.nch; c0 += 8) {
+      double p[8];
+#pragma unroll
+      for (int e = 0; e < 8; e++) p[e] = zp[(int64_t)min(c0 + e, q.nch - 1) * q.stride];
+#pragma unroll
+      for (int e = 0; e < 8; e++) {
+        const double t = acc + p[e];
+        acc = c0 + e < q.nch ? t : acc;
+      }
+    }
+    acc *= d;
     s[i] = z32 ? (double)(float)acc : acc;
   } else if (i == n + zlen) {
     s[i] = 0.0;
@@ -399,13 +414,14 @@ __device__ __forceinline__ void s2_body(const RowChunk *__restrict__ chunks, int
   const RowChunk *__restrict__ chunks, int64_t nchunks, const double *__restrict__ v64,                         \
       const float *__restrict__ v32, const unsigned short *__restrict__ v16, const int32_t *__restrict__ g64,   \
       const int32_t *__restrict__ g32, const int32_t *__restrict__ g16, const double *__restrict__ src,         \
-      int64_t src_len, double *__restrict__ y, int64_t ldy
+      int64_t src_len, double *__restrict__ y, int64_t ldy, const int32_t *__restrict__ skip
 #define HM_S2_PASS chunks, nchunks, v64, v32, v16, g64, g32, g16, src, src_len, y, ldy
 
 // One storage class: double-buffered operand tiles.
 template <int MASK>
 __global__ __launch_bounds__(kS2Threads, 4) void k_stage2(HM_S2_ARGS) {
   static_assert(MASK == 1 || MASK == 2 || MASK == 4, "one class");
+  if (skip && *skip) return;
   constexpr int CLS = MASK == 1 ? F64 : MASK == 2 ? F32 : BF16;
   const void *vals = CLS == F64 ? (const void *)v64 : CLS == F32 ? (const void *)v32 : (const void *)v16;
   const int32_t *gidx = CLS == F64 ? g64 : CLS == F32 ? g32 : g16;
@@ -414,6 +430,7 @@ __global__ __launch_bounds__(kS2Threads, 4) void k_stage2(HM_S2_ARGS) {
 // Two or three classes: let the compiler size the registers (no spills).
 template <int MASK>
 __global__ __launch_bounds__(kS2Threads) void k_stage2_multi(HM_S2_ARGS) {
+  if (skip && *skip) return;
   s2_body<MASK>(HM_S2_PASS);
 }
 
@@ -421,7 +438,7 @@ static_assert(kRowChunk == kS2Waves * kRowsPerLane, "each wave owns 8 rows of a 
 
 typedef void (*Stage2Fn)(const RowChunk *, int64_t, const double *, const float *, const unsigned short *,
                          const int32_t *, const int32_t *, const int32_t *, const double *, int64_t, double *,
-                         int64_t);
+                         int64_t, const int32_t *);
 static Stage2Fn stage2_fn(int mask) {
   switch (mask) {
     case 1: return k_stage2<1>;
@@ -433,7 +450,8 @@ static Stage2Fn stage2_fn(int mask) {
     default: return k_stage2_multi<7>;
   }
 }
-typedef void (*Stage1Fn)(const S1Item *, int64_t, const void *, const double *, int64_t, int, double *, int64_t);
+typedef void (*Stage1Fn)(const S1Item *, int64_t, const void *, const double *, int64_t, int, double *, int64_t,
+                         const int32_t *);
 static Stage1Fn stage1_fn(int cls) { return cls == F64 ? k_stage1<F64> : cls == F32 ? k_stage1<F32> : k_stage1<BF16>; }
 
 // Persistent grid sizes: as many workgroups as fit on the device at once
@@ -454,7 +472,8 @@ int size_grids(hmat_s *h) {
   return HMAT_OK;
 }
 
-int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream) {
+int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream,
+                  const int32_t *skip) {
   hipStream_t st = (hipStream_t)stream;
   const dim3 blk(256);
   prof_mark(h, 0, stream);
@@ -463,20 +482,20 @@ int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int
     if (cnt <= 0) continue;
     hipLaunchKernelGGL(stage1_fn(c), dim3((unsigned)h->grid1[c], (unsigned)nrhs), blk, 0, st,
                        h->items + h->item_begin[c], cnt, (const void *)h->vals[c], x, ld, h->x32, h->zpart,
-                       h->zpart_len);
+                       h->zpart_len, skip);
   }
   prof_mark(h, 1, stream);
   {
     const int64_t tot = h->n + h->zlen + 1;
     dim3 grd((unsigned)((tot + 255) / 256), (unsigned)nrhs);
     hipLaunchKernelGGL(k_stage1b, grd, blk, 0, st, h->n, h->zlen, x, ld, h->x32, h->z32, h->zinfo, h->dscale,
-                       h->zpart, h->zpart_len, h->src, h->src_len);
+                       h->zpart, h->zpart_len, h->src, h->src_len, skip);
   }
   prof_mark(h, 2, stream);
   hipLaunchKernelGGL(stage2_fn(h->cls_mask), dim3((unsigned)h->grid2, (unsigned)nrhs), dim3(kS2Threads), 0, st, h->chunks,
                      h->nchunks, (const double *)h->vals[F64], (const float *)h->vals[F32],
                      (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16], h->src,
-                     h->src_len, y, ld);
+                     h->src_len, y, ld, skip);
   prof_mark(h, 3, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(HMAT_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));

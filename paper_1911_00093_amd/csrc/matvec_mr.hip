@@ -63,7 +63,9 @@ __device__ __forceinline__ int mr_row(int lane, int e) { return (lane >> 4) + 4 
 
 // ----------------------------------------------------------------- K0
 __global__ __launch_bounds__(256) void k_mr_prologue(int64_t n, int64_t nrhs, const double *__restrict__ x,
-                                                     int64_t ldx, int x32, double *__restrict__ s64) {
+                                                     int64_t ldx, int x32, double *__restrict__ s64,
+                                                     const int32_t *__restrict__ skip) {
+  if (skip && *skip) return;  // the caller's recurrence has stopped
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * kMRhs) return;
   const int64_t i = e / kMRhs, r = e % kMRhs;
@@ -145,7 +147,9 @@ template <int CLS, int NB>
 __global__ __launch_bounds__(kMRThreads) void k_mr_stage1(const MRItem *__restrict__ items, XcdSplit sp,
                                                           const void *__restrict__ vals, int64_t n, int z32,
                                                           const double *__restrict__ dscale,
-                                                          double *__restrict__ s64, double *__restrict__ zpart) {
+                                                          double *__restrict__ s64, double *__restrict__ zpart,
+                                                          const int32_t *__restrict__ skip) {
+  if (skip && *skip) return;
   const int lane = threadIdx.x & (kWave - 1);
   XCD_UNIT_LOOP(q, sp) {
     const MRItem it = items[q];
@@ -161,7 +165,9 @@ __global__ __launch_bounds__(kMRThreads) void k_mr_stage1(const MRItem *__restri
 // ---------------------------------------------------------------- K1b
 __global__ __launch_bounds__(256) void k_mr_stage1b(int64_t n, int64_t zlen, int z32, const ZInfo *__restrict__ zi,
                                                     const double *__restrict__ dscale,
-                                                    const double *__restrict__ zpart, double *__restrict__ s64) {
+                                                    const double *__restrict__ zpart, double *__restrict__ s64,
+                                                    const int32_t *__restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (zlen + 1) * kMRhs) return;
   const int64_t j = e / kMRhs, r = e % kMRhs;
@@ -169,8 +175,20 @@ __global__ __launch_bounds__(256) void k_mr_stage1b(int64_t n, int64_t zlen, int
   if (j < zlen) {
     const ZInfo q = zi[j];
     if (q.nch == 1) return;  // finished by stage 1
-    for (int c = 0; c < q.nch; c++) acc += zpart[(q.zp + (int64_t)c * q.stride) * kMRhs + r];
-    acc *= dscale[j];
+    const double d = dscale[j];
+    // partials in chunk order, eight loads in flight at a time (indices past
+    // the last chunk repeat it and are not added)
+    for (int c0 = 0; c0 < q.nch; c0 += 8) {
+      double p[8];
+#pragma unroll
+      for (int u = 0; u < 8; u++) p[u] = zpart[(q.zp + (int64_t)min(c0 + u, q.nch - 1) * q.stride) * kMRhs + r];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        const double t = acc + p[u];
+        acc = c0 + u < q.nch ? t : acc;
+      }
+    }
+    acc *= d;
     if (z32) acc = (double)(float)acc;
   }
   s64[(n + j) * kMRhs + r] = acc;  // j == zlen: the zero slot
@@ -265,7 +283,8 @@ __global__ __launch_bounds__(kMRThreads) void k_mr_stage2(const MRChunk *__restr
                                                           const int32_t *__restrict__ g64, const int32_t *__restrict__ g32,
                                                           const int32_t *__restrict__ g16,
                                                           const double *__restrict__ s64, double *__restrict__ y,
-                                                          int64_t ldy, int64_t nrhs) {
+                                                          int64_t ldy, int64_t nrhs, const int32_t *__restrict__ skip) {
+  if (skip && *skip) return;
   const int lane = threadIdx.x & (kWave - 1);
   XCD_UNIT_LOOP(q, sp) {
     const MRChunk ch = chunks[q];
@@ -281,7 +300,7 @@ __global__ __launch_bounds__(kMRThreads) void k_mr_stage2(const MRChunk *__restr
 // ------------------------------------------------------------- launch
 typedef void (*MRStage2Fn)(const MRChunk *, XcdSplit, const double *, const float *, const unsigned short *,
                            const int32_t *, const int32_t *, const int32_t *, const double *, double *, int64_t,
-                           int64_t);
+                           int64_t, const int32_t *);
 template <int NB>
 static MRStage2Fn mr_stage2_nb(int mask) {
   switch (mask) {
@@ -297,7 +316,8 @@ static MRStage2Fn mr_stage2_nb(int mask) {
 static MRStage2Fn mr_stage2_fn(int mask, int nb) {
   return nb == 1 ? mr_stage2_nb<1>(mask) : nb == 4 ? mr_stage2_nb<4>(mask) : mr_stage2_nb<2>(mask);
 }
-typedef void (*MRStage1Fn)(const MRItem *, XcdSplit, const void *, int64_t, int, const double *, double *, double *);
+typedef void (*MRStage1Fn)(const MRItem *, XcdSplit, const void *, int64_t, int, const double *, double *, double *,
+                           const int32_t *);
 template <int NB>
 static MRStage1Fn mr_stage1_nb(int cls) {
   return cls == F64 ? k_mr_stage1<F64, NB> : cls == F32 ? k_mr_stage1<F32, NB> : k_mr_stage1<BF16, NB>;
@@ -325,7 +345,8 @@ int size_grids_mr(hmat_s *h) {
   return HMAT_OK;
 }
 
-int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream) {
+int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream,
+                     const int32_t *skip) {
   hipStream_t st = (hipStream_t)stream;
   for (int64_t r0 = 0; r0 < nrhs; r0 += kMRhs) {
     const int64_t nr = std::min<int64_t>(kMRhs, nrhs - r0);
@@ -335,26 +356,26 @@ int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, 
     {
       const int64_t tot = h->n * kMRhs;
       hipLaunchKernelGGL(k_mr_prologue, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, h->n, nr, xr, ld,
-                         h->x32, h->src64);
+                         h->x32, h->src64, skip);
     }
     for (int c = 0; c < NCLS; c++) {
       if (h->mr_nitems[c] <= 0) continue;
       hipLaunchKernelGGL(mr_stage1_fn(c, h->mr_nb1[c]), dim3((unsigned)h->mr_grid1[c]), dim3(kMRThreads), 0, st,
                          h->mri + h->mr_item_begin[c], h->mr_split1[c], (const void *)h->vals[c], h->n, h->z32,
-                         h->dscale, h->src64, h->zpart);
+                         h->dscale, h->src64, h->zpart, skip);
     }
     prof_mark(h, 1, stream);
     {
       const int64_t tot = (h->zlen + 1) * kMRhs;
       hipLaunchKernelGGL(k_mr_stage1b, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, h->n, h->zlen, h->z32,
-                         h->zinfo, h->dscale, h->zpart, h->src64);
+                         h->zinfo, h->dscale, h->zpart, h->src64, skip);
     }
     prof_mark(h, 2, stream);
     hipLaunchKernelGGL(mr_stage2_fn(h->cls_mask, h->mr_nb2), dim3((unsigned)h->mr_grid2), dim3(kMRThreads), 0, st,
                        h->mrc,
                        h->mr_split2, (const double *)h->vals[F64], (const float *)h->vals[F32],
                        (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16], h->src64,
-                       yr, ld, nr);
+                       yr, ld, nr, skip);
     prof_mark(h, 3, stream);
   }
   hipError_t e = hipGetLastError();
@@ -409,7 +430,7 @@ extern "C" int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps,
         const double t = time_ms(st, reps, [&]() {
           hipLaunchKernelGGL(mr_stage1_fn(c, nb), dim3((unsigned)h->mr_grid1[c]), dim3(kMRThreads), 0, st,
                              h->mri + h->mr_item_begin[c], h->mr_split1[c], (const void *)h->vals[c], h->n, h->z32,
-                             h->dscale, h->src64, h->zpart);
+                             h->dscale, h->src64, h->zpart, nullptr);
         });
         if (t >= 0 && t < best) {
           best = t;
@@ -436,7 +457,7 @@ extern "C" int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps,
           hipLaunchKernelGGL(mr_stage2_fn(h->cls_mask, nb), dim3((unsigned)h->mr_grid2), dim3(kMRThreads), 0, st,
                              h->mrc, h->mr_split2, (const double *)h->vals[F64], (const float *)h->vals[F32],
                              (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16],
-                             h->src64, y, n, nr);
+                             h->src64, y, n, nr, nullptr);
         });
         if (t >= 0 && t < best) {
           best = t;

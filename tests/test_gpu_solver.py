@@ -117,16 +117,26 @@ def test_bicgstab_nonfinite():
     assert info["status"] in (hmat.HMAT_E_NONFINITE, hmat.HMAT_E_BREAKDOWN)
 
 
-def test_bicgstab_poll_every_same_result():
+@pytest.mark.parametrize("nrhs_max", [1, 16])
+def test_bicgstab_poll_every_same_result(nrhs_max):
+    """Iterations queued past convergence (the rest of a poll window) are
+    no-ops on the device, products included: the same x bit for bit and the
+    same product count whatever the window; a multi-RHS handle (matrix-core
+    product) serves the single solver too."""
     need_gpu()
     m, h = oracle_hmatrix("sphere-L4")
     b = to_dev(m.rhs()[h.perm])
-    H = hmat.HMatrix(blockset(h), oracle.M2_MIXED)
-    H64 = hmat.HMatrix(blockset(h), oracle.M1_DOUBLE)
+    H = hmat.HMatrix(blockset(h), oracle.M2_MIXED, nrhs_max=nrhs_max)
+    H64 = hmat.HMatrix(blockset(h), oracle.M1_DOUBLE, nrhs_max=nrhs_max)
     x1, i1 = hmat.hmat_bicgstab(H, b, h_fp64=H64, poll_every=1)
     x5, i5 = hmat.hmat_bicgstab(H, b, h_fp64=H64, poll_every=5)
-    assert i1["iterations"] == i5["iterations"]
+    x7, i7 = hmat.hmat_bicgstab(H, b, h_fp64=H64, poll_every=7, use_graph=True)
+    print(i1, i5, i7)
+    assert i1["status"] == 0 and i1["iterations"] == i5["iterations"] == i7["iterations"]
+    assert i1["matvecs"] == i5["matvecs"] == i7["matvecs"] == 1 + 2 * i1["iterations"]
+    assert i1["matvecs_fp64"] == i5["matvecs_fp64"] == i7["matvecs_fp64"]
     assert np.array_equal(x1.cpu().numpy(), x5.cpu().numpy())
+    assert np.array_equal(x1.cpu().numpy(), x7.cpu().numpy())
 
 
 def test_jacobi_apply_and_preconditioned_solve():
