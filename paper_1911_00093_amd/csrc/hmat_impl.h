@@ -216,12 +216,30 @@ int pack_into(Packed *p, std::vector<unsigned char> &staging, hmat_s *h);
 void packed_free(Packed *p);
 XcdSplit xcd_split(const std::vector<double> &cost);
 
+// Inner products of the product's result y, fused into stage 2 (one
+// right-hand side): every stage-2 workgroup b sums, over the rows it
+// writes, y_i w1_i (mode 1) or y_i y_i and y_i w2_i (mode 2), and writes the
+// sums to part[4 b + slot], slot = slot0 and slot0 + 1; workgroup 0 also
+// zeroes those slots of the workgroups b in [grid2, nparts), so a consumer
+// can always sum nparts partials in index order.
+struct S2Dot {
+  const double *w1, *w2;
+  double *part;
+  int32_t mode;   // 0 none, 1 y.w1, 2 y.y and y.w2
+  int32_t slot0;  // first slot of part[4 b + ...]
+  int32_t nparts;
+  int32_t pad;
+};
+
 // Kernel launchers (matvec.hip)
 // skip: optional device flag read by every product kernel at its start; a
 // nonzero value makes the product a no-op (a solver whose recurrence has
 // stopped inside a batch of queued iterations).
+// dot: optional fused inner products (single-vector handles, nrhs == 1,
+// grid2 <= dot->nparts: see matvec_dot_fusable).
 int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream,
-                  const int32_t *skip = nullptr);
+                  const int32_t *skip = nullptr, const S2Dot *dot = nullptr);
+bool matvec_dot_fusable(const hmat_s *h, int nparts);
 int size_grids(hmat_s *h);
 int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream,
                      const int32_t *skip = nullptr);

@@ -7,7 +7,9 @@
 // in the same fixed order, so all workgroups derive bit-identical scalars
 // (alpha, omega, breakdown decisions) without a separate reduction launch.
 // One small single-workgroup kernel per iteration ("finalize") owns the
-// status word; the host reads it every `poll_every` iterations.
+// status word; the host reads it every `poll_every` iterations.  On
+// single-vector handles the two inner products of the product results are
+// taken by the products' stage 2 itself (one partial per stage-2 workgroup).
 //
 // Per iteration (right preconditioning with K; K = I when none):
 //   p <- r (restart) or r + beta (p - omega v);  p^ = K p
@@ -700,16 +702,23 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
   }
   if (o->history) o->history[0] = hs.relres;
   // one iteration of Algorithm 1 (K = precond, identity when none)
+  // On single-vector handles the inner products r~^T v and t^T t, t^T s are
+  // fused into the products' stage 2 (one partial per stage-2 workgroup, in
+  // the same partial slots the separate kernels fill).
+  const bool fuse = matvec_dot_fusable(h_iter, kParts);
+  const S2Dot dot_v{w.rt, nullptr, w.part, 1, 0, kParts, 0};  // slot 0: r~^T v
+  const S2Dot dot_t{nullptr, w.s, w.part, 2, 2, kParts, 0};   // slots 2, 3: t^T t, t^T s
   auto iteration = [&](hipStream_t s2) -> int {
     hipLaunchKernelGGL(k_pupdate, G, B, 0, s2, n, w.st, w.r, w.p, w.v);
     if (pre) hmat_precond_apply(o->precond, w.p, w.ph, s2);
-    int r2 = product(h_iter, ph, w.v, s2, stopped);
+    int r2 = fuse ? launch_matvec(h_iter, ph, w.v, 1, n, s2, stopped, &dot_v) : product(h_iter, ph, w.v, s2, stopped);
     if (r2) return r2;
-    hipLaunchKernelGGL(k_dot_rtv, G, B, 0, s2, n, w.st, w.rt, w.v, w.part);
+    if (!fuse) hipLaunchKernelGGL(k_dot_rtv, G, B, 0, s2, n, w.st, w.rt, w.v, w.part);
     hipLaunchKernelGGL(k_supdate, G, B, 0, s2, n, w.st, w.r, w.v, w.s, w.part);
     if (pre) hmat_precond_apply(o->precond, w.s, w.sh, s2);
-    if ((r2 = product(h_iter, sh, w.t, s2, stopped))) return r2;
-    hipLaunchKernelGGL(k_dot_t, G, B, 0, s2, n, w.st, w.t, w.s, w.part);
+    r2 = fuse ? launch_matvec(h_iter, sh, w.t, 1, n, s2, stopped, &dot_t) : product(h_iter, sh, w.t, s2, stopped);
+    if (r2) return r2;
+    if (!fuse) hipLaunchKernelGGL(k_dot_t, G, B, 0, s2, n, w.st, w.t, w.s, w.part);
     hipLaunchKernelGGL(k_xupdate, G, B, 0, s2, n, w.st, x, w.r, w.rt, ph, w.s, sh, w.t, w.part, bank);
     hipLaunchKernelGGL(k_finalize, dim3(1), B, 0, s2, w.st, bank, w.hist);
     return HMAT_OK;

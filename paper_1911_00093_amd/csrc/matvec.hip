@@ -289,12 +289,54 @@ __device__ __forceinline__ void s2_class(const RowChunk &ch, const void *vals, c
   }
 }
 
-// Chunk rows to y: one reduction per row, each row written once.
-__device__ __forceinline__ void s2_write(int r0, int h, double (&acc)[kRowsPerLane], double *y, int wave, int lane) {
+// Chunk rows to y: one reduction per row, each row written once; the fused
+// inner products (S2Dot) take each row's value as it is written.
+__device__ __forceinline__ void s2_write(int r0, int h, double (&acc)[kRowsPerLane], double *y, int wave, int lane,
+                                         const S2Dot &dot, double (&dacc)[2]) {
   const double sum = reduce_rows(acc, lane, kWave);
   if ((lane & 7) == 0) {
     const int row = wave + kS2Waves * (lane >> 3);
-    if (row < h) y[r0 + row] = sum;
+    if (row < h) {
+      y[r0 + row] = sum;
+      if (dot.mode == 1) {
+        dacc[0] += sum * dot.w1[r0 + row];
+      } else if (dot.mode == 2) {
+        dacc[0] += sum * sum;
+        dacc[1] += sum * dot.w2[r0 + row];
+      }
+    }
+  }
+}
+
+// The workgroup's fused inner products: fixed-order reduction over its
+// threads, one partial per workgroup (and zeros for the slots of workgroups
+// beyond the grid).  Called by every thread of the workgroup.
+__device__ __forceinline__ void s2_dot_finish(const S2Dot &dot, double (&dacc)[2]) {
+  if (dot.mode == 0) return;  // uniform
+  __shared__ double red[2][kS2Waves];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int q = 0; q < 2; q++)
+#pragma unroll
+    for (int m = kWave / 2; m >= 1; m >>= 1) dacc[q] += __shfl_xor(dacc[q], m, kWave);
+  if (lane == 0) {
+    red[0][wave] = dacc[0];
+    red[1][wave] = dacc[1];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < kS2Waves; w++) {
+      a += red[0][w];
+      b += red[1][w];
+    }
+    dot.part[4 * blockIdx.x + dot.slot0] = a;
+    if (dot.mode == 2) dot.part[4 * blockIdx.x + dot.slot0 + 1] = b;
+    if (blockIdx.x == 0)
+      for (int g = gridDim.x; g < dot.nparts; g++) {
+        dot.part[4 * g + dot.slot0] = 0.0;
+        if (dot.mode == 2) dot.part[4 * g + dot.slot0 + 1] = 0.0;
+      }
   }
 }
 
@@ -319,14 +361,19 @@ __device__ __forceinline__ S2Cur s2_cur(const RowChunk *chunks, int64_t c) {
 template <int CLS>
 __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, int64_t nchunks,
                                           const void *__restrict__ vals, const int32_t *__restrict__ gidx,
-                                          const double *__restrict__ src, double *__restrict__ y) {
+                                          const double *__restrict__ src, double *__restrict__ y,
+                                          const S2Dot &dot) {
   constexpr int SLAB = kWave * vec_of(CLS);
   constexpr int PER = kS2Tile / kS2Threads;  // gathered operands per thread and tile
   static_assert(kS2Tile % kS2Threads == 0 && kS2Tile % SLAB == 0, "whole slabs, equal shares");
   __shared__ double gbuf[2][kS2Tile];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
+  double dacc[2] = {0.0, 0.0};
   int64_t c = blockIdx.x;
-  if (c >= nchunks) return;  // uniform over the workgroup
+  if (c >= nchunks) {  // uniform over the workgroup
+    s2_dot_finish(dot, dacc);
+    return;
+  }
   S2Cur ch = s2_cur<CLS>(chunks, c);
   int kt0 = 0;
   s2_gather(gidx + ch.gidx_off, min(kS2Tile, ch.ld), src, gbuf[0]);
@@ -367,7 +414,7 @@ __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, i
     for (int j = 0; j < PER; j++) pre[j] = src[gn[j]];
     s2_slabs<CLS>(ch.panel_off, ch.ld, ch.h, vals, gt, kt0, first, kn, acc, wave, lane);
     if (!same) {  // the chunk is complete
-      s2_write(ch.r0, ch.h, acc, y, wave, lane);
+      s2_write(ch.r0, ch.h, acc, y, wave, lane, dot, dacc);
 #pragma unroll
       for (int i = 0; i < kRowsPerLane; i++) acc[i] = 0.0;
     }
@@ -384,6 +431,7 @@ __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, i
     kt0 = nkt;
     ch = nx;
   }
+  s2_dot_finish(dot, dacc);
 }
 
 template <int MASK>
@@ -392,8 +440,9 @@ __device__ __forceinline__ void s2_body(const RowChunk *__restrict__ chunks, int
                                         const unsigned short *__restrict__ v16, const int32_t *__restrict__ g64,
                                         const int32_t *__restrict__ g32, const int32_t *__restrict__ g16,
                                         const double *__restrict__ src, int64_t src_len, double *__restrict__ y,
-                                        int64_t ldy) {
+                                        int64_t ldy, const S2Dot &dot) {
   __shared__ double gbuf[kS2Tile];
+  double dacc[2] = {0.0, 0.0};
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   const int64_t rhs = blockIdx.y;
   const double *s = src + rhs * src_len;
@@ -406,16 +455,17 @@ __device__ __forceinline__ void s2_body(const RowChunk *__restrict__ chunks, int
     if constexpr ((MASK & 1) != 0) s2_class<F64>(ch, v64, g64, s, gbuf, acc, wave, lane);
     if constexpr ((MASK & 2) != 0) s2_class<F32>(ch, v32, g32, s, gbuf, acc, wave, lane);
     if constexpr ((MASK & 4) != 0) s2_class<BF16>(ch, v16, g16, s, gbuf, acc, wave, lane);
-    s2_write(ch.r0, ch.h, acc, y + rhs * ldy, wave, lane);
+    s2_write(ch.r0, ch.h, acc, y + rhs * ldy, wave, lane, dot, dacc);
   }
+  s2_dot_finish(dot, dacc);
 }
 
 #define HM_S2_ARGS                                                                                              \
   const RowChunk *__restrict__ chunks, int64_t nchunks, const double *__restrict__ v64,                         \
       const float *__restrict__ v32, const unsigned short *__restrict__ v16, const int32_t *__restrict__ g64,   \
       const int32_t *__restrict__ g32, const int32_t *__restrict__ g16, const double *__restrict__ src,         \
-      int64_t src_len, double *__restrict__ y, int64_t ldy, const int32_t *__restrict__ skip
-#define HM_S2_PASS chunks, nchunks, v64, v32, v16, g64, g32, g16, src, src_len, y, ldy
+      int64_t src_len, double *__restrict__ y, int64_t ldy, const int32_t *__restrict__ skip, S2Dot dot
+#define HM_S2_PASS chunks, nchunks, v64, v32, v16, g64, g32, g16, src, src_len, y, ldy, dot
 
 // One storage class: double-buffered operand tiles.
 template <int MASK>
@@ -425,7 +475,7 @@ __global__ __launch_bounds__(kS2Threads, 4) void k_stage2(HM_S2_ARGS) {
   constexpr int CLS = MASK == 1 ? F64 : MASK == 2 ? F32 : BF16;
   const void *vals = CLS == F64 ? (const void *)v64 : CLS == F32 ? (const void *)v32 : (const void *)v16;
   const int32_t *gidx = CLS == F64 ? g64 : CLS == F32 ? g32 : g16;
-  s2_single<CLS>(chunks, nchunks, vals, gidx, src + blockIdx.y * src_len, y + blockIdx.y * ldy);
+  s2_single<CLS>(chunks, nchunks, vals, gidx, src + blockIdx.y * src_len, y + blockIdx.y * ldy, dot);
 }
 // Two or three classes: let the compiler size the registers (no spills).
 template <int MASK>
@@ -438,7 +488,7 @@ static_assert(kRowChunk == kS2Waves * kRowsPerLane, "each wave owns 8 rows of a 
 
 typedef void (*Stage2Fn)(const RowChunk *, int64_t, const double *, const float *, const unsigned short *,
                          const int32_t *, const int32_t *, const int32_t *, const double *, int64_t, double *,
-                         int64_t, const int32_t *);
+                         int64_t, const int32_t *, S2Dot);
 static Stage2Fn stage2_fn(int mask) {
   switch (mask) {
     case 1: return k_stage2<1>;
@@ -472,8 +522,16 @@ int size_grids(hmat_s *h) {
   return HMAT_OK;
 }
 
+bool matvec_dot_fusable(const hmat_s *h, int nparts) { return !h->mr && h->grid2 >= 1 && h->grid2 <= nparts; }
+
 int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream,
-                  const int32_t *skip) {
+                  const int32_t *skip, const S2Dot *dot) {
+  S2Dot d{};
+  if (dot && dot->mode != 0) {
+    if (nrhs != 1 || !matvec_dot_fusable(h, dot->nparts))
+      return fail(HMAT_E_ARG, "fused inner products need one right-hand side and a stage-2 grid within the partials");
+    d = *dot;
+  }
   hipStream_t st = (hipStream_t)stream;
   const dim3 blk(256);
   prof_mark(h, 0, stream);
@@ -495,7 +553,7 @@ int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int
   hipLaunchKernelGGL(stage2_fn(h->cls_mask), dim3((unsigned)h->grid2, (unsigned)nrhs), dim3(kS2Threads), 0, st, h->chunks,
                      h->nchunks, (const double *)h->vals[F64], (const float *)h->vals[F32],
                      (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16], h->src,
-                     h->src_len, y, ld, skip);
+                     h->src_len, y, ld, skip, d);
   prof_mark(h, 3, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(HMAT_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
