@@ -347,6 +347,21 @@ def bench_batched(args, W, variant, dev, stream):
     stm, st64 = Hm.stats(), H64.stats()
     Bm, Bm2 = mr_product_bytes(stm, nrhs, variant)
     B64, _ = mr_product_bytes(st64, nrhs, hmat.M1_DOUBLE)
+    # per-system bytes of a 16-column product (the products skip the systems
+    # whose recurrences have all stopped, so work is counted per system)
+    def system_bytes(precision, c):
+        xs = 4 if precision in (hmat.M1_SINGLE, hmat.M2_SINGLE) else 8
+        out = []
+        for bs_ in bss:
+            pl = hmat.hmat_plan(bs_, precision, c, nrhs)
+            zd = pl.algorithmic_bytes - pl.matrix_bytes - xs * bs_.n - 8 * bs_.n
+            out.append(pl.matrix_bytes + zd + nrhs * 16 * bs_.n)
+        return np.array(out, dtype=np.float64)
+
+    Bsys, Bsys64 = system_bytes(variant, -1), system_bytes(hmat.M1_DOUBLE, 0)
+    for nm, tot, ref in (("mixed", Bsys.sum(), Bm), ("fp64", Bsys64.sum(), B64)):
+        if abs(tot - ref) > 1e-9 * ref:
+            log(f"[warn] {nm}: per-system bytes {tot:.0f} != handle bytes {ref:.0f}")
     rng = np.random.default_rng(1)
     b = torch.as_tensor(rng.standard_normal((nrhs, n))).to(dev).T  # (n, nrhs), column-major
     work = torch.empty(hmat.hmat_bicgstab_batched_workspace_bytes(Hm, nrhs), dtype=torch.uint8, device=dev)
@@ -371,7 +386,9 @@ def bench_batched(args, W, variant, dev, stream):
     t_mixed = time.perf_counter() - t_start
     for _, summ, per in runs:
         assert summ["status"] == 0, summ
-    mv_bytes = sum(s["matvecs"] * Bm + s["matvecs_fp64"] * B64 for _, s, _ in runs)
+    # executed work: each system's products (results[].products) and the
+    # FP64 true-residual products over all systems
+    mv_bytes = sum(float(Bsys @ p["products"][:, 0]) + s["matvecs_fp64"] * B64 for _, s, p in runs)
     value = mv_bytes / t_mixed / 1e9
     per = runs[-1][2]
     torch.cuda.synchronize()
@@ -438,7 +455,9 @@ def bench_batched(args, W, variant, dev, stream):
                        "fp64_max": int(per64["iterations"].max()),
                        "fp64_median": float(np.median(per64["iterations"])),
                        "mixed_max_restarts": int(per["restarts"].max())},
-        "products": {"mixed": runs[-1][1]["matvecs"], "fp64_checks": runs[-1][1]["matvecs_fp64"]},
+        "products": {"mixed_launched": runs[-1][1]["matvecs"], "fp64_checks": runs[-1][1]["matvecs_fp64"],
+                     "mixed_work_fraction": round(float(Bsys @ per["products"][:, 0]) / (runs[-1][1]["matvecs"] * Bm), 4),
+                     "fp64_work_fraction": round(float(Bsys64 @ per64["products"][:, 0]) / (runs64[-1][1]["matvecs"] * B64), 4)},
         "solution_rel_err_mixed_vs_fp64": err,
         "max_true_rel_res": {"mixed": float(per["true_rel_res"].max()), "fp64": float(per64["true_rel_res"].max())},
         "bytes_per_product": {"mixed": int(Bm), "fp64": int(B64)},

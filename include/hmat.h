@@ -284,6 +284,7 @@ typedef struct {
     int64_t iterations;
     double rel_res;           /* final |r|/|b| (the true one once converged) */
     double true_rel_res;      /* |b - A~64 x| / |b| at the end */
+    int64_t products;         /* products with h_iter that covered this recurrence's system */
 } hmat_batch_result;
 
 /* Device bytes of workspace hmat_bicgstab_batched needs for handle h and nrhs
@@ -295,7 +296,10 @@ uint64_t hmat_bicgstab_batched_workspace_bytes(hmat_t h, int64_t nrhs);
  * with its own FP64 scalars, the same stopping rule and FP64 true-residual
  * confirmation (Sec. 4.1.3) as hmat_bicgstab, and the same restart on a
  * failed check.  A recurrence that converges or breaks down stops while the
- * others continue; the products still run over all nrhs columns.
+ * others continue; the products still run over all nrhs columns, but on
+ * multi-right-hand-side handles (nrhs_max > 1) an iteration's products skip
+ * the systems none of whose recurrences is iterating (results[].products
+ * counts the products that covered each system).
  * b, x: device, n x nrhs with column k at offset k * n (column-major, the
  * layout of hmat_matvec with ld = n); x holds x_0 on entry.  1 <= nrhs <=
  * min(16, nrhs_max of both handles).  h_fp64 (may be NULL = h_iter) must
@@ -304,7 +308,7 @@ uint64_t hmat_bicgstab_batched_workspace_bytes(hmat_t h, int64_t nrhs);
  * stream and replays it on `stream`.  results: host, nsys x nrhs entries,
  * system-major (entry s * nrhs + k).  summary (may be NULL): status = the
  * first failing status, iterations and restarts = maxima, matvecs = batched
- * products.  Returns HMAT_OK when every recurrence converged.  Synchronises
+ * products launched.  Returns HMAT_OK when every recurrence converged.  Synchronises
  * `stream` before returning. */
 int hmat_bicgstab_batched(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, int64_t nrhs,
                           const hmat_solve_opts *opts, hmat_batch_result *results, hmat_solve_info *summary,

@@ -130,6 +130,7 @@ struct MRChunk {  // stage 2, multi-RHS: rows [r0, r0 + h), h <= 64
   int64_t gidx_off[NCLS];
   int32_t nkb[NCLS];        // column blocks (K padded to CB)
   int32_t r0, h;
+  int32_t sys;              // system of a batched handle the rows belong to
 };
 
 struct MRItem {  // stage 1, multi-RHS: rows [k0, k0 + nrows) (<= 64) of a group
@@ -138,6 +139,7 @@ struct MRItem {  // stage 1, multi-RHS: rows [k0, k0 + nrows) (<= 64) of a group
   int64_t out_off;  // zpart row of k0 (entries are rows x 16 right-hand sides)
   int64_t z_off;    // z index of k0 when the item spans the group's columns, else -1
   int32_t ncols, nrows, cls, nkb;
+  int32_t sys;      // system of a batched handle the columns belong to
 };
 
 // Stage-1 reduction: z entry j = round_z(dscale[j] * sum_c zpart[zp[j] + c * stride[j]]).
@@ -241,8 +243,11 @@ int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int
                   const int32_t *skip = nullptr, const S2Dot *dot = nullptr);
 bool matvec_dot_fusable(const hmat_s *h, int nparts);
 int size_grids(hmat_s *h);
+// active (multi-RHS only): optional device array, one entry per system of a
+// batched handle; the units (stage-1 items, stage-2 chunks) of a system
+// whose entry is 0 are skipped, leaving its rows of y unwritten.
 int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream,
-                     const int32_t *skip = nullptr);
+                     const int32_t *skip = nullptr, const int32_t *active = nullptr);
 int size_grids_mr(hmat_s *h);
 
 // Kernel timing (diag.hip): mark(h, k, stream) records event k (0..3) of the

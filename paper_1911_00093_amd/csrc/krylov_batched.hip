@@ -58,6 +58,8 @@ struct BWork {
   BTile *tiles;
   int32_t *sys_tb;                       // nsys + 1 tile offsets
   int32_t *status;                       // [iterating, pending]
+  int32_t *active;                       // nsys: a recurrence of the system is iterating
+  int64_t *runs;                         // nsys: iterations in which it was
 };
 
 static uint64_t al256(uint64_t b) { return (b + 255) / 256 * 256; }
@@ -65,7 +67,8 @@ static uint64_t al256(uint64_t b) { return (b + 255) / 256 * 256; }
 static uint64_t bwork_bytes(int64_t n, int64_t nrhs, int64_t nsys, int64_t ntiles) {
   return 7 * al256((uint64_t)n * nrhs * 8) + al256((uint64_t)ntiles * nrhs * 4 * 8) +
          al256((uint64_t)ntiles * nrhs * 2 * 8) + al256((uint64_t)nsys * nrhs * sizeof(BState)) +
-         al256((uint64_t)ntiles * sizeof(BTile)) + al256((uint64_t)(nsys + 1) * 4) + 256;
+         al256((uint64_t)ntiles * sizeof(BTile)) + al256((uint64_t)(nsys + 1) * 4) + 256 + al256((uint64_t)nsys * 4) +
+         al256((uint64_t)nsys * 8);
 }
 
 static BWork bcarve(void *base, int64_t n, int64_t nrhs, int64_t nsys, int64_t ntiles) {
@@ -87,6 +90,10 @@ static BWork bcarve(void *base, int64_t n, int64_t nrhs, int64_t nsys, int64_t n
   w.sys_tb = (int32_t *)p;
   p += al256((uint64_t)(nsys + 1) * 4);
   w.status = (int32_t *)p;
+  p += 256;
+  w.active = (int32_t *)p;
+  p += al256((uint64_t)nsys * 4);
+  w.runs = (int64_t *)p;
   return w;
 }
 
@@ -361,6 +368,23 @@ __global__ void kb_finalize(int nsys, int nrhs, const int32_t *__restrict__ sys_
   else if (rtr == 0.0) S.flag = 2;
 }
 
+// Per system: is one of its recurrences iterating (then the iteration's
+// products cover the system, and it counts one more run)?
+__global__ void kb_active(int nsys, int nrhs, const BState *__restrict__ st, int32_t *__restrict__ active,
+                          int64_t *__restrict__ runs) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsys) return;
+  int a = 0;
+  for (int k = 0; k < nrhs; k++) a |= st[(int64_t)s * nrhs + k].flag == 0;
+  active[s] = a;
+  if (a) runs[s] += 1;
+}
+
+__global__ void kb_zero_runs(int nsys, int64_t *__restrict__ runs) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nsys) runs[s] = 0;
+}
+
 // status word: [recurrences iterating, recurrences awaiting the true residual]
 __global__ void kb_status(int R, const BState *__restrict__ st, int32_t *__restrict__ status) {
   __shared__ int cnt[2];
@@ -414,8 +438,10 @@ struct ProfPause {
   ~ProfPause() { h->prof = saved; }
 };
 
-static int product(hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t n, hipStream_t st) {
-  return h->mr ? launch_matvec_mr(h, x, y, nrhs, n, st) : launch_matvec(h, x, y, nrhs, n, st);
+// active: per-system flags (multi-RHS handles skip the systems marked 0)
+static int product(hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t n, hipStream_t st,
+                   const int32_t *active = nullptr) {
+  return h->mr ? launch_matvec_mr(h, x, y, nrhs, n, st, nullptr, active) : launch_matvec(h, x, y, nrhs, n, st);
 }
 
 }  // namespace hm
@@ -470,14 +496,20 @@ int hmat_bicgstab_batched(hmat_t h_iter, hmat_t h_fp64, const double *b, double 
   hipLaunchKernelGGL(kb_residual, GT, B, 0, st, n, nr, w.tiles, w.st, b, w.tmp, w.r, w.rt, w.part, -1);
   hipLaunchKernelGGL(kb_start, GR, BR, 0, st, ns, nr, w.sys_tb, w.st, w.part, o->tol, 0, 1);
   hipLaunchKernelGGL(kb_zero_b, GT, B, 0, st, n, nr, w.tiles, w.st, x);
+  const dim3 GS((unsigned)((nsys + 255) / 256));
+  hipLaunchKernelGGL(kb_zero_runs, GS, BR, 0, st, ns, w.runs);
 
+  // On multi-RHS handles the products of an iteration skip the systems none
+  // of whose recurrences is iterating (their rows of v and t are not used).
+  const int32_t *act = h_iter->mr ? w.active : nullptr;
   auto iteration = [&](hipStream_t s2) -> int {
+    hipLaunchKernelGGL(kb_active, GS, BR, 0, s2, ns, nr, w.st, w.active, w.runs);
     hipLaunchKernelGGL(kb_pupdate, GT, B, 0, s2, n, nr, w.tiles, w.st, w.r, w.p, w.v);
-    int r2 = product(h_iter, w.p, w.v, nrhs, n, s2);
+    int r2 = product(h_iter, w.p, w.v, nrhs, n, s2, act);
     if (r2) return r2;
     hipLaunchKernelGGL(kb_dot_rtv, GT, B, 0, s2, n, nr, w.tiles, w.st, w.rt, w.v, w.part);
     hipLaunchKernelGGL(kb_supdate, GT, B, 0, s2, n, nr, w.tiles, w.st, w.r, w.v, w.s, w.part);
-    if ((r2 = product(h_iter, w.s, w.t, nrhs, n, s2))) return r2;
+    if ((r2 = product(h_iter, w.s, w.t, nrhs, n, s2, act))) return r2;
     hipLaunchKernelGGL(kb_dot_t, GT, B, 0, s2, n, nr, w.tiles, w.st, w.t, w.s, w.part);
     hipLaunchKernelGGL(kb_xupdate, GT, B, 0, s2, n, nr, w.tiles, w.st, x, w.r, w.rt, w.p, w.s, w.t, w.part, w.bank,
                        o->tol);
@@ -567,7 +599,9 @@ int hmat_bicgstab_batched(hmat_t h_iter, hmat_t h_fp64, const double *b, double 
   }
   cleanup();
   std::vector<BState> hs(R);
+  std::vector<int64_t> runs(nsys);
   hipError_t e = hipMemcpyAsync(hs.data(), w.st, R * sizeof(BState), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(runs.data(), w.runs, nsys * sizeof(int64_t), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fail(HMAT_E_HIP, "result copy failed");
   int worst = HMAT_OK;
@@ -582,6 +616,10 @@ int hmat_bicgstab_batched(hmat_t h_iter, hmat_t h_fp64, const double *b, double 
     q.iterations = S.iter;
     q.rel_res = S.flag == 5 ? S.truerel : S.relres;
     q.true_rel_res = S.truerel;
+    // products of h_iter that covered this system: the initial residual and
+    // two per iteration in which one of its recurrences was iterating
+    // (single-vector handles cover every system in every product)
+    q.products = h_iter->mr ? 1 + 2 * runs[i / nrhs] : nmv;
     if (q.status != HMAT_OK && worst == HMAT_OK) worst = q.status;
     maxit = std::max<int64_t>(maxit, S.iter);
     restarts = std::max(restarts, S.restarts);

@@ -148,11 +148,13 @@ __global__ __launch_bounds__(kMRThreads) void k_mr_stage1(const MRItem *__restri
                                                           const void *__restrict__ vals, int64_t n, int z32,
                                                           const double *__restrict__ dscale,
                                                           double *__restrict__ s64, double *__restrict__ zpart,
-                                                          const int32_t *__restrict__ skip) {
+                                                          const int32_t *__restrict__ skip,
+                                                          const int32_t *__restrict__ active) {
   if (skip && *skip) return;
   const int lane = threadIdx.x & (kWave - 1);
   XCD_UNIT_LOOP(q, sp) {
     const MRItem it = items[q];
+    if (active && !active[it.sys]) continue;  // every recurrence of the system has stopped
     switch ((it.nrows + kMRTile - 1) / kMRTile) {
       case 1: mr_s1_item<CLS, 1, NB>(it, vals, n, z32, dscale, s64, zpart, lane); break;
       case 2: mr_s1_item<CLS, 2, NB>(it, vals, n, z32, dscale, s64, zpart, lane); break;
@@ -283,11 +285,13 @@ __global__ __launch_bounds__(kMRThreads) void k_mr_stage2(const MRChunk *__restr
                                                           const int32_t *__restrict__ g64, const int32_t *__restrict__ g32,
                                                           const int32_t *__restrict__ g16,
                                                           const double *__restrict__ s64, double *__restrict__ y,
-                                                          int64_t ldy, int64_t nrhs, const int32_t *__restrict__ skip) {
+                                                          int64_t ldy, int64_t nrhs, const int32_t *__restrict__ skip,
+                                                          const int32_t *__restrict__ active) {
   if (skip && *skip) return;
   const int lane = threadIdx.x & (kWave - 1);
   XCD_UNIT_LOOP(q, sp) {
     const MRChunk ch = chunks[q];
+    if (active && !active[ch.sys]) continue;
     switch ((ch.h + kMRTile - 1) / kMRTile) {
       case 1: mr_s2_chunk<MASK, 1, NB>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
       case 2: mr_s2_chunk<MASK, 2, NB>(ch, v64, v32, v16, g64, g32, g16, s64, y, ldy, nrhs, lane); break;
@@ -300,7 +304,7 @@ __global__ __launch_bounds__(kMRThreads) void k_mr_stage2(const MRChunk *__restr
 // ------------------------------------------------------------- launch
 typedef void (*MRStage2Fn)(const MRChunk *, XcdSplit, const double *, const float *, const unsigned short *,
                            const int32_t *, const int32_t *, const int32_t *, const double *, double *, int64_t,
-                           int64_t, const int32_t *);
+                           int64_t, const int32_t *, const int32_t *);
 template <int NB>
 static MRStage2Fn mr_stage2_nb(int mask) {
   switch (mask) {
@@ -317,7 +321,7 @@ static MRStage2Fn mr_stage2_fn(int mask, int nb) {
   return nb == 1 ? mr_stage2_nb<1>(mask) : nb == 4 ? mr_stage2_nb<4>(mask) : mr_stage2_nb<2>(mask);
 }
 typedef void (*MRStage1Fn)(const MRItem *, XcdSplit, const void *, int64_t, int, const double *, double *, double *,
-                           const int32_t *);
+                           const int32_t *, const int32_t *);
 template <int NB>
 static MRStage1Fn mr_stage1_nb(int cls) {
   return cls == F64 ? k_mr_stage1<F64, NB> : cls == F32 ? k_mr_stage1<F32, NB> : k_mr_stage1<BF16, NB>;
@@ -346,7 +350,7 @@ int size_grids_mr(hmat_s *h) {
 }
 
 int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream,
-                     const int32_t *skip) {
+                     const int32_t *skip, const int32_t *active) {
   hipStream_t st = (hipStream_t)stream;
   for (int64_t r0 = 0; r0 < nrhs; r0 += kMRhs) {
     const int64_t nr = std::min<int64_t>(kMRhs, nrhs - r0);
@@ -362,7 +366,7 @@ int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, 
       if (h->mr_nitems[c] <= 0) continue;
       hipLaunchKernelGGL(mr_stage1_fn(c, h->mr_nb1[c]), dim3((unsigned)h->mr_grid1[c]), dim3(kMRThreads), 0, st,
                          h->mri + h->mr_item_begin[c], h->mr_split1[c], (const void *)h->vals[c], h->n, h->z32,
-                         h->dscale, h->src64, h->zpart, skip);
+                         h->dscale, h->src64, h->zpart, skip, active);
     }
     prof_mark(h, 1, stream);
     {
@@ -375,7 +379,7 @@ int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, 
                        h->mrc,
                        h->mr_split2, (const double *)h->vals[F64], (const float *)h->vals[F32],
                        (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16], h->src64,
-                       yr, ld, nr, skip);
+                       yr, ld, nr, skip, active);
     prof_mark(h, 3, stream);
   }
   hipError_t e = hipGetLastError();
@@ -430,7 +434,7 @@ extern "C" int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps,
         const double t = time_ms(st, reps, [&]() {
           hipLaunchKernelGGL(mr_stage1_fn(c, nb), dim3((unsigned)h->mr_grid1[c]), dim3(kMRThreads), 0, st,
                              h->mri + h->mr_item_begin[c], h->mr_split1[c], (const void *)h->vals[c], h->n, h->z32,
-                             h->dscale, h->src64, h->zpart, nullptr);
+                             h->dscale, h->src64, h->zpart, nullptr, nullptr);
         });
         if (t >= 0 && t < best) {
           best = t;
@@ -457,7 +461,7 @@ extern "C" int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps,
           hipLaunchKernelGGL(mr_stage2_fn(h->cls_mask, nb), dim3((unsigned)h->mr_grid2), dim3(kMRThreads), 0, st,
                              h->mrc, h->mr_split2, (const double *)h->vals[F64], (const float *)h->vals[F32],
                              (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16],
-                             h->src64, y, n, nr, nullptr);
+                             h->src64, y, n, nr, nullptr, nullptr);
         });
         if (t >= 0 && t < best) {
           best = t;

@@ -81,6 +81,11 @@ struct ChunkPlan {
 
 inline int64_t pad_to(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// system of index i given the boundaries {0, ..., n}
+inline int32_t sys_index(const std::vector<int64_t> &off, int64_t i) {
+  return (int32_t)(std::upper_bound(off.begin(), off.end(), i) - off.begin()) - 1;
+}
+
 }  // namespace
 
 struct Packed {
@@ -411,6 +416,7 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
       m.nkb = (int32_t)((q.it.ncols + mr_cb(c) - 1) / mr_cb(c));
       const Group &g = P->groups[q.group];
       m.z_off = g.nch == 1 ? g.z0 + q.k0 : -1;
+      m.sys = sys_index(P->sys_off, m.x0);
       m.w_off = P->vals_elems[c];
       P->vals_elems[c] += (int64_t)m.nkb * 4 * vec_of(c) * m.nrows;
       P->mri.push_back(m);
@@ -464,6 +470,7 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
       MRChunk &R = P->mrc[q];
       R.r0 = (int32_t)cp.r0;
       R.h = (int32_t)cp.h;
+      R.sys = sys_index(P->sys_off, cp.r0);
       for (int c = 0; c < NCLS; c++) {
         R.nkb[c] = (int32_t)((cp.K[c] + mr_cb(c) - 1) / mr_cb(c));
         R.panel_off[c] = P->vals_elems[c];

@@ -91,7 +91,7 @@ class hmat_tune_info(C.Structure):
 
 class hmat_batch_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("restarts", C.c_int32), ("iterations", C.c_int64),
-                ("rel_res", C.c_double), ("true_rel_res", C.c_double)]
+                ("rel_res", C.c_double), ("true_rel_res", C.c_double), ("products", C.c_int64)]
 
 
 class hmat_assemble_opts(C.Structure):
@@ -551,7 +551,7 @@ def hmat_bicgstab_batched(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = N
     summary = dict(status=info.status, restarts=info.restarts, iterations=info.iterations, matvecs=info.matvecs,
                    matvecs_fp64=info.matvecs_fp64, rel_res=info.rel_res, true_rel_res=info.true_rel_res)
     per = {f: np.array([getattr(r, f) for r in res]).reshape(nsys, nrhs)
-           for f in ("status", "restarts", "iterations", "rel_res", "true_rel_res")}
+           for f in ("status", "restarts", "iterations", "rel_res", "true_rel_res", "products")}
     return x, summary, per
 
 

@@ -155,6 +155,39 @@ def test_batched_columns_independent():
     assert np.all(xc[3] == 0) and np.all(per["iterations"][:, 3] == 0) and np.all(per["status"][:, 3] == 0)
 
 
+def test_batched_systems_independent_and_products_counted():
+    """On a multi-RHS handle an iteration's products skip the systems whose
+    recurrences have all stopped.  A system's solution does not depend on the
+    others, bit for bit (the same system solved in a handle of its own), and
+    each system reports the products that covered it: the initial residual
+    plus two per iteration it took part in; systems that finish early count
+    fewer than the batch launched.  Single-vector handles count every
+    product for every system."""
+    need_gpu()
+    sysl = systems()
+    Hi, H64 = handles(sysl, oracle.M2_MIXED, 16)
+    B = rhs_columns(sysl, 4, seed=3)
+    x, summ, per = hmat.hmat_bicgstab_batched(Hi, to_cols(B), h_fp64=H64)
+    x = x.cpu().numpy().T
+    assert summ["status"] == 0
+    prod, its = per["products"], per["iterations"]
+    print("iterations", its.tolist(), "products", prod[:, 0].tolist(), "launched", summ["matvecs"])
+    assert np.all(prod == prod[:, :1])  # one count per system
+    assert np.all(prod[:, 0] >= 1 + 2 * its.max(axis=1)) and np.all(prod[:, 0] <= summ["matvecs"])
+    assert prod[:, 0].min() < summ["matvecs"]  # the systems finish at different times
+    off = Hi.system_offsets()
+    for s in (1, 3):
+        bs1 = [blockset(sysl[s][1])]
+        H1 = hmat.HMatrix(bs1, oracle.M2_MIXED, c=1, nrhs_max=16)
+        H164 = hmat.HMatrix(bs1, oracle.M1_DOUBLE, nrhs_max=16)
+        x1, s1, p1 = hmat.hmat_bicgstab_batched(H1, to_cols(B[:, off[s]:off[s + 1]]), h_fp64=H164)
+        assert np.array_equal(x1.cpu().numpy().T, x[:, off[s]:off[s + 1]]), s
+        assert np.array_equal(p1["iterations"][0], its[s]) and p1["products"][0, 0] == prod[s, 0]
+    Hs, Hs64 = handles(sysl, oracle.M2_MIXED, 1)
+    _, summ1, per1 = hmat.hmat_bicgstab_batched(Hs, to_cols(B[:1]), h_fp64=Hs64)
+    assert np.all(per1["products"] == summ1["matvecs"])
+
+
 def test_batched_edges():
     need_gpu()
     import torch

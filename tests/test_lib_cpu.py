@@ -171,6 +171,18 @@ def test_plan_batched_systems():
     assert e.value.code == hmat.HMAT_E_LAYOUT
 
 
+@pytest.mark.parametrize("prec", [oracle.M1_DOUBLE, oracle.M2_MIXED, oracle.M3, oracle.BF16_SCALED])
+def test_plan_batched_bytes_are_sums(prec):
+    """A batched handle's matrix and algorithmic bytes are the sums of its
+    systems' own plans (per-system work accounting relies on it)."""
+    hs = [oracle_hmatrix(k)[1] for k in ("sphere-L2", "plates-16", "spheres-mixed")]
+    bss = [blockset_from_oracle(h) for h in hs]
+    tot = hmat.hmat_plan_batched(bss, prec, -1, 16)
+    parts = [hmat.hmat_plan(b, prec, -1, 16) for b in bss]
+    assert tot.matrix_bytes == sum(p.matrix_bytes for p in parts)
+    assert tot.algorithmic_bytes == sum(p.algorithmic_bytes for p in parts)
+
+
 @pytest.mark.parametrize("nrhs_max", [1, 16])
 def test_plan_multirhs_sizes(nrhs_max):
     m, h = oracle_hmatrix("sphere-L3")
