@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--eps", type=float, default=None, help="ACA tolerance (default: the workload's)")
     ap.add_argument("--refine", type=float, default=None,
                     help="early FP64 true-residual check ratio (default 1e-2 for BF16-scaled, else 0)")
+    ap.add_argument("--drop", type=int, default=0,
+                    help="Methods 2/3: delete low-rank terms with d_i < d_max 10^-drop (Sec. 4.5; 0 = off)")
     ap.add_argument("--train-leaves", type=int, default=20000)
     ap.add_argument("--epochs", type=int, default=100)
     args = ap.parse_args()
@@ -134,7 +136,7 @@ def main():
     log(f"[setup] {args.workload}: n={bs.n} blocks={bs.nblocks} assembly {time.time() - t0:.1f}s")
     t0 = time.time()
     H64 = hmat.HMatrix(bs, hmat.M1_DOUBLE)
-    Hm = hmat.HMatrix(bs, variant, c=-1)
+    Hm = hmat.HMatrix(bs, variant, c=-1, drop=args.drop)
     log(f"[setup] builds {time.time() - t0:.1f}s")
     st64, stm = H64.stats(), Hm.stats()
     B64, Bm = st64.algorithmic_bytes, stm.algorithmic_bytes
@@ -272,6 +274,7 @@ def main():
             "n": n,
             "step": "one BiCGSTAB solve x0=0 -> |r|/|b|<1e-8 confirmed by the FP64 true residual",
             "refine": args.refine,
+            "drop": args.drop,
             "parallelism": "1 GPU",
         },
         "time_to_tol_ms": {"mixed": round(ms_per_step, 3), "fp64": round(1e3 * t_fp64 / args.steps, 3),
@@ -300,7 +303,7 @@ def main():
     }
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh, W, variant, args.cpu_matvecs, Bm)
+        out["cpu_baseline"] = cpu_baseline(mesh, W, variant, args.cpu_matvecs, Bm, args.drop)
     print(json.dumps(out), flush=True)
 
 
@@ -639,7 +642,7 @@ def _plan_stats(bs, precision):
                            algorithmic_bytes=info.algorithmic_bytes)
 
 
-def cpu_baseline(mesh, W, variant, reps, B):
+def cpu_baseline(mesh, W, variant, reps, B, drop=0):
     """The oracle as it stands (plain single-threaded C, FP64 arithmetic) on
     the same workload: its own assembly (untimed; it reproduces the library's
     blocks bit for bit, so the product moves the same B bytes), then `reps`
@@ -648,7 +651,7 @@ def cpu_baseline(mesh, W, variant, reps, B):
 
     t0 = time.time()
     h = oracle.HMatrix(mesh.centroids, mesh.areas, leaf=W["leaf"], eta=W["eta"], eps=W["eps"])
-    conv = oracle.Converted(h, variant, -1)
+    conv = oracle.Converted(h, variant, -1, drop=drop)
     log(f"[cpu] oracle assembly + conversion {time.time() - t0:.1f}s")
     x = np.random.default_rng(0).standard_normal(h.n)
     conv.matvec(x)

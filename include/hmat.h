@@ -106,7 +106,11 @@ typedef struct {
     int32_t precision;        /* hmat_precision */
     int32_t c;                /* Method 3 split constant (Eqs. 19-20); the paper uses -1, 1..7 */
     int32_t nrhs_max;         /* largest nrhs later passed to hmat_matvec, >= 1 */
-    int32_t reserved;         /* must be 0 */
+    int32_t drop;             /* 0, or t in 1..15 (Methods 2 and 3 only): omit every low-rank term
+                                 whose D_m entry d_i is below d_max 10^-t of its block, i.e. delete
+                                 that column of V' and row of W' (the deletion Sec. 4.5 proposes for
+                                 terms much smaller than the largest; not a measured variant of the
+                                 paper) */
 } hmat_build_opts;
 
 typedef struct {

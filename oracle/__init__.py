@@ -73,6 +73,8 @@ def _load():
         L.ora_exact_matvec.argtypes = [P, P, P]
         L.ora_convert.restype = P
         L.ora_convert.argtypes = [P, C.c_int, C.c_int]
+        L.ora_convert_drop.restype = P
+        L.ora_convert_drop.argtypes = [P, C.c_int, C.c_int, C.c_int]
         L.ora_conv_free.argtypes = [P]
         L.ora_conv_rank.restype = I32
         L.ora_conv_rank.argtypes = [P, I64]
@@ -222,13 +224,16 @@ class HMatrix:
 class Converted:
     """An oracle H-matrix converted to one precision variant (Sec. 3)."""
 
-    def __init__(self, h: HMatrix, variant: int, c: int = 0):
+    def __init__(self, h: HMatrix, variant: int, c: int = 0, drop: int = 0):
+        """drop > 0 (Methods 2 and 3): omit the terms with d_i < d_max 10^-drop
+        (the deletion of much smaller terms proposed in Sec. 4.5)."""
         self.h = h
         self.variant = variant
         self.c = c
-        p = _load().ora_convert(h._h, int(variant), int(c))
+        self.drop = drop
+        p = _load().ora_convert_drop(h._h, int(variant), int(c), int(drop))
         if not p:
-            raise ValueError("bad variant")
+            raise ValueError("bad variant or drop")
         self._p = p
 
     def __del__(self):

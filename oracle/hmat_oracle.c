@@ -548,9 +548,13 @@ static double ora_pow2_ceil(double m)
     return f == 0.5 ? ldexp(1.0, e - 1) : ldexp(1.0, e);
 }
 
-ora_conv *ora_convert(const ora_hmat *h, int variant, int c)
+/* drop (Methods 2 and 3): 0, or omit the terms with d_i < d_max 10^-drop,
+ * the deletion of much smaller terms that Sec. 4.5 proposes. */
+ora_conv *ora_convert_drop(const ora_hmat *h, int variant, int c, int drop)
 {
     if (variant < 0 || variant > 7) return NULL;
+    if (drop < 0 || (drop > 0 && !(variant == V_M2D || variant == V_M2S || variant == V_M2M || variant == V_M3)))
+        return NULL;
     ora_conv *v = (ora_conv *)calloc(1, sizeof(ora_conv));
     v->variant = variant;
     v->c = c;
@@ -630,10 +634,12 @@ ora_conv *ora_convert(const ora_hmat *h, int variant, int c)
              * d_i < d_max 10^-c, FP64 otherwise; FP64 terms are stored first
              * (the paper notes the terms may be reordered freely). */
             double thr = dmax * pow(10.0, -(double)c);
+            double cut = drop > 0 ? dmax * pow(10.0, -(double)drop) : 0.0;
             for (int pass = 0; pass < 2; pass++) {
                 for (int64_t l = 0; l < r; l++) {
                     if (!(dv[l] > 0.0 && dw[l] > 0.0)) continue;
                     double d = dv[l] * dw[l];
+                    if (d < cut) continue; /* deleted (drop) */
                     int p64;
                     if (variant == V_M2D) p64 = 1;
                     else if (variant == V_M2S || variant == V_M2M) p64 = 0;
@@ -664,6 +670,8 @@ ora_conv *ora_convert(const ora_hmat *h, int variant, int c)
     }
     return v;
 }
+
+ora_conv *ora_convert(const ora_hmat *h, int variant, int c) { return ora_convert_drop(h, variant, c, 0); }
 
 void ora_conv_free(ora_conv *v)
 {

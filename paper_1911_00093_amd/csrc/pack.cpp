@@ -185,7 +185,9 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   if (o->precision < HMAT_M1_DOUBLE || o->precision > HMAT_BF16_SCALED)
     return fail(HMAT_E_ARG, "unknown precision %d", o->precision);
   if (o->nrhs_max < 1 || o->nrhs_max > 4096) return fail(HMAT_E_ARG, "nrhs_max %d out of range", o->nrhs_max);
-  if (o->reserved != 0) return fail(HMAT_E_ARG, "reserved field must be 0");
+  if (o->drop < 0 || o->drop > 15) return fail(HMAT_E_ARG, "drop %d outside 0..15", o->drop);
+  if (o->drop != 0 && (o->precision < HMAT_M2_DOUBLE || o->precision > HMAT_M3))
+    return fail(HMAT_E_ARG, "drop applies to Methods 2 and 3 (their D_m scales)");
   const int64_t n = b->n;
   if (n <= 0 || n > (int64_t(1) << 30)) return fail(HMAT_E_ARG, "matrix order %lld out of range", (long long)n);
   if (b->nblocks <= 0) return fail(HMAT_E_ARG, "no blocks");
@@ -309,10 +311,13 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
       }
       // Method 3 (Eqs. 19-20): FP32 iff d_i < d_max 10^-c; FP64 terms first.
       const double thr = dmax * std::pow(10.0, -(double)o->c);
+      // deletion (Sec. 4.5): terms with d_i < d_max 10^-drop are omitted
+      const double cut = o->drop > 0 ? dmax * std::pow(10.0, -(double)o->drop) : 0.0;
       for (int pass = 0; pass < 2; pass++)
         for (int32_t l = 0; l < r; l++) {
           if (!(dv[l] > 0.0 && dw[l] > 0.0)) continue;  // an all-zero term is dropped
           const double d = dv[l] * dw[l];
+          if (d < cut) continue;
           int cls;
           if (prec == HMAT_M2_DOUBLE) cls = F64;
           else if (prec == HMAT_M2_SINGLE || prec == HMAT_M2_MIXED) cls = F32;

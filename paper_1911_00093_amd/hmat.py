@@ -54,7 +54,7 @@ class hmat_blocks(C.Structure):
 
 
 class hmat_build_opts(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("c", C.c_int32), ("nrhs_max", C.c_int32), ("reserved", C.c_int32)]
+    _fields_ = [("precision", C.c_int32), ("c", C.c_int32), ("nrhs_max", C.c_int32), ("drop", C.c_int32)]
 
 
 class hmat_plan_info(C.Structure):
@@ -244,19 +244,19 @@ def hmat_assemble_bem(centroids, areas, leaf=64, eta=2.0, eps=1e-5, threads=0) -
                     perm, owner)
 
 
-def hmat_plan(blocks: BlockSet, precision: int, c: int = 0, nrhs_max: int = 1) -> hmat_plan_info:
+def hmat_plan(blocks: BlockSet, precision: int, c: int = 0, nrhs_max: int = 1, drop: int = 0) -> hmat_plan_info:
     info = hmat_plan_info()
     s = blocks.struct()
-    o = hmat_build_opts(int(precision), int(c), int(nrhs_max), 0)
+    o = hmat_build_opts(int(precision), int(c), int(nrhs_max), int(drop))
     _check(lib().hmat_plan(C.byref(s), C.byref(o), C.byref(info)))
     return info
 
 
 # ----------------------------------------------------------------- device
-def hmat_plan_batched(systems, precision: int, c: int = 0, nrhs_max: int = 1) -> hmat_plan_info:
+def hmat_plan_batched(systems, precision: int, c: int = 0, nrhs_max: int = 1, drop: int = 0) -> hmat_plan_info:
     info = hmat_plan_info()
     arr = (hmat_blocks * len(systems))(*[b.struct() for b in systems])
-    o = hmat_build_opts(int(precision), int(c), int(nrhs_max), 0)
+    o = hmat_build_opts(int(precision), int(c), int(nrhs_max), int(drop))
     _check(lib().hmat_plan_batched(arr, len(systems), C.byref(o), C.byref(info)))
     return info
 
@@ -265,22 +265,23 @@ class HMatrix:
     """A packed H-matrix on the device (hmat_build / hmat_build_batched);
     owns its torch buffer."""
 
-    def __init__(self, blocks, precision: int, c: int = 0, nrhs_max: int = 1, device="cuda", stream=None):
+    def __init__(self, blocks, precision: int, c: int = 0, nrhs_max: int = 1, device="cuda", stream=None,
+                 drop: int = 0):
         import torch
 
-        self.precision, self.c, self.nrhs_max = int(precision), int(c), int(nrhs_max)
+        self.precision, self.c, self.nrhs_max, self.drop = int(precision), int(c), int(nrhs_max), int(drop)
         batched = isinstance(blocks, (list, tuple))
-        o = hmat_build_opts(self.precision, self.c, self.nrhs_max, 0)
+        o = hmat_build_opts(self.precision, self.c, self.nrhs_max, self.drop)
         h = C.c_void_p()
         if batched:
-            self.plan = hmat_plan_batched(blocks, precision, c, nrhs_max)
+            self.plan = hmat_plan_batched(blocks, precision, c, nrhs_max, drop)
             self.n = sum(b.n for b in blocks)
             self.buf = torch.empty(int(self.plan.device_bytes), dtype=torch.uint8, device=device)
             arr = (hmat_blocks * len(blocks))(*[b.struct() for b in blocks])
             _check(lib().hmat_build_batched(arr, len(blocks), C.byref(o), C.c_void_p(self.buf.data_ptr()),
                                             self.buf.numel(), _stream_ptr(stream), C.byref(h)))
         else:
-            self.plan = hmat_plan(blocks, precision, c, nrhs_max)
+            self.plan = hmat_plan(blocks, precision, c, nrhs_max, drop)
             self.n = blocks.n
             self.buf = torch.empty(int(self.plan.device_bytes), dtype=torch.uint8, device=device)
             s = blocks.struct()

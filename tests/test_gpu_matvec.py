@@ -31,6 +31,35 @@ def test_matvec_parity_small(key, variant):
         assert err <= tolerance(variant), (key, variant, err)
 
 
+@pytest.mark.parametrize("variant,t", [(oracle.M2_DOUBLE, 3), (oracle.M2_MIXED, 2), (oracle.M2_SINGLE, 5),
+                                       (oracle.M3, 4)])
+@pytest.mark.parametrize("nrhs_max", [1, 16])
+def test_matvec_drop_parity(variant, t, nrhs_max):
+    """Terms deleted by drop t (Sec. 4.5): the library's product equals the
+    oracle's product on the same deletion, at the variant's tolerance, for
+    the single-vector and the matrix-core product."""
+    need_gpu()
+    import torch
+
+    m, h = oracle_hmatrix("spheres-mixed")
+    H = hmat.HMatrix(blockset(h), variant, c=2, nrhs_max=nrhs_max, drop=t)
+    conv = oracle.Converted(h, variant, 2, drop=t)
+    full = oracle.Converted(h, variant, 2)
+    X = np.random.default_rng(12).standard_normal((3, h.n))
+    X[0] = 1.0
+    if nrhs_max > 1:
+        Y = H.matvec(torch.as_tensor(X).cuda().T).cpu().numpy()
+    else:
+        Y = np.stack([H.matvec(to_dev(X[k])).cpu().numpy() for k in range(3)], axis=1)
+    for k in range(3):
+        scale = abs_scale(h, X[k]).max()
+        err = np.abs(Y[:, k] - conv.matvec(X[k])).max() / scale
+        moved = np.abs(full.matvec(X[k]) - conv.matvec(X[k])).max() / scale
+        print(f"{oracle.VARIANT_NAMES[variant]} drop {t}: error {err:.2e}, deletion moved y by {moved:.2e}")
+        assert err <= tolerance(variant), (k, err)
+        assert moved > 10 * tolerance(variant)  # the deletion is visible, the parity is not luck
+
+
 @pytest.mark.parametrize("variant", [oracle.M1_DOUBLE, oracle.M2_MIXED, oracle.M3, oracle.BF16_SCALED])
 def test_matvec_vs_fp64_error(variant):
     """FP32-storage variants stay within 1e-6 of the FP64 product on a smooth

@@ -122,6 +122,34 @@ def test_plan_algorithmic_bytes(prec):
     assert info.algorithmic_bytes == mat + extra + h.n * xs + h.n * 8
 
 
+@pytest.mark.parametrize("prec,t", [(oracle.M2_MIXED, 2), (oracle.M2_DOUBLE, 4), (oracle.M3, 3)])
+def test_plan_drop_bytes(prec, t):
+    """With drop t the library stores exactly the terms with d_i >= d_max
+    10^-t (d from the FP64 factors, computed here): the plan's matrix bytes
+    fall by the deleted terms' (#I + #J) values, and its z count with them."""
+    m, h = oracle_hmatrix("sphere-L3")
+    bs = blockset_from_oracle(h)
+    full = hmat.hmat_plan(bs, prec, c=2)
+    cut = hmat.hmat_plan(bs, prec, c=2, drop=t)
+    conv = oracle.Converted(h, prec, 2)
+    gone = 0
+    for b in range(h.nblocks):
+        if h.kind[b] == 1:
+            _, V, W = h.block_factors(b)
+            d = np.abs(V).max(axis=0) * np.abs(W).max(axis=1)
+            _, _, D, _, P = conv.block(b)
+            dd = np.array(sorted(zip(D.tolist(), P.tolist())))
+            for dv, pv in dd:
+                if dv < d.max() * 10.0 ** (-t):
+                    gone += (h.nrows[b] + h.ncols[b]) * (8 if pv == 64 else 4)
+    assert gone > 0 and full.matrix_bytes - cut.matrix_bytes == gone
+    for bad in (oracle.M1_DOUBLE, oracle.BF16_SCALED):
+        with pytest.raises(hmat.HmatError):
+            hmat.hmat_plan(bs, bad, drop=t)
+    with pytest.raises(hmat.HmatError):
+        hmat.hmat_plan(bs, prec, drop=16)
+
+
 @pytest.mark.parametrize("key", ["sphere-L3", "plates-16", "spheres-mixed", "ellipsoid-12"])
 def test_library_assembly_matches_oracle(key):
     m, h = oracle_hmatrix(key)

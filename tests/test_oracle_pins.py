@@ -15,6 +15,7 @@ import pytest
 import oracle
 from paper_1911_00093_amd import meshes
 from tests.conftest import oracle_hmatrix
+from tests.gpu_util import abs_scale
 
 
 def f32(a):
@@ -285,6 +286,55 @@ def test_method3_c_minus1_equals_fp64_dense_plus_fp32_lowrank():
             r0, c0 = h.row0[b], h.col0[b]
             dense_diff[r0:r0 + A.shape[0]] += (A - f32(A)) @ x[c0:c0 + A.shape[1]]
     assert np.allclose(y3 - ym, dense_diff, rtol=1e-6, atol=1e-12 * np.abs(y1).max())
+
+
+@pytest.mark.parametrize("t", [1, 2, 3, 4])
+def test_drop_deletes_the_small_terms(t):
+    """Deletion of terms much smaller than the largest (Sec. 4.5): with drop t
+    a block keeps exactly the terms with d_i >= d_max 10^-t (d from the FP64
+    factors' column and row maxima, computed here), and the product changes
+    by exactly minus the deleted terms' V_i (W_i x), summed from the original
+    FP64 factors."""
+    m, h = oracle_hmatrix("sphere-L3")
+    x = np.random.default_rng(8).standard_normal(h.n)
+    full = oracle.Converted(h, oracle.M2_DOUBLE)
+    cut = oracle.Converted(h, oracle.M2_DOUBLE, drop=t)
+    removed = np.zeros(h.n)
+    ndropped = 0
+    for b in _lr_blocks(h):
+        _, V, W = h.block_factors(b)
+        d = np.abs(V).max(axis=0) * np.abs(W).max(axis=1)
+        keep = (d >= d.max() * 10.0 ** (-t)) & (d > 0)
+        _, Vp, D, Wp, P = cut.block(b)
+        assert Vp.shape[1] == int(keep.sum())
+        assert sorted(D.tolist()) == sorted(d[keep].tolist())
+        r0, c0 = h.row0[b], h.col0[b]
+        gone = ~keep & (d > 0)
+        removed[r0:r0 + V.shape[0]] += V[:, gone] @ (W[gone] @ x[c0:c0 + W.shape[1]])
+        ndropped += int(gone.sum())
+    assert ndropped > 0
+    scale = abs_scale(h, x)
+    err = np.abs(cut.matvec(x) - (full.matvec(x) - removed)).max() / scale.max()
+    assert err <= 1e-13, err
+
+
+def test_drop_limits():
+    """drop beyond every ratio keeps Method 2 bit for bit; Method 3's split
+    applies to the kept terms; Methods 1 and BF16 have no D_m to drop by."""
+    m, h = oracle_hmatrix("sphere-L3")
+    x = np.random.default_rng(9).standard_normal(h.n)
+    assert np.array_equal(oracle.Converted(h, oracle.M2_MIXED, drop=15).matvec(x),
+                          oracle.Converted(h, oracle.M2_MIXED).matvec(x))
+    c3, c3d = oracle.Converted(h, oracle.M3, 2), oracle.Converted(h, oracle.M3, 2, drop=4)
+    for b in _lr_blocks(h)[:100]:
+        _, _, D, _, P = c3.block(b)
+        _, _, Dd, _, Pd = c3d.block(b)
+        keep = D >= D.max() * 1e-4
+        assert np.array_equal(np.sort(Dd), np.sort(D[keep]))
+        assert np.all((Pd == 32) == (Dd < Dd.max() * 1e-2))
+    for v in (oracle.M1_DOUBLE, oracle.M1_MIXED, oracle.BF16_SCALED):
+        with pytest.raises(ValueError):
+            oracle.Converted(h, v, drop=3)
 
 
 def test_bf16_values_and_scales():
