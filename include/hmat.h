@@ -281,6 +281,26 @@ uint64_t hmat_solver_workspace_bytes(int64_t n);
 int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, const hmat_solve_opts *opts,
                   hmat_solve_info *info, void *work, uint64_t work_bytes, void *stream);
 
+/* Restarted GMRES(restart) (the further solver Sec. 5 names; the textbook
+ * method, not from the paper): Arnoldi with classical Gram-Schmidt applied
+ * twice, Givens rotations, right preconditioning x = K u (opts->precond, or
+ * none), every vector and scalar FP64 on the device.  A cycle of at most
+ * `restart` steps (1..128) uses h_iter; it ends when the residual estimate
+ * |g_{j+1}|/|b| falls below tol, the basis is full, the Krylov space
+ * contains the solution or opts->maxiter steps have run; then x is updated
+ * and the true residual b - A~ x is computed with h_fp64 (Sec. 4.1.3): below
+ * tol the solve is done, else the next cycle starts from that residual.
+ * iterations = steps (one h_iter product each); matvecs counts the h_iter
+ * products (the initial residual and one per step), matvecs_fp64 the cycles'
+ * true residuals, restarts the cycles after the first, rel_res the last
+ * estimate.  opts->refine must be 0; opts->history receives the estimate
+ * after every step.  x holds x_0 on entry.  `work`: device, 256-byte
+ * aligned, hmat_gmres_workspace_bytes(n, restart) bytes.  Synchronises
+ * `stream` before returning; `info` is filled in every case. */
+uint64_t hmat_gmres_workspace_bytes(int64_t n, int32_t restart);
+int hmat_gmres(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, int32_t restart, const hmat_solve_opts *opts,
+               hmat_solve_info *info, void *work, uint64_t work_bytes, void *stream);
+
 /* Outcome of one recurrence of the batched solver. */
 typedef struct {
     int32_t status;           /* HMAT_OK, HMAT_E_BREAKDOWN, HMAT_E_NOCONV or HMAT_E_NONFINITE */

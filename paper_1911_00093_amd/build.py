@@ -18,7 +18,8 @@ CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhmat.so")
 
-HIP_SOURCES = ["matvec.hip", "matvec_mr.hip", "krylov.hip", "krylov_batched.hip", "learned.hip", "diag.hip"]
+HIP_SOURCES = ["matvec.hip", "matvec_mr.hip", "krylov.hip", "krylov_batched.hip", "gmres.hip", "learned.hip",
+               "diag.hip"]
 HOST_SOURCES = ["pack.cpp", "assemble.cpp"]
 ARCH = "gfx950"
 

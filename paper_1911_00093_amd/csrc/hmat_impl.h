@@ -249,6 +249,8 @@ int size_grids(hmat_s *h);
 int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream,
                      const int32_t *skip = nullptr, const int32_t *active = nullptr);
 int size_grids_mr(hmat_s *h);
+// order of a preconditioner (krylov.hip)
+int64_t precond_order(const hmat_precond_s *p);
 
 // Kernel timing (diag.hip): mark(h, k, stream) records event k (0..3) of the
 // current product when timing is enabled.

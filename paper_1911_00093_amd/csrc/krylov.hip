@@ -416,6 +416,8 @@ struct hmat_precond_s {
   int any_uncovered = 0;
 };
 
+int64_t hm::precond_order(const hmat_precond_s *p) { return p->n; }
+
 namespace hm {
 
 // Gauss-Jordan with partial pivoting on [A | I] (FP64); A column-major m x m.

@@ -31,7 +31,8 @@ MLP_PARAMS = 512 * 128 + 128 + 128 * 128 + 128 + 128 * 2048 + 2048
 EXPORTED = [
     "hmat_last_error", "hmat_plan", "hmat_build", "hmat_matvec", "hmat_destroy", "hmat_get_stats",
     "hmat_precond_plan", "hmat_precond_create", "hmat_precond_apply", "hmat_precond_destroy",
-    "hmat_solver_workspace_bytes", "hmat_bicgstab", "hmat_assemble_bem", "hmat_assembly_blocks",
+    "hmat_solver_workspace_bytes", "hmat_bicgstab", "hmat_gmres_workspace_bytes", "hmat_gmres",
+    "hmat_assemble_bem", "hmat_assembly_blocks",
     "hmat_assembly_perm", "hmat_assembly_free", "hmat_version", "hmat_set_profiling", "hmat_kernel_times",
     "hmat_stream_read", "hmat_stream_copy", "hmat_plan_batched", "hmat_build_batched", "hmat_system_offsets",
     "hmat_bicgstab_batched_workspace_bytes", "hmat_bicgstab_batched", "hmat_precond_create_learned",
@@ -125,6 +126,8 @@ def lib():
         "hmat_precond_destroy": (C.c_int, [P]),
         "hmat_solver_workspace_bytes": (U64, [I64]),
         "hmat_bicgstab": (C.c_int, [P, P, P, P, P, P, P, U64, P]),
+        "hmat_gmres_workspace_bytes": (U64, [I64, C.c_int32]),
+        "hmat_gmres": (C.c_int, [P, P, P, P, C.c_int32, P, P, P, U64, P]),
         "hmat_assemble_bem": (C.c_int, [I64, P, P, P, P]),
         "hmat_assembly_blocks": (C.c_int, [P, P]),
         "hmat_assembly_perm": (C.POINTER(C.c_int64), [P]),
@@ -507,6 +510,35 @@ def hmat_bicgstab(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = None, tol
     info = hmat_solve_info()
     rc = lib().hmat_bicgstab(h_iter.h, (h_fp64 or h_iter).h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
                              C.byref(o), C.byref(info), C.c_void_p(work.data_ptr()), work.numel(), _stream_ptr(stream))
+    if rc != HMAT_OK and (raise_on_error or rc not in (HMAT_E_BREAKDOWN, HMAT_E_NOCONV, HMAT_E_NONFINITE)):
+        _check(rc)
+    d = dict(status=info.status, restarts=info.restarts, iterations=info.iterations, matvecs=info.matvecs,
+             matvecs_fp64=info.matvecs_fp64, rel_res=info.rel_res, true_rel_res=info.true_rel_res)
+    if hist is not None:
+        d["history"] = hist[:info.iterations + 1]
+    return x, d
+
+
+def hmat_gmres(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = None, tol=1e-8, maxiter=1000, restart=30,
+               poll_every=1, use_graph=False, precond: Precond | None = None, history=False, work=None, stream=None,
+               raise_on_error=False):
+    """Restarted GMRES on the device (hmat_gmres); returns (x, info dict)."""
+    import torch
+
+    n = h_iter.n
+    x = torch.zeros(n, dtype=torch.float64, device=b.device) if x is None else x
+    wb = int(lib().hmat_gmres_workspace_bytes(int(n), int(restart)))
+    if wb == 0:
+        raise HmatError(HMAT_E_ARG, f"restart {restart} out of range")
+    if work is None or work.numel() < wb:
+        work = torch.empty(wb, dtype=torch.uint8, device=b.device)
+    hist = np.full(maxiter + 1, np.nan) if history else None
+    o = hmat_solve_opts(float(tol), int(maxiter), int(poll_every), int(bool(use_graph)),
+                        precond.p if precond is not None else None, _p(hist) if hist is not None else None, 0.0)
+    info = hmat_solve_info()
+    rc = lib().hmat_gmres(h_iter.h, (h_fp64 or h_iter).h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
+                          int(restart), C.byref(o), C.byref(info), C.c_void_p(work.data_ptr()), work.numel(),
+                          _stream_ptr(stream))
     if rc != HMAT_OK and (raise_on_error or rc not in (HMAT_E_BREAKDOWN, HMAT_E_NOCONV, HMAT_E_NONFINITE)):
         _check(rc)
     d = dict(status=info.status, restarts=info.restarts, iterations=info.iterations, matvecs=info.matvecs,
