@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--eps", type=float, default=None, help="ACA tolerance (default: the workload's)")
     ap.add_argument("--refine", type=float, default=None,
                     help="early FP64 true-residual check ratio (default 1e-2 for BF16-scaled, else 0)")
+    ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "gmres"],
+                    help="Krylov solver of the single-system workloads (GMRES: restarted, --restart steps)")
+    ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--drop", type=int, default=0,
                     help="Methods 2/3: delete low-rank terms with d_i < d_max 10^-drop (Sec. 4.5; 0 = off)")
     ap.add_argument("--train-leaves", type=int, default=20000)
@@ -142,12 +145,20 @@ def main():
     B64, Bm = st64.algorithmic_bytes, stm.algorithmic_bytes
     b = torch.as_tensor(mesh.rhs()[bs.perm], device=dev)
     n = bs.n
-    work = torch.empty(hmat.hmat_solver_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    gm = args.solver == "gmres"
+    wbytes = (hmat.lib().hmat_gmres_workspace_bytes(n, args.restart) if gm else hmat.hmat_solver_workspace_bytes(n))
+    work = torch.empty(int(wbytes), dtype=torch.uint8, device=dev)
+
+    def run(H, tol, x, use_graph=False):
+        if gm:
+            return hmat.hmat_gmres(H, b, x=x, h_fp64=H64, tol=tol, maxiter=2000, restart=args.restart,
+                                   poll_every=args.poll_every, work=work, use_graph=use_graph)
+        return hmat.hmat_bicgstab(H, b, x=x, h_fp64=H64, tol=tol, maxiter=2000, poll_every=args.poll_every,
+                                  work=work, refine=args.refine if H is Hm else 0.0, use_graph=use_graph)
 
     def solve(H, tol, x=None):
         x = torch.zeros(n, dtype=torch.float64, device=dev) if x is None else x.zero_()
-        return hmat.hmat_bicgstab(H, b, x=x, h_fp64=H64, tol=tol, maxiter=2000, poll_every=args.poll_every,
-                                  work=work, refine=args.refine if H is Hm else 0.0)
+        return run(H, tol, x)
 
     # reference solution: FP64 to 1e-12
     xref, iref = solve(H64, 1e-12)
@@ -188,8 +199,7 @@ def main():
     t_start = time.perf_counter()
     for _ in range(args.steps):
         xg.zero_()
-        hmat.hmat_bicgstab(Hm, b, x=xg, h_fp64=H64, tol=args.tol, maxiter=2000, poll_every=args.poll_every,
-                           work=work, refine=args.refine, use_graph=True)
+        run(Hm, args.tol, xg, use_graph=True)
     torch.cuda.synchronize()
     t_graph = time.perf_counter() - t_start
 
@@ -272,7 +282,9 @@ def main():
             "precision": args.variant,
             "storage": "fp32 matrix, fp64 D_m / x / y / Krylov",
             "n": n,
-            "step": "one BiCGSTAB solve x0=0 -> |r|/|b|<1e-8 confirmed by the FP64 true residual",
+            "step": (f"one restarted GMRES({args.restart}) solve" if gm else "one BiCGSTAB solve")
+                    + " x0=0 -> |r|/|b|<1e-8 confirmed by the FP64 true residual",
+            "solver": f"GMRES({args.restart})" if gm else "BiCGSTAB",
             "refine": args.refine,
             "drop": args.drop,
             "parallelism": "1 GPU",
