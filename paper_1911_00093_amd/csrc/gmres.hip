@@ -23,7 +23,7 @@ namespace hm {
 
 constexpr int kGThreads = 256;
 constexpr int kGParts = 512;  // workgroups of the element-wise kernels
-constexpr int kGDot = 64;     // workgroups per basis vector of the inner-product kernel
+constexpr int kGDot = 128;    // workgroups per eight basis vectors of the inner-product kernel
 constexpr int kGMaxRestart = 128;
 constexpr int kGHist = 100000;
 
@@ -108,18 +108,53 @@ __device__ __forceinline__ void gsum(double (&v)[NV]) {
 
 #define G_LOOP(i, n) for (int64_t i = (int64_t)blockIdx.x * kGThreads + threadIdx.x; i < (n); i += (int64_t)gridDim.x * kGThreads)
 
-// partials of V_i^T w, i <= j: workgroup (x, i) sums its strided share of
-// the elements of basis vector i
+// sum_{i < k} h_i V_i[e] in i order; eight loads in flight at a time
+// (indices past k repeat the last one and are not added)
+__device__ __forceinline__ double vsum(const double *__restrict__ V, int64_t n, int64_t e,
+                                       const double *__restrict__ h, int k) {
+  double s = 0.0;
+  for (int i0 = 0; i0 < k; i0 += 8) {
+    double hv[8], vv[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const int i = min(i0 + u, k - 1);
+      hv[u] = h[i];
+      vv[u] = V[(int64_t)i * n + e];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const double t = s + hv[u] * vv[u];
+      s = i0 + u < k ? t : s;
+    }
+  }
+  return s;
+}
+
+// partials of V_i^T w, i <= j: workgroup (x, y) sums, for the eight basis
+// vectors i = 8y .. 8y + 7, its strided share of the elements (w read once
+// per element for all eight; rows past j re-read row j and are not written)
 __global__ __launch_bounds__(kGThreads) void k_gm_dots(int64_t n, const GState *__restrict__ st,
                                                        const double *__restrict__ V, const double *__restrict__ w,
                                                        double *__restrict__ part) {
-  const int i = blockIdx.y;
-  if (st->flag != 0 || i > st->j) return;  // uniform
-  const double *v = V + (int64_t)i * n;
-  double a[1] = {0.0};
-  G_LOOP(e, n) a[0] += v[e] * w[e];
-  gsum<1>(a);
-  if (threadIdx.x == 0) part[(int64_t)i * kGDot + blockIdx.x] = a[0];
+  const int i0 = blockIdx.y * 8;
+  if (st->flag != 0 || i0 > st->j) return;  // uniform
+  const int J = st->j;
+  double acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; u++) acc[u] = 0.0;
+  G_LOOP(e, n) {
+    double vv[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) vv[u] = V[(int64_t)min(i0 + u, J) * n + e];
+    const double we = w[e];
+#pragma unroll
+    for (int u = 0; u < 8; u++) acc[u] += vv[u] * we;
+  }
+  gsum<8>(acc);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+      if (i0 + u <= J) part[(int64_t)(i0 + u) * kGDot + blockIdx.x] = acc[u];
 }
 
 // h_i = sum of the partials of V_i^T w in workgroup order (one thread per i);
@@ -147,9 +182,7 @@ __global__ __launch_bounds__(kGThreads) void k_gm_update(int64_t n, const GState
   const int J = st->j;
   double a[1] = {0.0};
   G_LOOP(e, n) {
-    double s = 0.0;
-    for (int i = 0; i <= J; i++) s += h[i] * V[(int64_t)i * n + e];
-    const double we = w[e] - s;
+    const double we = w[e] - vsum(V, n, e, h, J + 1);
     w[e] = we;
     a[0] += we * we;
   }
@@ -163,34 +196,44 @@ __global__ __launch_bounds__(kGThreads) void k_gm_update(int64_t n, const GState
 // column, the rotation that zeroes its subdiagonal, the rotated right-hand
 // side g and its last entry, the residual estimate; decides whether the
 // cycle goes on.
-__global__ void k_gm_step_end(GState *__restrict__ st, const double *__restrict__ pn, const double *__restrict__ hc,
-                              double *__restrict__ R, double *__restrict__ g, double *__restrict__ cs,
-                              double *__restrict__ sn, double *__restrict__ hist) {
-  if (st->flag != 0 || threadIdx.x != 0) return;
+// Launched with kGThreads threads: the partials and the column are read by
+// all of them, the rotations run on one.
+__global__ __launch_bounds__(kGThreads) void k_gm_step_end(GState *__restrict__ st, const double *__restrict__ pn,
+                                                           const double *__restrict__ hc, double *__restrict__ R,
+                                                           double *__restrict__ g, double *__restrict__ cs,
+                                                           double *__restrict__ sn, double *__restrict__ hist) {
+  __shared__ double col[kGMaxRestart + 1], rc[kGMaxRestart], rs[kGMaxRestart];
+  if (st->flag != 0) return;  // uniform
   const int J = st->j, m = st->m;
-  double nn = 0.0;
-  for (int x = 0; x < kGParts; x++) nn += pn[x];
-  const double hn = sqrt(nn);
-  double *col = R + (int64_t)J * (m + 1);
-  bool finite = isfinite(hn);
-  for (int i = 0; i <= J; i++) {
-    col[i] = hc[i];
-    finite = finite && isfinite(hc[i]);
+  double a1[1] = {0.0};
+  for (int x = threadIdx.x; x < kGParts; x += kGThreads) a1[0] += pn[x];
+  gsum<1>(a1);
+  for (int i = threadIdx.x; i <= J; i += kGThreads) col[i] = hc[i];
+  for (int i = threadIdx.x; i < J; i += kGThreads) {
+    rc[i] = cs[i];
+    rs[i] = sn[i];
   }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double hn = sqrt(a1[0]);
+  bool finite = isfinite(hn);
+  for (int i = 0; i <= J; i++) finite = finite && isfinite(col[i]);
   if (!finite) {
     st->flag = 3;
     return;
   }
   for (int i = 0; i < J; i++) {
     const double a = col[i], c = col[i + 1];
-    col[i] = cs[i] * a + sn[i] * c;
-    col[i + 1] = -sn[i] * a + cs[i] * c;
+    col[i] = rc[i] * a + rs[i] * c;
+    col[i + 1] = -rs[i] * a + rc[i] * c;
   }
   const double rho = hypot(col[J], hn);
   const double c = rho == 0.0 ? 1.0 : col[J] / rho, s = rho == 0.0 ? 0.0 : hn / rho;
   cs[J] = c;
   sn[J] = s;
   col[J] = rho;
+  double *Rc = R + (int64_t)J * (m + 1);
+  for (int i = 0; i <= J; i++) Rc[i] = col[i];
   g[J + 1] = -s * g[J];
   g[J] = c * g[J];
   st->est = fabs(g[J + 1]) / st->bnorm;
@@ -235,13 +278,16 @@ __global__ __launch_bounds__(kGThreads) void k_gm_resid(int64_t n, const double 
 
 // start of a cycle from the residual partials (one thread): |b| (first
 // cycle), beta = |r|, the last true residual, g = beta e_1, j = 0
-__global__ void k_gm_cycle(GState *__restrict__ st, const double *__restrict__ pn, double *__restrict__ g, int first) {
-  if (threadIdx.x != 0) return;
-  double rr = 0.0, bb = 0.0;
-  for (int x = 0; x < kGParts; x++) {
-    rr += pn[2 * x];
-    bb += pn[2 * x + 1];
+__global__ __launch_bounds__(kGThreads) void k_gm_cycle(GState *__restrict__ st, const double *__restrict__ pn,
+                                                        double *__restrict__ g, int first) {
+  double a2[2] = {0.0, 0.0};
+  for (int x = threadIdx.x; x < kGParts; x += kGThreads) {
+    a2[0] += pn[2 * x];
+    a2[1] += pn[2 * x + 1];
   }
+  gsum<2>(a2);
+  if (threadIdx.x != 0) return;
+  const double rr = a2[0], bb = a2[1];
   if (first) st->bnorm = sqrt(bb);
   const double beta = sqrt(rr);
   st->beta = beta;
@@ -283,11 +329,7 @@ __global__ __launch_bounds__(kGThreads) void k_gm_combine(int64_t n, const GStat
                                                           const double *__restrict__ V, const double *__restrict__ y,
                                                           double *__restrict__ u) {
   const int k = st->j;
-  G_LOOP(e, n) {
-    double s = 0.0;
-    for (int i = 0; i < k; i++) s += y[i] * V[(int64_t)i * n + e];
-    u[e] = s;
-  }
+  G_LOOP(e, n) u[e] = k > 0 ? vsum(V, n, e, y, k) : 0.0;
 }
 
 __global__ __launch_bounds__(kGThreads) void k_gm_axpy(int64_t n, const double *__restrict__ u, double *__restrict__ x) {
@@ -332,7 +374,7 @@ int hmat_gmres(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, int32_t
   hipStream_t st = (hipStream_t)stream;
   const int m = restart;
   GWork w = gcarve(work, n, m);
-  const dim3 G(kGParts), B(kGThreads), GD(kGDot, m + 1);
+  const dim3 G(kGParts), B(kGThreads), GD(kGDot, (m + 8) / 8);
   const bool pre = o->precond != nullptr;
   const int32_t *stopped = &w.st->flag;
   int64_t nmv = 0, nmv64 = 0;
@@ -351,7 +393,7 @@ int hmat_gmres(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, int32_t
   if ((rc = product(h_iter, x, w.tmp, st, nullptr))) return rc;
   nmv++;
   hipLaunchKernelGGL(k_gm_resid, G, B, 0, st, n, b, w.tmp, w.r, w.pn);
-  hipLaunchKernelGGL(k_gm_cycle, dim3(1), dim3(64), 0, st, w.st, w.pn, w.g, 1);
+  hipLaunchKernelGGL(k_gm_cycle, dim3(1), B, 0, st, w.st, w.pn, w.g, 1);
   hipLaunchKernelGGL(k_gm_first, G, B, 0, st, n, w.st, w.r, w.V, w.vcur);
   if (poll() != hipSuccess) return fail(HMAT_E_HIP, "GMRES start failed");
   if (hs.bnorm == 0.0) {  // b = 0: x = 0
@@ -374,7 +416,7 @@ int hmat_gmres(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, int32_t
     hipLaunchKernelGGL(k_gm_dots, GD, B, 0, s2, n, w.st, w.V, w.w, w.part);
     hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(kGMaxRestart + 1), 0, s2, w.st, w.part, w.hc, w.h2, 1);
     hipLaunchKernelGGL(k_gm_update, G, B, 0, s2, n, w.st, w.V, w.h2, w.w, w.pn, 1);
-    hipLaunchKernelGGL(k_gm_step_end, dim3(1), dim3(64), 0, s2, w.st, w.pn, w.hc, w.R, w.g, w.cs, w.sn, w.hist);
+    hipLaunchKernelGGL(k_gm_step_end, dim3(1), B, 0, s2, w.st, w.pn, w.hc, w.R, w.g, w.cs, w.sn, w.hist);
     hipLaunchKernelGGL(k_gm_scale, G, B, 0, s2, n, w.st, w.w, w.V, w.vcur);
     return HMAT_OK;
   };
@@ -432,7 +474,7 @@ int hmat_gmres(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, int32_t
     if ((rc = product(h_fp64, x, w.tmp, st, nullptr))) return rc;
     nmv64++;
     hipLaunchKernelGGL(k_gm_resid, G, B, 0, st, n, b, w.tmp, w.r, w.pn);
-    hipLaunchKernelGGL(k_gm_cycle, dim3(1), dim3(64), 0, st, w.st, w.pn, w.g, 0);
+    hipLaunchKernelGGL(k_gm_cycle, dim3(1), B, 0, st, w.st, w.pn, w.g, 0);
     if (poll() != hipSuccess) return fail(HMAT_E_HIP, "GMRES cycle end failed");
     if (hs.truerel < o->tol) break;
     if (hs.flag == 3) {
