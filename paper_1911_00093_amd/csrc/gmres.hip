@@ -192,12 +192,10 @@ __global__ __launch_bounds__(kGThreads) void k_gm_update(int64_t n, const GState
   }
 }
 
-// End of a step (one thread): |w|, the earlier rotations applied to the new
-// column, the rotation that zeroes its subdiagonal, the rotated right-hand
-// side g and its last entry, the residual estimate; decides whether the
-// cycle goes on.
-// Launched with kGThreads threads: the partials and the column are read by
-// all of them, the rotations run on one.
+// End of a step (one workgroup): |w| from the partials in a fixed order,
+// then on one thread the earlier rotations applied to the new column, the
+// rotation that zeroes its subdiagonal, the rotated right-hand side g and
+// its last entry, the residual estimate; decides whether the cycle goes on.
 __global__ __launch_bounds__(kGThreads) void k_gm_step_end(GState *__restrict__ st, const double *__restrict__ pn,
                                                            const double *__restrict__ hc, double *__restrict__ R,
                                                            double *__restrict__ g, double *__restrict__ cs,
@@ -276,8 +274,9 @@ __global__ __launch_bounds__(kGThreads) void k_gm_resid(int64_t n, const double 
   }
 }
 
-// start of a cycle from the residual partials (one thread): |b| (first
-// cycle), beta = |r|, the last true residual, g = beta e_1, j = 0
+// start of a cycle from the residual partials (one workgroup, sums in a
+// fixed order): |b| (first cycle), beta = |r|, the last true residual,
+// g = beta e_1, j = 0
 __global__ __launch_bounds__(kGThreads) void k_gm_cycle(GState *__restrict__ st, const double *__restrict__ pn,
                                                         double *__restrict__ g, int first) {
   double a2[2] = {0.0, 0.0};
