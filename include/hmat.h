@@ -408,6 +408,39 @@ typedef struct hmat_assembly_s *hmat_assembly_t;
 
 int hmat_assemble_bem(int64_t n, const double *centroids, const double *areas, const hmat_assemble_opts *opts,
                       hmat_assembly_t *out);
+/* The same H-matrix built with its entries and ACA on the GPU (the paper's
+ * Sec. 4.5 outlook; generation itself is Sec. 4.1.3's FP64 step): cluster
+ * tree and partition on the host as above, then one workgroup per admissible
+ * block runs the partially pivoted ACA of hmat_assemble_bem with the same
+ * operations in the same order (residual rows and columns term by term,
+ * every norm and inner product summed in index order, no fused multiply-add),
+ * and a second kernel evaluates the dense blocks and writes the factors in
+ * the host layout; the result is copied back into an assembly identical, bit
+ * for bit, to hmat_assemble_bem's.  rank_cap (1..127, 0: 48) bounds the
+ * ranks kept on the device per block; a block whose ACA has not stopped
+ * by then (and cannot yet be known to end dense) is redone on the host.
+ * Device memory: the library allocates its scratch on the current device
+ * (about 8 (#I + #J) rank_cap bytes per admissible block plus the result) and
+ * frees it before returning; HMAT_E_NOMEM if that fails.  Work is queued on
+ * `stream` and the call synchronises it before returning. */
+int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const double *areas, const hmat_assemble_opts *opts,
+                          int32_t rank_cap, void *stream, hmat_assembly_t *out);
+
+/* What an assembly did (either path). */
+typedef struct {
+    int64_t blocks;          /* blocks of the partition */
+    int64_t lowrank;         /* blocks stored low rank */
+    int64_t host_blocks;     /* blocks whose entries were computed on the host */
+    int32_t rank_cap;        /* device path: ranks kept per block (0: host path) */
+    int32_t reserved;
+    uint64_t device_bytes;   /* device path: scratch allocated */
+    double ms_partition;     /* cluster tree and partition (host) */
+    double ms_fill;          /* entries and ACA: host threads, or the device path from upload to copy-back */
+    double ms_aca, ms_emit;  /* device path: the two kernels (HIP events) */
+    double ms_copy;          /* device path: result copied to the host */
+} hmat_assembly_stats;
+int hmat_assembly_get_stats(hmat_assembly_t a, hmat_assembly_stats *stats);
+
 /* Fill `view` with pointers into the assembly (valid until hmat_assembly_free). */
 int hmat_assembly_blocks(hmat_assembly_t a, hmat_blocks *view);
 /* perm[k] = original panel index at cluster position k (length n). */

@@ -17,6 +17,7 @@
 //    |u||v| <= eps |S_k|_F, dense fallback when r (m + n) >= m n.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -36,58 +37,36 @@ struct Cluster {
   bool leaf() const { return kid[0] < 0; }
 };
 
-struct BlockRec {
-  int64_t t, s;  // cluster ids
-  int kind;      // 0 dense, 1 admissible
-  int32_t rank = 0;
-  std::vector<double> data;
-};
-
-class Assembler {
+// Cluster tree and block partition (host, sequential: O(n log n) and
+// O(blocks), small next to the entries).
+class Partitioner {
  public:
-  Assembler(int64_t n, const double *cent, const double *area, const hmat_assemble_opts &o)
-      : n_(n), opt_(o), c_(3 * n), a_(n), perm_(n) {
-    for (int64_t i = 0; i < n; i++) perm_[i] = i;
-    orig_c_ = cent;
-    orig_a_ = area;
+  Partitioner(int64_t n, const double *cent, const hmat_assemble_opts &o, hm::BemPartition &P)
+      : opt_(o), cent_(cent), P_(P) {
+    P.perm.resize(n);
+    for (int64_t i = 0; i < n; i++) P.perm[i] = i;
   }
 
   void run() {
-    build_tree();
-    for (int64_t k = 0; k < n_; k++) {
-      for (int d = 0; d < 3; d++) c_[3 * k + d] = orig_c_[3 * perm_[k] + d];
-      a_[k] = orig_a_[perm_[k]];
-    }
+    build_node(0, (int64_t)P_.perm.size());
     partition(0, 0);
-    fill_blocks();
   }
-
-  int64_t n_;
-  hmat_assemble_opts opt_;
-  std::vector<double> c_, a_;
-  std::vector<int64_t> perm_;
-  std::vector<Cluster> cl_;
-  std::vector<BlockRec> blocks_;
-  const double *orig_c_, *orig_a_;
 
  private:
-  double entry(int64_t i, int64_t j) const {
-    if (i == j) return 0.5 * std::sqrt(a_[i] / kPi);
-    const double dx = c_[3 * i + 0] - c_[3 * j + 0];
-    const double dy = c_[3 * i + 1] - c_[3 * j + 1];
-    const double dz = c_[3 * i + 2] - c_[3 * j + 2];
-    const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
-    return a_[j] / (4.0 * kPi * r);
-  }
+  hmat_assemble_opts opt_;
+  const double *cent_;
+  hm::BemPartition &P_;
+  std::vector<Cluster> cl_;
 
-  // cluster tree over perm_[lo, hi), partitioned in place
+  // cluster tree over perm[lo, hi), partitioned in place
   int64_t build_node(int64_t lo, int64_t hi) {
+    std::vector<int64_t> &perm = P_.perm;
     const int64_t id = (int64_t)cl_.size();
     cl_.push_back(Cluster{lo, hi, {-1, -1}, {0, 0, 0}, {0, 0, 0}});
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t k = lo; k < hi; k++)
       for (int d = 0; d < 3; d++) {
-        const double v = orig_c_[3 * perm_[k] + d];
+        const double v = cent_[3 * perm[k] + d];
         mn[d] = std::min(mn[d], v);
         mx[d] = std::max(mx[d], v);
       }
@@ -99,8 +78,8 @@ class Assembler {
     for (int d = 1; d < 3; d++)
       if (mx[d] - mn[d] > mx[ax] - mn[ax]) ax = d;
     const double mid = 0.5 * (mn[ax] + mx[ax]);
-    auto below = [&](int64_t p) { return orig_c_[3 * p + ax] < mid; };
-    auto first = perm_.begin() + lo, last = perm_.begin() + hi;
+    auto below = [&](int64_t p) { return cent_[3 * p + ax] < mid; };
+    auto first = perm.begin() + lo, last = perm.begin() + hi;
     int64_t nl = std::count_if(first, last, below);
     if (nl == 0 || nl == m) nl = m / 2;
     else std::stable_partition(first, last, below);
@@ -110,8 +89,6 @@ class Assembler {
     cl_[id].kid[1] = r;
     return id;
   }
-
-  void build_tree() { build_node(0, n_); }
 
   static double diag(const Cluster &c) {
     double s = 0;
@@ -139,14 +116,22 @@ class Assembler {
     return std::min(diag(a), diag(b)) <= opt_.eta * dist;
   }
 
+  void add(int64_t t, int64_t s, int adm) {
+    P_.row0.push_back(cl_[t].lo);
+    P_.nrows.push_back(cl_[t].hi - cl_[t].lo);
+    P_.col0.push_back(cl_[s].lo);
+    P_.ncols.push_back(cl_[s].hi - cl_[s].lo);
+    P_.admissible.push_back(adm);
+  }
+
   void partition(int64_t t, int64_t s) {
     const Cluster &a = cl_[t], &b = cl_[s];
     if (admissible(a, b)) {
-      blocks_.push_back(BlockRec{t, s, 1});
+      add(t, s, 1);
       return;
     }
     if (a.leaf() && b.leaf()) {
-      blocks_.push_back(BlockRec{t, s, 0});
+      add(t, s, 0);
       return;
     }
     const int64_t a0 = a.kid[0], a1 = a.kid[1], b0 = b.kid[0], b1 = b.kid[1];
@@ -163,129 +148,129 @@ class Assembler {
       partition(a1, b1);
     }
   }
-
-  void dense(BlockRec &B) {
-    const Cluster &t = cl_[B.t], &s = cl_[B.s];
-    const int64_t m = t.hi - t.lo, nc = s.hi - s.lo;
-    B.kind = 0;
-    B.rank = 0;
-    B.data.resize(m * nc);
-    for (int64_t j = 0; j < nc; j++)
-      for (int64_t i = 0; i < m; i++) B.data[i + j * m] = entry(t.lo + i, s.lo + j);
-  }
-
-  // Partially pivoted ACA on rows tau, columns sigma.
-  void aca(BlockRec &B) {
-    const Cluster &t = cl_[B.t], &s = cl_[B.s];
-    const int64_t m = t.hi - t.lo, nc = s.hi - s.lo, kmax = std::min(m, nc);
-    std::vector<double> U, V;  // column k of U at U[k*m], of V at V[k*nc]
-    U.reserve(m * std::min<int64_t>(kmax, 32));
-    V.reserve(nc * std::min<int64_t>(kmax, 32));
-    std::vector<double> row(nc), col(m);
-    std::vector<char> used(m, 0);
-    int64_t k = 0, piv_row = 0;
-    double norm2 = 0.0, biggest = 0.0;
-    while (k < kmax) {
-      for (int64_t j = 0; j < nc; j++) {
-        const double e = entry(t.lo + piv_row, s.lo + j);
-        biggest = std::max(biggest, std::fabs(e));
-        double r = e;
-        for (int64_t l = 0; l < k; l++) r -= U[piv_row + l * m] * V[j + l * nc];
-        row[j] = r;
-      }
-      used[piv_row] = 1;
-      int64_t pc = 0;
-      for (int64_t j = 1; j < nc; j++)
-        if (std::fabs(row[j]) > std::fabs(row[pc])) pc = j;
-      if (std::fabs(row[pc]) <= 1e-14 * biggest) {
-        auto it = std::find(used.begin(), used.end(), 0);
-        if (it == used.end()) break;
-        piv_row = it - used.begin();
-        continue;
-      }
-      const double pv = row[pc];
-      V.resize((k + 1) * nc);
-      U.resize((k + 1) * m);
-      double *v = &V[k * nc], *u = &U[k * m];
-      for (int64_t j = 0; j < nc; j++) v[j] = row[j] / pv;
-      for (int64_t i = 0; i < m; i++) {
-        const double e = entry(t.lo + i, s.lo + pc);
-        biggest = std::max(biggest, std::fabs(e));
-        double r = e;
-        for (int64_t l = 0; l < k; l++) r -= V[pc + l * nc] * U[i + l * m];
-        col[i] = r;
-      }
-      std::memcpy(u, col.data(), m * sizeof(double));
-      double uu = 0.0, vv = 0.0;
-      for (int64_t i = 0; i < m; i++) uu += u[i] * u[i];
-      for (int64_t j = 0; j < nc; j++) vv += v[j] * v[j];
-      double cross = 0.0;
-      for (int64_t l = 0; l < k; l++) {
-        double pu = 0.0, pq = 0.0;
-        for (int64_t i = 0; i < m; i++) pu += U[i + l * m] * u[i];
-        for (int64_t j = 0; j < nc; j++) pq += V[j + l * nc] * v[j];
-        cross += pu * pq;
-      }
-      norm2 += 2.0 * cross + uu * vv;
-      k++;
-      if (std::sqrt(uu) * std::sqrt(vv) <= opt_.eps * std::sqrt(norm2)) break;
-      int64_t nxt = -1;
-      double best = -1.0;
-      for (int64_t i = 0; i < m; i++)
-        if (!used[i] && std::fabs(u[i]) > best) {
-          best = std::fabs(u[i]);
-          nxt = i;
-        }
-      if (nxt < 0) break;
-      piv_row = nxt;
-    }
-    if (k * (m + nc) >= m * nc) {
-      dense(B);
-      return;
-    }
-    B.kind = 1;
-    B.rank = (int32_t)k;
-    B.data.resize(k * (m + nc));
-    std::memcpy(B.data.data(), U.data(), m * k * sizeof(double));
-    std::memcpy(B.data.data() + m * k, V.data(), nc * k * sizeof(double));
-  }
-
-  void fill_blocks() {
-    // largest blocks first so the threads finish together
-    std::vector<int64_t> order(blocks_.size());
-    for (size_t i = 0; i < order.size(); i++) order[i] = (int64_t)i;
-    auto area = [&](int64_t i) {
-      const BlockRec &B = blocks_[i];
-      return (cl_[B.t].hi - cl_[B.t].lo) * (cl_[B.s].hi - cl_[B.s].lo);
-    };
-    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return area(a) > area(b); });
-    std::atomic<int64_t> next{0};
-    int nt = opt_.threads > 0 ? opt_.threads : (int)std::max(1u, std::thread::hardware_concurrency());
-    nt = std::min<int64_t>(nt, (int64_t)order.size());
-    auto work = [&]() {
-      for (;;) {
-        const int64_t q = next.fetch_add(1);
-        if (q >= (int64_t)order.size()) break;
-        BlockRec &B = blocks_[order[q]];
-        if (B.kind == 0) dense(B);
-        else aca(B);
-      }
-    };
-    std::vector<std::thread> th;
-    for (int i = 1; i < nt; i++) th.emplace_back(work);
-    work();
-    for (auto &x : th) x.join();
-  }
 };
+
+double entry(const hm::BemPartition &P, int64_t i, int64_t j) {
+  if (i == j) return 0.5 * std::sqrt(P.a[i] / kPi);
+  const double dx = P.c[3 * i + 0] - P.c[3 * j + 0];
+  const double dy = P.c[3 * i + 1] - P.c[3 * j + 1];
+  const double dz = P.c[3 * i + 2] - P.c[3 * j + 2];
+  const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+  return P.a[j] / (4.0 * kPi * r);
+}
+
+void dense(const hm::BemPartition &P, int64_t b, std::vector<double> &data) {
+  const int64_t m = P.nrows[b], nc = P.ncols[b], r0 = P.row0[b], c0 = P.col0[b];
+  data.resize(m * nc);
+  for (int64_t j = 0; j < nc; j++)
+    for (int64_t i = 0; i < m; i++) data[i + j * m] = entry(P, r0 + i, c0 + j);
+}
+
+// Partially pivoted ACA on rows tau, columns sigma.
+void aca(const hm::BemPartition &P, int64_t b, int32_t *kind, int32_t *rank, std::vector<double> &data) {
+  const int64_t m = P.nrows[b], nc = P.ncols[b], r0 = P.row0[b], c0 = P.col0[b], kmax = std::min(m, nc);
+  std::vector<double> U, V;  // column k of U at U[k*m], of V at V[k*nc]
+  U.reserve(m * std::min<int64_t>(kmax, 32));
+  V.reserve(nc * std::min<int64_t>(kmax, 32));
+  std::vector<double> row(nc), col(m);
+  std::vector<char> used(m, 0);
+  int64_t k = 0, piv_row = 0;
+  double norm2 = 0.0, biggest = 0.0;
+  while (k < kmax) {
+    for (int64_t j = 0; j < nc; j++) {
+      const double e = entry(P, r0 + piv_row, c0 + j);
+      biggest = std::max(biggest, std::fabs(e));
+      double r = e;
+      for (int64_t l = 0; l < k; l++) r -= U[piv_row + l * m] * V[j + l * nc];
+      row[j] = r;
+    }
+    used[piv_row] = 1;
+    int64_t pc = 0;
+    for (int64_t j = 1; j < nc; j++)
+      if (std::fabs(row[j]) > std::fabs(row[pc])) pc = j;
+    if (std::fabs(row[pc]) <= 1e-14 * biggest) {
+      auto it = std::find(used.begin(), used.end(), 0);
+      if (it == used.end()) break;
+      piv_row = it - used.begin();
+      continue;
+    }
+    const double pv = row[pc];
+    V.resize((k + 1) * nc);
+    U.resize((k + 1) * m);
+    double *v = &V[k * nc], *u = &U[k * m];
+    for (int64_t j = 0; j < nc; j++) v[j] = row[j] / pv;
+    for (int64_t i = 0; i < m; i++) {
+      const double e = entry(P, r0 + i, c0 + pc);
+      biggest = std::max(biggest, std::fabs(e));
+      double r = e;
+      for (int64_t l = 0; l < k; l++) r -= V[pc + l * nc] * U[i + l * m];
+      col[i] = r;
+    }
+    std::memcpy(u, col.data(), m * sizeof(double));
+    double uu = 0.0, vv = 0.0;
+    for (int64_t i = 0; i < m; i++) uu += u[i] * u[i];
+    for (int64_t j = 0; j < nc; j++) vv += v[j] * v[j];
+    double cross = 0.0;
+    for (int64_t l = 0; l < k; l++) {
+      double pu = 0.0, pq = 0.0;
+      for (int64_t i = 0; i < m; i++) pu += U[i + l * m] * u[i];
+      for (int64_t j = 0; j < nc; j++) pq += V[j + l * nc] * v[j];
+      cross += pu * pq;
+    }
+    norm2 += 2.0 * cross + uu * vv;
+    k++;
+    if (std::sqrt(uu) * std::sqrt(vv) <= P.eps * std::sqrt(norm2)) break;
+    int64_t nxt = -1;
+    double best = -1.0;
+    for (int64_t i = 0; i < m; i++)
+      if (!used[i] && std::fabs(u[i]) > best) {
+        best = std::fabs(u[i]);
+        nxt = i;
+      }
+    if (nxt < 0) break;
+    piv_row = nxt;
+  }
+  if (k * (m + nc) >= m * nc) {
+    *kind = 0;
+    *rank = 0;
+    dense(P, b, data);
+    return;
+  }
+  *kind = 1;
+  *rank = (int32_t)k;
+  data.resize(k * (m + nc));
+  std::memcpy(data.data(), U.data(), m * k * sizeof(double));
+  std::memcpy(data.data() + m * k, V.data(), nc * k * sizeof(double));
+}
 
 }  // namespace
 
-struct hmat_assembly_s {
-  int64_t n = 0;
-  std::vector<int64_t> perm, row0, nrows, col0, ncols, offset;
-  std::vector<int32_t> kind, rank;
-  std::vector<double> data;
-};
+namespace hm {
+
+void bem_partition(int64_t n, const double *cent, const double *area, const hmat_assemble_opts &o, BemPartition &P) {
+  P = BemPartition();
+  P.n = n;
+  P.eps = o.eps;
+  Partitioner(n, cent, o, P).run();
+  P.c.resize(3 * n);
+  P.a.resize(n);
+  for (int64_t k = 0; k < n; k++) {
+    for (int d = 0; d < 3; d++) P.c[3 * k + d] = cent[3 * P.perm[k] + d];
+    P.a[k] = area[P.perm[k]];
+  }
+}
+
+void bem_fill_host(const BemPartition &P, int64_t b, int32_t *kind, int32_t *rank, std::vector<double> &data) {
+  if (P.admissible[b]) {
+    aca(P, b, kind, rank, data);
+  } else {
+    *kind = 0;
+    *rank = 0;
+    dense(P, b, data);
+  }
+}
+
+}  // namespace hm
 
 extern "C" {
 
@@ -296,36 +281,59 @@ int hmat_assemble_bem(int64_t n, const double *centroids, const double *areas, c
   if (n <= 0 || !centroids || !areas || !opts) return hm::fail(HMAT_E_ARG, "bad arguments");
   if (opts->leaf < 1 || !(opts->eta > 0) || !(opts->eps > 0)) return hm::fail(HMAT_E_ARG, "bad assembly options");
   try {
-    Assembler A(n, centroids, areas, *opts);
-    A.run();
+    using clk = std::chrono::steady_clock;
+    auto ms = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+    const auto t0 = clk::now();
+    hm::BemPartition P;
+    hm::bem_partition(n, centroids, areas, *opts, P);
+    const auto t1 = clk::now();
+    const int64_t nb = (int64_t)P.row0.size();
+    std::vector<int32_t> kind(nb), rank(nb);
+    std::vector<std::vector<double>> data(nb);
+    // largest blocks first so the threads finish together
+    std::vector<int64_t> order(nb);
+    for (int64_t i = 0; i < nb; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t x, int64_t y) { return P.nrows[x] * P.ncols[x] > P.nrows[y] * P.ncols[y]; });
+    std::atomic<int64_t> next{0};
+    int nt = opts->threads > 0 ? opts->threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    nt = (int)std::max<int64_t>(1, std::min<int64_t>(nt, nb));
+    auto work = [&]() {
+      for (;;) {
+        const int64_t q = next.fetch_add(1);
+        if (q >= nb) break;
+        hm::bem_fill_host(P, order[q], &kind[order[q]], &rank[order[q]], data[order[q]]);
+      }
+    };
+    std::vector<std::thread> th;
+    for (int i = 1; i < nt; i++) th.emplace_back(work);
+    work();
+    for (auto &x : th) x.join();
     auto *R = new hmat_assembly_s();
     R->n = n;
-    R->perm = A.perm_;
-    const size_t nb = A.blocks_.size();
+    R->perm = std::move(P.perm);
     int64_t tot = 0;
-    for (auto &B : A.blocks_) tot += (int64_t)B.data.size();
+    for (auto &d : data) tot += (int64_t)d.size();
     R->data.resize(tot);
-    R->row0.resize(nb);
-    R->nrows.resize(nb);
-    R->col0.resize(nb);
-    R->ncols.resize(nb);
     R->offset.resize(nb);
-    R->kind.resize(nb);
-    R->rank.resize(nb);
     int64_t at = 0;
-    for (size_t i = 0; i < nb; i++) {
-      BlockRec &B = A.blocks_[i];
-      R->row0[i] = A.cl_[B.t].lo;
-      R->nrows[i] = A.cl_[B.t].hi - A.cl_[B.t].lo;
-      R->col0[i] = A.cl_[B.s].lo;
-      R->ncols[i] = A.cl_[B.s].hi - A.cl_[B.s].lo;
-      R->kind[i] = B.kind;
-      R->rank[i] = B.rank;
+    for (int64_t i = 0; i < nb; i++) {
       R->offset[i] = at;
-      std::memcpy(R->data.data() + at, B.data.data(), B.data.size() * sizeof(double));
-      at += (int64_t)B.data.size();
-      std::vector<double>().swap(B.data);
+      std::memcpy(R->data.data() + at, data[i].data(), data[i].size() * sizeof(double));
+      at += (int64_t)data[i].size();
+      std::vector<double>().swap(data[i]);
     }
+    R->row0 = std::move(P.row0);
+    R->nrows = std::move(P.nrows);
+    R->col0 = std::move(P.col0);
+    R->ncols = std::move(P.ncols);
+    R->kind = std::move(kind);
+    R->rank = std::move(rank);
+    R->stats.blocks = nb;
+    R->stats.host_blocks = nb;
+    for (int64_t i = 0; i < nb; i++) R->stats.lowrank += R->kind[i] == 1;
+    R->stats.ms_partition = ms(t0, t1);
+    R->stats.ms_fill = ms(t1, clk::now());
     *out = R;
   } catch (const std::bad_alloc &) {
     return hm::fail(HMAT_E_NOMEM, "out of host memory during assembly");
@@ -346,6 +354,12 @@ int hmat_assembly_blocks(hmat_assembly_t a, hmat_blocks *v) {
   v->offset = a->offset.data();
   v->data = a->data.data();
   v->ndata = (int64_t)a->data.size();
+  return HMAT_OK;
+}
+
+int hmat_assembly_get_stats(hmat_assembly_t a, hmat_assembly_stats *st) {
+  if (!a || !st) return hm::fail(HMAT_E_ARG, "null argument");
+  *st = a->stats;
   return HMAT_OK;
 }
 

@@ -1,0 +1,453 @@
+// Setup builder on the GPU: the entries and the ACA factors of the BEM
+// H-matrix (the step before the product; the paper generates the matrix in
+// FP64 and converts it afterwards, Sec. 4.1.3, and names faster generation
+// as the cost that remains, Sec. 4.5).  The cluster tree and the block
+// partition stay on the host (assemble.cpp); here
+//  * k_aca: one workgroup per admissible block runs partially pivoted ACA
+//    with the host builder's operations in the host builder's order, so the
+//    factors, ranks and dense fallbacks are the same bit for bit;
+//  * k_emit: one workgroup per block writes the dense entries and the
+//    factors into the host layout (column-major U, then column-major V).
+//
+// Scratch layout per admissible block: U as m x cap and V as nc x cap with
+// the rank index fastest, so the inner products of a new column with the
+// earlier ones (one per lane, summed sequentially down the column) read
+// contiguous rows across the lanes.  cap = min(rank_cap, kd) where kd is the
+// smallest rank that makes the block dense (k (m + nc) >= m nc): a block
+// that reaches kd ends dense on the host as well, so only blocks reaching a
+// smaller rank_cap without converging (status 2) go back to the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <thread>
+#include <vector>
+
+#include "hmat_impl.h"
+
+// Bit-identical to the host builder: no multiply-add contraction.
+#pragma clang fp contract(off)
+
+namespace hm {
+namespace {
+
+constexpr int kAThreads = 256;
+constexpr int kAWaves = kAThreads / kWave;
+constexpr int kAMaxCap = 127;  // ranks per block: lanes 0..k and 128..128+k hold the inner products
+constexpr int kADefaultCap = 48;
+constexpr double kPiG = 3.14159265358979323846;
+
+struct AcaDesc {
+  int64_t row0, col0;
+  int64_t u_off;     // U (m x cap), then V (nc x cap), in doubles from the scratch base
+  int64_t used_off;  // m pivot flags, in bytes from the flag base
+  int32_t m, nc, cap, pad;
+};
+
+struct EmitDesc {
+  int64_t row0, col0, out_off, u_off;
+  int32_t m, nc;
+  int32_t mode;  // 0 dense entries, 1 factors from the scratch, 2 filled on the host
+  int32_t rank, cap, pad;
+};
+
+// A_ij in cluster order: a_j / (4 pi |c_i - c_j|), self term sqrt(a_i / pi) / 2
+__device__ __forceinline__ double entry_at(double cix, double ciy, double ciz, const double *__restrict__ c,
+                                           const double *__restrict__ a, int64_t i, int64_t j) {
+  if (i == j) return 0.5 * sqrt(a[i] / kPiG);
+  const double dx = cix - c[3 * j + 0];
+  const double dy = ciy - c[3 * j + 1];
+  const double dz = ciz - c[3 * j + 2];
+  const double r = sqrt(dx * dx + dy * dy + dz * dz);
+  return a[j] / (4.0 * kPiG * r);
+}
+
+// Candidate (key, index, value): larger key wins, the lower index on ties,
+// which is the first maximum of a scan in index order.
+struct Arg {
+  double key;
+  int idx;
+  double val;
+};
+
+__device__ __forceinline__ void arg_take(Arg &a, double key, int idx, double val) {
+  if (key > a.key || (key == a.key && idx < a.idx)) {
+    a.key = key;
+    a.idx = idx;
+    a.val = val;
+  }
+}
+
+// Workgroup reduction of a candidate and a maximum; every thread gets both.
+__device__ void wg_best(Arg &a, double &mx, Arg *s_arg, double *s_mx) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double k = __shfl_xor(a.key, o, kWave);
+    const int i = __shfl_xor(a.idx, o, kWave);
+    const double v = __shfl_xor(a.val, o, kWave);
+    const double m2 = __shfl_xor(mx, o, kWave);
+    arg_take(a, k, i, v);
+    mx = m2 > mx ? m2 : mx;
+  }
+  const int wave = threadIdx.x / kWave;
+  __syncthreads();  // earlier readers of s_arg are done
+  if (threadIdx.x % kWave == 0) {
+    s_arg[wave] = a;
+    s_mx[wave] = mx;
+  }
+  __syncthreads();
+  a = s_arg[0];
+  mx = s_mx[0];
+#pragma unroll
+  for (int w = 1; w < kAWaves; w++) {
+    arg_take(a, s_arg[w].key, s_arg[w].idx, s_arg[w].val);
+    mx = s_mx[w] > mx ? s_mx[w] : mx;
+  }
+}
+
+__global__ __launch_bounds__(kAThreads) void k_aca(const AcaDesc *__restrict__ D, const double *__restrict__ c,
+                                                   const double *__restrict__ a, double *__restrict__ ws,
+                                                   unsigned char *__restrict__ flags, double eps,
+                                                   int32_t *__restrict__ out_rank, int32_t *__restrict__ out_status) {
+  __shared__ double s_prev[kAMaxCap];       // earlier factors at the pivot row / column
+  __shared__ double s_pu[kAMaxCap + 1], s_pq[kAMaxCap + 1];
+  __shared__ Arg s_arg[kAWaves];
+  __shared__ double s_mx[kAWaves];
+  const AcaDesc d = D[blockIdx.x];
+  const int m = d.m, nc = d.nc, cap = d.cap, tid = threadIdx.x;
+  double *__restrict__ U = ws + d.u_off;
+  double *__restrict__ V = U + (int64_t)m * cap;
+  unsigned char *__restrict__ used = flags + d.used_off;
+  for (int i = tid; i < m; i += kAThreads) used[i] = 0;
+  const int kmax = min(m, nc);
+  int k = 0, istar = 0;
+  double seen = 0.0, S2 = 0.0;
+  bool ended = false;
+  __syncthreads();
+  while (k < kmax && k < cap) {
+    // residual of row istar: A(istar, :) - sum_l U(istar, l) V(:, l)
+    if (tid < k) s_prev[tid] = U[(int64_t)istar * cap + tid];
+    __syncthreads();
+    if (tid == 0) used[istar] = 1;
+    const int64_t gi = d.row0 + istar;
+    const double cix = c[3 * gi + 0], ciy = c[3 * gi + 1], ciz = c[3 * gi + 2];
+    Arg best{-1.0, INT_MAX, 0.0};
+    double mx = seen;
+    for (int j = tid; j < nc; j += kAThreads) {
+      const double e = entry_at(cix, ciy, ciz, c, a, gi, d.col0 + j);
+      const double ae = fabs(e);
+      mx = ae > mx ? ae : mx;
+      double r = e;
+      const double *vr = V + (int64_t)j * cap;
+      for (int l = 0; l < k; l++) r -= s_prev[l] * vr[l];
+      V[(int64_t)j * cap + k] = r;
+      arg_take(best, fabs(r), j, r);
+    }
+    wg_best(best, mx, s_arg, s_mx);
+    seen = mx;
+    if (fabs(best.val) <= 1e-14 * seen) {
+      // numerically zero row: next pivot is the lowest unused row
+      Arg f{-2.0, INT_MAX, 0.0};
+      double none = 0.0;
+      for (int i = tid; i < m; i += kAThreads)
+        if (!used[i]) {
+          arg_take(f, 0.0, i, 0.0);
+          break;
+        }
+      wg_best(f, none, s_arg, s_mx);
+      if (f.key < -1.0) {
+        ended = true;
+        break;
+      }
+      istar = f.idx;
+      continue;
+    }
+    const int pc = best.idx;
+    const double pv = best.val;
+    for (int j = tid; j < nc; j += kAThreads) V[(int64_t)j * cap + k] = V[(int64_t)j * cap + k] / pv;
+    if (tid < k) s_prev[tid] = V[(int64_t)pc * cap + tid];
+    __syncthreads();
+    // residual of column pc: A(:, pc) - sum_l V(pc, l) U(:, l); next pivot candidates
+    const int64_t gj = d.col0 + pc;
+    Arg nxt{-2.0, INT_MAX, 0.0};
+    mx = seen;
+    for (int i = tid; i < m; i += kAThreads) {
+      const int64_t gr = d.row0 + i;
+      const double e = entry_at(c[3 * gr + 0], c[3 * gr + 1], c[3 * gr + 2], c, a, gr, gj);
+      const double ae = fabs(e);
+      mx = ae > mx ? ae : mx;
+      double s = e;
+      const double *ur = U + (int64_t)i * cap;
+      for (int l = 0; l < k; l++) s -= s_prev[l] * ur[l];
+      U[(int64_t)i * cap + k] = s;
+      if (!used[i]) arg_take(nxt, fabs(s), i, s);
+    }
+    wg_best(nxt, mx, s_arg, s_mx);
+    seen = mx;
+    // inner products of the new column pair with every column pair so far,
+    // each summed in index order by one lane
+    if (tid <= k) {
+      double p = 0.0;
+      for (int i = 0; i < m; i++) p += U[(int64_t)i * cap + tid] * U[(int64_t)i * cap + k];
+      s_pu[tid] = p;
+    } else if (tid >= 128 && tid - 128 <= k) {
+      const int l = tid - 128;
+      double q = 0.0;
+      for (int j = 0; j < nc; j++) q += V[(int64_t)j * cap + l] * V[(int64_t)j * cap + k];
+      s_pq[l] = q;
+    }
+    __syncthreads();
+    double cross = 0.0;
+    for (int l = 0; l < k; l++) cross += s_pu[l] * s_pq[l];
+    const double uu = s_pu[k], vv = s_pq[k];
+    S2 += 2.0 * cross + uu * vv;
+    k++;
+    __syncthreads();  // s_pu / s_pq read by every thread before the next step writes them
+    if (sqrt(uu) * sqrt(vv) <= eps * sqrt(S2)) {
+      ended = true;
+      break;
+    }
+    if (nxt.key < -1.0) {
+      ended = true;
+      break;
+    }
+    istar = nxt.idx;
+  }
+  if (tid == 0) {
+    const bool dense = (int64_t)k * (m + nc) >= (int64_t)m * nc;
+    out_rank[blockIdx.x] = k;
+    out_status[blockIdx.x] = (!ended && k < kmax && !dense) ? 2 : (dense ? 1 : 0);
+  }
+}
+
+__global__ __launch_bounds__(kAThreads) void k_emit(const EmitDesc *__restrict__ D, const double *__restrict__ c,
+                                                    const double *__restrict__ a, const double *__restrict__ ws,
+                                                    double *__restrict__ out) {
+  const EmitDesc d = D[blockIdx.x];
+  double *__restrict__ o = out + d.out_off;
+  if (d.mode == 0) {
+    const int tot = d.m * d.nc;  // < 2^31 (checked on the host)
+    for (int e = threadIdx.x; e < tot; e += kAThreads) {
+      const int i = e % d.m, j = e / d.m;
+      const int64_t gi = d.row0 + i;
+      o[e] = entry_at(c[3 * gi + 0], c[3 * gi + 1], c[3 * gi + 2], c, a, gi, d.col0 + j);
+    }
+  } else if (d.mode == 1) {
+    const double *U = ws + d.u_off;
+    const double *V = U + (int64_t)d.m * d.cap;
+    const int tu = d.m * d.rank, tv = d.nc * d.rank;
+    for (int e = threadIdx.x; e < tu; e += kAThreads) o[e] = U[(int64_t)(e % d.m) * d.cap + e / d.m];
+    for (int e = threadIdx.x; e < tv; e += kAThreads) o[tu + e] = V[(int64_t)(e % d.nc) * d.cap + e / d.nc];
+  }
+}
+
+// device allocations released on every exit path
+struct DevBufs {
+  std::vector<void *> p;
+  ~DevBufs() {
+    for (void *q : p) (void)hipFree(q);
+  }
+  template <class T>
+  hipError_t get(T **out, uint64_t bytes) {
+    void *q = nullptr;
+    const hipError_t e = hipMalloc(&q, bytes ? bytes : 16);
+    if (e == hipSuccess) p.push_back(q);
+    *out = (T *)q;
+    return e;
+  }
+};
+
+struct Events {
+  hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+  ~Events() {
+    for (hipEvent_t x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+
+}  // namespace
+}  // namespace hm
+
+#define HM_TRY(expr, what)                                                                       \
+  do {                                                                                           \
+    const hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                        \
+      return hm::fail(e_ == hipErrorOutOfMemory ? HMAT_E_NOMEM : HMAT_E_HIP, "%s: %s", what,     \
+                      hipGetErrorString(e_));                                                    \
+  } while (0)
+
+extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const double *areas,
+                                     const hmat_assemble_opts *opts, int32_t rank_cap, void *stream,
+                                     hmat_assembly_t *out) {
+  using namespace hm;
+  using clk = std::chrono::steady_clock;
+  auto ms = [](clk::time_point x, clk::time_point y) { return std::chrono::duration<double, std::milli>(y - x).count(); };
+  if (!out) return fail(HMAT_E_ARG, "null output");
+  *out = nullptr;
+  if (n <= 0 || n >= INT_MAX || !centroids || !areas || !opts) return fail(HMAT_E_ARG, "bad arguments");
+  if (opts->leaf < 1 || !(opts->eta > 0) || !(opts->eps > 0)) return fail(HMAT_E_ARG, "bad assembly options");
+  if (rank_cap == 0) rank_cap = kADefaultCap;
+  if (rank_cap < 1 || rank_cap > kAMaxCap) return fail(HMAT_E_ARG, "rank_cap %d outside 1..%d", rank_cap, kAMaxCap);
+  hipStream_t st = (hipStream_t)stream;
+  const auto t0 = clk::now();
+  BemPartition P;
+  std::vector<int32_t> kind, rank, status;
+  std::vector<int64_t> offset;
+  std::vector<std::vector<double>> hostdata;
+  int64_t total = 0;
+  hmat_assembly_stats S{};
+  S.rank_cap = rank_cap;
+  try {
+    bem_partition(n, centroids, areas, *opts, P);
+  } catch (const std::bad_alloc &) {
+    return fail(HMAT_E_NOMEM, "out of host memory during partition");
+  }
+  const auto t1 = clk::now();
+  const int64_t nb = (int64_t)P.row0.size();
+  S.blocks = nb;
+
+  // admissible blocks, longest first (the sequential sums grow with m + nc)
+  std::vector<int64_t> adm;
+  for (int64_t b = 0; b < nb; b++)
+    if (P.admissible[b]) adm.push_back(b);
+  std::stable_sort(adm.begin(), adm.end(),
+                   [&](int64_t x, int64_t y) { return P.nrows[x] + P.ncols[x] > P.nrows[y] + P.ncols[y]; });
+  const int64_t na = (int64_t)adm.size();
+  std::vector<AcaDesc> ad(na);
+  std::vector<int64_t> slot(nb, -1);
+  int64_t ws_len = 0, fl_len = 0;
+  for (int64_t q = 0; q < na; q++) {
+    const int64_t b = adm[q], m = P.nrows[b], nc = P.ncols[b];
+    const int64_t kd = (m * nc + m + nc - 1) / (m + nc);
+    const int32_t cap = (int32_t)std::min<int64_t>(rank_cap, kd);
+    ad[q] = AcaDesc{P.row0[b], P.col0[b], ws_len, fl_len, (int32_t)m, (int32_t)nc, cap, 0};
+    ws_len += (m + nc) * cap;
+    fl_len += m;
+    slot[b] = q;
+  }
+
+  DevBufs buf;
+  Events ev;
+  double *d_c, *d_a, *d_ws;
+  unsigned char *d_fl;
+  AcaDesc *d_ad;
+  int32_t *d_rank, *d_status;
+  HM_TRY(buf.get(&d_c, 3 * n * sizeof(double)), "device centroids");
+  HM_TRY(buf.get(&d_a, n * sizeof(double)), "device areas");
+  HM_TRY(buf.get(&d_ws, ws_len * sizeof(double)), "ACA scratch");
+  HM_TRY(buf.get(&d_fl, fl_len), "ACA pivot flags");
+  HM_TRY(buf.get(&d_ad, na * sizeof(AcaDesc)), "ACA descriptors");
+  HM_TRY(buf.get(&d_rank, na * sizeof(int32_t)), "ACA ranks");
+  HM_TRY(buf.get(&d_status, na * sizeof(int32_t)), "ACA status");
+  for (int i = 0; i < 4; i++) HM_TRY(hipEventCreate(&ev.e[i]), "event");
+  HM_TRY(hipMemcpyAsync(d_c, P.c.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice, st), "upload");
+  HM_TRY(hipMemcpyAsync(d_a, P.a.data(), n * sizeof(double), hipMemcpyHostToDevice, st), "upload");
+  if (na) HM_TRY(hipMemcpyAsync(d_ad, ad.data(), na * sizeof(AcaDesc), hipMemcpyHostToDevice, st), "upload");
+  HM_TRY(hipEventRecord(ev.e[0], st), "event");
+  if (na) {
+    hipLaunchKernelGGL(k_aca, dim3((unsigned)na), dim3(kAThreads), 0, st, d_ad, d_c, d_a, d_ws, d_fl, P.eps, d_rank,
+                       d_status);
+    HM_TRY(hipGetLastError(), "k_aca launch");
+  }
+  HM_TRY(hipEventRecord(ev.e[1], st), "event");
+  std::vector<int32_t> arank(na), astat(na);
+  if (na) {
+    HM_TRY(hipMemcpyAsync(arank.data(), d_rank, na * sizeof(int32_t), hipMemcpyDeviceToHost, st), "download");
+    HM_TRY(hipMemcpyAsync(astat.data(), d_status, na * sizeof(int32_t), hipMemcpyDeviceToHost, st), "download");
+  }
+  HM_TRY(hipStreamSynchronize(st), "k_aca");
+
+  try {
+    // blocks the device did not finish: the host builder, threaded
+    std::vector<int64_t> redo;
+    for (int64_t q = 0; q < na; q++)
+      if (astat[q] == 2) redo.push_back(adm[q]);
+    kind.assign(nb, 0);
+    rank.assign(nb, 0);
+    hostdata.resize(nb);
+    std::atomic<int64_t> next{0};
+    auto work = [&]() {
+      for (;;) {
+        const int64_t q = next.fetch_add(1);
+        if (q >= (int64_t)redo.size()) break;
+        const int64_t b = redo[q];
+        bem_fill_host(P, b, &kind[b], &rank[b], hostdata[b]);
+      }
+    };
+    const int nt = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), (int64_t)redo.size());
+    std::vector<std::thread> th;
+    for (int i = 1; i < nt; i++) th.emplace_back(work);
+    if (!redo.empty()) work();
+    for (auto &x : th) x.join();
+    S.host_blocks = (int64_t)redo.size();
+
+    std::vector<EmitDesc> ed(nb);
+    offset.resize(nb);
+    for (int64_t b = 0; b < nb; b++) {
+      const int64_t m = P.nrows[b], nc = P.ncols[b], q = slot[b];
+      EmitDesc e{P.row0[b], P.col0[b], total, 0, (int32_t)m, (int32_t)nc, 0, 0, 0, 0};
+      if (q >= 0 && astat[q] == 2) {
+        e.mode = 2;
+      } else if (q >= 0 && astat[q] == 0) {
+        kind[b] = 1;
+        rank[b] = arank[q];
+        e.mode = 1;
+        e.rank = arank[q];
+        e.cap = ad[q].cap;
+        e.u_off = ad[q].u_off;
+      }
+      if (e.mode == 0 && m * nc >= INT_MAX) return fail(HMAT_E_ARG, "dense block too large");
+      ed[b] = e;
+      offset[b] = total;
+      total += e.mode == 2 ? (int64_t)hostdata[b].size() : (kind[b] == 1 ? (m + nc) * rank[b] : m * nc);
+    }
+    EmitDesc *d_ed;
+    double *d_out;
+    HM_TRY(buf.get(&d_ed, nb * sizeof(EmitDesc)), "emit descriptors");
+    HM_TRY(buf.get(&d_out, total * sizeof(double)), "assembly output");
+    HM_TRY(hipMemcpyAsync(d_ed, ed.data(), nb * sizeof(EmitDesc), hipMemcpyHostToDevice, st), "upload");
+    HM_TRY(hipEventRecord(ev.e[2], st), "event");
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kAThreads), 0, st, d_ed, d_c, d_a, d_ws, d_out);
+    HM_TRY(hipGetLastError(), "k_emit launch");
+    HM_TRY(hipEventRecord(ev.e[3], st), "event");
+    S.device_bytes = (uint64_t)(3 * n + n + ws_len + total) * sizeof(double) + (uint64_t)fl_len +
+                     (uint64_t)na * (sizeof(AcaDesc) + 8) + (uint64_t)nb * sizeof(EmitDesc);
+
+    auto *R = new hmat_assembly_s();
+    std::unique_ptr<hmat_assembly_s> keep(R);
+    R->data.resize(total);
+    HM_TRY(hipStreamSynchronize(st), "k_emit");
+    const auto tc = clk::now();
+    HM_TRY(hipMemcpy(R->data.data(), d_out, total * sizeof(double), hipMemcpyDeviceToHost), "download");
+    S.ms_copy = ms(tc, clk::now());
+    for (int64_t b = 0; b < nb; b++)
+      if (ed[b].mode == 2) std::memcpy(R->data.data() + offset[b], hostdata[b].data(), hostdata[b].size() * 8);
+    float f1 = 0.f, f2 = 0.f;
+    HM_TRY(hipEventElapsedTime(&f1, ev.e[0], ev.e[1]), "event time");
+    HM_TRY(hipEventElapsedTime(&f2, ev.e[2], ev.e[3]), "event time");
+    S.ms_aca = f1;
+    S.ms_emit = f2;
+    R->n = n;
+    R->perm = std::move(P.perm);
+    R->row0 = std::move(P.row0);
+    R->nrows = std::move(P.nrows);
+    R->col0 = std::move(P.col0);
+    R->ncols = std::move(P.ncols);
+    R->kind = std::move(kind);
+    R->rank = std::move(rank);
+    R->offset = std::move(offset);
+    for (int64_t b = 0; b < nb; b++) S.lowrank += R->kind[b] == 1;
+    S.ms_partition = ms(t0, t1);
+    S.ms_fill = ms(t1, clk::now());
+    R->stats = S;
+    *out = keep.release();
+  } catch (const std::bad_alloc &) {
+    return fail(HMAT_E_NOMEM, "out of host memory during assembly");
+  }
+  return HMAT_OK;
+}

@@ -32,7 +32,7 @@ EXPORTED = [
     "hmat_last_error", "hmat_plan", "hmat_build", "hmat_matvec", "hmat_destroy", "hmat_get_stats",
     "hmat_precond_plan", "hmat_precond_create", "hmat_precond_apply", "hmat_precond_destroy",
     "hmat_solver_workspace_bytes", "hmat_bicgstab", "hmat_gmres_workspace_bytes", "hmat_gmres",
-    "hmat_assemble_bem", "hmat_assembly_blocks",
+    "hmat_assemble_bem", "hmat_assemble_bem_gpu", "hmat_assembly_get_stats", "hmat_assembly_blocks",
     "hmat_assembly_perm", "hmat_assembly_free", "hmat_version", "hmat_set_profiling", "hmat_kernel_times",
     "hmat_stream_read", "hmat_stream_copy", "hmat_plan_batched", "hmat_build_batched", "hmat_system_offsets",
     "hmat_bicgstab_batched_workspace_bytes", "hmat_bicgstab_batched", "hmat_precond_create_learned",
@@ -100,6 +100,13 @@ class hmat_assemble_opts(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class hmat_assembly_stats(C.Structure):
+    _fields_ = [("blocks", C.c_int64), ("lowrank", C.c_int64), ("host_blocks", C.c_int64),
+                ("rank_cap", C.c_int32), ("reserved", C.c_int32), ("device_bytes", C.c_uint64),
+                ("ms_partition", C.c_double), ("ms_fill", C.c_double), ("ms_aca", C.c_double),
+                ("ms_emit", C.c_double), ("ms_copy", C.c_double)]
+
+
 _lib = None
 
 
@@ -110,6 +117,9 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"native library {LIB_PATH} is missing: run `python -m paper_1911_00093_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # so both share one device context, its memory and its streams
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P, I32, I64, U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
     sig = {
@@ -129,6 +139,8 @@ def lib():
         "hmat_gmres_workspace_bytes": (U64, [I64, C.c_int32]),
         "hmat_gmres": (C.c_int, [P, P, P, P, C.c_int32, P, P, P, U64, P]),
         "hmat_assemble_bem": (C.c_int, [I64, P, P, P, P]),
+        "hmat_assemble_bem_gpu": (C.c_int, [I64, P, P, P, I32, P, P]),
+        "hmat_assembly_get_stats": (C.c_int, [P, P]),
         "hmat_assembly_blocks": (C.c_int, [P, P]),
         "hmat_assembly_perm": (C.POINTER(C.c_int64), [P]),
         "hmat_assembly_free": (C.c_int, [P]),
@@ -192,6 +204,7 @@ class BlockSet:
     data: np.ndarray
     perm: np.ndarray | None = None
     _owner: object = None
+    stats: dict | None = None
 
     @classmethod
     def from_arrays(cls, n, row0, nrows, col0, ncols, kind, rank, offset, data, perm=None):
@@ -221,14 +234,14 @@ class _Assembly:
             self.ptr = None
 
 
-def hmat_assemble_bem(centroids, areas, leaf=64, eta=2.0, eps=1e-5, threads=0) -> BlockSet:
-    """Setup: FP64 H-matrix of the BEM collocation problem (host, multi-threaded)."""
+def _mesh_arrays(centroids, areas):
     cent = np.ascontiguousarray(centroids, dtype=np.float64).reshape(-1, 3)
     area = np.ascontiguousarray(areas, dtype=np.float64)
-    n = cent.shape[0]
-    o = hmat_assemble_opts(int(leaf), float(eta), float(eps), int(threads), 0)
-    out = C.c_void_p()
-    _check(lib().hmat_assemble_bem(n, _p(cent), _p(area), C.byref(o), C.byref(out)))
+    return cent, area, cent.shape[0]
+
+
+def _assembly_blockset(out, n) -> BlockSet:
+    """BlockSet viewing an assembly handle's arrays (the handle lives as long as the BlockSet)."""
     owner = _Assembly(out)
     v = hmat_blocks()
     _check(lib().hmat_assembly_blocks(out, C.byref(v)))
@@ -240,11 +253,35 @@ def hmat_assemble_bem(centroids, areas, leaf=64, eta=2.0, eps=1e-5, threads=0) -
         return np.ctypeslib.as_array(C.cast(addr, C.POINTER(ctype)), shape=(count,)).view(dtype)
 
     perm = np.ctypeslib.as_array(lib().hmat_assembly_perm(out), shape=(n,))
-    return BlockSet(n, view(v.row0, nb, C.c_int64, np.int64), view(v.nrows, nb, C.c_int64, np.int64),
-                    view(v.col0, nb, C.c_int64, np.int64), view(v.ncols, nb, C.c_int64, np.int64),
-                    view(v.kind, nb, C.c_int32, np.int32), view(v.rank, nb, C.c_int32, np.int32),
-                    view(v.offset, nb, C.c_int64, np.int64), view(v.data, v.ndata, C.c_double, np.float64),
-                    perm, owner)
+    bs = BlockSet(n, view(v.row0, nb, C.c_int64, np.int64), view(v.nrows, nb, C.c_int64, np.int64),
+                  view(v.col0, nb, C.c_int64, np.int64), view(v.ncols, nb, C.c_int64, np.int64),
+                  view(v.kind, nb, C.c_int32, np.int32), view(v.rank, nb, C.c_int32, np.int32),
+                  view(v.offset, nb, C.c_int64, np.int64), view(v.data, v.ndata, C.c_double, np.float64),
+                  perm, owner)
+    st = hmat_assembly_stats()
+    _check(lib().hmat_assembly_get_stats(out, C.byref(st)))
+    bs.stats = {f: getattr(st, f) for f, _ in hmat_assembly_stats._fields_ if f != "reserved"}
+    return bs
+
+
+def hmat_assemble_bem(centroids, areas, leaf=64, eta=2.0, eps=1e-5, threads=0) -> BlockSet:
+    """Setup: FP64 H-matrix of the BEM collocation problem (host, multi-threaded)."""
+    cent, area, n = _mesh_arrays(centroids, areas)
+    o = hmat_assemble_opts(int(leaf), float(eta), float(eps), int(threads), 0)
+    out = C.c_void_p()
+    _check(lib().hmat_assemble_bem(n, _p(cent), _p(area), C.byref(o), C.byref(out)))
+    return _assembly_blockset(out, n)
+
+
+def hmat_assemble_bem_gpu(centroids, areas, leaf=64, eta=2.0, eps=1e-5, rank_cap=0, stream=None) -> BlockSet:
+    """Setup on the GPU: the same H-matrix as hmat_assemble_bem, bit for bit
+    (entries and ACA in HIP kernels; partition on the host)."""
+    cent, area, n = _mesh_arrays(centroids, areas)
+    o = hmat_assemble_opts(int(leaf), float(eta), float(eps), 0, 0)
+    out = C.c_void_p()
+    _check(lib().hmat_assemble_bem_gpu(n, _p(cent), _p(area), C.byref(o), int(rank_cap), _stream_ptr(stream),
+                                       C.byref(out)))
+    return _assembly_blockset(out, n)
 
 
 def hmat_plan(blocks: BlockSet, precision: int, c: int = 0, nrhs_max: int = 1, drop: int = 0) -> hmat_plan_info:

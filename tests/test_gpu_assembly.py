@@ -1,0 +1,78 @@
+"""GPU setup builder (hmat_assemble_bem_gpu): entries and ACA in HIP kernels
+against the oracle's assembly (oracle/hmat_oracle.c), which evaluates the
+same definitions in the same order, so every array must be identical."""
+
+import numpy as np
+import pytest
+
+from paper_1911_00093_amd import hmat, meshes
+from tests.conftest import oracle_hmatrix
+from tests.gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("perm", "row0", "nrows", "col0", "ncols", "kind", "rank", "offset", "data")
+
+
+def same_as_oracle(bs, h):
+    for f in FIELDS:
+        assert np.array_equal(getattr(bs, f), getattr(h, f)), f
+
+
+@pytest.mark.parametrize("key", ["sphere-L2", "sphere-L3", "sphere-L4", "plates-16", "plates-32", "ellipsoid-12",
+                                 "spheres-mixed"])
+def test_gpu_assembly_identical_to_oracle(key):
+    need_gpu()
+    m, h = oracle_hmatrix(key)
+    bs = hmat.hmat_assemble_bem_gpu(m.centroids, m.areas, leaf=h.leaf, eta=h.eta, eps=h.eps)
+    st = bs.stats
+    print(key, {k: st[k] for k in ("blocks", "lowrank", "host_blocks", "ms_aca", "ms_emit")})
+    same_as_oracle(bs, h)
+    assert st["host_blocks"] == 0 and st["rank_cap"] == 48 and st["lowrank"] == int((h.kind == 1).sum())
+
+
+@pytest.mark.parametrize("cap", [1, 3, 9, 127])
+def test_gpu_assembly_rank_cap(cap):
+    """A small cap sends the blocks that have not converged by then back to
+    the host builder; any cap gives the same matrix."""
+    need_gpu()
+    m, h = oracle_hmatrix("plates-16")
+    bs = hmat.hmat_assemble_bem_gpu(m.centroids, m.areas, leaf=h.leaf, eta=h.eta, eps=h.eps, rank_cap=cap)
+    same_as_oracle(bs, h)
+    # a low-rank block of final rank r > cap cannot stop on the device; with
+    # cap 127 every block stops (or is known to end dense) there
+    if cap < h.rank.max():
+        assert bs.stats["host_blocks"] > 0
+    if cap == 127:
+        assert bs.stats["host_blocks"] == 0
+
+
+def test_gpu_assembly_small_and_degenerate():
+    need_gpu()
+    import oracle
+
+    # one leaf: a single dense block, no ACA launch
+    m = meshes.icosphere(0)
+    h = oracle.HMatrix(m.centroids, m.areas, leaf=32, eta=2.0, eps=1e-6)
+    same_as_oracle(hmat.hmat_assemble_bem_gpu(m.centroids, m.areas, leaf=32, eta=2.0, eps=1e-6), h)
+    # leaf 1 on a tiny mesh: 1 x 1 blocks, admissible 1 x n strips
+    m = meshes.icosphere(1)
+    h = oracle.HMatrix(m.centroids, m.areas, leaf=1, eta=2.0, eps=1e-6)
+    same_as_oracle(hmat.hmat_assemble_bem_gpu(m.centroids, m.areas, leaf=1, eta=2.0, eps=1e-6), h)
+    # a loose tolerance (rank-1 blocks) and a tight one (dense fallbacks)
+    for eps in (1e-1, 1e-13):
+        m = meshes.icosphere(2)
+        h = oracle.HMatrix(m.centroids, m.areas, leaf=16, eta=2.0, eps=eps)
+        same_as_oracle(hmat.hmat_assemble_bem_gpu(m.centroids, m.areas, leaf=16, eta=2.0, eps=eps), h)
+    # a single panel
+    h = oracle.HMatrix(np.zeros((1, 3)), np.ones(1), leaf=4, eta=2.0, eps=1e-6)
+    same_as_oracle(hmat.hmat_assemble_bem_gpu(np.zeros((1, 3)), np.ones(1), leaf=4, eta=2.0, eps=1e-6), h)
+
+
+def test_gpu_assembly_rejects_bad_arguments():
+    need_gpu()
+    m = meshes.icosphere(1)
+    for kw in (dict(rank_cap=128), dict(rank_cap=-1), dict(leaf=0), dict(eps=0.0)):
+        with pytest.raises(hmat.HmatError) as e:
+            hmat.hmat_assemble_bem_gpu(m.centroids, m.areas, **kw)
+        assert e.value.code == hmat.HMAT_E_ARG

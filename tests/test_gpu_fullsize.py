@@ -41,6 +41,20 @@ def test_fullsize_library_assembly_identical():
     assert np.array_equal(bs.data, h.data)
 
 
+def test_fullsize_gpu_assembly_identical():
+    """The GPU setup builder on plates-128 (60,400 blocks, ranks up to 25):
+    every array identical to the oracle's assembly."""
+    need_gpu()
+    d = c2()
+    m, h = d["m"], d["h"]
+    bs = hmat.hmat_assemble_bem_gpu(m.centroids, m.areas, leaf=64, eta=2.0, eps=1e-5)
+    print("GPU assembly:", bs.stats)
+    for f in ("perm", "row0", "nrows", "col0", "ncols", "kind", "rank", "offset"):
+        assert np.array_equal(getattr(bs, f), getattr(h, f)), f
+    assert np.array_equal(bs.data, h.data)
+    assert bs.stats["host_blocks"] == 0
+
+
 @pytest.mark.parametrize("variant", range(8))
 def test_fullsize_matvec_parity(variant):
     need_gpu()
