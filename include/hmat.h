@@ -438,6 +438,7 @@ typedef struct {
     double ms_fill;          /* entries and ACA: host threads, or the device path from upload to copy-back */
     double ms_aca, ms_emit;  /* device path: the two kernels (HIP events) */
     double ms_copy;          /* device path: result copied to the host */
+    double ms_upload;        /* device path: scratch allocated, mesh and descriptors uploaded */
 } hmat_assembly_stats;
 int hmat_assembly_get_stats(hmat_assembly_t a, hmat_assembly_stats *stats);
 

@@ -19,10 +19,13 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <thread>
 #include <vector>
+
+#include <sys/mman.h>
 
 #include "hmat_impl.h"
 
@@ -247,6 +250,22 @@ void aca(const hm::BemPartition &P, int64_t b, int32_t *kind, int32_t *rank, std
 
 namespace hm {
 
+HostDoubles::~HostDoubles() { std::free(p); }
+
+bool HostDoubles::alloc(int64_t count) {
+  std::free(p);
+  p = nullptr;
+  n = 0;
+  const size_t huge = size_t(2) << 20;
+  const size_t bytes = ((size_t)std::max<int64_t>(count, 1) * sizeof(double) + huge - 1) / huge * huge;
+  void *q = std::aligned_alloc(huge, bytes);
+  if (!q) return false;
+  (void)madvise(q, bytes, MADV_HUGEPAGE);  // advisory only
+  p = (double *)q;
+  n = count;
+  return true;
+}
+
 void bem_partition(int64_t n, const double *cent, const double *area, const hmat_assemble_opts &o, BemPartition &P) {
   P = BemPartition();
   P.n = n;
@@ -314,7 +333,10 @@ int hmat_assemble_bem(int64_t n, const double *centroids, const double *areas, c
     R->perm = std::move(P.perm);
     int64_t tot = 0;
     for (auto &d : data) tot += (int64_t)d.size();
-    R->data.resize(tot);
+    if (!R->data.alloc(tot)) {
+      delete R;
+      return hm::fail(HMAT_E_NOMEM, "out of host memory for the assembly");
+    }
     R->offset.resize(nb);
     int64_t at = 0;
     for (int64_t i = 0; i < nb; i++) {
@@ -353,7 +375,7 @@ int hmat_assembly_blocks(hmat_assembly_t a, hmat_blocks *v) {
   v->rank = a->rank.data();
   v->offset = a->offset.data();
   v->data = a->data.data();
-  v->ndata = (int64_t)a->data.size();
+  v->ndata = a->data.size();
   return HMAT_OK;
 }
 

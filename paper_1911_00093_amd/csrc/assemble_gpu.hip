@@ -9,10 +9,11 @@
 //  * k_emit: one workgroup per block writes the dense entries and the
 //    factors into the host layout (column-major U, then column-major V).
 //
-// Scratch layout per admissible block: U as m x cap and V as nc x cap with
-// the rank index fastest, so the inner products of a new column with the
-// earlier ones (one per lane, summed sequentially down the column) read
-// contiguous rows across the lanes.  cap = min(rank_cap, kd) where kd is the
+// Scratch per admissible block: U as m x cap and V as nc x cap, column-major
+// like the result, so the residual rows and columns (one entry per thread,
+// the earlier terms subtracted in order) read coalesced columns, and the
+// inner products of a new column with the earlier ones (one per lane,
+// summed in index order) read row tiles staged in LDS.  cap = min(rank_cap, kd) where kd is the
 // smallest rank that makes the block dense (k (m + nc) >= m nc): a block
 // that reaches kd ends dense on the host as well, so only blocks reaching a
 // smaller rank_cap without converging (status 2) go back to the host.
@@ -38,13 +39,14 @@ namespace {
 
 constexpr int kAThreads = 256;
 constexpr int kAWaves = kAThreads / kWave;
-constexpr int kAMaxCap = 127;  // ranks per block: lanes 0..k and 128..128+k hold the inner products
+constexpr int kAMaxCap = 127;  // ranks per block (lanes 0..k of one workgroup hold the inner products)
 constexpr int kADefaultCap = 48;
+constexpr int kATile = 3072;   // doubles of LDS per inner-product tile (24 KB)
 constexpr double kPiG = 3.14159265358979323846;
 
 struct AcaDesc {
   int64_t row0, col0;
-  int64_t u_off;     // U (m x cap), then V (nc x cap), in doubles from the scratch base
+  int64_t u_off;     // U (m x cap), then V (nc x cap), column-major, in doubles from the scratch base
   int64_t used_off;  // m pivot flags, in bytes from the flag base
   int32_t m, nc, cap, pad;
 };
@@ -110,18 +112,62 @@ __device__ void wg_best(Arg &a, double &mx, Arg *s_arg, double *s_mx) {
   }
 }
 
+// r = e - sum_{l < k} s_prev[l] X[l stride + idx], subtracted in l order;
+// eight independent loads in flight (l past k repeats k - 1, not used)
+__device__ __forceinline__ double residual(double e, const double *__restrict__ X, int64_t stride, int idx, int k,
+                                           const double *__restrict__ s_prev) {
+  double r = e;
+  for (int l0 = 0; l0 < k; l0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) v[u] = X[(int64_t)min(l0 + u, k - 1) * stride + idx];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+      const double t = r - s_prev[min(l0 + u, k - 1)] * v[u];
+      r = l0 + u < k ? t : r;
+    }
+  }
+  return r;
+}
+
+// out[l] = sum_{i < len} X[l len + i] X[k len + i] for l = 0..k, each summed
+// in index order by lane l; the columns pass through LDS in row tiles loaded
+// by the whole workgroup (coalesced), so the sums wait on LDS, not on HBM.
+__device__ void column_dots(const double *__restrict__ X, int len, int k, double *__restrict__ s_tile,
+                            double *__restrict__ out) {
+  const int kk = k + 1;
+  const int t1 = (kATile / kk - 1) | 1;  // odd row stride: lanes l spread over the LDS banks
+  double p = 0.0;
+  for (int i0 = 0; i0 < len; i0 += t1) {
+    const int t = min(t1, len - i0);
+    __syncthreads();  // the previous tile is consumed
+    for (int e = threadIdx.x; e < kk * t; e += kAThreads) {
+      const int l = e / t, r = e - l * t;
+      s_tile[l * t1 + r] = X[(int64_t)l * len + i0 + r];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x <= k) {
+      const double *xl = s_tile + threadIdx.x * t1, *xk = s_tile + k * t1;
+      for (int r = 0; r < t; r++) p += xl[r] * xk[r];
+    }
+  }
+  if ((int)threadIdx.x <= k) out[threadIdx.x] = p;
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kAThreads) void k_aca(const AcaDesc *__restrict__ D, const double *__restrict__ c,
                                                    const double *__restrict__ a, double *__restrict__ ws,
                                                    unsigned char *__restrict__ flags, double eps,
                                                    int32_t *__restrict__ out_rank, int32_t *__restrict__ out_status) {
-  __shared__ double s_prev[kAMaxCap];       // earlier factors at the pivot row / column
+  __shared__ double s_prev[kAMaxCap];  // earlier factors at the pivot row / column
   __shared__ double s_pu[kAMaxCap + 1], s_pq[kAMaxCap + 1];
+  __shared__ double s_tile[kATile];
   __shared__ Arg s_arg[kAWaves];
   __shared__ double s_mx[kAWaves];
   const AcaDesc d = D[blockIdx.x];
   const int m = d.m, nc = d.nc, cap = d.cap, tid = threadIdx.x;
-  double *__restrict__ U = ws + d.u_off;
-  double *__restrict__ V = U + (int64_t)m * cap;
+  double *__restrict__ U = ws + d.u_off;            // column l at U + l m
+  double *__restrict__ V = U + (int64_t)m * cap;    // column l at V + l nc
   unsigned char *__restrict__ used = flags + d.used_off;
   for (int i = tid; i < m; i += kAThreads) used[i] = 0;
   const int kmax = min(m, nc);
@@ -131,7 +177,7 @@ __global__ __launch_bounds__(kAThreads) void k_aca(const AcaDesc *__restrict__ D
   __syncthreads();
   while (k < kmax && k < cap) {
     // residual of row istar: A(istar, :) - sum_l U(istar, l) V(:, l)
-    if (tid < k) s_prev[tid] = U[(int64_t)istar * cap + tid];
+    if (tid < k) s_prev[tid] = U[(int64_t)tid * m + istar];
     __syncthreads();
     if (tid == 0) used[istar] = 1;
     const int64_t gi = d.row0 + istar;
@@ -142,10 +188,8 @@ __global__ __launch_bounds__(kAThreads) void k_aca(const AcaDesc *__restrict__ D
       const double e = entry_at(cix, ciy, ciz, c, a, gi, d.col0 + j);
       const double ae = fabs(e);
       mx = ae > mx ? ae : mx;
-      double r = e;
-      const double *vr = V + (int64_t)j * cap;
-      for (int l = 0; l < k; l++) r -= s_prev[l] * vr[l];
-      V[(int64_t)j * cap + k] = r;
+      const double r = residual(e, V, nc, j, k, s_prev);
+      V[(int64_t)k * nc + j] = r;
       arg_take(best, fabs(r), j, r);
     }
     wg_best(best, mx, s_arg, s_mx);
@@ -169,8 +213,8 @@ __global__ __launch_bounds__(kAThreads) void k_aca(const AcaDesc *__restrict__ D
     }
     const int pc = best.idx;
     const double pv = best.val;
-    for (int j = tid; j < nc; j += kAThreads) V[(int64_t)j * cap + k] = V[(int64_t)j * cap + k] / pv;
-    if (tid < k) s_prev[tid] = V[(int64_t)pc * cap + tid];
+    for (int j = tid; j < nc; j += kAThreads) V[(int64_t)k * nc + j] = V[(int64_t)k * nc + j] / pv;
+    if (tid < k) s_prev[tid] = V[(int64_t)tid * nc + pc];
     __syncthreads();
     // residual of column pc: A(:, pc) - sum_l V(pc, l) U(:, l); next pivot candidates
     const int64_t gj = d.col0 + pc;
@@ -181,27 +225,15 @@ __global__ __launch_bounds__(kAThreads) void k_aca(const AcaDesc *__restrict__ D
       const double e = entry_at(c[3 * gr + 0], c[3 * gr + 1], c[3 * gr + 2], c, a, gr, gj);
       const double ae = fabs(e);
       mx = ae > mx ? ae : mx;
-      double s = e;
-      const double *ur = U + (int64_t)i * cap;
-      for (int l = 0; l < k; l++) s -= s_prev[l] * ur[l];
-      U[(int64_t)i * cap + k] = s;
+      const double s = residual(e, U, m, i, k, s_prev);
+      U[(int64_t)k * m + i] = s;
       if (!used[i]) arg_take(nxt, fabs(s), i, s);
     }
     wg_best(nxt, mx, s_arg, s_mx);
     seen = mx;
-    // inner products of the new column pair with every column pair so far,
-    // each summed in index order by one lane
-    if (tid <= k) {
-      double p = 0.0;
-      for (int i = 0; i < m; i++) p += U[(int64_t)i * cap + tid] * U[(int64_t)i * cap + k];
-      s_pu[tid] = p;
-    } else if (tid >= 128 && tid - 128 <= k) {
-      const int l = tid - 128;
-      double q = 0.0;
-      for (int j = 0; j < nc; j++) q += V[(int64_t)j * cap + l] * V[(int64_t)j * cap + k];
-      s_pq[l] = q;
-    }
-    __syncthreads();
+    // inner products of the new column pair with every column pair so far
+    column_dots(U, m, k, s_tile, s_pu);
+    column_dots(V, nc, k, s_tile, s_pq);
     double cross = 0.0;
     for (int l = 0; l < k; l++) cross += s_pu[l] * s_pq[l];
     const double uu = s_pu[k], vv = s_pq[k];
@@ -238,11 +270,12 @@ __global__ __launch_bounds__(kAThreads) void k_emit(const EmitDesc *__restrict__
       o[e] = entry_at(c[3 * gi + 0], c[3 * gi + 1], c[3 * gi + 2], c, a, gi, d.col0 + j);
     }
   } else if (d.mode == 1) {
+    // the first rank columns of U, then of V: contiguous in the scratch
     const double *U = ws + d.u_off;
     const double *V = U + (int64_t)d.m * d.cap;
     const int tu = d.m * d.rank, tv = d.nc * d.rank;
-    for (int e = threadIdx.x; e < tu; e += kAThreads) o[e] = U[(int64_t)(e % d.m) * d.cap + e / d.m];
-    for (int e = threadIdx.x; e < tv; e += kAThreads) o[tu + e] = V[(int64_t)(e % d.nc) * d.cap + e / d.nc];
+    for (int e = threadIdx.x; e < tu; e += kAThreads) o[e] = U[e];
+    for (int e = threadIdx.x; e < tv; e += kAThreads) o[tu + e] = V[e];
   }
 }
 
@@ -261,6 +294,54 @@ struct DevBufs {
     return e;
   }
 };
+
+// Device-to-host copy of n doubles into pageable memory: the DMA engine fills
+// two pinned staging buffers in turn while host threads move the previous
+// chunk out (a single pageable copy runs at about a fifth of the link rate).
+hipError_t download(double *dst, const double *src, int64_t n, hipStream_t st) {
+  constexpr int64_t kChunk = int64_t(32) << 20;  // doubles (256 MB)
+  if (n <= 0) return hipSuccess;
+  const int64_t len = std::min(n, kChunk);
+  double *stage[2] = {nullptr, nullptr};
+  hipEvent_t done[2] = {nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  auto cleanup = [&]() {
+    for (int b = 0; b < 2; b++) {
+      if (stage[b]) (void)hipHostFree(stage[b]);
+      if (done[b]) (void)hipEventDestroy(done[b]);
+    }
+  };
+  for (int b = 0; b < 2 && e == hipSuccess; b++) {
+    e = hipHostMalloc((void **)&stage[b], len * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&done[b], hipEventDisableTiming);
+  }
+  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int64_t nchunks = (n + len - 1) / len;
+  auto issue = [&](int64_t c) {
+    const int64_t off = c * len, cnt = std::min(len, n - off);
+    hipError_t r = hipMemcpyAsync(stage[c % 2], src + off, cnt * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (r == hipSuccess) r = hipEventRecord(done[c % 2], st);
+    return r;
+  };
+  if (e == hipSuccess) e = issue(0);
+  for (int64_t c = 0; c < nchunks && e == hipSuccess; c++) {
+    if (c + 1 < nchunks) e = issue(c + 1);
+    if (e == hipSuccess) e = hipEventSynchronize(done[c % 2]);
+    if (e != hipSuccess) break;
+    const int64_t off = c * len, cnt = std::min(len, n - off);
+    const double *from = stage[c % 2];
+    std::vector<std::thread> th;
+    const int64_t part = (cnt + nt - 1) / nt;
+    for (int t = 0; t < nt; t++) {
+      const int64_t lo = t * part, hi = std::min(cnt, lo + part);
+      if (lo >= hi) break;
+      th.emplace_back([=]() { std::memcpy(dst + off + lo, from + lo, (hi - lo) * sizeof(double)); });
+    }
+    for (auto &x : th) x.join();
+  }
+  cleanup();
+  return e;
+}
 
 struct Events {
   hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -349,6 +430,7 @@ extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const d
   HM_TRY(hipMemcpyAsync(d_a, P.a.data(), n * sizeof(double), hipMemcpyHostToDevice, st), "upload");
   if (na) HM_TRY(hipMemcpyAsync(d_ad, ad.data(), na * sizeof(AcaDesc), hipMemcpyHostToDevice, st), "upload");
   HM_TRY(hipEventRecord(ev.e[0], st), "event");
+  const auto tu = clk::now();
   if (na) {
     hipLaunchKernelGGL(k_aca, dim3((unsigned)na), dim3(kAThreads), 0, st, d_ad, d_c, d_a, d_ws, d_fl, P.eps, d_rank,
                        d_status);
@@ -420,10 +502,10 @@ extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const d
 
     auto *R = new hmat_assembly_s();
     std::unique_ptr<hmat_assembly_s> keep(R);
-    R->data.resize(total);
     HM_TRY(hipStreamSynchronize(st), "k_emit");
     const auto tc = clk::now();
-    HM_TRY(hipMemcpy(R->data.data(), d_out, total * sizeof(double), hipMemcpyDeviceToHost), "download");
+    if (!R->data.alloc(total)) return fail(HMAT_E_NOMEM, "out of host memory for the assembly");
+    HM_TRY(download(R->data.data(), d_out, total, st), "download");
     S.ms_copy = ms(tc, clk::now());
     for (int64_t b = 0; b < nb; b++)
       if (ed[b].mode == 2) std::memcpy(R->data.data() + offset[b], hostdata[b].data(), hostdata[b].size() * 8);
@@ -443,6 +525,7 @@ extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const d
     R->offset = std::move(offset);
     for (int64_t b = 0; b < nb; b++) S.lowrank += R->kind[b] == 1;
     S.ms_partition = ms(t0, t1);
+    S.ms_upload = ms(t1, tu);
     S.ms_fill = ms(t1, clk::now());
     R->stats = S;
     *out = keep.release();

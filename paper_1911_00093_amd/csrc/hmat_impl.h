@@ -275,10 +275,27 @@ void bem_partition(int64_t n, const double *cent, const double *area, const hmat
 void bem_fill_host(const BemPartition &P, int64_t b, int32_t *kind, int32_t *rank, std::vector<double> &data);
 }  // namespace hm
 
+namespace hm {
+// Host array of doubles left uninitialised (its producer writes every
+// element), in transparent huge pages where the kernel allows, so a large
+// result costs no zero fill and few page faults (assemble.cpp).
+struct HostDoubles {
+  double *p = nullptr;
+  int64_t n = 0;
+  HostDoubles() = default;
+  HostDoubles(const HostDoubles &) = delete;
+  HostDoubles &operator=(const HostDoubles &) = delete;
+  ~HostDoubles();
+  bool alloc(int64_t count);  // false when out of memory
+  double *data() { return p; }
+  int64_t size() const { return n; }
+};
+}  // namespace hm
+
 struct hmat_assembly_s {
   int64_t n = 0;
   std::vector<int64_t> perm, row0, nrows, col0, ncols, offset;
   std::vector<int32_t> kind, rank;
-  std::vector<double> data;
+  hm::HostDoubles data;
   hmat_assembly_stats stats{};
 };

@@ -104,7 +104,7 @@ class hmat_assembly_stats(C.Structure):
     _fields_ = [("blocks", C.c_int64), ("lowrank", C.c_int64), ("host_blocks", C.c_int64),
                 ("rank_cap", C.c_int32), ("reserved", C.c_int32), ("device_bytes", C.c_uint64),
                 ("ms_partition", C.c_double), ("ms_fill", C.c_double), ("ms_aca", C.c_double),
-                ("ms_emit", C.c_double), ("ms_copy", C.c_double)]
+                ("ms_emit", C.c_double), ("ms_copy", C.c_double), ("ms_upload", C.c_double)]
 
 
 _lib = None
