@@ -29,6 +29,7 @@
 #include <thread>
 #include <vector>
 
+#include "assemble_impl.h"
 #include "hmat_impl.h"
 
 // Bit-identical to the host builder: no multiply-add contraction.
@@ -41,7 +42,8 @@ constexpr int kAThreads = 256;
 constexpr int kAWaves = kAThreads / kWave;
 constexpr int kAMaxCap = 127;  // ranks per block (lanes 0..k of one workgroup hold the inner products)
 constexpr int kADefaultCap = 48;
-constexpr int kATile = 3072;   // doubles of LDS per inner-product tile (24 KB)
+constexpr int kATileSmall = 2048;  // doubles of LDS per inner-product tile: many small blocks (16 KB)
+constexpr int kATileLong = 6144;   // few long blocks (48 KB)
 constexpr double kPiG = 3.14159265358979323846;
 
 struct AcaDesc {
@@ -112,56 +114,107 @@ __device__ void wg_best(Arg &a, double &mx, Arg *s_arg, double *s_mx) {
   }
 }
 
-// r = e - sum_{l < k} s_prev[l] X[l stride + idx], subtracted in l order;
-// eight independent loads in flight (l past k repeats k - 1, not used)
-__device__ __forceinline__ double residual(double e, const double *__restrict__ X, int64_t stride, int idx, int k,
-                                           const double *__restrict__ s_prev) {
-  double r = e;
-  for (int l0 = 0; l0 < k; l0 += 8) {
-    double v[8];
+// Residual entries of the new row (or column) of a block: for j < len,
+//   r_j = f(j) - sum_{l < k} s_prev[l] X[l len + j], subtracted in l order,
+// then take(j, f(j), r_j).  Each thread works on E entries at once with
+// eight terms of each loaded ahead (terms past k repeat k - 1 and are not
+// subtracted), so 8 E independent loads are in flight.
+template <int E, class F, class T>
+__device__ __forceinline__ void residuals(const double *__restrict__ X, int len, int k,
+                                          const double *__restrict__ s_prev, F f, T take) {
+  for (int j0 = threadIdx.x; j0 < len; j0 += E * kAThreads) {
+    int jc[E];
+    double e[E], r[E];
 #pragma unroll
-    for (int u = 0; u < 8; u++) v[u] = X[(int64_t)min(l0 + u, k - 1) * stride + idx];
-#pragma unroll
-    for (int u = 0; u < 8; u++) {
-      const double t = r - s_prev[min(l0 + u, k - 1)] * v[u];
-      r = l0 + u < k ? t : r;
+    for (int q = 0; q < E; q++) {
+      const int j = j0 + q * kAThreads;
+      jc[q] = j < len ? j : j0;
+      e[q] = f(jc[q]);
+      r[q] = e[q];
     }
+    for (int l0 = 0; l0 < k; l0 += 8) {
+      double v[E][8];
+#pragma unroll
+      for (int q = 0; q < E; q++)
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[q][u] = X[(int64_t)min(l0 + u, k - 1) * len + jc[q]];
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        const double sp = s_prev[min(l0 + u, k - 1)];
+#pragma unroll
+        for (int q = 0; q < E; q++) {
+          const double t = r[q] - sp * v[q][u];
+          r[q] = l0 + u < k ? t : r[q];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < E; q++)
+      if (j0 + q * kAThreads < len) take(j0 + q * kAThreads, e[q], r[q]);
   }
-  return r;
 }
 
 // out[l] = sum_{i < len} X[l len + i] X[k len + i] for l = 0..k, each summed
-// in index order by lane l; the columns pass through LDS in row tiles loaded
-// by the whole workgroup (coalesced), so the sums wait on LDS, not on HBM.
+// in index order by lane l.  The columns pass through LDS in row tiles
+// loaded by the whole workgroup (coalesced); the next tile is fetched into
+// registers while the lanes sum the current one, and each lane reads its
+// products PB at a time, so the sums wait on neither HBM nor LDS.
+// TILE: LDS doubles per tile; PB: products read per batch.
+template <int TILE, int PB>
 __device__ void column_dots(const double *__restrict__ X, int len, int k, double *__restrict__ s_tile,
                             double *__restrict__ out) {
+  constexpr int kATileRegs = TILE / kAThreads;
   const int kk = k + 1;
-  const int t1 = (kATile / kk - 1) | 1;  // odd row stride: lanes l spread over the LDS banks
+  const int t1 = (TILE / kk - 1) | 1;  // odd row stride: lanes l spread over the LDS banks
+  double nx[kATileRegs];
+  auto fetch = [&](int i0) {
+    const int t = min(t1, len - i0);
+#pragma unroll
+    for (int q = 0; q < kATileRegs; q++) {
+      const int e = threadIdx.x + q * kAThreads, l = e / t;
+      nx[q] = X[(int64_t)min(l, k) * len + i0 + (e - l * t)];  // rows past the tile's kk are not stored
+    }
+  };
   double p = 0.0;
+  fetch(0);
   for (int i0 = 0; i0 < len; i0 += t1) {
     const int t = min(t1, len - i0);
     __syncthreads();  // the previous tile is consumed
-    for (int e = threadIdx.x; e < kk * t; e += kAThreads) {
-      const int l = e / t, r = e - l * t;
-      s_tile[l * t1 + r] = X[(int64_t)l * len + i0 + r];
+#pragma unroll
+    for (int q = 0; q < kATileRegs; q++) {
+      const int e = threadIdx.x + q * kAThreads, l = e / t;
+      if (e < kk * t) s_tile[l * t1 + (e - l * t)] = nx[q];
     }
     __syncthreads();
+    if (i0 + t1 < len) fetch(i0 + t1);
     if ((int)threadIdx.x <= k) {
       const double *xl = s_tile + threadIdx.x * t1, *xk = s_tile + k * t1;
-      for (int r = 0; r < t; r++) p += xl[r] * xk[r];
+      int r = 0;
+      for (; r + PB <= t; r += PB) {
+        double pr[PB];
+#pragma unroll
+        for (int u = 0; u < PB; u++) pr[u] = xl[r + u] * xk[r + u];
+#pragma unroll
+        for (int u = 0; u < PB; u++) p += pr[u];
+      }
+      for (; r < t; r++) p += xl[r] * xk[r];
     }
   }
   if ((int)threadIdx.x <= k) out[threadIdx.x] = p;
   __syncthreads();
 }
 
+// E: residual entries per thread in flight (4 for blocks with a side of
+// 1024 or more, whose few long steps make up the critical path; 1 keeps the
+// registers, and so the occupancy, of the many small blocks low).
+template <int E, int TILE>
 __global__ __launch_bounds__(kAThreads) void k_aca(const AcaDesc *__restrict__ D, const double *__restrict__ c,
                                                    const double *__restrict__ a, double *__restrict__ ws,
                                                    unsigned char *__restrict__ flags, double eps,
                                                    int32_t *__restrict__ out_rank, int32_t *__restrict__ out_status) {
   __shared__ double s_prev[kAMaxCap];  // earlier factors at the pivot row / column
   __shared__ double s_pu[kAMaxCap + 1], s_pq[kAMaxCap + 1];
-  __shared__ double s_tile[kATile];
+  __shared__ double s_tile[TILE];
   __shared__ Arg s_arg[kAWaves];
   __shared__ double s_mx[kAWaves];
   const AcaDesc d = D[blockIdx.x];
@@ -184,13 +237,14 @@ __global__ __launch_bounds__(kAThreads) void k_aca(const AcaDesc *__restrict__ D
     const double cix = c[3 * gi + 0], ciy = c[3 * gi + 1], ciz = c[3 * gi + 2];
     Arg best{-1.0, INT_MAX, 0.0};
     double mx = seen;
-    for (int j = tid; j < nc; j += kAThreads) {
-      const double e = entry_at(cix, ciy, ciz, c, a, gi, d.col0 + j);
-      const double ae = fabs(e);
-      mx = ae > mx ? ae : mx;
-      const double r = residual(e, V, nc, j, k, s_prev);
-      V[(int64_t)k * nc + j] = r;
-      arg_take(best, fabs(r), j, r);
+    {
+      auto f = [&](int j) { return entry_at(cix, ciy, ciz, c, a, gi, d.col0 + j); };
+      auto take = [&](int j, double e, double r) {
+        mx = fabs(e) > mx ? fabs(e) : mx;
+        V[(int64_t)k * nc + j] = r;
+        arg_take(best, fabs(r), j, r);
+      };
+      residuals<E>(V, nc, k, s_prev, f, take);
     }
     wg_best(best, mx, s_arg, s_mx);
     seen = mx;
@@ -220,20 +274,23 @@ __global__ __launch_bounds__(kAThreads) void k_aca(const AcaDesc *__restrict__ D
     const int64_t gj = d.col0 + pc;
     Arg nxt{-2.0, INT_MAX, 0.0};
     mx = seen;
-    for (int i = tid; i < m; i += kAThreads) {
-      const int64_t gr = d.row0 + i;
-      const double e = entry_at(c[3 * gr + 0], c[3 * gr + 1], c[3 * gr + 2], c, a, gr, gj);
-      const double ae = fabs(e);
-      mx = ae > mx ? ae : mx;
-      const double s = residual(e, U, m, i, k, s_prev);
-      U[(int64_t)k * m + i] = s;
-      if (!used[i]) arg_take(nxt, fabs(s), i, s);
+    {
+      auto f = [&](int i) {
+        const int64_t gr = d.row0 + i;
+        return entry_at(c[3 * gr + 0], c[3 * gr + 1], c[3 * gr + 2], c, a, gr, gj);
+      };
+      auto take = [&](int i, double e, double r) {
+        mx = fabs(e) > mx ? fabs(e) : mx;
+        U[(int64_t)k * m + i] = r;
+        if (!used[i]) arg_take(nxt, fabs(r), i, r);
+      };
+      residuals<E>(U, m, k, s_prev, f, take);
     }
     wg_best(nxt, mx, s_arg, s_mx);
     seen = mx;
     // inner products of the new column pair with every column pair so far
-    column_dots(U, m, k, s_tile, s_pu);
-    column_dots(V, nc, k, s_tile, s_pq);
+    column_dots<TILE, E == 1 ? 8 : 16>(U, m, k, s_tile, s_pu);
+    column_dots<TILE, E == 1 ? 8 : 16>(V, nc, k, s_tile, s_pq);
     double cross = 0.0;
     for (int l = 0; l < k; l++) cross += s_pu[l] * s_pq[l];
     const double uu = s_pu[k], vv = s_pq[k];
@@ -343,8 +400,15 @@ hipError_t download(double *dst, const double *src, int64_t n, hipStream_t st) {
   return e;
 }
 
+struct SideStream {  // default priority
+  hipStream_t s = nullptr;
+  ~SideStream() {
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
 struct Events {
-  hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   ~Events() {
     for (hipEvent_t x : e)
       if (x) (void)hipEventDestroy(x);
@@ -425,17 +489,30 @@ extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const d
   HM_TRY(buf.get(&d_ad, na * sizeof(AcaDesc)), "ACA descriptors");
   HM_TRY(buf.get(&d_rank, na * sizeof(int32_t)), "ACA ranks");
   HM_TRY(buf.get(&d_status, na * sizeof(int32_t)), "ACA status");
-  for (int i = 0; i < 4; i++) HM_TRY(hipEventCreate(&ev.e[i]), "event");
+  for (int i = 0; i < 5; i++) HM_TRY(hipEventCreate(&ev.e[i]), "event");
+  SideStream side;
+  HM_TRY(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking), "stream");
   HM_TRY(hipMemcpyAsync(d_c, P.c.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice, st), "upload");
   HM_TRY(hipMemcpyAsync(d_a, P.a.data(), n * sizeof(double), hipMemcpyHostToDevice, st), "upload");
   if (na) HM_TRY(hipMemcpyAsync(d_ad, ad.data(), na * sizeof(AcaDesc), hipMemcpyHostToDevice, st), "upload");
   HM_TRY(hipEventRecord(ev.e[0], st), "event");
   const auto tu = clk::now();
-  if (na) {
-    hipLaunchKernelGGL(k_aca, dim3((unsigned)na), dim3(kAThreads), 0, st, d_ad, d_c, d_a, d_ws, d_fl, P.eps, d_rank,
-                       d_status);
+  // the long blocks (a prefix of the list) on a second stream, the rest on `st`
+  int64_t nbig = 0;
+  while (nbig < na && (int64_t)ad[nbig].m + ad[nbig].nc >= 2048) nbig++;
+  if (nbig) {
+    HM_TRY(hipStreamWaitEvent(side.s, ev.e[0], 0), "stream wait");
+    hipLaunchKernelGGL((k_aca<4, kATileLong>), dim3((unsigned)nbig), dim3(kAThreads), 0, side.s, d_ad, d_c, d_a, d_ws, d_fl, P.eps,
+                       d_rank, d_status);
+    HM_TRY(hipGetLastError(), "k_aca launch");
+    HM_TRY(hipEventRecord(ev.e[4], side.s), "event");
+  }
+  if (na > nbig) {
+    hipLaunchKernelGGL((k_aca<1, kATileSmall>), dim3((unsigned)(na - nbig)), dim3(kAThreads), 0, st, d_ad + nbig, d_c, d_a, d_ws,
+                       d_fl, P.eps, d_rank + nbig, d_status + nbig);
     HM_TRY(hipGetLastError(), "k_aca launch");
   }
+  if (nbig) HM_TRY(hipStreamWaitEvent(st, ev.e[4], 0), "stream wait");
   HM_TRY(hipEventRecord(ev.e[1], st), "event");
   std::vector<int32_t> arank(na), astat(na);
   if (na) {
