@@ -80,6 +80,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def assemble(args, mesh, W):
+    """FP64 H-matrix of one mesh with the chosen setup builder (untimed)."""
+    from paper_1911_00093_amd import hmat
+
+    if args.assembly == "gpu":
+        return hmat.hmat_assemble_bem_gpu(mesh.centroids, mesh.areas, leaf=W["leaf"], eta=W["eta"], eps=W["eps"])
+    return hmat.hmat_assemble_bem(mesh.centroids, mesh.areas, leaf=W["leaf"], eta=W["eta"], eps=W["eps"])
+
+
+def assembly_note(bs):
+    st = bs.stats
+    return (f"{'GPU' if st['rank_cap'] else 'host'} assembly: partition {st['ms_partition']:.0f} ms, "
+            f"entries + ACA {st['ms_fill']:.0f} ms" +
+            (f" (k_aca {st['ms_aca']:.1f} ms, k_emit {st['ms_emit']:.1f} ms, copy-back {st['ms_copy']:.0f} ms, "
+             f"host-filled blocks {st['host_blocks']})" if st["rank_cap"] else ""))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +117,8 @@ def main():
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--drop", type=int, default=0,
                     help="Methods 2/3: delete low-rank terms with d_i < d_max 10^-drop (Sec. 4.5; 0 = off)")
+    ap.add_argument("--assembly", default="gpu", choices=["gpu", "host"],
+                    help="setup builder: entries and ACA on the GPU (default) or on the host threads")
     ap.add_argument("--train-leaves", type=int, default=20000)
     ap.add_argument("--epochs", type=int, default=100)
     args = ap.parse_args()
@@ -135,8 +154,9 @@ def main():
     # ---------------- setup (untimed): mesh, FP64 H-matrix, conversions
     t0 = time.time()
     mesh = meshes.workload(args.workload)
-    bs = hmat.hmat_assemble_bem(mesh.centroids, mesh.areas, leaf=W["leaf"], eta=W["eta"], eps=W["eps"])
-    log(f"[setup] {args.workload}: n={bs.n} blocks={bs.nblocks} assembly {time.time() - t0:.1f}s")
+    bs = assemble(args, mesh, W)
+    log(f"[setup] {args.workload}: n={bs.n} blocks={bs.nblocks} assembly {time.time() - t0:.1f}s; "
+        f"{assembly_note(bs)}")
     t0 = time.time()
     H64 = hmat.HMatrix(bs, hmat.M1_DOUBLE)
     Hm = hmat.HMatrix(bs, variant, c=-1, drop=args.drop)
@@ -343,7 +363,7 @@ def bench_batched(args, W, variant, dev, stream):
     nsys, nrhs = W["nsys"], W["nrhs"]
     t0 = time.time()
     ms = meshes.random_ellipsoids(nsys, seed=0)
-    bss = [hmat.hmat_assemble_bem(m.centroids, m.areas, leaf=W["leaf"], eta=W["eta"], eps=W["eps"]) for m in ms]
+    bss = [assemble(args, m, W) for m in ms]
     n = sum(b.n for b in bss)
     log(f"[setup] {args.workload}: {nsys} meshes, n={n}, blocks={sum(b.nblocks for b in bss)}, "
         f"assembly {time.time() - t0:.1f}s")
@@ -517,8 +537,9 @@ def bench_learned(args, W, variant, dev, stream):
 
     t0 = time.time()
     mesh = meshes.workload(args.workload)
-    bs = hmat.hmat_assemble_bem(mesh.centroids, mesh.areas, leaf=W["leaf"], eta=W["eta"], eps=W["eps"])
-    log(f"[setup] {args.workload}: n={bs.n} blocks={bs.nblocks} assembly {time.time() - t0:.1f}s")
+    bs = assemble(args, mesh, W)
+    log(f"[setup] {args.workload}: n={bs.n} blocks={bs.nblocks} assembly {time.time() - t0:.1f}s; "
+        f"{assembly_note(bs)}")
     H64 = hmat.HMatrix(bs, hmat.M1_DOUBLE)
     Hm = hmat.HMatrix(bs, variant, c=-1)
     Bm, B64 = Hm.stats().algorithmic_bytes, H64.stats().algorithmic_bytes
@@ -663,8 +684,9 @@ def cpu_baseline(mesh, W, variant, reps, B, drop=0):
 
     t0 = time.time()
     h = oracle.HMatrix(mesh.centroids, mesh.areas, leaf=W["leaf"], eta=W["eta"], eps=W["eps"])
+    t1 = time.time()
     conv = oracle.Converted(h, variant, -1, drop=drop)
-    log(f"[cpu] oracle assembly + conversion {time.time() - t0:.1f}s")
+    log(f"[cpu] oracle assembly {t1 - t0:.2f}s (1 thread), conversion {time.time() - t1:.2f}s")
     x = np.random.default_rng(0).standard_normal(h.n)
     conv.matvec(x)
     t0 = time.perf_counter()
