@@ -165,6 +165,19 @@ def test_library_assembly_matches_oracle(key):
         assert np.array_equal(a, o), b
 
 
+def test_library_assembly_stats():
+    m, h = oracle_hmatrix("plates-16")
+    bs = hmat.hmat_assemble_bem(m.centroids, m.areas, leaf=h.leaf, eta=h.eta, eps=h.eps, threads=3)
+    st = bs.stats
+    assert st["blocks"] == h.nblocks == st["host_blocks"] and st["lowrank"] == int((h.kind == 1).sum())
+    assert st["rank_cap"] == 0 and st["device_bytes"] == 0 and st["ms_aca"] == 0.0
+    assert st["ms_partition"] > 0 and st["ms_fill"] > 0
+    # the uninitialised result buffer is fully written: the last block ends at ndata
+    last = h.nblocks - 1
+    size = lambda b: bs.nrows[b] * bs.ncols[b] if bs.kind[b] == 0 else bs.rank[b] * (bs.nrows[b] + bs.ncols[b])
+    assert bs.offset[last] + size(last) == bs.data.size and np.all(np.isfinite(bs.data))
+
+
 def test_library_assembly_threads_deterministic():
     m = meshes.icosphere(3)
     a = hmat.hmat_assemble_bem(m.centroids, m.areas, leaf=32, eta=2.0, eps=1e-6, threads=1)
