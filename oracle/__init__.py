@@ -75,6 +75,8 @@ def _load():
         L.ora_convert.argtypes = [P, C.c_int, C.c_int]
         L.ora_convert_drop.restype = P
         L.ora_convert_drop.argtypes = [P, C.c_int, C.c_int, C.c_int]
+        L.ora_convert_opts.restype = P
+        L.ora_convert_opts.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int]
         L.ora_conv_free.argtypes = [P]
         L.ora_conv_rank.restype = I32
         L.ora_conv_rank.argtypes = [P, I64]
@@ -224,16 +226,19 @@ class HMatrix:
 class Converted:
     """An oracle H-matrix converted to one precision variant (Sec. 3)."""
 
-    def __init__(self, h: HMatrix, variant: int, c: int = 0, drop: int = 0):
+    def __init__(self, h: HMatrix, variant: int, c: int = 0, drop: int = 0, dense_split: bool = False):
         """drop > 0 (Methods 2 and 3): omit the terms with d_i < d_max 10^-drop
-        (the deletion of much smaller terms proposed in Sec. 4.5)."""
+        (the deletion of much smaller terms proposed in Sec. 4.5).
+        dense_split (Method 3): the dense leaves split by column like the
+        low-rank terms, with the same c (Sec. 4.5's other proposal)."""
         self.h = h
         self.variant = variant
         self.c = c
         self.drop = drop
-        p = _load().ora_convert_drop(h._h, int(variant), int(c), int(drop))
+        self.dense_split = bool(dense_split)
+        p = _load().ora_convert_opts(h._h, int(variant), int(c), int(drop), int(bool(dense_split)))
         if not p:
-            raise ValueError("bad variant or drop")
+            raise ValueError("bad variant, drop or dense_split")
         self._p = p
 
     def __del__(self):

@@ -549,12 +549,19 @@ static double ora_pow2_ceil(double m)
 }
 
 /* drop (Methods 2 and 3): 0, or omit the terms with d_i < d_max 10^-drop,
- * the deletion of much smaller terms that Sec. 4.5 proposes. */
-ora_conv *ora_convert_drop(const ora_hmat *h, int variant, int c, int drop)
+ * the deletion of much smaller terms that Sec. 4.5 proposes.
+ * dense_split (Method 3 only): Method 3's split applied to the dense leaves
+ * as well, the other proposal of Sec. 4.5: column j of a dense block, whose
+ * entries all multiply x_j as the entries of a low-rank term all scale one
+ * z entry, is stored in FP32 when its largest magnitude is below
+ * (largest magnitude in the block) 10^-c, in FP64 otherwise (ties FP64, as
+ * in Eq. 20). */
+ora_conv *ora_convert_opts(const ora_hmat *h, int variant, int c, int drop, int dense_split)
 {
     if (variant < 0 || variant > 7) return NULL;
     if (drop < 0 || (drop > 0 && !(variant == V_M2D || variant == V_M2S || variant == V_M2M || variant == V_M3)))
         return NULL;
+    if (dense_split && variant != V_M3) return NULL;
     ora_conv *v = (ora_conv *)calloc(1, sizeof(ora_conv));
     v->variant = variant;
     v->c = c;
@@ -579,8 +586,21 @@ ora_conv *ora_convert_drop(const ora_hmat *h, int variant, int c, int drop)
         const double *src = h->data + b->off;
         if (b->kind == 0) {
             int64_t cnt = b->nrows * b->ncols;
-            for (int64_t e = 0; e < cnt; e++)
-                v->data[dpos + e] = v->dense32 ? ora_rnd32(src[e]) : src[e];
+            if (dense_split) {
+                double bmax = 0.0;
+                for (int64_t e = 0; e < cnt; e++) if (fabs(src[e]) > bmax) bmax = fabs(src[e]);
+                double thr = bmax * pow(10.0, -(double)c);
+                for (int64_t j = 0; j < b->ncols; j++) {
+                    const double *col = src + j * b->nrows;
+                    double cmax = 0.0;
+                    for (int64_t i = 0; i < b->nrows; i++) if (fabs(col[i]) > cmax) cmax = fabs(col[i]);
+                    for (int64_t i = 0; i < b->nrows; i++)
+                        v->data[dpos + j * b->nrows + i] = cmax < thr ? ora_rnd32(col[i]) : col[i];
+                }
+            } else {
+                for (int64_t e = 0; e < cnt; e++)
+                    v->data[dpos + e] = v->dense32 ? ora_rnd32(src[e]) : src[e];
+            }
             v->toff[bi] = -1;
             v->toff_data[bi] = dpos;
             dpos += cnt;
@@ -671,7 +691,12 @@ ora_conv *ora_convert_drop(const ora_hmat *h, int variant, int c, int drop)
     return v;
 }
 
-ora_conv *ora_convert(const ora_hmat *h, int variant, int c) { return ora_convert_drop(h, variant, c, 0); }
+ora_conv *ora_convert_drop(const ora_hmat *h, int variant, int c, int drop)
+{
+    return ora_convert_opts(h, variant, c, drop, 0);
+}
+
+ora_conv *ora_convert(const ora_hmat *h, int variant, int c) { return ora_convert_opts(h, variant, c, 0, 0); }
 
 void ora_conv_free(ora_conv *v)
 {

@@ -337,6 +337,69 @@ def test_drop_limits():
             oracle.Converted(h, v, drop=3)
 
 
+def _dense_blocks(h):
+    return [b for b in range(h.nblocks) if h.kind[b] == 0]
+
+
+def test_dense_split_limits():
+    """Method 3's split on the dense leaves (Sec. 4.5) at its two ends: with
+    c = -1 every dense column is below ten times its block's maximum, so
+    the dense leaves are stored as Method 2-Mixed stores them (all FP32,
+    Table 1); with c = 20 none is, so Method 3 is unchanged bit for bit.
+    The low-rank part never changes; the split exists for Method 3 only."""
+    m, h = oracle_hmatrix("plates-16")
+    x = np.random.default_rng(21).standard_normal(h.n)
+    lo = oracle.Converted(h, oracle.M3, -1, dense_split=True)
+    m2 = oracle.Converted(h, oracle.M2_MIXED)
+    hi = oracle.Converted(h, oracle.M3, 20, dense_split=True)
+    m3 = oracle.Converted(h, oracle.M3, 20)
+    for b in _dense_blocks(h):
+        assert np.array_equal(lo.block(b)[1], m2.block(b)[1])
+        assert np.array_equal(hi.block(b)[1], m3.block(b)[1])
+    for b in _lr_blocks(h)[:50]:
+        for u, v in zip(lo.block(b)[1:], oracle.Converted(h, oracle.M3, -1).block(b)[1:]):
+            assert np.array_equal(u, v)
+    assert np.array_equal(hi.matvec(x), m3.matvec(x))
+    for v in (oracle.M1_DOUBLE, oracle.M2_MIXED, oracle.BF16_SCALED):
+        with pytest.raises(ValueError):
+            oracle.Converted(h, v, 1, dense_split=True)
+
+
+@pytest.mark.parametrize("c", [0, 1])
+def test_dense_split_rounds_whole_columns_within_the_fp32_bound(c):
+    """Each dense column is stored either exactly or rounded to FP32 as a
+    whole (every entry within half an FP32 ulp, 2^-24 relative, of the FP64
+    value), fewer columns round as c grows, and the product differs from
+    Method 3 without the split by exactly the rounding of the stored values
+    times x, which is bounded by 2^-24 |A| |x| over the dense leaves."""
+    m, h = oracle_hmatrix("plates-16")
+    x = np.random.default_rng(22).standard_normal(h.n)
+    split = oracle.Converted(h, oracle.M3, c, dense_split=True)
+    base = oracle.Converted(h, oracle.M3, c)
+    diff, bound = np.zeros(h.n), np.zeros(h.n)
+    rounded = 0
+    for b in _dense_blocks(h):
+        _, A = h.block_factors(b)
+        As = split.block(b)[1]
+        exact = np.all(As == A, axis=0)
+        assert np.all(np.abs(As - A) <= 2.0 ** -24 * np.abs(A))
+        # Eq. 20's >=: the column holding the block's largest entry stays FP64 for c >= 0
+        assert exact[np.argmax(np.abs(A).max(axis=0))]
+        rounded += int((~exact).sum())
+        r0, c0 = h.row0[b], h.col0[b]
+        xs = x[c0:c0 + A.shape[1]]
+        diff[r0:r0 + A.shape[0]] += (As - A) @ xs
+        bound[r0:r0 + A.shape[0]] += 2.0 ** -24 * np.abs(A) @ np.abs(xs)
+    assert rounded > 0
+    dy = split.matvec(x) - base.matvec(x)
+    scale = abs_scale(h, x).max()
+    assert np.abs(dy - diff).max() <= 1e-14 * scale
+    assert np.all(np.abs(dy) <= bound + 1e-14 * scale)
+    nxt = oracle.Converted(h, oracle.M3, c + 1, dense_split=True)
+    more = sum(int((~np.all(nxt.block(b)[1] == h.block_factors(b)[1], axis=0)).sum()) for b in _dense_blocks(h))
+    assert more < rounded
+
+
 def test_bf16_values_and_scales():
     m, h = oracle_hmatrix("sphere-L3")
     conv = oracle.Converted(h, oracle.BF16_SCALED)
