@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--drop", type=int, default=0,
                     help="Methods 2/3: delete low-rank terms with d_i < d_max 10^-drop (Sec. 4.5; 0 = off)")
+    ap.add_argument("--c", type=int, default=-1, help="Method 3 split constant (Eqs. 19-20)")
+    ap.add_argument("--dense-split", action="store_true",
+                    help="Method 3: split the dense leaves by column with the same c (Sec. 4.5)")
     ap.add_argument("--assembly", default="gpu", choices=["gpu", "host"],
                     help="setup builder: entries and ACA on the GPU (default) or on the host threads")
     ap.add_argument("--train-leaves", type=int, default=20000)
@@ -159,7 +162,7 @@ def main():
         f"{assembly_note(bs)}")
     t0 = time.time()
     H64 = hmat.HMatrix(bs, hmat.M1_DOUBLE)
-    Hm = hmat.HMatrix(bs, variant, c=-1, drop=args.drop)
+    Hm = hmat.HMatrix(bs, variant, c=args.c, drop=args.drop, dense_split=args.dense_split)
     log(f"[setup] builds {time.time() - t0:.1f}s")
     st64, stm = H64.stats(), Hm.stats()
     B64, Bm = st64.algorithmic_bytes, stm.algorithmic_bytes
@@ -307,6 +310,8 @@ def main():
             "solver": f"GMRES({args.restart})" if gm else "BiCGSTAB",
             "refine": args.refine,
             "drop": args.drop,
+            "c": args.c,
+            "dense_split": args.dense_split,
             "parallelism": "1 GPU",
         },
         "time_to_tol_ms": {"mixed": round(ms_per_step, 3), "fp64": round(1e3 * t_fp64 / args.steps, 3),
@@ -335,7 +340,8 @@ def main():
     }
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mesh, W, variant, args.cpu_matvecs, Bm, args.drop)
+        out["cpu_baseline"] = cpu_baseline(mesh, W, variant, args.cpu_matvecs, Bm, args.drop, args.c,
+                                           args.dense_split)
     print(json.dumps(out), flush=True)
 
 
@@ -675,7 +681,7 @@ def _plan_stats(bs, precision):
                            algorithmic_bytes=info.algorithmic_bytes)
 
 
-def cpu_baseline(mesh, W, variant, reps, B, drop=0):
+def cpu_baseline(mesh, W, variant, reps, B, drop=0, c=-1, dense_split=False):
     """The oracle as it stands (plain single-threaded C, FP64 arithmetic) on
     the same workload: its own assembly (untimed; it reproduces the library's
     blocks bit for bit, so the product moves the same B bytes), then `reps`
@@ -685,7 +691,7 @@ def cpu_baseline(mesh, W, variant, reps, B, drop=0):
     t0 = time.time()
     h = oracle.HMatrix(mesh.centroids, mesh.areas, leaf=W["leaf"], eta=W["eta"], eps=W["eps"])
     t1 = time.time()
-    conv = oracle.Converted(h, variant, -1, drop=drop)
+    conv = oracle.Converted(h, variant, c, drop=drop, dense_split=dense_split)
     log(f"[cpu] oracle assembly {t1 - t0:.2f}s (1 thread), conversion {time.time() - t1:.2f}s")
     x = np.random.default_rng(0).standard_normal(h.n)
     conv.matvec(x)

@@ -111,6 +111,11 @@ typedef struct {
                                  that column of V' and row of W' (the deletion Sec. 4.5 proposes for
                                  terms much smaller than the largest; not a measured variant of the
                                  paper) */
+    int32_t dense_split;      /* 0, or 1 (Method 3 only): split the dense leaves like the low-rank
+                                 terms, the other proposal of Sec. 4.5: column j of a dense block is
+                                 stored in FP32 when its largest magnitude is below the block's
+                                 largest times 10^-c, in FP64 otherwise (ties FP64, as Eq. 20) */
+    int32_t reserved;         /* 0 */
 } hmat_build_opts;
 
 typedef struct {

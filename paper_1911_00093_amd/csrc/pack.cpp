@@ -92,6 +92,10 @@ struct Packed {
   hmat_blocks b{};
   int precision = 0, c = 0, nrhs_max = 1;
   int dense_cls = F64;
+  // dense_split: class of every column of each dense block (dcol_off[k] into
+  // dcol_cls, -1 for low-rank blocks); empty when the dense leaves are not split
+  std::vector<int64_t> dcol_off;
+  std::vector<uint8_t> dcol_cls;
   int x32 = 0, z32 = 0;
   std::vector<std::vector<Term>> terms;  // per block (empty for dense)
   std::vector<Group> groups;
@@ -188,6 +192,8 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   if (o->drop < 0 || o->drop > 15) return fail(HMAT_E_ARG, "drop %d outside 0..15", o->drop);
   if (o->drop != 0 && (o->precision < HMAT_M2_DOUBLE || o->precision > HMAT_M3))
     return fail(HMAT_E_ARG, "drop applies to Methods 2 and 3 (their D_m scales)");
+  if (o->dense_split != 0 && o->dense_split != 1) return fail(HMAT_E_ARG, "dense_split must be 0 or 1");
+  if (o->dense_split && o->precision != HMAT_M3) return fail(HMAT_E_ARG, "dense_split applies to Method 3");
   const int64_t n = b->n;
   if (n <= 0 || n > (int64_t(1) << 30)) return fail(HMAT_E_ARG, "matrix order %lld out of range", (long long)n);
   if (b->nblocks <= 0) return fail(HMAT_E_ARG, "no blocks");
@@ -279,12 +285,23 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   // ---- conversion decisions per low-rank block
   P->terms.assign(nb, {});
   int64_t nterms[NCLS] = {0, 0, 0}, max_rank = 0, ndense = 0, nlr = 0;
+  if (o->dense_split) P->dcol_off.assign(nb, -1);
   for (int64_t k = 0; k < nb; k++) {
     if (b->kind[k] == HMAT_DENSE) {
       ndense++;
       if (b->row0[k] == b->col0[k] && b->nrows[k] == b->ncols[k]) {
         P->diag_r0.push_back(b->row0[k]);
         P->diag_m.push_back(b->nrows[k]);
+      }
+      if (o->dense_split) {
+        // Method 3 on the dense leaves (Sec. 4.5): a column whose largest
+        // magnitude is below the block's largest times 10^-c goes to FP32
+        const int64_t m = b->nrows[k], nc = b->ncols[k];
+        const double *A = b->data + b->offset[k];
+        const double thr = max_abs(A, m * nc, 1) * std::pow(10.0, -(double)o->c);
+        P->dcol_off[k] = (int64_t)P->dcol_cls.size();
+        for (int64_t j = 0; j < nc; j++)
+          P->dcol_cls.push_back((uint8_t)(max_abs(A + j * m, m, 1) < thr ? F32 : F64));
       }
       continue;
     }
@@ -438,7 +455,17 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
       cp.r0 = r0;
       cp.h = std::min<int64_t>(kRowChunk, cuts[s + 1] - r0);
       for (int64_t k : seg_blocks[s]) {
-        if (b->kind[k] == HMAT_DENSE) {
+        if (b->kind[k] == HMAT_DENSE && !P->dcol_off.empty()) {
+          const uint8_t *cc = P->dcol_cls.data() + P->dcol_off[k];
+          const int32_t nc = (int32_t)b->ncols[k];
+          for (int32_t j = 0; j < nc;) {  // runs of columns of one class
+            int32_t e = j;
+            while (e < nc && cc[e] == cc[j]) e++;
+            cp.runs[cc[j]].push_back({k, j, e - j});
+            cp.K[cc[j]] += e - j;
+            j = e;
+          }
+        } else if (b->kind[k] == HMAT_DENSE) {
           cp.runs[P->dense_cls].push_back({k, 0, (int32_t)b->ncols[k]});
           cp.K[P->dense_cls] += b->ncols[k];
         } else {
@@ -553,7 +580,10 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   // ---- sizes and statistics
   uint64_t bd = 0, bv = 0, bw = 0;
   for (int64_t k = 0; k < nb; k++) {
-    if (b->kind[k] == HMAT_DENSE) {
+    if (b->kind[k] == HMAT_DENSE && !P->dcol_off.empty()) {
+      for (int64_t j = 0; j < b->ncols[k]; j++)
+        bd += (uint64_t)b->nrows[k] * bytes_of(P->dcol_cls[P->dcol_off[k] + j]);
+    } else if (b->kind[k] == HMAT_DENSE) {
       bd += (uint64_t)b->nrows[k] * b->ncols[k] * bytes_of(P->dense_cls);
     } else {
       for (auto &t : P->terms[k]) {

@@ -55,7 +55,8 @@ class hmat_blocks(C.Structure):
 
 
 class hmat_build_opts(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("c", C.c_int32), ("nrhs_max", C.c_int32), ("drop", C.c_int32)]
+    _fields_ = [("precision", C.c_int32), ("c", C.c_int32), ("nrhs_max", C.c_int32), ("drop", C.c_int32),
+                ("dense_split", C.c_int32), ("reserved", C.c_int32)]
 
 
 class hmat_plan_info(C.Structure):
@@ -284,19 +285,21 @@ def hmat_assemble_bem_gpu(centroids, areas, leaf=64, eta=2.0, eps=1e-5, rank_cap
     return _assembly_blockset(out, n)
 
 
-def hmat_plan(blocks: BlockSet, precision: int, c: int = 0, nrhs_max: int = 1, drop: int = 0) -> hmat_plan_info:
+def hmat_plan(blocks: BlockSet, precision: int, c: int = 0, nrhs_max: int = 1, drop: int = 0,
+              dense_split: bool = False) -> hmat_plan_info:
     info = hmat_plan_info()
     s = blocks.struct()
-    o = hmat_build_opts(int(precision), int(c), int(nrhs_max), int(drop))
+    o = hmat_build_opts(int(precision), int(c), int(nrhs_max), int(drop), int(bool(dense_split)), 0)
     _check(lib().hmat_plan(C.byref(s), C.byref(o), C.byref(info)))
     return info
 
 
 # ----------------------------------------------------------------- device
-def hmat_plan_batched(systems, precision: int, c: int = 0, nrhs_max: int = 1, drop: int = 0) -> hmat_plan_info:
+def hmat_plan_batched(systems, precision: int, c: int = 0, nrhs_max: int = 1, drop: int = 0,
+                      dense_split: bool = False) -> hmat_plan_info:
     info = hmat_plan_info()
     arr = (hmat_blocks * len(systems))(*[b.struct() for b in systems])
-    o = hmat_build_opts(int(precision), int(c), int(nrhs_max), int(drop))
+    o = hmat_build_opts(int(precision), int(c), int(nrhs_max), int(drop), int(bool(dense_split)), 0)
     _check(lib().hmat_plan_batched(arr, len(systems), C.byref(o), C.byref(info)))
     return info
 
@@ -306,22 +309,23 @@ class HMatrix:
     owns its torch buffer."""
 
     def __init__(self, blocks, precision: int, c: int = 0, nrhs_max: int = 1, device="cuda", stream=None,
-                 drop: int = 0):
+                 drop: int = 0, dense_split: bool = False):
         import torch
 
         self.precision, self.c, self.nrhs_max, self.drop = int(precision), int(c), int(nrhs_max), int(drop)
+        self.dense_split = bool(dense_split)
         batched = isinstance(blocks, (list, tuple))
-        o = hmat_build_opts(self.precision, self.c, self.nrhs_max, self.drop)
+        o = hmat_build_opts(self.precision, self.c, self.nrhs_max, self.drop, int(self.dense_split), 0)
         h = C.c_void_p()
         if batched:
-            self.plan = hmat_plan_batched(blocks, precision, c, nrhs_max, drop)
+            self.plan = hmat_plan_batched(blocks, precision, c, nrhs_max, drop, dense_split)
             self.n = sum(b.n for b in blocks)
             self.buf = torch.empty(int(self.plan.device_bytes), dtype=torch.uint8, device=device)
             arr = (hmat_blocks * len(blocks))(*[b.struct() for b in blocks])
             _check(lib().hmat_build_batched(arr, len(blocks), C.byref(o), C.c_void_p(self.buf.data_ptr()),
                                             self.buf.numel(), _stream_ptr(stream), C.byref(h)))
         else:
-            self.plan = hmat_plan(blocks, precision, c, nrhs_max, drop)
+            self.plan = hmat_plan(blocks, precision, c, nrhs_max, drop, dense_split)
             self.n = blocks.n
             self.buf = torch.empty(int(self.plan.device_bytes), dtype=torch.uint8, device=device)
             s = blocks.struct()

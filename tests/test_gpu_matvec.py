@@ -31,6 +31,36 @@ def test_matvec_parity_small(key, variant):
         assert err <= tolerance(variant), (key, variant, err)
 
 
+@pytest.mark.parametrize("key,c", [("plates-16", 0), ("plates-16", 1), ("sphere-L4", -1), ("sphere-L4", 0),
+                                   ("spheres-mixed", 0)])
+@pytest.mark.parametrize("nrhs_max", [1, 16])
+def test_matvec_dense_split_parity(key, c, nrhs_max):
+    """Method 3 with the dense leaves split by column (Sec. 4.5): the
+    library's product equals the oracle's on the same split, for the
+    single-vector and the matrix-core product."""
+    need_gpu()
+    import torch
+
+    m, h = oracle_hmatrix(key)
+    H = hmat.HMatrix(blockset(h), oracle.M3, c=c, nrhs_max=nrhs_max, dense_split=True)
+    conv = oracle.Converted(h, oracle.M3, c, dense_split=True)
+    plain = oracle.Converted(h, oracle.M3, c)
+    X = np.random.default_rng(13).standard_normal((3, h.n))
+    X[0] = 1.0
+    if nrhs_max > 1:
+        Y = H.matvec(torch.as_tensor(X).cuda().T).cpu().numpy()
+    else:
+        Y = np.stack([H.matvec(to_dev(X[k])).cpu().numpy() for k in range(3)], axis=1)
+    for k in range(3):
+        scale = abs_scale(h, X[k]).max()
+        err = np.abs(Y[:, k] - conv.matvec(X[k])).max() / scale
+        moved = np.abs(plain.matvec(X[k]) - conv.matvec(X[k])).max() / scale
+        print(f"{key} c={c}: error {err:.2e}, split moved y by {moved:.2e}")
+        assert err <= tolerance(oracle.M3), (k, err)
+        if c <= 0:
+            assert moved > 10 * tolerance(oracle.M3)  # the split is visible, the parity is not luck
+
+
 @pytest.mark.parametrize("variant,t", [(oracle.M2_DOUBLE, 3), (oracle.M2_MIXED, 2), (oracle.M2_SINGLE, 5),
                                        (oracle.M3, 4)])
 @pytest.mark.parametrize("nrhs_max", [1, 16])

@@ -165,6 +165,30 @@ def test_library_assembly_matches_oracle(key):
         assert np.array_equal(a, o), b
 
 
+@pytest.mark.parametrize("c", [-1, 0, 1])
+def test_plan_dense_split_bytes(c):
+    """Method 3 with the dense leaves split (Sec. 4.5): the plan stores
+    exactly the dense columns the oracle rounds to FP32 in 4 bytes per entry
+    instead of 8, and nothing else changes; other methods refuse the split."""
+    m, h = oracle_hmatrix("plates-16")
+    bs = blockset_from_oracle(h)
+    base = hmat.hmat_plan(bs, hmat.M3, c=c)
+    split = hmat.hmat_plan(bs, hmat.M3, c=c, dense_split=True)
+    conv = oracle.Converted(h, oracle.M3, c, dense_split=True)
+    saved = 0
+    for b in range(h.nblocks):
+        if h.kind[b] == 0:
+            _, A = h.block_factors(b)
+            rounded = ~np.all(conv.block(b)[1] == A, axis=0)
+            saved += int(rounded.sum()) * int(h.nrows[b]) * 4
+    assert saved > 0 or c > 0
+    assert base.matrix_bytes - split.matrix_bytes == saved
+    assert base.terms_fp64 == split.terms_fp64 and base.terms_fp32 == split.terms_fp32
+    for bad in (hmat.M1_DOUBLE, hmat.M2_MIXED, hmat.BF16_SCALED):
+        with pytest.raises(hmat.HmatError):
+            hmat.hmat_plan(bs, bad, c=c, dense_split=True)
+
+
 def test_library_assembly_stats():
     m, h = oracle_hmatrix("plates-16")
     bs = hmat.hmat_assemble_bem(m.centroids, m.areas, leaf=h.leaf, eta=h.eta, eps=h.eps, threads=3)
