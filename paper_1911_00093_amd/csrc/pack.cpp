@@ -146,6 +146,29 @@ XcdSplit xcd_split(const std::vector<double> &cost) {
   return s;
 }
 
+// Spread every system of a batched launch over the XCD ranges: unit q of
+// system sys[q] (units in their natural order, each system's units
+// contiguous) gets piece p = the eighth of its system's cost that its middle
+// falls in; ordering the units by piece (stably) makes each of xcd_split's
+// ranges hold about an eighth of every system, so the XCDs stay evenly
+// loaded when the units of stopped systems are skipped.
+static std::vector<int> xcd_pieces(const std::vector<int32_t> &sys, const std::vector<double> &cost) {
+  std::vector<double> tot;
+  for (size_t q = 0; q < sys.size(); q++) {
+    if ((size_t)sys[q] >= tot.size()) tot.resize(sys[q] + 1, 0.0);
+    tot[sys[q]] += cost[q];
+  }
+  std::vector<double> run(tot.size(), 0.0);
+  std::vector<int> piece(sys.size());
+  for (size_t q = 0; q < sys.size(); q++) {
+    const double t = tot[sys[q]];
+    const double mid = run[sys[q]] + 0.5 * cost[q];
+    piece[q] = t > 0.0 ? std::min(kXcds - 1, (int)(kXcds * mid / t)) : 0;
+    run[sys[q]] += cost[q];
+  }
+  return piece;
+}
+
 // Round a double to the nearest bfloat16 (8 significant bits, ties to even)
 // and return its bit pattern.  Works on the binary64 encoding: the 45 low
 // mantissa bits are rounded away, then the value (exact in binary32) is
@@ -413,11 +436,36 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   // consecutive memory.  The multi-RHS layout keeps column-group order
   // instead (items reading the same x columns run side by side; the launch
   // is balanced by contiguous per-XCD ranges, see xcd_split).
-  std::stable_sort(isrc.begin(), isrc.end(), [&](const ItemSrc &a, const ItemSrc &c) {
-    if (a.it.cls != c.it.cls) return a.it.cls < c.it.cls;  // one launch per class
-    if (P->mr) return false;
-    return (int64_t)a.it.ncols * a.it.nrows * bytes_of(a.it.cls) > (int64_t)c.it.ncols * c.it.nrows * bytes_of(c.it.cls);
-  });
+  if (P->mr) {
+    // multi-RHS: class, then XCD piece of the item's system (xcd_pieces),
+    // then column-group order
+    std::stable_sort(isrc.begin(), isrc.end(), [](const ItemSrc &a, const ItemSrc &c) { return a.it.cls < c.it.cls; });
+    std::vector<int32_t> sy(isrc.size());
+    std::vector<double> co(isrc.size());
+    for (size_t q = 0; q < isrc.size(); q++) {
+      const S1Item &it = isrc[q].it;
+      sy[q] = sys_index(P->sys_off, it.x0) + (int32_t)P->sys_off.size() * it.cls;  // pieces per class
+      const int nkb = (it.ncols + mr_cb(it.cls) - 1) / mr_cb(it.cls);
+      co[q] = 4.0 * it.nrows * (double)nkb * 16.0 + it.ncols * kMRhs * 8.0;
+    }
+    const std::vector<int> pc = xcd_pieces(sy, co);
+    std::vector<size_t> ord(isrc.size());
+    for (size_t q = 0; q < ord.size(); q++) ord[q] = q;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t c) {
+      if (isrc[a].it.cls != isrc[c].it.cls) return isrc[a].it.cls < isrc[c].it.cls;
+      return pc[a] < pc[c];
+    });
+    std::vector<ItemSrc> sorted;
+    sorted.reserve(isrc.size());
+    for (size_t q : ord) sorted.push_back(isrc[q]);
+    isrc.swap(sorted);
+  } else {
+    std::stable_sort(isrc.begin(), isrc.end(), [&](const ItemSrc &a, const ItemSrc &c) {
+      if (a.it.cls != c.it.cls) return a.it.cls < c.it.cls;  // one launch per class
+      return (int64_t)a.it.ncols * a.it.nrows * bytes_of(a.it.cls) >
+             (int64_t)c.it.ncols * c.it.nrows * bytes_of(c.it.cls);
+    });
+  }
   for (auto &q : isrc) {
     const int c = q.it.cls;
     if (!P->mr) {
@@ -491,10 +539,27 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
     for (int c = 0; c < NCLS; c++) s += P->chunks[i].h * P->chunks[i].K[c] * bytes_of(c);
     return s;
   };
-  // (multi-RHS: row order, so chunks sharing z and x operands are neighbours)
-  if (!P->mr)
+  // (multi-RHS: row order, so chunks sharing z and x operands are neighbours,
+  // within the XCD piece of each chunk's system)
+  if (!P->mr) {
     std::stable_sort(P->chunk_order.begin(), P->chunk_order.end(),
                      [&](int64_t a, int64_t c) { return cbytes(a) > cbytes(c); });
+  } else {
+    std::vector<int32_t> sy(P->chunks.size());
+    std::vector<double> co(P->chunks.size());
+    for (size_t i = 0; i < P->chunks.size(); i++) {
+      const ChunkPlan &cp = P->chunks[i];
+      sy[i] = sys_index(P->sys_off, cp.r0);
+      double c = 0.0;
+      for (int k = 0; k < NCLS; k++) {
+        const double nkb = (double)((cp.K[k] + mr_cb(k) - 1) / mr_cb(k));
+        c += nkb * (4.0 * cp.h * 16.0 + mr_cb(k) * (kMRhs * 8.0 + 4.0));
+      }
+      co[i] = c;
+    }
+    const std::vector<int> pc = xcd_pieces(sy, co);
+    std::stable_sort(P->chunk_order.begin(), P->chunk_order.end(), [&](int64_t a, int64_t c) { return pc[a] < pc[c]; });
+  }
   if (P->mr) {
     P->mrc.resize(P->chunks.size());
     for (size_t q = 0; q < P->chunk_order.size(); q++) {
