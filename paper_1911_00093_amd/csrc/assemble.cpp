@@ -21,12 +21,14 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <memory>
 #include <thread>
 #include <vector>
 
 #include <sys/mman.h>
 
+#include "assemble_impl.h"
 #include "hmat_impl.h"
 
 namespace {
@@ -359,6 +361,8 @@ int hmat_assemble_bem(int64_t n, const double *centroids, const double *areas, c
     *out = R;
   } catch (const std::bad_alloc &) {
     return hm::fail(HMAT_E_NOMEM, "out of host memory during assembly");
+  } catch (const std::exception &x) {  // e.g. no thread could be started
+    return hm::fail(HMAT_E_NOMEM, "host resources exhausted during assembly: %s", x.what());
   }
   return HMAT_OK;
 }

@@ -25,6 +25,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <memory>
 #include <thread>
 #include <vector>
@@ -426,10 +427,9 @@ struct Events {
                       hipGetErrorString(e_));                                                    \
   } while (0)
 
-extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const double *areas,
-                                     const hmat_assemble_opts *opts, int32_t rank_cap, void *stream,
-                                     hmat_assembly_t *out) {
-  using namespace hm;
+namespace hm {
+static int assemble_gpu(int64_t n, const double *centroids, const double *areas, const hmat_assemble_opts *opts,
+                        int32_t rank_cap, void *stream, hmat_assembly_t *out) {
   using clk = std::chrono::steady_clock;
   auto ms = [](clk::time_point x, clk::time_point y) { return std::chrono::duration<double, std::milli>(y - x).count(); };
   if (!out) return fail(HMAT_E_ARG, "null output");
@@ -447,11 +447,7 @@ extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const d
   int64_t total = 0;
   hmat_assembly_stats S{};
   S.rank_cap = rank_cap;
-  try {
-    bem_partition(n, centroids, areas, *opts, P);
-  } catch (const std::bad_alloc &) {
-    return fail(HMAT_E_NOMEM, "out of host memory during partition");
-  }
+  bem_partition(n, centroids, areas, *opts, P);
   const auto t1 = clk::now();
   const int64_t nb = (int64_t)P.row0.size();
   S.blocks = nb;
@@ -521,7 +517,7 @@ extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const d
   }
   HM_TRY(hipStreamSynchronize(st), "k_aca");
 
-  try {
+  {
     // blocks the device did not finish: the host builder, threaded
     std::vector<int64_t> redo;
     for (int64_t q = 0; q < na; q++)
@@ -606,8 +602,19 @@ extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const d
     S.ms_fill = ms(t1, clk::now());
     R->stats = S;
     *out = keep.release();
-  } catch (const std::bad_alloc &) {
-    return fail(HMAT_E_NOMEM, "out of host memory during assembly");
   }
   return HMAT_OK;
+}
+}  // namespace hm
+
+extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const double *areas,
+                                     const hmat_assemble_opts *opts, int32_t rank_cap, void *stream,
+                                     hmat_assembly_t *out) {
+  try {
+    return hm::assemble_gpu(n, centroids, areas, opts, rank_cap, stream, out);
+  } catch (const std::bad_alloc &) {
+    return hm::fail(HMAT_E_NOMEM, "out of host memory during assembly");
+  } catch (const std::exception &x) {  // e.g. no thread could be started
+    return hm::fail(HMAT_E_NOMEM, "host resources exhausted during assembly: %s", x.what());
+  }
 }
