@@ -117,7 +117,9 @@ struct Packed {
   // batched build: the merged block description owns these
   std::vector<int64_t> m_row0, m_nrows, m_col0, m_ncols, m_off;
   std::vector<int32_t> m_kind, m_rank;
-  std::vector<double> m_data;
+  // first stored value of each block: into the caller's data (one system),
+  // or into each system's own data (batched; nothing is copied)
+  std::vector<const double *> bsrc;
   // multi-RHS layout (MFMA fragment order)
   bool mr = false;
   std::vector<MRChunk> mrc;
@@ -206,8 +208,36 @@ static double pow2_at_least(double m) {
   return std::ldexp(1.0, f == 0.5 ? e - 1 : e);
 }
 
+// Run f(i) for i in [0, count) on the host's threads (disjoint outputs).
+template <class F>
+static void parallel_for(int64_t count, F f) {
+  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::atomic<int64_t> next{0};
+  auto work = [&]() {
+    for (;;) {
+      const int64_t i = next.fetch_add(1);
+      if (i >= count) break;
+      f(i);
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt && t < count; t++) th.emplace_back(work);
+  work();
+  for (auto &x : th) x.join();
+}
+
+// block_src: per block, the address of its first value (plan_batched, whose
+// merged description has no data array of its own); null: data + offset.
+static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *info, Packed **out_keep,
+                           const int64_t *sys_off, int64_t nsys, const double *const *block_src);
+
 int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *info, Packed **out_keep,
                 const int64_t *sys_off, int64_t nsys) {
+  return plan_blocks_src(b, o, info, out_keep, sys_off, nsys, nullptr);
+}
+
+static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *info, Packed **out_keep,
+                           const int64_t *sys_off, int64_t nsys, const double *const *block_src) {
   if (!b || !o) return fail(HMAT_E_ARG, "null argument");
   if (o->precision < HMAT_M1_DOUBLE || o->precision > HMAT_BF16_SCALED)
     return fail(HMAT_E_ARG, "unknown precision %d", o->precision);
@@ -220,7 +250,8 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   const int64_t n = b->n;
   if (n <= 0 || n > (int64_t(1) << 30)) return fail(HMAT_E_ARG, "matrix order %lld out of range", (long long)n);
   if (b->nblocks <= 0) return fail(HMAT_E_ARG, "no blocks");
-  if (!b->row0 || !b->nrows || !b->col0 || !b->ncols || !b->kind || !b->rank || !b->offset || (!b->data && b->ndata))
+  if (!b->row0 || !b->nrows || !b->col0 || !b->ncols || !b->kind || !b->rank || !b->offset ||
+      (!block_src && !b->data && b->ndata))
     return fail(HMAT_E_ARG, "null block array");
   const int64_t nb = b->nblocks;
   for (int64_t k = 0; k < nb; k++) {
@@ -237,12 +268,14 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
     } else {
       return fail(HMAT_E_ARG, "block %lld: unknown kind %d", (long long)k, b->kind[k]);
     }
-    if (b->offset[k] < 0 || b->offset[k] + need > b->ndata)
+    if (!block_src && (b->offset[k] < 0 || b->offset[k] + need > b->ndata))
       return fail(HMAT_E_ARG, "block %lld: data range outside the data array", (long long)k);
   }
 
   auto *P = new Packed();
   P->b = *b;
+  P->bsrc.resize(nb);
+  for (int64_t k = 0; k < nb; k++) P->bsrc[k] = block_src ? block_src[k] : b->data + b->offset[k];
   P->precision = o->precision;
   P->c = o->c;
   P->nrhs_max = o->nrhs_max;
@@ -309,29 +342,11 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
   P->terms.assign(nb, {});
   int64_t nterms[NCLS] = {0, 0, 0}, max_rank = 0, ndense = 0, nlr = 0;
   if (o->dense_split) P->dcol_off.assign(nb, -1);
-  for (int64_t k = 0; k < nb; k++) {
-    if (b->kind[k] == HMAT_DENSE) {
-      ndense++;
-      if (b->row0[k] == b->col0[k] && b->nrows[k] == b->ncols[k]) {
-        P->diag_r0.push_back(b->row0[k]);
-        P->diag_m.push_back(b->nrows[k]);
-      }
-      if (o->dense_split) {
-        // Method 3 on the dense leaves (Sec. 4.5): a column whose largest
-        // magnitude is below the block's largest times 10^-c goes to FP32
-        const int64_t m = b->nrows[k], nc = b->ncols[k];
-        const double *A = b->data + b->offset[k];
-        const double thr = max_abs(A, m * nc, 1) * std::pow(10.0, -(double)o->c);
-        P->dcol_off[k] = (int64_t)P->dcol_cls.size();
-        for (int64_t j = 0; j < nc; j++)
-          P->dcol_cls.push_back((uint8_t)(max_abs(A + j * m, m, 1) < thr ? F32 : F64));
-      }
-      continue;
-    }
-    nlr++;
+  // the terms of every low-rank block (independent blocks: host threads)
+  parallel_for(nb, [&](int64_t k) {
+    if (b->kind[k] == HMAT_DENSE) return;
     const int64_t m = b->nrows[k], nc = b->ncols[k], r = b->rank[k];
-    max_rank = std::max(max_rank, r);
-    const double *U = b->data + b->offset[k];
+    const double *U = P->bsrc[k];
     const double *Wt = U + m * r;
     auto &T = P->terms[k];
     if (prec <= HMAT_M1_MIXED) {
@@ -366,7 +381,29 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
           T.push_back({l, cls, dv[l], dw[l], d, 0});
         }
     }
-    for (auto &t : T) nterms[t.cls]++;
+  });
+  for (int64_t k = 0; k < nb; k++) {
+    if (b->kind[k] == HMAT_DENSE) {
+      ndense++;
+      if (b->row0[k] == b->col0[k] && b->nrows[k] == b->ncols[k]) {
+        P->diag_r0.push_back(b->row0[k]);
+        P->diag_m.push_back(b->nrows[k]);
+      }
+      if (o->dense_split) {
+        // Method 3 on the dense leaves (Sec. 4.5): a column whose largest
+        // magnitude is below the block's largest times 10^-c goes to FP32
+        const int64_t m = b->nrows[k], nc = b->ncols[k];
+        const double *A = P->bsrc[k];
+        const double thr = max_abs(A, m * nc, 1) * std::pow(10.0, -(double)o->c);
+        P->dcol_off[k] = (int64_t)P->dcol_cls.size();
+        for (int64_t j = 0; j < nc; j++)
+          P->dcol_cls.push_back((uint8_t)(max_abs(A + j * m, m, 1) < thr ? F32 : F64));
+      }
+      continue;
+    }
+    nlr++;
+    max_rank = std::max<int64_t>(max_rank, b->rank[k]);
+    for (auto &t : P->terms[k]) nterms[t.cls]++;
   }
 
   // ---- stage-1 column groups and z numbering
@@ -704,24 +741,21 @@ int plan_batched(const hmat_blocks *sys, int64_t count, const hmat_build_opts *o
                  Packed **out_keep) {
   if (!sys || count < 1) return fail(HMAT_E_ARG, "no systems");
   std::vector<int64_t> off(count + 1, 0);
-  int64_t nbt = 0, ndt = 0;
+  int64_t nbt = 0;
   for (int64_t s = 0; s < count; s++) {
     if (sys[s].n <= 0 || sys[s].nblocks <= 0 || sys[s].ndata < 0) return fail(HMAT_E_ARG, "system %lld is empty", (long long)s);
     off[s + 1] = off[s] + sys[s].n;
     nbt += sys[s].nblocks;
-    ndt += sys[s].ndata;
   }
   std::vector<int64_t> row0, nrows, col0, ncols, offs;
   std::vector<int32_t> kind, rank;
-  std::vector<double> data;
+  std::vector<const double *> src;  // each block's values stay in its system's array
   try {
     row0.reserve(nbt); nrows.reserve(nbt); col0.reserve(nbt); ncols.reserve(nbt); offs.reserve(nbt);
-    kind.reserve(nbt); rank.reserve(nbt);
-    data.resize(ndt);
+    kind.reserve(nbt); rank.reserve(nbt); src.reserve(nbt);
   } catch (...) {
     return fail(HMAT_E_NOMEM, "cannot merge the systems");
   }
-  int64_t dat = 0;
   for (int64_t s = 0; s < count; s++) {
     const hmat_blocks &B = sys[s];
     if (!B.row0 || !B.nrows || !B.col0 || !B.ncols || !B.kind || !B.rank || !B.offset || (!B.data && B.ndata))
@@ -730,16 +764,20 @@ int plan_batched(const hmat_blocks *sys, int64_t count, const hmat_build_opts *o
       if (B.row0[k] < 0 || B.nrows[k] <= 0 || B.row0[k] + B.nrows[k] > B.n || B.col0[k] < 0 || B.ncols[k] <= 0 ||
           B.col0[k] + B.ncols[k] > B.n)
         return fail(HMAT_E_ARG, "system %lld: block %lld outside the matrix", (long long)s, (long long)k);
+      const int64_t need = B.kind[k] == HMAT_DENSE ? B.nrows[k] * B.ncols[k]
+                                                   : (int64_t)B.rank[k] * (B.nrows[k] + B.ncols[k]);
+      if (B.offset[k] < 0 || need < 0 || B.offset[k] + need > B.ndata)
+        return fail(HMAT_E_ARG, "system %lld: block %lld: data range outside the data array", (long long)s,
+                    (long long)k);
       row0.push_back(B.row0[k] + off[s]);
       nrows.push_back(B.nrows[k]);
       col0.push_back(B.col0[k] + off[s]);
       ncols.push_back(B.ncols[k]);
       kind.push_back(B.kind[k]);
       rank.push_back(B.rank[k]);
-      offs.push_back(B.offset[k] + dat);
+      offs.push_back(B.offset[k]);
+      src.push_back(B.data + B.offset[k]);
     }
-    if (B.ndata) std::memcpy(data.data() + dat, B.data, (size_t)B.ndata * sizeof(double));
-    dat += B.ndata;
   }
   hmat_blocks m{};
   m.n = off[count];
@@ -751,10 +789,10 @@ int plan_batched(const hmat_blocks *sys, int64_t count, const hmat_build_opts *o
   m.kind = kind.data();
   m.rank = rank.data();
   m.offset = offs.data();
-  m.data = data.data();
-  m.ndata = ndt;
+  m.data = nullptr;
+  m.ndata = 0;
   Packed *P = nullptr;
-  int rc = plan_blocks(&m, o, info, &P, off.data(), count);
+  int rc = plan_blocks_src(&m, o, info, &P, off.data(), count, src.data());
   if (rc) return rc;
   // hand the merged arrays to the plan (moving keeps their addresses)
   P->m_row0 = std::move(row0);
@@ -764,29 +802,11 @@ int plan_batched(const hmat_blocks *sys, int64_t count, const hmat_build_opts *o
   P->m_off = std::move(offs);
   P->m_kind = std::move(kind);
   P->m_rank = std::move(rank);
-  P->m_data = std::move(data);
   if (out_keep) *out_keep = P;
   else delete P;
   return HMAT_OK;
 }
 
-// Run f(i) for i in [0, count) on the host's threads (disjoint outputs).
-template <class F>
-static void parallel_for(int64_t count, F f) {
-  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  std::atomic<int64_t> next{0};
-  auto work = [&]() {
-    for (;;) {
-      const int64_t i = next.fetch_add(1);
-      if (i >= count) break;
-      f(i);
-    }
-  };
-  std::vector<std::thread> th;
-  for (int t = 1; t < nt && t < count; t++) th.emplace_back(work);
-  work();
-  for (auto &x : th) x.join();
-}
 
 // Fill the staging image of the device buffer.
 int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
@@ -806,12 +826,12 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
     else ((uint16_t *)p)[idx] = bf16_bits(v);
   };
   // converted value of a low-rank term's V' entry (row i) / W' entry (column j)
-  auto vval = [b](int64_t k, const Term &t, int64_t i) {
-    const double *U = b->data + b->offset[k];
+  auto vval = [b, P](int64_t k, const Term &t, int64_t i) {
+    const double *U = P->bsrc[k];
     return U[i + (int64_t)t.l * b->nrows[k]] / t.div_v;
   };
-  auto wval = [b](int64_t k, const Term &t, int64_t j) {
-    const double *Wt = b->data + b->offset[k] + b->nrows[k] * (int64_t)b->rank[k];
+  auto wval = [b, P](int64_t k, const Term &t, int64_t j) {
+    const double *Wt = P->bsrc[k] + b->nrows[k] * (int64_t)b->rank[k];
     return Wt[j + (int64_t)t.l * b->ncols[k]] / t.div_w;
   };
 
@@ -833,7 +853,7 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
   auto panel_value = [&](const std::pair<int64_t, int32_t> &src, int64_t row) {
     if (src.first < 0) return 0.0;
     const int64_t k = src.first;
-    if (b->kind[k] == HMAT_DENSE) return b->data[b->offset[k] + (row - b->row0[k]) + (int64_t)src.second * b->nrows[k]];
+    if (b->kind[k] == HMAT_DENSE) return P->bsrc[k][(row - b->row0[k]) + (int64_t)src.second * b->nrows[k]];
     return vval(k, P->terms[k][src.second], row - b->row0[k]);
   };
   if (P->mr) {
@@ -919,7 +939,7 @@ int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
             if (src.first >= 0) {
               const int64_t k = src.first;
               if (b->kind[k] == HMAT_DENSE)
-                v = b->data[b->offset[k] + (row - b->row0[k]) + (int64_t)src.second * b->nrows[k]];
+                v = P->bsrc[k][(row - b->row0[k]) + (int64_t)src.second * b->nrows[k]];
               else
                 v = vval(k, P->terms[k][src.second], row - b->row0[k]);
             }
