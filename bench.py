@@ -85,7 +85,11 @@ def assemble(args, mesh, W):
     from paper_1911_00093_amd import hmat
 
     if args.assembly == "gpu":
-        return hmat.hmat_assemble_bem_gpu(mesh.centroids, mesh.areas, leaf=W["leaf"], eta=W["eta"], eps=W["eps"])
+        try:
+            return hmat.hmat_assemble_bem_gpu(mesh.centroids, mesh.areas, leaf=W["leaf"], eta=W["eta"],
+                                              eps=W["eps"])
+        except hmat.HmatError as e:  # setup only (the same matrix either way): say so and go on
+            log(f"[setup] GPU assembly failed ({e}); using the host builder")
     return hmat.hmat_assemble_bem(mesh.centroids, mesh.areas, leaf=W["leaf"], eta=W["eta"], eps=W["eps"])
 
 

@@ -55,6 +55,35 @@ def test_fullsize_gpu_assembly_identical():
     assert bs.stats["host_blocks"] == 0
 
 
+def test_fullsize_dense_split_parity():
+    """Method 3 with the dense leaves split (c = 0) on plates-128: the
+    library's product equals the oracle's on the same split."""
+    need_gpu()
+    d = c2()
+    h = d["h"]
+    H = hmat.HMatrix(blockset(h), oracle.M3, c=0, dense_split=True)
+    conv = oracle.Converted(h, oracle.M3, 0, dense_split=True)
+    for x, scale in zip(d["x"], d["scale"]):
+        err = np.abs(H.matvec(to_dev(x)).cpu().numpy() - conv.matvec(x)).max() / scale
+        print(f"M3 c=0 dense split: max |y - y_oracle| / max |A||x| = {err:.2e}")
+        assert err <= tolerance(oracle.M3)
+    del conv, H
+
+
+def test_fullsize_gpu_assembly_largest_ellipsoid():
+    """The largest mesh of the 64-ellipsoid batch (frequency 44, N = 38,720,
+    leaf 32, ACA 1e-6) through the GPU setup builder: identical to the
+    oracle's assembly."""
+    need_gpu()
+    ms = meshes.random_ellipsoids(64, seed=0)
+    m = max(ms, key=lambda q: q.centroids.shape[0])
+    h = oracle.HMatrix(m.centroids, m.areas, leaf=32, eta=2.0, eps=1e-6)
+    bs = hmat.hmat_assemble_bem_gpu(m.centroids, m.areas, leaf=32, eta=2.0, eps=1e-6)
+    print(f"n={h.n}, blocks={h.nblocks}:", bs.stats)
+    for f in ("perm", "row0", "nrows", "col0", "ncols", "kind", "rank", "offset", "data"):
+        assert np.array_equal(getattr(bs, f), getattr(h, f)), f
+
+
 @pytest.mark.parametrize("variant", range(8))
 def test_fullsize_matvec_parity(variant):
     need_gpu()
