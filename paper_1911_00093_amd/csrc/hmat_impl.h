@@ -214,7 +214,21 @@ int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *
 // Packed object, then plan it (pack.cpp).
 int plan_batched(const hmat_blocks *systems, int64_t count, const hmat_build_opts *o, hmat_plan_info *info,
                  Packed **out_keep);
-int pack_into(Packed *p, std::vector<unsigned char> &staging, hmat_s *h);
+// Host staging of a device image: left uninitialised by alloc (pack_into
+// zeroes it on the host threads), in transparent huge pages where the kernel
+// allows, so a multi-GB image costs no single-threaded zero fill.
+struct HostImage {
+  unsigned char *p = nullptr;
+  uint64_t n = 0;
+  HostImage() = default;
+  HostImage(const HostImage &) = delete;
+  HostImage &operator=(const HostImage &) = delete;
+  ~HostImage();
+  bool alloc(uint64_t bytes);  // false when out of memory
+  unsigned char *data() { return p; }
+  uint64_t size() const { return n; }
+};
+int pack_into(Packed *p, HostImage &staging, hmat_s *h);
 void packed_free(Packed *p);
 XcdSplit xcd_split(const std::vector<double> &cost);
 

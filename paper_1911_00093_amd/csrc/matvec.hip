@@ -592,7 +592,7 @@ static int build_planned(Packed *P, const hmat_plan_info &info, void *dev_mem, u
     packed_free(P);
     return fail(HMAT_E_NOMEM, "handle allocation failed");
   }
-  std::vector<unsigned char> img;
+  HostImage img;
   int rc = pack_into(P, img, h);
   packed_free(P);
   if (rc) {

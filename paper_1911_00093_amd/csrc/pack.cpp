@@ -16,10 +16,13 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <thread>
 #include <tuple>
+
+#include <sys/mman.h>
 
 #include "hmat_impl.h"
 
@@ -809,14 +812,38 @@ int plan_batched(const hmat_blocks *sys, int64_t count, const hmat_build_opts *o
 
 
 // Fill the staging image of the device buffer.
-int pack_into(Packed *P, std::vector<unsigned char> &img, hmat_s *h) {
+HostImage::~HostImage() { std::free(p); }
+
+bool HostImage::alloc(uint64_t bytes) {
+  std::free(p);
+  p = nullptr;
+  n = 0;
+  const size_t huge = size_t(2) << 20;
+  const size_t sz = (std::max<uint64_t>(bytes, 1) + huge - 1) / huge * huge;
+  void *q = std::aligned_alloc(huge, sz);
+  if (!q) return false;
+  (void)madvise(q, sz, MADV_HUGEPAGE);  // advisory only
+  p = (unsigned char *)q;
+  n = bytes;
+  return true;
+}
+
+int pack_into(Packed *P, HostImage &img, hmat_s *h) {
   const hmat_blocks *b = &P->b;
   const DevLayout &L = P->lay;
   const int64_t n = b->n;
-  try {
-    img.assign(L.ws_begin, 0);  // the workspace after it needs no initial contents
-  } catch (...) {
+  // the packed part of the image starts zeroed (padding, compact tiles); the
+  // workspace after it needs no initial contents
+  if (!img.alloc(L.ws_begin))
     return fail(HMAT_E_NOMEM, "cannot allocate %llu bytes of host staging", (unsigned long long)L.ws_begin);
+  {
+    constexpr uint64_t kPiece = uint64_t(64) << 20;
+    unsigned char *z = img.data();
+    const uint64_t total = L.ws_begin;
+    parallel_for((int64_t)((total + kPiece - 1) / kPiece), [z, total](int64_t q) {
+      const uint64_t lo = (uint64_t)q * kPiece, hi = std::min(total, lo + kPiece);
+      std::memset(z + lo, 0, hi - lo);
+    });
   }
   unsigned char *base = img.data();
   auto put = [base, &L](int cls, int64_t idx, double v) {
