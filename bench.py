@@ -373,10 +373,17 @@ def bench_batched(args, W, variant, dev, stream):
     nsys, nrhs = W["nsys"], W["nrhs"]
     t0 = time.time()
     ms = meshes.random_ellipsoids(nsys, seed=0)
-    bss = [assemble(args, m, W) for m in ms]
+    if args.assembly == "gpu":
+        try:
+            bss = hmat.hmat_assemble_bem_gpu_batched(ms, leaf=W["leaf"], eta=W["eta"], eps=W["eps"])
+        except hmat.HmatError as e:  # setup only (the same matrices either way): say so and go on
+            log(f"[setup] GPU assembly failed ({e}); using the host builder")
+            args.assembly = "host"
+    if args.assembly != "gpu":
+        bss = [assemble(args, m, W) for m in ms]
     n = sum(b.n for b in bss)
     log(f"[setup] {args.workload}: {nsys} meshes, n={n}, blocks={sum(b.nblocks for b in bss)}, "
-        f"assembly {time.time() - t0:.1f}s")
+        f"meshes + assembly {time.time() - t0:.1f}s; {assembly_note(bss[0])} (batch)")
     t0 = time.time()
     Hm = hmat.HMatrix(bss, variant, c=-1, nrhs_max=nrhs)
     H64 = hmat.HMatrix(bss, hmat.M1_DOUBLE, nrhs_max=nrhs)

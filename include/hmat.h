@@ -431,6 +431,18 @@ int hmat_assemble_bem(int64_t n, const double *centroids, const double *areas, c
 int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const double *areas, const hmat_assemble_opts *opts,
                           int32_t rank_cap, void *stream, hmat_assembly_t *out);
 
+/* Several meshes at once (independent systems, e.g. the systems of a
+ * batched build): mesh s has n[s] panels, centroids[s] (n[s] x 3 row-major)
+ * and areas[s], all host; out[s] receives its assembly, the same, bit for
+ * bit, as hmat_assemble_bem_gpu (and hmat_assemble_bem) gives for that mesh
+ * alone.  The meshes' admissible blocks share one ACA launch and their blocks
+ * one emit launch, so small meshes fill the GPU together.  Each handle's
+ * stats report its own block counts and the batch's phase times.  On error
+ * every out[s] is null. */
+int hmat_assemble_bem_gpu_batched(int64_t count, const int64_t *n, const double *const *centroids,
+                                  const double *const *areas, const hmat_assemble_opts *opts, int32_t rank_cap,
+                                  void *stream, hmat_assembly_t *out);
+
 /* What an assembly did (either path). */
 typedef struct {
     int64_t blocks;          /* blocks of the partition */

@@ -353,54 +353,6 @@ struct DevBufs {
   }
 };
 
-// Device-to-host copy of n doubles into pageable memory: the DMA engine fills
-// two pinned staging buffers in turn while host threads move the previous
-// chunk out (a single pageable copy runs at about a fifth of the link rate).
-hipError_t download(double *dst, const double *src, int64_t n, hipStream_t st) {
-  constexpr int64_t kChunk = int64_t(32) << 20;  // doubles (256 MB)
-  if (n <= 0) return hipSuccess;
-  const int64_t len = std::min(n, kChunk);
-  double *stage[2] = {nullptr, nullptr};
-  hipEvent_t done[2] = {nullptr, nullptr};
-  hipError_t e = hipSuccess;
-  auto cleanup = [&]() {
-    for (int b = 0; b < 2; b++) {
-      if (stage[b]) (void)hipHostFree(stage[b]);
-      if (done[b]) (void)hipEventDestroy(done[b]);
-    }
-  };
-  for (int b = 0; b < 2 && e == hipSuccess; b++) {
-    e = hipHostMalloc((void **)&stage[b], len * sizeof(double), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&done[b], hipEventDisableTiming);
-  }
-  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  const int64_t nchunks = (n + len - 1) / len;
-  auto issue = [&](int64_t c) {
-    const int64_t off = c * len, cnt = std::min(len, n - off);
-    hipError_t r = hipMemcpyAsync(stage[c % 2], src + off, cnt * sizeof(double), hipMemcpyDeviceToHost, st);
-    if (r == hipSuccess) r = hipEventRecord(done[c % 2], st);
-    return r;
-  };
-  if (e == hipSuccess) e = issue(0);
-  for (int64_t c = 0; c < nchunks && e == hipSuccess; c++) {
-    if (c + 1 < nchunks) e = issue(c + 1);
-    if (e == hipSuccess) e = hipEventSynchronize(done[c % 2]);
-    if (e != hipSuccess) break;
-    const int64_t off = c * len, cnt = std::min(len, n - off);
-    const double *from = stage[c % 2];
-    std::vector<std::thread> th;
-    const int64_t part = (cnt + nt - 1) / nt;
-    for (int t = 0; t < nt; t++) {
-      const int64_t lo = t * part, hi = std::min(cnt, lo + part);
-      if (lo >= hi) break;
-      th.emplace_back([=]() { std::memcpy(dst + off + lo, from + lo, (hi - lo) * sizeof(double)); });
-    }
-    for (auto &x : th) x.join();
-  }
-  cleanup();
-  return e;
-}
-
 struct SideStream {  // default priority
   hipStream_t s = nullptr;
   ~SideStream() {
@@ -428,48 +380,134 @@ struct Events {
   } while (0)
 
 namespace hm {
-static int assemble_gpu(int64_t n, const double *centroids, const double *areas, const hmat_assemble_opts *opts,
-                        int32_t rank_cap, void *stream, hmat_assembly_t *out) {
+// Copy out of a contiguous device range [0, total) whose pieces belong to
+// several host buffers: piece s is [start[s], start[s + 1]) and goes to dst[s].
+// The DMA engine fills two pinned staging buffers in turn while host threads
+// move the previous chunk out (one pageable copy runs at about a fifth of the
+// link rate).
+static hipError_t download_pieces(const std::vector<double *> &dst, const std::vector<int64_t> &start,
+                                  const double *src, hipStream_t st) {
+  constexpr int64_t kChunk = int64_t(32) << 20;  // doubles (256 MB)
+  const int64_t n = start.back();
+  if (n <= 0) return hipSuccess;
+  const int64_t len = std::min(n, kChunk);
+  double *stage[2] = {nullptr, nullptr};
+  hipEvent_t done[2] = {nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  for (int q = 0; q < 2 && e == hipSuccess; q++) {
+    e = hipHostMalloc((void **)&stage[q], len * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&done[q], hipEventDisableTiming);
+  }
+  // host copy of source range [lo, hi) out of the staging buffer holding [base, ...)
+  auto scatter = [&](const double *from, int64_t base, int64_t lo, int64_t hi) {
+    int64_t s = std::upper_bound(start.begin(), start.end(), lo) - start.begin() - 1;
+    while (lo < hi) {
+      const int64_t end = std::min(hi, start[s + 1]);
+      if (end > lo) std::memcpy(dst[s] + (lo - start[s]), from + (lo - base), (end - lo) * sizeof(double));
+      lo = end;
+      s++;
+    }
+  };
+  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int64_t nchunks = (n + len - 1) / len;
+  auto issue = [&](int64_t c) {
+    const int64_t off = c * len, cnt = std::min(len, n - off);
+    hipError_t r = hipMemcpyAsync(stage[c % 2], src + off, cnt * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (r == hipSuccess) r = hipEventRecord(done[c % 2], st);
+    return r;
+  };
+  if (e == hipSuccess) e = issue(0);
+  for (int64_t c = 0; c < nchunks && e == hipSuccess; c++) {
+    if (c + 1 < nchunks) e = issue(c + 1);
+    if (e == hipSuccess) e = hipEventSynchronize(done[c % 2]);
+    if (e != hipSuccess) break;
+    const int64_t off = c * len, cnt = std::min(len, n - off);
+    const double *from = stage[c % 2];
+    std::vector<std::thread> th;
+    const int64_t part = (cnt + nt - 1) / nt;
+    for (int t = 0; t < nt; t++) {
+      const int64_t lo = t * part, hi = std::min(cnt, lo + part);
+      if (lo >= hi) break;
+      th.emplace_back([&, lo, hi, off, from]() { scatter(from, off, off + lo, off + hi); });
+    }
+    for (auto &x : th) x.join();
+  }
+  for (int q = 0; q < 2; q++) {
+    if (stage[q]) (void)hipHostFree(stage[q]);
+    if (done[q]) (void)hipEventDestroy(done[q]);
+  }
+  return e;
+}
+
+// The meshes of a batch side by side: mesh s owns panels [noff[s], noff[s+1])
+// of one centroid / area array and blocks [boff[s], boff[s+1]) of one block
+// list (global indices), so one ACA launch and one emit launch serve all.
+static int assemble_gpu(int64_t count, const int64_t *nv, const double *const *cents, const double *const *areas,
+                        const hmat_assemble_opts *opts, int32_t rank_cap, void *stream, hmat_assembly_t *out) {
   using clk = std::chrono::steady_clock;
   auto ms = [](clk::time_point x, clk::time_point y) { return std::chrono::duration<double, std::milli>(y - x).count(); };
-  if (!out) return fail(HMAT_E_ARG, "null output");
-  *out = nullptr;
-  if (n <= 0 || n >= INT_MAX || !centroids || !areas || !opts) return fail(HMAT_E_ARG, "bad arguments");
+  if (!out || count < 1 || !nv || !cents || !areas || !opts) return fail(HMAT_E_ARG, "bad arguments");
+  for (int64_t s = 0; s < count; s++) out[s] = nullptr;
+  int64_t ntot = 0;
+  for (int64_t s = 0; s < count; s++) {
+    if (nv[s] <= 0 || !cents[s] || !areas[s]) return fail(HMAT_E_ARG, "mesh %lld: bad arguments", (long long)s);
+    ntot += nv[s];
+  }
+  if (ntot >= INT_MAX) return fail(HMAT_E_ARG, "too many panels in one batch");
   if (opts->leaf < 1 || !(opts->eta > 0) || !(opts->eps > 0)) return fail(HMAT_E_ARG, "bad assembly options");
   if (rank_cap == 0) rank_cap = kADefaultCap;
   if (rank_cap < 1 || rank_cap > kAMaxCap) return fail(HMAT_E_ARG, "rank_cap %d outside 1..%d", rank_cap, kAMaxCap);
   hipStream_t st = (hipStream_t)stream;
   const auto t0 = clk::now();
-  BemPartition P;
-  std::vector<int32_t> kind, rank, status;
-  std::vector<int64_t> offset;
-  std::vector<std::vector<double>> hostdata;
-  int64_t total = 0;
-  hmat_assembly_stats S{};
-  S.rank_cap = rank_cap;
-  bem_partition(n, centroids, areas, *opts, P);
+  // partitions, one host thread per mesh at a time
+  std::vector<BemPartition> P(count);
+  {
+    std::atomic<int64_t> next{0};
+    auto work = [&]() {
+      for (int64_t s; (s = next.fetch_add(1)) < count;) bem_partition(nv[s], cents[s], areas[s], *opts, P[s]);
+    };
+    const int nt = (int)std::min<int64_t>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())), count);
+    std::vector<std::thread> th;
+    for (int i = 1; i < nt; i++) th.emplace_back(work);
+    work();
+    for (auto &x : th) x.join();
+  }
   const auto t1 = clk::now();
-  const int64_t nb = (int64_t)P.row0.size();
-  S.blocks = nb;
+  std::vector<int64_t> noff(count + 1, 0), boff(count + 1, 0);
+  for (int64_t s = 0; s < count; s++) {
+    noff[s + 1] = noff[s] + nv[s];
+    boff[s + 1] = boff[s] + (int64_t)P[s].row0.size();
+  }
+  const int64_t nb = boff[count];
+  std::vector<int32_t> bmesh(nb);
+  for (int64_t s = 0; s < count; s++)
+    for (int64_t g = boff[s]; g < boff[s + 1]; g++) bmesh[g] = (int32_t)s;
+  auto lb = [&](int64_t g) { return g - boff[bmesh[g]]; };  // local block index
+  auto rows = [&](int64_t g) { return P[bmesh[g]].nrows[lb(g)]; };
+  auto cols = [&](int64_t g) { return P[bmesh[g]].ncols[lb(g)]; };
+  std::vector<double> call(3 * ntot), aall(ntot);
+  for (int64_t s = 0; s < count; s++) {
+    std::memcpy(call.data() + 3 * noff[s], P[s].c.data(), 3 * nv[s] * sizeof(double));
+    std::memcpy(aall.data() + noff[s], P[s].a.data(), nv[s] * sizeof(double));
+  }
 
   // admissible blocks, longest first (the sequential sums grow with m + nc)
   std::vector<int64_t> adm;
-  for (int64_t b = 0; b < nb; b++)
-    if (P.admissible[b]) adm.push_back(b);
-  std::stable_sort(adm.begin(), adm.end(),
-                   [&](int64_t x, int64_t y) { return P.nrows[x] + P.ncols[x] > P.nrows[y] + P.ncols[y]; });
+  for (int64_t g = 0; g < nb; g++)
+    if (P[bmesh[g]].admissible[lb(g)]) adm.push_back(g);
+  std::stable_sort(adm.begin(), adm.end(), [&](int64_t x, int64_t y) { return rows(x) + cols(x) > rows(y) + cols(y); });
   const int64_t na = (int64_t)adm.size();
   std::vector<AcaDesc> ad(na);
   std::vector<int64_t> slot(nb, -1);
   int64_t ws_len = 0, fl_len = 0;
   for (int64_t q = 0; q < na; q++) {
-    const int64_t b = adm[q], m = P.nrows[b], nc = P.ncols[b];
+    const int64_t g = adm[q], s = bmesh[g], b = lb(g), m = rows(g), nc = cols(g);
     const int64_t kd = (m * nc + m + nc - 1) / (m + nc);
     const int32_t cap = (int32_t)std::min<int64_t>(rank_cap, kd);
-    ad[q] = AcaDesc{P.row0[b], P.col0[b], ws_len, fl_len, (int32_t)m, (int32_t)nc, cap, 0};
+    ad[q] = AcaDesc{P[s].row0[b] + noff[s], P[s].col0[b] + noff[s], ws_len, fl_len, (int32_t)m, (int32_t)nc, cap, 0};
     ws_len += (m + nc) * cap;
     fl_len += m;
-    slot[b] = q;
+    slot[g] = q;
   }
 
   DevBufs buf;
@@ -478,8 +516,8 @@ static int assemble_gpu(int64_t n, const double *centroids, const double *areas,
   unsigned char *d_fl;
   AcaDesc *d_ad;
   int32_t *d_rank, *d_status;
-  HM_TRY(buf.get(&d_c, 3 * n * sizeof(double)), "device centroids");
-  HM_TRY(buf.get(&d_a, n * sizeof(double)), "device areas");
+  HM_TRY(buf.get(&d_c, 3 * ntot * sizeof(double)), "device centroids");
+  HM_TRY(buf.get(&d_a, ntot * sizeof(double)), "device areas");
   HM_TRY(buf.get(&d_ws, ws_len * sizeof(double)), "ACA scratch");
   HM_TRY(buf.get(&d_fl, fl_len), "ACA pivot flags");
   HM_TRY(buf.get(&d_ad, na * sizeof(AcaDesc)), "ACA descriptors");
@@ -488,8 +526,8 @@ static int assemble_gpu(int64_t n, const double *centroids, const double *areas,
   for (int i = 0; i < 5; i++) HM_TRY(hipEventCreate(&ev.e[i]), "event");
   SideStream side;
   HM_TRY(hipStreamCreateWithFlags(&side.s, hipStreamNonBlocking), "stream");
-  HM_TRY(hipMemcpyAsync(d_c, P.c.data(), 3 * n * sizeof(double), hipMemcpyHostToDevice, st), "upload");
-  HM_TRY(hipMemcpyAsync(d_a, P.a.data(), n * sizeof(double), hipMemcpyHostToDevice, st), "upload");
+  HM_TRY(hipMemcpyAsync(d_c, call.data(), 3 * ntot * sizeof(double), hipMemcpyHostToDevice, st), "upload");
+  HM_TRY(hipMemcpyAsync(d_a, aall.data(), ntot * sizeof(double), hipMemcpyHostToDevice, st), "upload");
   if (na) HM_TRY(hipMemcpyAsync(d_ad, ad.data(), na * sizeof(AcaDesc), hipMemcpyHostToDevice, st), "upload");
   HM_TRY(hipEventRecord(ev.e[0], st), "event");
   const auto tu = clk::now();
@@ -498,14 +536,14 @@ static int assemble_gpu(int64_t n, const double *centroids, const double *areas,
   while (nbig < na && (int64_t)ad[nbig].m + ad[nbig].nc >= 2048) nbig++;
   if (nbig) {
     HM_TRY(hipStreamWaitEvent(side.s, ev.e[0], 0), "stream wait");
-    hipLaunchKernelGGL((k_aca<4, kATileLong>), dim3((unsigned)nbig), dim3(kAThreads), 0, side.s, d_ad, d_c, d_a, d_ws, d_fl, P.eps,
-                       d_rank, d_status);
+    hipLaunchKernelGGL((k_aca<4, kATileLong>), dim3((unsigned)nbig), dim3(kAThreads), 0, side.s, d_ad, d_c, d_a, d_ws,
+                       d_fl, opts->eps, d_rank, d_status);
     HM_TRY(hipGetLastError(), "k_aca launch");
     HM_TRY(hipEventRecord(ev.e[4], side.s), "event");
   }
   if (na > nbig) {
-    hipLaunchKernelGGL((k_aca<1, kATileSmall>), dim3((unsigned)(na - nbig)), dim3(kAThreads), 0, st, d_ad + nbig, d_c, d_a, d_ws,
-                       d_fl, P.eps, d_rank + nbig, d_status + nbig);
+    hipLaunchKernelGGL((k_aca<1, kATileSmall>), dim3((unsigned)(na - nbig)), dim3(kAThreads), 0, st, d_ad + nbig, d_c,
+                       d_a, d_ws, d_fl, opts->eps, d_rank + nbig, d_status + nbig);
     HM_TRY(hipGetLastError(), "k_aca launch");
   }
   if (nbig) HM_TRY(hipStreamWaitEvent(st, ev.e[4], 0), "stream wait");
@@ -517,21 +555,18 @@ static int assemble_gpu(int64_t n, const double *centroids, const double *areas,
   }
   HM_TRY(hipStreamSynchronize(st), "k_aca");
 
+  // blocks the device did not finish: the host builder, threaded
+  std::vector<int64_t> redo;
+  for (int64_t q = 0; q < na; q++)
+    if (astat[q] == 2) redo.push_back(adm[q]);
+  std::vector<int32_t> kind(nb, 0), rank(nb, 0);
+  std::vector<std::vector<double>> hostdata(nb);
   {
-    // blocks the device did not finish: the host builder, threaded
-    std::vector<int64_t> redo;
-    for (int64_t q = 0; q < na; q++)
-      if (astat[q] == 2) redo.push_back(adm[q]);
-    kind.assign(nb, 0);
-    rank.assign(nb, 0);
-    hostdata.resize(nb);
     std::atomic<int64_t> next{0};
     auto work = [&]() {
-      for (;;) {
-        const int64_t q = next.fetch_add(1);
-        if (q >= (int64_t)redo.size()) break;
-        const int64_t b = redo[q];
-        bem_fill_host(P, b, &kind[b], &rank[b], hostdata[b]);
+      for (int64_t q; (q = next.fetch_add(1)) < (int64_t)redo.size();) {
+        const int64_t g = redo[q];
+        bem_fill_host(P[bmesh[g]], lb(g), &kind[g], &rank[g], hostdata[g]);
       }
     };
     const int nt = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), (int64_t)redo.size());
@@ -539,70 +574,91 @@ static int assemble_gpu(int64_t n, const double *centroids, const double *areas,
     for (int i = 1; i < nt; i++) th.emplace_back(work);
     if (!redo.empty()) work();
     for (auto &x : th) x.join();
-    S.host_blocks = (int64_t)redo.size();
+  }
 
-    std::vector<EmitDesc> ed(nb);
-    offset.resize(nb);
-    for (int64_t b = 0; b < nb; b++) {
-      const int64_t m = P.nrows[b], nc = P.ncols[b], q = slot[b];
-      EmitDesc e{P.row0[b], P.col0[b], total, 0, (int32_t)m, (int32_t)nc, 0, 0, 0, 0};
-      if (q >= 0 && astat[q] == 2) {
-        e.mode = 2;
-      } else if (q >= 0 && astat[q] == 0) {
-        kind[b] = 1;
-        rank[b] = arank[q];
-        e.mode = 1;
-        e.rank = arank[q];
-        e.cap = ad[q].cap;
-        e.u_off = ad[q].u_off;
-      }
-      if (e.mode == 0 && m * nc >= INT_MAX) return fail(HMAT_E_ARG, "dense block too large");
-      ed[b] = e;
-      offset[b] = total;
-      total += e.mode == 2 ? (int64_t)hostdata[b].size() : (kind[b] == 1 ? (m + nc) * rank[b] : m * nc);
+  // every block's place in the output: mesh by mesh, block by block
+  std::vector<EmitDesc> ed(nb);
+  std::vector<int64_t> offset(nb), mstart(count + 1, 0);
+  int64_t total = 0;
+  for (int64_t g = 0; g < nb; g++) {
+    const int64_t s = bmesh[g], b = lb(g), m = rows(g), nc = cols(g), q = slot[g];
+    if (b == 0) mstart[s] = total;
+    EmitDesc e{P[s].row0[b] + noff[s], P[s].col0[b] + noff[s], total, 0, (int32_t)m, (int32_t)nc, 0, 0, 0, 0};
+    if (q >= 0 && astat[q] == 2) {
+      e.mode = 2;
+    } else if (q >= 0 && astat[q] == 0) {
+      kind[g] = 1;
+      rank[g] = arank[q];
+      e.mode = 1;
+      e.rank = arank[q];
+      e.cap = ad[q].cap;
+      e.u_off = ad[q].u_off;
     }
-    EmitDesc *d_ed;
-    double *d_out;
-    HM_TRY(buf.get(&d_ed, nb * sizeof(EmitDesc)), "emit descriptors");
-    HM_TRY(buf.get(&d_out, total * sizeof(double)), "assembly output");
-    HM_TRY(hipMemcpyAsync(d_ed, ed.data(), nb * sizeof(EmitDesc), hipMemcpyHostToDevice, st), "upload");
-    HM_TRY(hipEventRecord(ev.e[2], st), "event");
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kAThreads), 0, st, d_ed, d_c, d_a, d_ws, d_out);
-    HM_TRY(hipGetLastError(), "k_emit launch");
-    HM_TRY(hipEventRecord(ev.e[3], st), "event");
-    S.device_bytes = (uint64_t)(3 * n + n + ws_len + total) * sizeof(double) + (uint64_t)fl_len +
-                     (uint64_t)na * (sizeof(AcaDesc) + 8) + (uint64_t)nb * sizeof(EmitDesc);
+    if (e.mode == 0 && m * nc >= INT_MAX) return fail(HMAT_E_ARG, "dense block too large");
+    ed[g] = e;
+    offset[g] = total - mstart[s];
+    total += e.mode == 2 ? (int64_t)hostdata[g].size() : (kind[g] == 1 ? (m + nc) * rank[g] : m * nc);
+  }
+  mstart[count] = total;
+  EmitDesc *d_ed;
+  double *d_out;
+  HM_TRY(buf.get(&d_ed, nb * sizeof(EmitDesc)), "emit descriptors");
+  HM_TRY(buf.get(&d_out, total * sizeof(double)), "assembly output");
+  HM_TRY(hipMemcpyAsync(d_ed, ed.data(), nb * sizeof(EmitDesc), hipMemcpyHostToDevice, st), "upload");
+  HM_TRY(hipEventRecord(ev.e[2], st), "event");
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)nb), dim3(kAThreads), 0, st, d_ed, d_c, d_a, d_ws, d_out);
+  HM_TRY(hipGetLastError(), "k_emit launch");
+  HM_TRY(hipEventRecord(ev.e[3], st), "event");
 
-    auto *R = new hmat_assembly_s();
-    std::unique_ptr<hmat_assembly_s> keep(R);
-    HM_TRY(hipStreamSynchronize(st), "k_emit");
-    const auto tc = clk::now();
-    if (!R->data.alloc(total)) return fail(HMAT_E_NOMEM, "out of host memory for the assembly");
-    HM_TRY(download(R->data.data(), d_out, total, st), "download");
-    S.ms_copy = ms(tc, clk::now());
-    for (int64_t b = 0; b < nb; b++)
-      if (ed[b].mode == 2) std::memcpy(R->data.data() + offset[b], hostdata[b].data(), hostdata[b].size() * 8);
-    float f1 = 0.f, f2 = 0.f;
-    HM_TRY(hipEventElapsedTime(&f1, ev.e[0], ev.e[1]), "event time");
-    HM_TRY(hipEventElapsedTime(&f2, ev.e[2], ev.e[3]), "event time");
-    S.ms_aca = f1;
-    S.ms_emit = f2;
-    R->n = n;
-    R->perm = std::move(P.perm);
-    R->row0 = std::move(P.row0);
-    R->nrows = std::move(P.nrows);
-    R->col0 = std::move(P.col0);
-    R->ncols = std::move(P.ncols);
-    R->kind = std::move(kind);
-    R->rank = std::move(rank);
-    R->offset = std::move(offset);
-    for (int64_t b = 0; b < nb; b++) S.lowrank += R->kind[b] == 1;
+  std::vector<std::unique_ptr<hmat_assembly_s>> R(count);
+  std::vector<double *> dst(count);
+  for (int64_t s = 0; s < count; s++) {
+    R[s].reset(new hmat_assembly_s());
+    if (!R[s]->data.alloc(mstart[s + 1] - mstart[s])) return fail(HMAT_E_NOMEM, "out of host memory for the assembly");
+    dst[s] = R[s]->data.data();
+  }
+  HM_TRY(hipStreamSynchronize(st), "k_emit");
+  const auto tc = clk::now();
+  HM_TRY(download_pieces(dst, mstart, d_out, st), "download");
+  const double ms_copy = ms(tc, clk::now());
+  for (int64_t g = 0; g < nb; g++)
+    if (ed[g].mode == 2)
+      std::memcpy(dst[bmesh[g]] + offset[g], hostdata[g].data(), hostdata[g].size() * sizeof(double));
+  float f1 = 0.f, f2 = 0.f;
+  HM_TRY(hipEventElapsedTime(&f1, ev.e[0], ev.e[1]), "event time");
+  HM_TRY(hipEventElapsedTime(&f2, ev.e[2], ev.e[3]), "event time");
+  const uint64_t dev_bytes = (uint64_t)(4 * ntot + ws_len + total) * sizeof(double) + (uint64_t)fl_len +
+                             (uint64_t)na * (sizeof(AcaDesc) + 8) + (uint64_t)nb * sizeof(EmitDesc);
+  const double ms_fill = ms(t1, clk::now());
+  for (int64_t s = 0; s < count; s++) {
+    hmat_assembly_s &A = *R[s];
+    hmat_assembly_stats S{};
+    S.rank_cap = rank_cap;
+    S.blocks = boff[s + 1] - boff[s];
+    for (int64_t g = boff[s]; g < boff[s + 1]; g++) {
+      S.lowrank += kind[g] == 1;
+      S.host_blocks += slot[g] >= 0 && astat[slot[g]] == 2;
+    }
+    // the batch's phases, shared by its meshes
+    S.device_bytes = dev_bytes;
     S.ms_partition = ms(t0, t1);
     S.ms_upload = ms(t1, tu);
-    S.ms_fill = ms(t1, clk::now());
-    R->stats = S;
-    *out = keep.release();
+    S.ms_aca = f1;
+    S.ms_emit = f2;
+    S.ms_copy = ms_copy;
+    S.ms_fill = ms_fill;
+    A.n = nv[s];
+    A.perm = std::move(P[s].perm);
+    A.row0 = std::move(P[s].row0);
+    A.nrows = std::move(P[s].nrows);
+    A.col0 = std::move(P[s].col0);
+    A.ncols = std::move(P[s].ncols);
+    A.kind.assign(kind.begin() + boff[s], kind.begin() + boff[s + 1]);
+    A.rank.assign(rank.begin() + boff[s], rank.begin() + boff[s + 1]);
+    A.offset.assign(offset.begin() + boff[s], offset.begin() + boff[s + 1]);
+    A.stats = S;
   }
+  for (int64_t s = 0; s < count; s++) out[s] = R[s].release();
   return HMAT_OK;
 }
 }  // namespace hm
@@ -610,8 +666,23 @@ static int assemble_gpu(int64_t n, const double *centroids, const double *areas,
 extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const double *areas,
                                      const hmat_assemble_opts *opts, int32_t rank_cap, void *stream,
                                      hmat_assembly_t *out) {
+  if (!out) return hm::fail(HMAT_E_ARG, "null output");
+  *out = nullptr;
+  if (n <= 0 || n >= INT_MAX || !centroids || !areas || !opts) return hm::fail(HMAT_E_ARG, "bad arguments");
   try {
-    return hm::assemble_gpu(n, centroids, areas, opts, rank_cap, stream, out);
+    return hm::assemble_gpu(1, &n, &centroids, &areas, opts, rank_cap, stream, out);
+  } catch (const std::bad_alloc &) {
+    return hm::fail(HMAT_E_NOMEM, "out of host memory during assembly");
+  } catch (const std::exception &x) {  // e.g. no thread could be started
+    return hm::fail(HMAT_E_NOMEM, "host resources exhausted during assembly: %s", x.what());
+  }
+}
+
+extern "C" int hmat_assemble_bem_gpu_batched(int64_t count, const int64_t *n, const double *const *centroids,
+                                             const double *const *areas, const hmat_assemble_opts *opts,
+                                             int32_t rank_cap, void *stream, hmat_assembly_t *out) {
+  try {
+    return hm::assemble_gpu(count, n, centroids, areas, opts, rank_cap, stream, out);
   } catch (const std::bad_alloc &) {
     return hm::fail(HMAT_E_NOMEM, "out of host memory during assembly");
   } catch (const std::exception &x) {  // e.g. no thread could be started

@@ -32,7 +32,8 @@ EXPORTED = [
     "hmat_last_error", "hmat_plan", "hmat_build", "hmat_matvec", "hmat_destroy", "hmat_get_stats",
     "hmat_precond_plan", "hmat_precond_create", "hmat_precond_apply", "hmat_precond_destroy",
     "hmat_solver_workspace_bytes", "hmat_bicgstab", "hmat_gmres_workspace_bytes", "hmat_gmres",
-    "hmat_assemble_bem", "hmat_assemble_bem_gpu", "hmat_assembly_get_stats", "hmat_assembly_blocks",
+    "hmat_assemble_bem", "hmat_assemble_bem_gpu", "hmat_assemble_bem_gpu_batched", "hmat_assembly_get_stats",
+    "hmat_assembly_blocks",
     "hmat_assembly_perm", "hmat_assembly_free", "hmat_version", "hmat_set_profiling", "hmat_kernel_times",
     "hmat_stream_read", "hmat_stream_copy", "hmat_plan_batched", "hmat_build_batched", "hmat_system_offsets",
     "hmat_bicgstab_batched_workspace_bytes", "hmat_bicgstab_batched", "hmat_precond_create_learned",
@@ -141,6 +142,7 @@ def lib():
         "hmat_gmres": (C.c_int, [P, P, P, P, C.c_int32, P, P, P, U64, P]),
         "hmat_assemble_bem": (C.c_int, [I64, P, P, P, P]),
         "hmat_assemble_bem_gpu": (C.c_int, [I64, P, P, P, I32, P, P]),
+        "hmat_assemble_bem_gpu_batched": (C.c_int, [I64, P, P, P, P, I32, P, P]),
         "hmat_assembly_get_stats": (C.c_int, [P, P]),
         "hmat_assembly_blocks": (C.c_int, [P, P]),
         "hmat_assembly_perm": (C.POINTER(C.c_int64), [P]),
@@ -283,6 +285,22 @@ def hmat_assemble_bem_gpu(centroids, areas, leaf=64, eta=2.0, eps=1e-5, rank_cap
     _check(lib().hmat_assemble_bem_gpu(n, _p(cent), _p(area), C.byref(o), int(rank_cap), _stream_ptr(stream),
                                        C.byref(out)))
     return _assembly_blockset(out, n)
+
+
+def hmat_assemble_bem_gpu_batched(meshes, leaf=64, eta=2.0, eps=1e-5, rank_cap=0, stream=None) -> list:
+    """Setup on the GPU for several meshes at once ((centroids, areas) pairs or
+    objects with .centroids / .areas): one BlockSet per mesh, each identical
+    to what hmat_assemble_bem_gpu gives for that mesh alone."""
+    arrs = [_mesh_arrays(*((m.centroids, m.areas) if hasattr(m, "centroids") else m)) for m in meshes]
+    k = len(arrs)
+    ns = (C.c_int64 * k)(*[a[2] for a in arrs])
+    cps = (C.c_void_p * k)(*[a[0].ctypes.data for a in arrs])
+    aps = (C.c_void_p * k)(*[a[1].ctypes.data for a in arrs])
+    o = hmat_assemble_opts(int(leaf), float(eta), float(eps), 0, 0)
+    outs = (C.c_void_p * k)()
+    _check(lib().hmat_assemble_bem_gpu_batched(k, ns, cps, aps, C.byref(o), int(rank_cap), _stream_ptr(stream),
+                                               outs))
+    return [_assembly_blockset(C.c_void_p(outs[i]), arrs[i][2]) for i in range(k)]
 
 
 def hmat_plan(blocks: BlockSet, precision: int, c: int = 0, nrhs_max: int = 1, drop: int = 0,

@@ -76,3 +76,33 @@ def test_gpu_assembly_rejects_bad_arguments():
         with pytest.raises(hmat.HmatError) as e:
             hmat.hmat_assemble_bem_gpu(m.centroids, m.areas, **kw)
         assert e.value.code == hmat.HMAT_E_ARG
+
+
+@pytest.mark.parametrize("cap", [0, 3])
+def test_gpu_assembly_batched_meshes(cap):
+    """Several meshes in one call (one ACA and one emit launch for all): each
+    mesh's assembly identical to the oracle's for that mesh alone, with a
+    small rank cap too (host redo spread over the meshes)."""
+    need_gpu()
+    import oracle
+
+    specs = [(meshes.icosphere(2), 16, 1e-6), (meshes.parallel_plates(16, 0.1, True), 16, 1e-6),
+             (meshes.geodesic_ellipsoid(12, axes=(1.7, 0.8, 0.6)), 16, 1e-6), (meshes.icosphere(0), 16, 1e-6)]
+    ms = [sp[0] for sp in specs]
+    got = hmat.hmat_assemble_bem_gpu_batched(ms, leaf=16, eta=2.0, eps=1e-6, rank_cap=cap)
+    assert len(got) == len(ms)
+    for m, bs in zip(ms, got):
+        h = oracle.HMatrix(m.centroids, m.areas, leaf=16, eta=2.0, eps=1e-6)
+        same_as_oracle(bs, h)
+        assert bs.stats["blocks"] == h.nblocks and bs.stats["lowrank"] == int((h.kind == 1).sum())
+    if cap == 3:
+        assert sum(bs.stats["host_blocks"] for bs in got) > 0
+
+
+def test_gpu_assembly_batched_rejects_bad_arguments():
+    need_gpu()
+    m = meshes.icosphere(1)
+    with pytest.raises(hmat.HmatError):
+        hmat.hmat_assemble_bem_gpu_batched([m, (np.zeros((0, 3)), np.zeros(0))], leaf=16)
+    with pytest.raises(hmat.HmatError):
+        hmat.hmat_assemble_bem_gpu_batched([m], leaf=16, rank_cap=200)
