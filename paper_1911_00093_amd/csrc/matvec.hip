@@ -151,8 +151,10 @@ __device__ __forceinline__ void s1_item(const S1Item &it, const void *vals, cons
   }
 }
 
-// Persistent waves over a static round-robin of the size-sorted items:
-// wave g of G takes items g, g + G, g + 2G, ... (no atomics, no waiting).
+// One wave per item, the items in size order (largest first): the
+// hardware's dispatch of the workgroups balances the launch's end, which
+// measured 6-10% faster than persistent waves over a static round-robin.
+// The loop still covers any grid: wave g of G takes items g, g + G, ...
 template <int CLS>
 __global__ __launch_bounds__(256) void k_stage1(
     const S1Item *__restrict__ items, int64_t nitems, const void *__restrict__ vals, const double *__restrict__ x,
@@ -504,17 +506,17 @@ typedef void (*Stage1Fn)(const S1Item *, int64_t, const void *, const double *, 
                          const int32_t *);
 static Stage1Fn stage1_fn(int cls) { return cls == F64 ? k_stage1<F64> : cls == F32 ? k_stage1<F32> : k_stage1<BF16>; }
 
-// Persistent grid sizes: as many workgroups as fit on the device at once
-// (capped by the number of work units).
+// Grid sizes: stage 1 one wave per item (four per workgroup); stage 2 a
+// persistent grid, as many workgroups as fit on the device at once (capped
+// by the number of chunks), whose per-workgroup partials the fused inner
+// products reduce.
 int size_grids(hmat_s *h) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return fail(HMAT_E_HIP, "cannot query the device");
   for (int c = 0; c < NCLS; c++) {
     const int64_t cnt = h->item_end[c] - h->item_begin[c];
-    int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, stage1_fn(c), 256, 0) != hipSuccess || per < 1) per = 1;
-    h->grid1[c] = (int32_t)std::max<int64_t>(1, std::min<int64_t>((cnt + 3) / 4, (int64_t)per * cus));
+    h->grid1[c] = (int32_t)std::max<int64_t>(1, (cnt + 3) / 4);
   }
   int per = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, stage2_fn(h->cls_mask), kS2Threads, 0) != hipSuccess || per < 1) per = 1;
