@@ -394,7 +394,7 @@ def bench_batched(args, W, variant, dev, stream):
         info = H.autotune(reps=5)
         tune["fixed_ms"][name] = round(info["ms_fixed"], 4)
         tune["tuned_ms"][name] = round(info["ms_tuned"], 4)
-        tune["choice"][name] = {k: info[k] for k in ("stage1_batch", "stage1_half", "stage2_batch", "stage2_half")}
+        tune["choice"][name] = {k: info[k] for k in ("stage1_batch", "stage1_grid", "stage2_batch", "stage2_grid")}
     log(f"[setup] autotune {time.time() - t0:.1f}s: {tune}")
     stm, st64 = Hm.stats(), H64.stats()
     Bm, Bm2 = mr_product_bytes(stm, nrhs, variant)

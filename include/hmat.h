@@ -163,17 +163,18 @@ int hmat_matvec(hmat_t h, const double *x, double *y, int64_t nrhs, int64_t ld, 
 
 /* Tuning of a multi-right-hand-side handle (nrhs_max > 1; not from the
  * paper): for each stage-1 storage class and for stage 2, times every
- * choice of column blocks loaded per batch (1, 2, 4) and persistent grid
- * (full or half occupancy) on this handle's own blocks, and keeps the
- * fastest for later products.  x: device, n x min(16, nrhs_max) FP64
+ * choice of column blocks loaded per batch (1, 2, 4) and grid (persistent
+ * at full or half occupancy, or one wave per work unit) on this handle's
+ * own blocks, and keeps the fastest for later products.  x: device, n x min(16, nrhs_max) FP64
  * column-major (ld = n), the timing input; y (same shape) receives products.
  * reps: timed launches per choice (1 .. 1000).  Results are unchanged by the
  * choice (same arithmetic, same summation order).  Synchronises `stream`. */
 typedef struct {
     int32_t stage1_batch[3];  /* per storage class FP64 / FP32 / BF16 (0: no items) */
-    int32_t stage1_half[3];   /* 1: half-occupancy grid */
-    int32_t stage2_batch, stage2_half;
-    double ms_fixed;          /* one product with the default choice (batch 2, full grid) */
+    int32_t stage1_grid[3];   /* 0: persistent, 1: persistent at half occupancy, 2: one wave per item */
+    int32_t stage2_batch, stage2_grid;  /* grid as above, per output chunk */
+    double ms_fixed;          /* one product with the default choice (batch 2; stage 1
+                                 persistent, stage 2 one wave per chunk) */
     double ms_tuned;          /* one product with the chosen configuration */
 } hmat_tune_info;
 

@@ -191,7 +191,8 @@ struct hmat_s {
   double *src64 = nullptr;  // (n + zlen + 1) x 16, right-hand side fastest
   int32_t mr_grid1[hm::NCLS] = {0, 0, 0}, mr_grid2 = 0;
   int32_t mr_nb1[hm::NCLS] = {2, 2, 2}, mr_nb2 = 2;    // column blocks per load batch (1, 2, 4)
-  int32_t mr_half1[hm::NCLS] = {0, 0, 0}, mr_half2 = 0;  // 1: persistent grid at half occupancy
+  // grid modes (0 persistent, 1 persistent at half occupancy, 2 one wave per unit)
+  int32_t mr_mode1[hm::NCLS] = {0, 0, 0}, mr_mode2 = 2;
   hm::XcdSplit mr_split2{}, mr_split1[hm::NCLS]{};
   std::vector<int64_t> sys_off;  // system boundaries of a batched handle
   double *src = nullptr;    // nrhs_max x (n + zlen + 1)

@@ -334,18 +334,20 @@ int size_grids_mr(hmat_s *h) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return fail(HMAT_E_HIP, "cannot query the device");
-  // a multiple of 8 workgroups, at least 8: every XCD range has workgroups;
-  // full occupancy, or half of it when the tuner found that faster
-  auto groups = [&](int64_t units, const void *fn, int half) {
+  // a multiple of 8 workgroups, at least 8: every XCD range has workgroups.
+  // Grid mode 0: persistent at full occupancy; 1: persistent at half of it;
+  // 2: one wave per work unit (the dispatcher then balances the launch's end)
+  auto groups = [&](int64_t units, const void *fn, int mode) {
     int per = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kMRThreads, 0) != hipSuccess || per < 1) per = 1;
-    const int64_t slots = std::max<int64_t>(1, (int64_t)per * cus / (half ? 2 : 1));
-    const int64_t g = std::min<int64_t>((units + kMRWaves - 1) / kMRWaves, slots);
+    const int64_t slots = std::max<int64_t>(1, (int64_t)per * cus / (mode == 1 ? 2 : 1));
+    const int64_t need = (units + kMRWaves - 1) / kMRWaves;
+    const int64_t g = mode == 2 ? need : std::min<int64_t>(need, slots);
     return (int32_t)std::max<int64_t>(kXcds, (g + kXcds - 1) / kXcds * kXcds);
   };
   for (int c = 0; c < NCLS; c++)
-    h->mr_grid1[c] = groups(h->mr_nitems[c], (const void *)mr_stage1_fn(c, h->mr_nb1[c]), h->mr_half1[c]);
-  h->mr_grid2 = groups(h->nchunks, (const void *)mr_stage2_fn(h->cls_mask, h->mr_nb2), h->mr_half2);
+    h->mr_grid1[c] = groups(h->mr_nitems[c], (const void *)mr_stage1_fn(c, h->mr_nb1[c]), h->mr_mode1[c]);
+  h->mr_grid2 = groups(h->nchunks, (const void *)mr_stage2_fn(h->cls_mask, h->mr_nb2), h->mr_mode2);
   return HMAT_OK;
 }
 
@@ -425,11 +427,11 @@ extern "C" int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps,
     info->stage1_batch[c] = 0;
     if (h->mr_nitems[c] <= 0) continue;
     double best = 1e300;
-    int bnb = 2, bhalf = 0;
+    int bnb = 2, bmode = 0;
     for (int nb : nbs)
-      for (int half = 0; half < 2; half++) {
+      for (int mode = 0; mode < 3; mode++) {
         h->mr_nb1[c] = nb;
-        h->mr_half1[c] = half;
+        h->mr_mode1[c] = mode;
         if (size_grids_mr(h) != HMAT_OK) break;
         const double t = time_ms(st, reps, [&]() {
           hipLaunchKernelGGL(mr_stage1_fn(c, nb), dim3((unsigned)h->mr_grid1[c]), dim3(kMRThreads), 0, st,
@@ -439,23 +441,23 @@ extern "C" int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps,
         if (t >= 0 && t < best) {
           best = t;
           bnb = nb;
-          bhalf = half;
+          bmode = mode;
         }
       }
     h->mr_nb1[c] = bnb;
-    h->mr_half1[c] = bhalf;
+    h->mr_mode1[c] = bmode;
     info->stage1_batch[c] = bnb;
-    info->stage1_half[c] = bhalf;
+    info->stage1_grid[c] = bmode;
   }
   // stage 2 (z complete after one product)
   product();
   {
     double best = 1e300;
-    int bnb = 2, bhalf = 0;
+    int bnb = 2, bmode = 2;
     for (int nb : nbs)
-      for (int half = 0; half < 2; half++) {
+      for (int mode = 0; mode < 3; mode++) {
         h->mr_nb2 = nb;
-        h->mr_half2 = half;
+        h->mr_mode2 = mode;
         if (size_grids_mr(h) != HMAT_OK) break;
         const double t = time_ms(st, reps, [&]() {
           hipLaunchKernelGGL(mr_stage2_fn(h->cls_mask, nb), dim3((unsigned)h->mr_grid2), dim3(kMRThreads), 0, st,
@@ -466,13 +468,13 @@ extern "C" int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps,
         if (t >= 0 && t < best) {
           best = t;
           bnb = nb;
-          bhalf = half;
+          bmode = mode;
         }
       }
     h->mr_nb2 = bnb;
-    h->mr_half2 = bhalf;
+    h->mr_mode2 = bmode;
     info->stage2_batch = bnb;
-    info->stage2_half = bhalf;
+    info->stage2_grid = bmode;
   }
   int rc = size_grids_mr(h);
   if (rc == HMAT_OK) info->ms_tuned = time_ms(st, reps, product);

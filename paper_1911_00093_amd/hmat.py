@@ -88,8 +88,8 @@ class hmat_solve_info(C.Structure):
 
 
 class hmat_tune_info(C.Structure):
-    _fields_ = [("stage1_batch", C.c_int32 * 3), ("stage1_half", C.c_int32 * 3), ("stage2_batch", C.c_int32),
-                ("stage2_half", C.c_int32), ("ms_fixed", C.c_double), ("ms_tuned", C.c_double)]
+    _fields_ = [("stage1_batch", C.c_int32 * 3), ("stage1_grid", C.c_int32 * 3), ("stage2_batch", C.c_int32),
+                ("stage2_grid", C.c_int32), ("ms_fixed", C.c_double), ("ms_tuned", C.c_double)]
 
 
 class hmat_batch_result(C.Structure):
@@ -383,8 +383,8 @@ class HMatrix:
         info = hmat_tune_info()
         _check(lib().hmat_autotune(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), int(reps),
                                    C.byref(info), _stream_ptr(stream)))
-        return dict(stage1_batch=list(info.stage1_batch), stage1_half=list(info.stage1_half),
-                    stage2_batch=info.stage2_batch, stage2_half=info.stage2_half,
+        return dict(stage1_batch=list(info.stage1_batch), stage1_grid=list(info.stage1_grid),
+                    stage2_batch=info.stage2_batch, stage2_grid=info.stage2_grid,
                     ms_fixed=info.ms_fixed, ms_tuned=info.ms_tuned)
 
     def set_profiling(self, enable=True):
