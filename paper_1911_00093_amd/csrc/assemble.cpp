@@ -30,6 +30,7 @@
 
 #include "assemble_impl.h"
 #include "hmat_impl.h"
+#include "workers.h"
 
 namespace {
 
@@ -316,20 +317,10 @@ int hmat_assemble_bem(int64_t n, const double *centroids, const double *areas, c
     for (int64_t i = 0; i < nb; i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int64_t x, int64_t y) { return P.nrows[x] * P.ncols[x] > P.nrows[y] * P.ncols[y]; });
-    std::atomic<int64_t> next{0};
-    int nt = opts->threads > 0 ? opts->threads : (int)std::max(1u, std::thread::hardware_concurrency());
-    nt = (int)std::max<int64_t>(1, std::min<int64_t>(nt, nb));
-    auto work = [&]() {
-      for (;;) {
-        const int64_t q = next.fetch_add(1);
-        if (q >= nb) break;
-        hm::bem_fill_host(P, order[q], &kind[order[q]], &rank[order[q]], data[order[q]]);
-      }
-    };
-    std::vector<std::thread> th;
-    for (int i = 1; i < nt; i++) th.emplace_back(work);
-    work();
-    for (auto &x : th) x.join();
+    const int nt = opts->threads > 0 ? opts->threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    hm::parallel_items(nb, nt, [&](int64_t q) {
+      hm::bem_fill_host(P, order[q], &kind[order[q]], &rank[order[q]], data[order[q]]);
+    });
     auto *R = new hmat_assembly_s();
     R->n = n;
     R->perm = std::move(P.perm);
@@ -361,7 +352,7 @@ int hmat_assemble_bem(int64_t n, const double *centroids, const double *areas, c
     *out = R;
   } catch (const std::bad_alloc &) {
     return hm::fail(HMAT_E_NOMEM, "out of host memory during assembly");
-  } catch (const std::exception &x) {  // e.g. no thread could be started
+  } catch (const std::exception &x) {
     return hm::fail(HMAT_E_NOMEM, "host resources exhausted during assembly: %s", x.what());
   }
   return HMAT_OK;

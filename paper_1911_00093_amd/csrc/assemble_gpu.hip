@@ -32,6 +32,7 @@
 
 #include "assemble_impl.h"
 #include "hmat_impl.h"
+#include "workers.h"
 
 // Bit-identical to the host builder: no multiply-add contraction.
 #pragma clang fp contract(off)
@@ -408,7 +409,7 @@ static hipError_t download_pieces(const std::vector<double *> &dst, const std::v
       s++;
     }
   };
-  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int nt = host_threads();
   const int64_t nchunks = (n + len - 1) / len;
   auto issue = [&](int64_t c) {
     const int64_t off = c * len, cnt = std::min(len, n - off);
@@ -423,15 +424,14 @@ static hipError_t download_pieces(const std::vector<double *> &dst, const std::v
     if (e != hipSuccess) break;
     const int64_t off = c * len, cnt = std::min(len, n - off);
     const double *from = stage[c % 2];
-    std::vector<std::thread> th;
     const int64_t part = (cnt + nt - 1) / nt;
-    for (int t = 0; t < nt; t++) {
+    parallel_items((cnt + part - 1) / part, nt, [&](int64_t t) {
       const int64_t lo = t * part, hi = std::min(cnt, lo + part);
-      if (lo >= hi) break;
-      th.emplace_back([&, lo, hi, off, from]() { scatter(from, off, off + lo, off + hi); });
-    }
-    for (auto &x : th) x.join();
+      scatter(from, off, off + lo, off + hi);
+    });
   }
+  // a copy still in flight (error paths) must not land in freed memory
+  if (e != hipSuccess) (void)hipStreamSynchronize(st);
   for (int q = 0; q < 2; q++) {
     if (stage[q]) (void)hipHostFree(stage[q]);
     if (done[q]) (void)hipEventDestroy(done[q]);
@@ -461,17 +461,7 @@ static int assemble_gpu(int64_t count, const int64_t *nv, const double *const *c
   const auto t0 = clk::now();
   // partitions, one host thread per mesh at a time
   std::vector<BemPartition> P(count);
-  {
-    std::atomic<int64_t> next{0};
-    auto work = [&]() {
-      for (int64_t s; (s = next.fetch_add(1)) < count;) bem_partition(nv[s], cents[s], areas[s], *opts, P[s]);
-    };
-    const int nt = (int)std::min<int64_t>(std::max(1u, std::min(16u, std::thread::hardware_concurrency())), count);
-    std::vector<std::thread> th;
-    for (int i = 1; i < nt; i++) th.emplace_back(work);
-    work();
-    for (auto &x : th) x.join();
-  }
+  parallel_items(count, host_threads(), [&](int64_t s) { bem_partition(nv[s], cents[s], areas[s], *opts, P[s]); });
   const auto t1 = clk::now();
   std::vector<int64_t> noff(count + 1, 0), boff(count + 1, 0);
   for (int64_t s = 0; s < count; s++) {
@@ -561,20 +551,10 @@ static int assemble_gpu(int64_t count, const int64_t *nv, const double *const *c
     if (astat[q] == 2) redo.push_back(adm[q]);
   std::vector<int32_t> kind(nb, 0), rank(nb, 0);
   std::vector<std::vector<double>> hostdata(nb);
-  {
-    std::atomic<int64_t> next{0};
-    auto work = [&]() {
-      for (int64_t q; (q = next.fetch_add(1)) < (int64_t)redo.size();) {
-        const int64_t g = redo[q];
-        bem_fill_host(P[bmesh[g]], lb(g), &kind[g], &rank[g], hostdata[g]);
-      }
-    };
-    const int nt = (int)std::min<int64_t>(std::max(1u, std::thread::hardware_concurrency()), (int64_t)redo.size());
-    std::vector<std::thread> th;
-    for (int i = 1; i < nt; i++) th.emplace_back(work);
-    if (!redo.empty()) work();
-    for (auto &x : th) x.join();
-  }
+  parallel_items((int64_t)redo.size(), (int)std::max(1u, std::thread::hardware_concurrency()), [&](int64_t q) {
+    const int64_t g = redo[q];
+    bem_fill_host(P[bmesh[g]], lb(g), &kind[g], &rank[g], hostdata[g]);
+  });
 
   // every block's place in the output: mesh by mesh, block by block
   std::vector<EmitDesc> ed(nb);
@@ -673,7 +653,7 @@ extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const d
     return hm::assemble_gpu(1, &n, &centroids, &areas, opts, rank_cap, stream, out);
   } catch (const std::bad_alloc &) {
     return hm::fail(HMAT_E_NOMEM, "out of host memory during assembly");
-  } catch (const std::exception &x) {  // e.g. no thread could be started
+  } catch (const std::exception &x) {
     return hm::fail(HMAT_E_NOMEM, "host resources exhausted during assembly: %s", x.what());
   }
 }
@@ -685,7 +665,7 @@ extern "C" int hmat_assemble_bem_gpu_batched(int64_t count, const int64_t *n, co
     return hm::assemble_gpu(count, n, centroids, areas, opts, rank_cap, stream, out);
   } catch (const std::bad_alloc &) {
     return hm::fail(HMAT_E_NOMEM, "out of host memory during assembly");
-  } catch (const std::exception &x) {  // e.g. no thread could be started
+  } catch (const std::exception &x) {
     return hm::fail(HMAT_E_NOMEM, "host resources exhausted during assembly: %s", x.what());
   }
 }

@@ -2,6 +2,8 @@
 #pragma once
 
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -206,6 +208,19 @@ struct hmat_s {
 namespace hm {
 void set_error(const char *fmt, ...);
 int fail(int code, const char *fmt, ...);
+
+// Run a host step of an entry point; a host allocation or thread failure
+// inside it becomes HMAT_E_NOMEM instead of an exception crossing the C ABI.
+template <class F>
+int host_guarded(F f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc &) {
+    return fail(HMAT_E_NOMEM, "out of host memory");
+  } catch (const std::exception &x) {
+    return fail(HMAT_E_NOMEM, "host resources exhausted: %s", x.what());
+  }
+}
 
 // Host packer (pack.cpp): validation, conversion, layout and packing.
 struct Packed;

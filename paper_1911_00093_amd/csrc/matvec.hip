@@ -595,7 +595,7 @@ static int build_planned(Packed *P, const hmat_plan_info &info, void *dev_mem, u
     return fail(HMAT_E_NOMEM, "handle allocation failed");
   }
   HostImage img;
-  int rc = pack_into(P, img, h);
+  int rc = host_guarded([&]() { return pack_into(P, img, h); });
   packed_free(P);
   if (rc) {
     delete h;

@@ -19,12 +19,14 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <thread>
 #include <tuple>
 
 #include <sys/mman.h>
 
 #include "hmat_impl.h"
+#include "workers.h"
 
 namespace hm {
 
@@ -214,19 +216,7 @@ static double pow2_at_least(double m) {
 // Run f(i) for i in [0, count) on the host's threads (disjoint outputs).
 template <class F>
 static void parallel_for(int64_t count, F f) {
-  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  std::atomic<int64_t> next{0};
-  auto work = [&]() {
-    for (;;) {
-      const int64_t i = next.fetch_add(1);
-      if (i >= count) break;
-      f(i);
-    }
-  };
-  std::vector<std::thread> th;
-  for (int t = 1; t < nt && t < count; t++) th.emplace_back(work);
-  work();
-  for (auto &x : th) x.join();
+  parallel_items(count, host_threads(), f);
 }
 
 // block_src: per block, the address of its first value (plan_batched, whose
@@ -236,7 +226,7 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
 
 int plan_blocks(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *info, Packed **out_keep,
                 const int64_t *sys_off, int64_t nsys) {
-  return plan_blocks_src(b, o, info, out_keep, sys_off, nsys, nullptr);
+  return host_guarded([&]() { return plan_blocks_src(b, o, info, out_keep, sys_off, nsys, nullptr); });
 }
 
 static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_plan_info *info, Packed **out_keep,
@@ -275,7 +265,8 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
       return fail(HMAT_E_ARG, "block %lld: data range outside the data array", (long long)k);
   }
 
-  auto *P = new Packed();
+  std::unique_ptr<Packed> own(new Packed());  // freed on every early return
+  Packed *P = own.get();
   P->b = *b;
   P->bsrc.resize(nb);
   for (int64_t k = 0; k < nb; k++) P->bsrc[k] = block_src ? block_src[k] : b->data + b->offset[k];
@@ -304,7 +295,6 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
     const int64_t sr = sys_of(b->row0[k]);
     if (sys_of(b->row0[k] + b->nrows[k] - 1) != sr || sys_of(b->col0[k]) != sr ||
         sys_of(b->col0[k] + b->ncols[k] - 1) != sr) {
-      delete P;
       return fail(HMAT_E_LAYOUT, "block %lld crosses a system boundary", (long long)k);
     }
   }
@@ -326,7 +316,6 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
     int64_t at = sysb[sy];
     for (int64_t k : v) {
       if (b->col0[k] != at) {
-        delete P;
         return fail(HMAT_E_LAYOUT, "rows [%lld,%lld): %s at column %lld (Eqs. 1-2 require a disjoint cover)",
                     (long long)cuts[s], (long long)cuts[s + 1], b->col0[k] < at ? "blocks overlap" : "gap",
                     (long long)std::min(at, b->col0[k]));
@@ -334,7 +323,6 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
       at += b->ncols[k];
     }
     if (at != sysb[sy + 1]) {
-      delete P;
       return fail(HMAT_E_LAYOUT, "rows [%lld,%lld): columns [%lld,%lld) uncovered", (long long)cuts[s],
                   (long long)cuts[s + 1], (long long)at, (long long)sysb[sy + 1]);
     }
@@ -468,7 +456,6 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
   P->zlen = z;
   P->zpart_len = zp;
   if (n + z + 1 >= (int64_t(1) << 31)) {
-    delete P;
     return fail(HMAT_E_ARG, "n + z exceeds the 32-bit gather index range");
   }
   // stage-1 items: largest first so the tail of the launch is short; each
@@ -731,8 +718,7 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
   S.precision = prec;
   S.c = o->c;
   if (info) *info = I;
-  if (out_keep) *out_keep = P;
-  else delete P;
+  if (out_keep) *out_keep = own.release();
   return HMAT_OK;
 }
 
@@ -740,8 +726,8 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
 // H-matrix: system k occupies indices [off_k, off_k + n_k) of the merged
 // index space and keeps its own partition; the merged description is owned
 // by the returned plan.
-int plan_batched(const hmat_blocks *sys, int64_t count, const hmat_build_opts *o, hmat_plan_info *info,
-                 Packed **out_keep) {
+static int plan_batched_body(const hmat_blocks *sys, int64_t count, const hmat_build_opts *o, hmat_plan_info *info,
+                             Packed **out_keep) {
   if (!sys || count < 1) return fail(HMAT_E_ARG, "no systems");
   std::vector<int64_t> off(count + 1, 0);
   int64_t nbt = 0;
@@ -808,6 +794,11 @@ int plan_batched(const hmat_blocks *sys, int64_t count, const hmat_build_opts *o
   if (out_keep) *out_keep = P;
   else delete P;
   return HMAT_OK;
+}
+
+int plan_batched(const hmat_blocks *sys, int64_t count, const hmat_build_opts *o, hmat_plan_info *info,
+                 Packed **out_keep) {
+  return host_guarded([&]() { return plan_batched_body(sys, count, o, info, out_keep); });
 }
 
 

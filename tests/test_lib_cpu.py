@@ -10,6 +10,7 @@
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -307,3 +308,35 @@ def test_seeded_params_layout():
     assert np.array_equal(p, seeded.init_params(0))
     b = list(seeded.batch_order(1000, 256, 2, seed=3))
     assert len(b) == 6 and all(x.size == 256 for x in b) and len(set(b[0]) & set(b[1])) == 0
+
+
+_NOMEM_SCRIPT = r"""
+import resource, sys
+import numpy as np
+from paper_1911_00093_amd import hmat
+hmat.lib()
+n = 1024  # 1,048,576 dense 1 x 1 blocks
+i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+ones = np.ones(n * n)
+bs = hmat.BlockSet.from_arrays(n, i.ravel(), ones, j.ravel(), ones, np.zeros(n * n), np.zeros(n * n),
+                               np.arange(n * n), ones)
+vm = int([l for l in open("/proc/self/status") if l.startswith("VmSize")][0].split()[1]) * 1024
+resource.setrlimit(resource.RLIMIT_AS, (vm + (int(sys.argv[1]) << 20), resource.RLIM_INFINITY))
+try:
+    hmat.hmat_plan(bs, hmat.M2_MIXED)
+    print("rc", 0, flush=True)
+except hmat.HmatError as e:
+    print("rc", e.code, flush=True)
+"""
+
+
+@pytest.mark.parametrize("headroom_mb", [8, 64])
+def test_plan_out_of_host_memory_returns_code(headroom_mb):
+    """A plan that runs out of host memory (address space capped a few MB
+    above the process's size) returns HMAT_E_NOMEM; no exception crosses the
+    C ABI and the process ends normally."""
+    env = dict(os.environ, PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-c", _NOMEM_SCRIPT, str(headroom_mb)], capture_output=True, text=True,
+                       env=env, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.split()[-2:] == ["rc", str(hmat.HMAT_E_NOMEM)], r.stdout
