@@ -318,7 +318,7 @@ typedef struct {
 } hmat_batch_result;
 
 /* Device bytes of workspace hmat_bicgstab_batched needs for handle h and nrhs
- * right-hand sides (0 on bad arguments). */
+ * right-hand sides (0 on bad arguments or when the host is out of memory). */
 uint64_t hmat_bicgstab_batched_workspace_bytes(hmat_t h, int64_t nrhs);
 
 /* BiCGSTAB (Sec. 3.5, Algorithm 1) on every system of a batched handle for

@@ -96,6 +96,7 @@ hmat_s::~hmat_s() { delete prof; }
 extern "C" {
 
 int hmat_set_profiling(hmat_t h, int32_t enable) {
+  return hm::host_guarded([&]() -> int {
   if (!h) return hm::fail(HMAT_E_ARG, "null handle");
   if (enable && !h->prof) h->prof = new hm::Prof();
   if (!enable && h->prof) {
@@ -103,6 +104,7 @@ int hmat_set_profiling(hmat_t h, int32_t enable) {
     h->prof = nullptr;
   }
   return HMAT_OK;
+  });
 }
 
 int hmat_kernel_times(hmat_t h, double *avg_ms, int64_t *count) {

@@ -462,6 +462,7 @@ extern "C" {
 uint64_t hmat_solver_workspace_bytes(int64_t n) { return n > 0 ? hm::work_bytes(n) + 256 : 0; }
 
 int hmat_precond_plan(const hmat_blocks *b, int32_t kind, uint64_t *device_bytes) {
+  return hm::host_guarded([&]() -> int {
   if (!b || !device_bytes) return hm::fail(HMAT_E_ARG, "null argument");
   if (kind != HMAT_PRECOND_JACOBI && kind != HMAT_PRECOND_LEARNED)
     return hm::fail(HMAT_E_ARG, "unknown preconditioner kind %d", kind);
@@ -479,10 +480,12 @@ int hmat_precond_plan(const hmat_blocks *b, int32_t kind, uint64_t *device_bytes
   for (int64_t k : ids) vals += (uint64_t)b->nrows[k] * b->nrows[k];
   *device_bytes = hm::align256(ids.size() * sizeof(hm::JLeaf)) + hm::align256(vals * 8);
   return HMAT_OK;
+  });
 }
 
 int hmat_precond_leaves(const hmat_blocks *b, int32_t kind, int64_t *block, int64_t *row0, int64_t *rows,
                         int64_t capacity, int64_t *count) {
+  return hm::host_guarded([&]() -> int {
   if (!b || !count) return hm::fail(HMAT_E_ARG, "null argument");
   if (kind != HMAT_PRECOND_JACOBI && kind != HMAT_PRECOND_LEARNED)
     return hm::fail(HMAT_E_ARG, "unknown preconditioner kind %d", kind);
@@ -498,16 +501,20 @@ int hmat_precond_leaves(const hmat_blocks *b, int32_t kind, int64_t *block, int6
     if (rows) rows[q] = b->nrows[ids[q]];
   }
   return HMAT_OK;
+  });
 }
 
 int hmat_dense_inverse(int64_t m, const double *a, double *out) {
+  return hm::host_guarded([&]() -> int {
   if (!a || !out || m < 1) return hm::fail(HMAT_E_ARG, "bad argument");
   if (!hm::invert(m, a, out)) return hm::fail(HMAT_E_ARG, "singular matrix");
   return HMAT_OK;
+  });
 }
 
 int hmat_precond_create_learned(const hmat_blocks *b, const float *uv, void *dev_mem, uint64_t dev_bytes,
                                 void *stream, hmat_precond_t *out) {
+  return hm::host_guarded([&]() -> int {
   if (!out) return hm::fail(HMAT_E_ARG, "null output");
   *out = nullptr;
   uint64_t need = 0;
@@ -567,10 +574,12 @@ int hmat_precond_create_learned(const hmat_blocks *b, const float *uv, void *dev
   }
   *out = P;
   return HMAT_OK;
+  });
 }
 
 int hmat_precond_create(const hmat_blocks *b, int32_t kind, void *dev_mem, uint64_t dev_bytes, void *stream,
                         hmat_precond_t *out) {
+  return hm::host_guarded([&]() -> int {
   if (!out) return hm::fail(HMAT_E_ARG, "null output");
   *out = nullptr;
   if (kind != HMAT_PRECOND_JACOBI)
@@ -618,6 +627,7 @@ int hmat_precond_create(const hmat_blocks *b, int32_t kind, void *dev_mem, uint6
   }
   *out = P;
   return HMAT_OK;
+  });
 }
 
 int hmat_precond_apply(hmat_precond_t p, const double *x, double *y, void *stream) {

@@ -450,16 +450,21 @@ extern "C" {
 
 uint64_t hmat_bicgstab_batched_workspace_bytes(hmat_t h, int64_t nrhs) {
   if (!h || nrhs < 1 || h->sys_off.size() < 2) return 0;
-  std::vector<hm::BTile> tiles;
-  std::vector<int32_t> tb;
-  hm::build_tiles(h->sys_off, tiles, tb);
-  const int64_t nsys = (int64_t)h->sys_off.size() - 1;
-  return hm::bwork_bytes(h->n, nrhs, nsys, (int64_t)tiles.size());
+  try {
+    std::vector<hm::BTile> tiles;
+    std::vector<int32_t> tb;
+    hm::build_tiles(h->sys_off, tiles, tb);
+    const int64_t nsys = (int64_t)h->sys_off.size() - 1;
+    return hm::bwork_bytes(h->n, nrhs, nsys, (int64_t)tiles.size());
+  } catch (const std::exception &) {  // out of host memory: no size
+    return 0;
+  }
 }
 
 int hmat_bicgstab_batched(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, int64_t nrhs,
                           const hmat_solve_opts *o, hmat_batch_result *results, hmat_solve_info *summary, void *work,
                           uint64_t work_bytes, void *stream) {
+  return hm::host_guarded([&]() -> int {
   using namespace hm;
   if (summary) std::memset(summary, 0, sizeof *summary);
   if (!h_iter || !b || !x || !o || !results || !work) return fail(HMAT_E_ARG, "null argument");
@@ -637,6 +642,7 @@ int hmat_bicgstab_batched(hmat_t h_iter, hmat_t h_fp64, const double *b, double 
   }
   if (worst != HMAT_OK) return fail(worst, "batched BiCGSTAB: not every recurrence converged");
   return HMAT_OK;
+  });
 }
 
 }  // extern "C"
