@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # (scaled by the plain-copy calibration).  Valid only for the kernel and
 # layout sources it was measured with (their hash) and for that workload.
 PROFILED_TRAFFIC = {
-    "sources_sha256_16": "25d23c27184e43cf",
+    "sources_sha256_16": "9be1ab7bc1196c46",
     "workload": "plates-128",
     "variant": "M2-Mixed",
     "k_stage2_bytes": 899.1e6,
