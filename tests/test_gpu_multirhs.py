@@ -107,7 +107,10 @@ def test_autotune_keeps_results():
     info = H.autotune(reps=3)
     print(info)
     assert info["stage2_batch"] in (1, 2, 4) and info["ms_fixed"] > 0 and info["ms_tuned"] > 0
-    assert info["stage1_batch"][oracle.M1_DOUBLE] == 0  # no FP64 items in M2-Mixed
+    # per storage class FP64 / FP32 / BF16: M2-Mixed stores its W' in FP32 only
+    assert info["stage1_batch"][0] == 0 and info["stage1_batch"][1] in (1, 2, 4)
+    # grids: 0 persistent, 1 persistent at half occupancy, 2 one wave per unit
+    assert info["stage2_grid"] in (0, 1, 2) and info["stage1_grid"][1] in (0, 1, 2)
     Y1 = H.matvec(to_cols(X)).cpu().numpy()
     assert np.array_equal(Y0, Y1)
     H1 = hmat.HMatrix(blockset(h), oracle.M2_MIXED)
