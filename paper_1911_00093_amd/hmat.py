@@ -398,22 +398,66 @@ class HMatrix:
         return tuple(out), cnt.value
 
 
-def hmat_matvec(h: HMatrix, x, y=None, stream=None):
+def _vector(t, n, name, cols=False, device=True):
+    """Check a device FP64 vector argument of order n: shape (n,), or with
+    cols (n, nrhs) column-major (t.T contiguous or a strided view whose
+    columns are contiguous).  Returns (nrhs, ld).  Shape, dtype and layout
+    are checked before the device, so a wrong argument is named whatever
+    device it lives on."""
     import torch
 
-    if x.dtype != torch.float64 or not x.is_cuda:
-        raise TypeError("x must be a float64 device tensor")
-    if x.dim() == 1:
-        nrhs, ld = 1, x.shape[0]
-        if not x.is_contiguous():
-            raise ValueError("x must be contiguous")
-    else:  # (n, nrhs) with columns contiguous, i.e. a transposed (nrhs, n) tensor
-        nrhs = x.shape[1]
-        if x.stride(0) != 1:
-            raise ValueError("x must be column-major (x.T contiguous)")
-        ld = x.stride(1)
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, not {t.dtype}")
+    if t.dim() == 1:
+        if t.shape[0] != n:
+            raise ValueError(f"{name} has length {t.shape[0]}, the operator has order {n}")
+        if t.stride(0) != 1:
+            raise ValueError(f"{name} must be contiguous")
+        nrhs, ld = 1, n
+    elif t.dim() == 2 and cols:
+        if t.shape[0] != n:
+            raise ValueError(f"{name} has {t.shape[0]} rows, the operator has order {n}")
+        nrhs = t.shape[1]
+        if nrhs < 1 or (t.stride(0) != 1 and t.shape[0] > 1):
+            raise ValueError(f"{name} must be column-major ({name}.T contiguous)")
+        ld = t.stride(1) if nrhs > 1 else n
+        if ld < n:
+            raise ValueError(f"{name}: columns overlap (leading dimension {ld} < {n})")
+    else:
+        raise ValueError(f"{name} must have shape ({n},)" + (f" or ({n}, nrhs)" if cols else ""))
+    if device:
+        _on_device(t, name)
+    return nrhs, ld
+
+
+def _on_device(t, name):
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a device (GPU) tensor")
+
+
+def hmat_matvec(h: HMatrix, x, y=None, stream=None):
+    """y = A~ x.  x: device FP64 (n,) or column-major (n, nrhs) with leading
+    dimension ld (x.stride(1)); y (allocated when None) must have x's shape,
+    dtype, device and leading dimension, since the ABI takes one ld for
+    both."""
+    import torch
+
+    nrhs, ld = _vector(x, h.n, "x", cols=True, device=False)
+    if y is not None:
+        _, ldy = _vector(y, h.n, "y", cols=True, device=False)
+        if y.shape != x.shape or ldy != ld:
+            raise ValueError(f"y must have x's shape {tuple(x.shape)} and leading dimension {ld}")
+        _on_device(y, "y")
+        if y.device != x.device:
+            raise ValueError("x and y must be on one device")
+    _on_device(x, "x")
     if y is None:
-        y = torch.empty_like(x) if x.dim() == 1 else torch.empty((nrhs, h.n), dtype=torch.float64, device=x.device).T
+        if x.dim() == 1:
+            y = torch.empty_like(x)
+        else:
+            y = torch.empty((nrhs, ld), dtype=torch.float64, device=x.device).T[:h.n]
     _check(lib().hmat_matvec(h.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nrhs, ld, _stream_ptr(stream)))
     return y
 
@@ -457,7 +501,15 @@ class Precond:
     def apply(self, x, y=None, stream=None):
         import torch
 
-        y = torch.empty_like(x) if y is None else y
+        _vector(x, self.n, "x", device=False)
+        if y is not None:
+            _vector(y, self.n, "y", device=False)
+            _on_device(y, "y")
+            if y.device != x.device or y.data_ptr() == x.data_ptr():
+                raise ValueError("y must be another vector on x's device")
+        _on_device(x, "x")
+        if y is None:
+            y = torch.empty_like(x)
         _check(lib().hmat_precond_apply(self.p, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), _stream_ptr(stream)))
         return y
 
@@ -547,6 +599,26 @@ class MLP:
                                    C.c_float(lr), _stream_ptr(stream)))
 
 
+def _check_solve_args(h_iter, h_fp64, b, x, precond):
+    """b, x: device FP64 vectors of the operator's order on one device; the
+    FP64 operator and the preconditioner of the same order."""
+    n = h_iter.n
+    _vector(b, n, "b", device=False)
+    if x is not None:
+        _vector(x, n, "x", device=False)
+    if h_fp64 is not None and h_fp64.n != n:
+        raise ValueError(f"h_fp64 has order {h_fp64.n}, h_iter {n}")
+    if precond is not None and precond.n != n:
+        raise ValueError(f"the preconditioner has order {precond.n}, the operator {n}")
+    _on_device(b, "b")
+    if x is not None:
+        _on_device(x, "x")
+        if x.device != b.device:
+            raise ValueError("x and b must be on one device")
+        if x.data_ptr() == b.data_ptr():
+            raise ValueError("x must not alias b")
+
+
 def hmat_solver_workspace_bytes(n: int) -> int:
     return int(lib().hmat_solver_workspace_bytes(int(n)))
 
@@ -558,6 +630,7 @@ def hmat_bicgstab(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = None, tol
     import torch
 
     n = h_iter.n
+    _check_solve_args(h_iter, h_fp64, b, x, precond)
     x = torch.zeros(n, dtype=torch.float64, device=b.device) if x is None else x
     wb = hmat_solver_workspace_bytes(n)
     if work is None or work.numel() < wb:
@@ -585,6 +658,7 @@ def hmat_gmres(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = None, tol=1e
     import torch
 
     n = h_iter.n
+    _check_solve_args(h_iter, h_fp64, b, x, precond)
     x = torch.zeros(n, dtype=torch.float64, device=b.device) if x is None else x
     wb = int(lib().hmat_gmres_workspace_bytes(int(n), int(restart)))
     if wb == 0:
@@ -619,13 +693,16 @@ def hmat_bicgstab_batched(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = N
     import torch
 
     n = h_iter.n
-    if b.dim() != 2 or b.stride(0) != 1 or b.stride(1) != n:
+    _vector(b, n, "b", cols=True)
+    if b.dim() != 2 or (b.shape[1] > 1 and b.stride(1) != n):
         raise ValueError("b must be (n, nrhs) with b.T contiguous")
     nrhs = b.shape[1]
     if x is None:
         x = torch.zeros((nrhs, n), dtype=torch.float64, device=b.device).T
-    elif x.shape != b.shape or x.stride() != b.stride():
-        raise ValueError("x must have the shape and layout of b")
+    else:
+        _vector(x, n, "x", cols=True)
+        if x.shape != b.shape or (b.shape[1] > 1 and x.stride(1) != n) or x.device != b.device:
+            raise ValueError("x must have the shape, layout and device of b")
     wb = hmat_bicgstab_batched_workspace_bytes(h_iter, nrhs)
     if wb == 0:
         raise ValueError("bad handle or nrhs")

@@ -340,3 +340,53 @@ def test_plan_out_of_host_memory_returns_code(headroom_mb):
                        env=env, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.split()[-2:] == ["rc", str(hmat.HMAT_E_NOMEM)], r.stdout
+
+
+def test_binding_refuses_bad_vectors():
+    """The binding checks every vector argument before a pointer reaches the
+    C ABI: order, dtype, layout, one leading dimension shared by x and y, and
+    the device (checked last, so every other mistake is named on the CPU)."""
+    import types
+
+    import torch
+
+    n = 10
+    h = types.SimpleNamespace(n=n, h=None)
+    ok = torch.zeros(n, dtype=torch.float64)
+    with pytest.raises(ValueError, match="length 9"):
+        hmat.hmat_matvec(h, torch.zeros(n - 1, dtype=torch.float64))
+    with pytest.raises(TypeError, match="float64"):
+        hmat.hmat_matvec(h, torch.zeros(n, dtype=torch.float32))
+    with pytest.raises(ValueError, match="contiguous"):
+        hmat.hmat_matvec(h, torch.zeros(2 * n, dtype=torch.float64)[::2])
+    with pytest.raises(ValueError, match="column-major"):
+        hmat.hmat_matvec(h, torch.zeros((n, 3), dtype=torch.float64))
+    wide = torch.zeros((3, n + 5), dtype=torch.float64).T[:n]  # ld = n + 5
+    with pytest.raises(ValueError, match="leading dimension"):
+        hmat.hmat_matvec(h, wide, torch.zeros((3, n), dtype=torch.float64).T)
+    with pytest.raises(ValueError, match="y has length 11"):
+        hmat.hmat_matvec(h, ok, torch.zeros(n + 1, dtype=torch.float64))
+    with pytest.raises(ValueError, match="shape"):
+        hmat.hmat_matvec(h, ok, torch.zeros((1, n), dtype=torch.float64).T)
+    with pytest.raises(TypeError, match="device"):
+        hmat.hmat_matvec(h, ok)
+    with pytest.raises(TypeError, match="device"):
+        hmat.hmat_matvec(h, wide, torch.zeros((3, n + 5), dtype=torch.float64).T[:n])
+    # solvers and the preconditioner
+    with pytest.raises(ValueError, match="length 11"):
+        hmat.hmat_bicgstab(h, torch.zeros(n + 1, dtype=torch.float64))
+    with pytest.raises(ValueError, match="x has length"):
+        hmat.hmat_bicgstab(h, ok, x=torch.zeros(n + 1, dtype=torch.float64))
+    with pytest.raises(ValueError, match="h_fp64"):
+        hmat.hmat_bicgstab(h, ok, h_fp64=types.SimpleNamespace(n=n + 1))
+    with pytest.raises(ValueError, match="preconditioner"):
+        hmat.hmat_gmres(h, ok, precond=types.SimpleNamespace(n=n - 1))
+    with pytest.raises(TypeError, match="device"):
+        hmat.hmat_gmres(h, ok)
+    P = types.SimpleNamespace(n=n, p=None)
+    with pytest.raises(ValueError, match="length"):
+        hmat.Precond.apply(P, torch.zeros(n + 2, dtype=torch.float64))
+    with pytest.raises(TypeError, match="device"):
+        hmat.Precond.apply(P, ok)
+    with pytest.raises(ValueError, match="rows"):
+        hmat.hmat_bicgstab_batched(h, torch.zeros((2, n + 1), dtype=torch.float64).T)
