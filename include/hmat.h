@@ -287,6 +287,26 @@ uint64_t hmat_solver_workspace_bytes(int64_t n);
 int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, const hmat_solve_opts *opts,
                   hmat_solve_info *info, void *work, uint64_t work_bytes, void *stream);
 
+/* hmat_bicgstab for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve, bit for bit, with the solver workspace taken from a static
+ * device array that the library holds on every GPU it runs on (about 39 MB
+ * per GPU, kept until the process ends) instead of a `work` argument.  The
+ * caller still passes b, x, the handles and opts as for hmat_bicgstab.
+ * Limits: the order n must not exceed hmat_bicgstab_noalloc_max_n()
+ * (524,288; larger orders fail with HMAT_E_WORKSPACE before any work is
+ * queued) and opts->use_graph must be 0 (HMAT_E_ARG: instantiating a graph
+ * allocates).  Nothing is allocated on the device: no hipMalloc, hipFree or
+ * allocating library call.  Every call on one GPU uses that GPU's single
+ * array, so calls that overlap on one GPU (other host threads, other
+ * streams) race and must be serialised by the caller; the solver initialises
+ * every workspace entry it reads, so the previous call's contents never
+ * matter.  The first call on a device looks up the array's device address
+ * with that device current (HMAT_E_HIP if that fails). */
+int64_t hmat_bicgstab_noalloc_max_n(void);
+int hmat_bicgstab_noalloc(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, const hmat_solve_opts *opts,
+                          hmat_solve_info *info, void *stream);
+
 /* Restarted GMRES(restart) (the further solver Sec. 5 names; the textbook
  * method, not from the paper): Arnoldi with classical Gram-Schmidt applied
  * twice, Givens rotations, right preconditioning x = K u (opts->precond, or

@@ -22,6 +22,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "hmat_impl.h"
@@ -54,9 +55,9 @@ struct Work {
 constexpr int kHistMax = 100000;
 constexpr int kBank = kParts * 4 + 8;
 
-static uint64_t align256(uint64_t b) { return (b + 255) / 256 * 256; }
+static constexpr uint64_t align256(uint64_t b) { return (b + 255) / 256 * 256; }
 
-static uint64_t work_bytes(int64_t n) {
+static constexpr uint64_t work_bytes(int64_t n) {
   return 9 * align256((uint64_t)n * 8) + align256(kParts * 4 * 8) + align256(kBank * 8) +
          align256((kHistMax + 1) * 8) + align256(sizeof(SolverState));
 }
@@ -837,6 +838,64 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
     return fail(info->status, "BiCGSTAB ended with status %d after %lld iterations", info->status,
                 (long long)hs.iter);
   return HMAT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// BiCGSTAB with a static solver workspace, for callers that cannot allocate
+// device memory.  The workspace is one file-scope device array: every GPU the
+// library runs on holds its own copy (kNoAllocBytes, about 39 MB) until the
+// process ends.  Host code never passes the array's name to a kernel (in host
+// code it is a host-side stand-in, not a device address): its device address
+// is looked up once per device with hipGetSymbolAddress, with that device
+// current, and that pointer is what the solver receives.
+namespace hm {
+constexpr int64_t kNoAllocMaxN = int64_t(1) << 19;
+constexpr uint64_t kNoAllocBytes = work_bytes(kNoAllocMaxN);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's copy of `scratch` (null on error).
+static void *scratch_on_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    fail(HMAT_E_HIP, "cannot determine the current device");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      fail(HMAT_E_HIP, "static solver workspace unavailable on device %d: %s", dev, hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace hm
+
+extern "C" {
+
+int64_t hmat_bicgstab_noalloc_max_n(void) { return hm::kNoAllocMaxN; }
+
+int hmat_bicgstab_noalloc(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, const hmat_solve_opts *opts,
+                          hmat_solve_info *info, void *stream) {
+  if (info) std::memset(info, 0, sizeof *info);
+  if (!h_iter || !b || !x || !opts || !info) return hm::fail(HMAT_E_ARG, "null argument");
+  if (h_iter->n > hm::kNoAllocMaxN)
+    return hm::fail(HMAT_E_WORKSPACE, "order %lld exceeds the static solver workspace (at most %lld unknowns)",
+                    (long long)h_iter->n, (long long)hm::kNoAllocMaxN);
+  if (opts->use_graph)
+    return hm::fail(HMAT_E_ARG, "use_graph must be 0: instantiating a graph allocates");
+  void *work = hm::scratch_on_current_device();
+  if (!work) return HMAT_E_HIP;
+  return hmat_bicgstab(h_iter, h_fp64, b, x, opts, info, work, hm::kNoAllocBytes, stream);
 }
 
 }  // extern "C"

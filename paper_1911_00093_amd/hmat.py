@@ -39,6 +39,7 @@ EXPORTED = [
     "hmat_bicgstab_batched_workspace_bytes", "hmat_bicgstab_batched", "hmat_precond_create_learned",
     "hmat_precond_leaves", "hmat_leaf_features", "hmat_dense_inverse", "hmat_mlp_workspace_bytes",
     "hmat_mlp_forward", "hmat_mlp_loss_grad", "hmat_mlp_adam", "hmat_autotune", "hmat_permute",
+    "hmat_bicgstab_noalloc_max_n", "hmat_bicgstab_noalloc",
 ]
 
 
@@ -138,6 +139,8 @@ def lib():
         "hmat_precond_destroy": (C.c_int, [P]),
         "hmat_solver_workspace_bytes": (U64, [I64]),
         "hmat_bicgstab": (C.c_int, [P, P, P, P, P, P, P, U64, P]),
+        "hmat_bicgstab_noalloc_max_n": (I64, []),
+        "hmat_bicgstab_noalloc": (C.c_int, [P, P, P, P, P, P, P]),
         "hmat_gmres_workspace_bytes": (U64, [I64, C.c_int32]),
         "hmat_gmres": (C.c_int, [P, P, P, P, C.c_int32, P, P, P, U64, P]),
         "hmat_assemble_bem": (C.c_int, [I64, P, P, P, P]),
@@ -642,6 +645,33 @@ def hmat_bicgstab(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = None, tol
     info = hmat_solve_info()
     rc = lib().hmat_bicgstab(h_iter.h, (h_fp64 or h_iter).h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
                              C.byref(o), C.byref(info), C.c_void_p(work.data_ptr()), work.numel(), _stream_ptr(stream))
+    if rc != HMAT_OK and (raise_on_error or rc not in (HMAT_E_BREAKDOWN, HMAT_E_NOCONV, HMAT_E_NONFINITE)):
+        _check(rc)
+    d = dict(status=info.status, restarts=info.restarts, iterations=info.iterations, matvecs=info.matvecs,
+             matvecs_fp64=info.matvecs_fp64, rel_res=info.rel_res, true_rel_res=info.true_rel_res)
+    if hist is not None:
+        d["history"] = hist[:info.iterations + 1]
+    return x, d
+
+
+def hmat_bicgstab_noalloc(h_iter: HMatrix, b, x=None, h_fp64: HMatrix | None = None, tol=1e-8, maxiter=1000,
+                          poll_every=1, precond: Precond | None = None, history=False, stream=None,
+                          raise_on_error=False, refine=0.0):
+    """BiCGSTAB with the library's static device workspace
+    (hmat_bicgstab_noalloc); returns (x, info dict).  Allocates nothing on
+    the device when x is given."""
+    import torch
+
+    n = h_iter.n
+    _check_solve_args(h_iter, h_fp64, b, x, precond)
+    x = torch.zeros(n, dtype=torch.float64, device=b.device) if x is None else x
+    hist = np.full(maxiter + 1, np.nan) if history else None
+    o = hmat_solve_opts(float(tol), int(maxiter), int(poll_every), 0,
+                        precond.p if precond is not None else None, _p(hist) if hist is not None else None,
+                        float(refine))
+    info = hmat_solve_info()
+    rc = lib().hmat_bicgstab_noalloc(h_iter.h, (h_fp64 or h_iter).h, C.c_void_p(b.data_ptr()),
+                                     C.c_void_p(x.data_ptr()), C.byref(o), C.byref(info), _stream_ptr(stream))
     if rc != HMAT_OK and (raise_on_error or rc not in (HMAT_E_BREAKDOWN, HMAT_E_NOCONV, HMAT_E_NONFINITE)):
         _check(rc)
     d = dict(status=info.status, restarts=info.restarts, iterations=info.iterations, matvecs=info.matvecs,
