@@ -647,6 +647,10 @@ def bench_learned(args, W, variant, dev, stream):
     eval_loss = learned.mean_loss(net, learned.to_device(learned.leaf_inputs(mesh, bs, with_inverse=True)))
     pre = {"none": None, "block-jacobi": hmat.Precond(bs, hmat.PRECOND_JACOBI),
            "learned": hmat.Precond(bs, hmat.PRECOND_LEARNED, uv=uv)}
+    # the best map of the learned form in the training loss's own measure:
+    # per leaf, U V^T = s_tau x (rank-16 truncated SVD of A^-1 - diag(A)^-1),
+    # which bounds what any network of this output form can reach
+    pre["form-optimum"] = hmat.Precond(bs, hmat.PRECOND_LEARNED, uv=form_optimum_factors(bs).to(dev))
     work = torch.empty(hmat.hmat_solver_workspace_bytes(n), dtype=torch.uint8, device=dev)
     xref, _ = hmat.hmat_bicgstab(H64, b, tol=1e-12, maxiter=4000, work=work)
     xref = xref.clone()
@@ -704,6 +708,33 @@ def bench_learned(args, W, variant, dev, stream):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_training(data)
     print(json.dumps(out), flush=True)
+
+
+def form_optimum_factors(bs):
+    """Float32 (leaves, 2048) factors U, V (row-major 64 x 16 each) of the
+    map diag(A)^-1 + (1/s) U V^T closest to each leaf's exact inverse in the
+    Frobenius norm: U V^T = s (rank-16 truncated SVD of A^-1 - diag(A)^-1)."""
+    import torch
+
+    from paper_1911_00093_amd import hmat
+
+    blk, r0, rows = hmat.precond_leaves(bs, hmat.PRECOND_LEARNED)
+    R = hmat.MLP_RANK
+    out = np.zeros((blk.size, hmat.MLP_OUT), np.float32)
+    for q in range(blk.size):
+        m, off = int(rows[q]), int(bs.offset[blk[q]])
+        A = bs.data[off:off + m * m].reshape(m, m, order="F")
+        d = np.diag(A)
+        E = np.linalg.inv(A) - np.diag(1.0 / d)
+        u, sv, vt = np.linalg.svd(E)
+        k = min(R, m)
+        U = np.zeros((hmat.MLP_LEAF, R))
+        V = np.zeros((hmat.MLP_LEAF, R))
+        U[:m, :k] = u[:, :k] * sv[:k] * (d.sum() / m)
+        V[:m, :k] = vt[:k].T
+        out[q, :hmat.MLP_LEAF * R] = U.ravel()
+        out[q, hmat.MLP_LEAF * R:] = V.ravel()
+    return torch.as_tensor(out)
 
 
 def cpu_baseline_training(data, steps=200, batch=256):

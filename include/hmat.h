@@ -386,6 +386,14 @@ int hmat_bicgstab_batched(hmat_t h_iter, hmat_t h_fp64, const double *b, double 
  * m (FP64, cluster order, 1 <= m <= 64); out: 512 floats. */
 int hmat_leaf_features(int64_t m, const double *centroids, const double *normals, const double *areas, float *out);
 
+/* The fixed parts of the learned map of one leaf (host): a is the dense
+ * diagonal block A_tautau (m x m column-major, FP64, 1 <= m <= 64); dinv
+ * receives 64 floats, 1 / A_ii for i < m and 0 beyond, and *sinv the float
+ * 1 / s_tau = m / sum_i A_ii (the reciprocal of the mean self term), both
+ * computed in FP64 and rounded once, the same values the preconditioner
+ * applies in FP64.  HMAT_E_ARG for a zero diagonal entry. */
+int hmat_leaf_scales(int64_t m, const double *a, float *dinv, float *sinv);
+
 /* Exact inverse of a dense m x m block (host, FP64 Gauss-Jordan with
  * partial pivoting; column-major in and out).  HMAT_E_ARG if singular. */
 int hmat_dense_inverse(int64_t m, const double *a, double *out);

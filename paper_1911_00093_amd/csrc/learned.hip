@@ -251,6 +251,22 @@ static void forward(hipStream_t st, const float *P, const float *X, int B, float
 
 extern "C" {
 
+int hmat_leaf_scales(int64_t m, const double *a, float *dinv, float *sinv) {
+  using namespace hm;
+  if (!a || !dinv || !sinv) return fail(HMAT_E_ARG, "null argument");
+  if (m < 1 || m > kLeaf) return fail(HMAT_E_ARG, "leaf of %lld panels (1..64)", (long long)m);
+  double s = 0.0;
+  for (int64_t i = 0; i < m; i++) {
+    const double d = a[i + i * m];
+    if (d == 0.0) return fail(HMAT_E_ARG, "zero diagonal entry %lld", (long long)i);
+    dinv[i] = (float)(1.0 / d);
+    s += d;
+  }
+  for (int64_t i = m; i < kLeaf; i++) dinv[i] = 0.0f;
+  *sinv = (float)((double)m / s);
+  return HMAT_OK;
+}
+
 int hmat_leaf_features(int64_t m, const double *c, const double *nrm, const double *a, float *out) {
   using namespace hm;
   if (!c || !nrm || !a || !out) return fail(HMAT_E_ARG, "null argument");

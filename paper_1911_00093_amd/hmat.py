@@ -37,7 +37,7 @@ EXPORTED = [
     "hmat_assembly_perm", "hmat_assembly_free", "hmat_version", "hmat_set_profiling", "hmat_kernel_times",
     "hmat_stream_read", "hmat_stream_copy", "hmat_plan_batched", "hmat_build_batched", "hmat_system_offsets",
     "hmat_bicgstab_batched_workspace_bytes", "hmat_bicgstab_batched", "hmat_precond_create_learned",
-    "hmat_precond_leaves", "hmat_leaf_features", "hmat_dense_inverse", "hmat_mlp_workspace_bytes",
+    "hmat_precond_leaves", "hmat_leaf_features", "hmat_leaf_scales", "hmat_dense_inverse", "hmat_mlp_workspace_bytes",
     "hmat_mlp_forward", "hmat_mlp_loss_grad", "hmat_mlp_adam", "hmat_autotune", "hmat_permute",
     "hmat_bicgstab_noalloc_max_n", "hmat_bicgstab_noalloc",
 ]
@@ -162,6 +162,7 @@ def lib():
         "hmat_precond_create_learned": (C.c_int, [P, P, P, U64, P, P]),
         "hmat_precond_leaves": (C.c_int, [P, I32, P, P, P, I64, P]),
         "hmat_leaf_features": (C.c_int, [I64, P, P, P, P]),
+        "hmat_leaf_scales": (C.c_int, [I64, P, P, P]),
         "hmat_dense_inverse": (C.c_int, [I64, P, P]),
         "hmat_mlp_workspace_bytes": (U64, [I64]),
         "hmat_mlp_forward": (C.c_int, [P, P, I64, P, P, U64, P]),
@@ -536,6 +537,15 @@ def hmat_leaf_features(centroids, normals, areas) -> np.ndarray:
     out = np.zeros(MLP_IN, np.float32)
     _check(lib().hmat_leaf_features(a.size, _p(c), _p(nrm), _p(a), _p(out)))
     return out
+
+
+def hmat_leaf_scales(A):
+    """(dinv (64,) float32, sinv float32) of one dense diagonal leaf A (m x m)."""
+    A = np.asfortranarray(A, dtype=np.float64)
+    dinv = np.zeros(MLP_LEAF, np.float32)
+    sinv = np.zeros(1, np.float32)
+    _check(lib().hmat_leaf_scales(A.shape[0], _p(A), _p(dinv), _p(sinv)))
+    return dinv, sinv[0]
 
 
 def hmat_dense_inverse(A) -> np.ndarray:

@@ -34,9 +34,7 @@ def leaf_inputs(mesh, bs: hmat.BlockSet, with_inverse: bool = False):
         x[q] = hmat.hmat_leaf_features(cent[a:a + mm], nrm[a:a + mm], area[a:a + mm])
         off = int(bs.offset[blk[q]])
         A = bs.data[off:off + mm * mm].reshape(mm, mm, order="F")
-        d = np.diag(A)
-        dinv[q, :mm] = 1.0 / d
-        sinv[q] = mm / d.sum()
+        dinv[q], sinv[q] = hmat.hmat_leaf_scales(A)
         if with_inverse:
             ainv[q, :mm, :mm] = hmat.hmat_dense_inverse(A)
     return dict(x=x, dinv=dinv, sinv=sinv, m=m.astype(np.int32), ainv=ainv)

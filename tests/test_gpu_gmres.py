@@ -109,3 +109,27 @@ def test_gmres_edges_and_preconditioner():
     a, c = x0.cpu().numpy(), x1.cpu().numpy()
     assert np.linalg.norm(a - c) / np.linalg.norm(a) < 1e-7 and np.linalg.norm(c - xo) / np.linalg.norm(xo) < 1e-8
     print(f"iterations: none {i0['iterations']}, block-Jacobi {i1['iterations']} (oracle {io['iterations']})")
+
+
+@pytest.mark.parametrize("variant", [oracle.M1_DOUBLE, oracle.M2_MIXED, oracle.BF16_SCALED])
+@pytest.mark.parametrize("restart", [6, 20])
+def test_gmres_one_cycle_matches_oracle(variant, restart):
+    """Exactly one cycle of `restart` steps (tol unreachable): the solution
+    after the cycle's update, x = x_0 + V y, equals the oracle's element by
+    element.  The products differ from the oracle's by summation order only;
+    the Arnoldi vectors carry that difference (about 1e-12 after a few steps
+    on this smoothing operator) into y, so the bound is 1e-9."""
+    need_gpu()
+    m, h, H, H64 = setup("sphere-L4", variant)
+    b = m.rhs()[h.perm] + 0.2 * np.random.default_rng(3).standard_normal(h.n)
+    x, info = hmat.hmat_gmres(H, to_dev(b), h_fp64=H64, tol=1e-30, restart=restart, maxiter=restart, history=True)
+    op, op64 = oracle.Converted(h, variant, 1), oracle.Converted(h, oracle.M1_DOUBLE)
+    xo, io = OG.gmres(op.matvec, b, matvec64=op64.matvec, tol=1e-30, restart=restart, maxiter=restart)
+    assert info["iterations"] == io["iterations"] == restart
+    assert info["restarts"] == 0 and io["cycles"] == 1
+    x = x.cpu().numpy()
+    e = np.abs(x - xo).max() / np.abs(xo).max()
+    print(f"{oracle.VARIANT_NAMES[variant]} m={restart}: max |x - x_oracle| / max |x_oracle| = {e:.2e}")
+    assert e <= 1e-9
+    est = info["history"][1:restart + 1]
+    assert np.allclose(est, io["history"][:restart], rtol=1e-7, atol=0)
