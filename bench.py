@@ -42,6 +42,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # kernel and layout sources it was measured with (their hash).
 PROFILED_TRAFFIC = {
     ("plates-128", "M2-Mixed"): {"sources_sha256_16": "9be1ab7bc1196c46", "k_stage2_bytes": 899.1e6},
+    ("sphere-L7+8", "M2-Mixed"): {"sources_sha256_16": "9be1ab7bc1196c46", "k_stage2_bytes": 3111.7e6},
 }
 PROFILED_SOURCES = ["paper_1911_00093_amd/csrc/matvec.hip", "paper_1911_00093_amd/csrc/hmat_impl.h",
                     "paper_1911_00093_amd/csrc/pack.cpp"]
