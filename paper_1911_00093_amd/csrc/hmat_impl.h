@@ -35,8 +35,10 @@ constexpr int s1_lpr(int cls, int64_t ncols) {
 
 // Stage 2: one workgroup owns rows [r0, r0 + h) of y and streams its panel:
 // the h x K matrix made of the rows of every dense block and of every V'_m
-// that covers these rows, times the gathered vector g[k] = src[gidx[k]]
-// where src = [x_eff | z | 0].  Row r belongs to wave r % 8.  The panel is
+// that covers these rows, times the gathered vector g[k] = x_eff[gidx[k]]
+// for gidx[k] < n (x, rounded to FP32 in the Single variants) and
+// src[gidx[k]] otherwise, where src = [unused (n) | z | 0].  Row r belongs
+// to wave r % 8.  The panel is
 // stored in the order the waves consume it (see s2_elem): for each wave, for
 // each 64-lane slab of columns, the wave's rows one after another, so every
 // wave reads one contiguous stream.
@@ -48,15 +50,19 @@ struct RowChunk {
   int32_t r0, h;
 };
 
-// Stage 1: one wave computes partial z sums of rows [k0, k0 + nrows) of a
+// Stage 1: one wave computes the z sums of rows [k0, k0 + nrows) of a
 // column group (all low-rank factors W'_m of one class sharing J_m), over
-// columns [x0, x0 + ncols) of x; nrows <= 8 * 64 / lpr.  Row k's partial
-// goes to zpart[out_off + k] (out_off already includes the chunk offset).
-// The item's values are stored contiguously in consumption order (s1_elem).
+// columns [x0, x0 + ncols) of x; nrows <= 8 * 64 / lpr.  An item that spans
+// its group's columns finishes z itself (z_off >= 0: row k's z entry is
+// z_off + k, scaled by D_m and rounded where Table 1 keeps z in FP32);
+// otherwise row k's partial goes to zpart[out_off + k] (out_off already
+// includes the chunk offset) and the stage-1 reduction finishes it.  The
+// item's values are stored contiguously in consumption order (s1_elem).
 struct S1Item {
   int64_t w_off;   // element offset of the item's block in the class value array
   int64_t x0;      // first global column
-  int64_t out_off; // zpart offset of row k0
+  int64_t out_off; // zpart offset of row k0 (items of groups wider than one item)
+  int64_t z_off;   // z index of row k0 when the item spans its group's columns, else -1
   int32_t ncols;
   int32_t nrows;
   int32_t cls;
@@ -183,8 +189,12 @@ struct hmat_s {
   hm::ZInfo *zinfo = nullptr;
   double *dscale = nullptr;
   int64_t item_begin[hm::NCLS] = {0, 0, 0}, item_end[hm::NCLS] = {0, 0, 0};  // stage-1 items per class
+  int64_t zw0 = 0;          // z entries [zw0, zlen) come from groups wider than one item
   int32_t cls_mask = 0;     // classes present in the stage-2 panels
-  int32_t grid1[hm::NCLS] = {0, 0, 0}, grid2 = 0;  // persistent grid sizes
+  int32_t grid1[hm::NCLS] = {0, 0, 0}, grid2 = 0;  // grid sizes (multiples of 8)
+  // XCD ranges: stage-1 items of each class (relative to item_begin) and
+  // stage-2 chunks, each range served by the workgroups b with b % 8 == x
+  hm::XcdSplit s1_split[hm::NCLS]{}, s2_split{};
   // multi-RHS (MFMA) layout
   bool mr = false;
   int64_t mr_nitems[hm::NCLS] = {0, 0, 0}, mr_item_begin[hm::NCLS] = {0, 0, 0};

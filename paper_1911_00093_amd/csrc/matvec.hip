@@ -4,21 +4,28 @@
 //
 // Three launches per product, all deterministic (no atomics: every partial
 // sum has one owner and is reduced in a fixed order):
-//  K1  stage 1: z partials.  One wave per work item = (column group, chunk of
+//  K1  stage 1: z sums.  One wave per work item = (column group, chunk of
 //      columns, up to 16 row slots per lane).  Lanes split the columns
 //      (16, 32 or 64 lanes per W' row depending on the group width) and keep
 //      one FP64 accumulator per row slot while they stream the rows with
 //      16-byte non-temporal loads; the accumulators are reduced across the
-//      lanes of each row once, at the end of the item.            (Eq. 22)
-//  K1b stage-1 reduction in chunk order, times D_m (Eq. 23), rounding of z
-//      where Table 1 keeps it in FP32, and the source-vector copy x_eff
-//      (rounded to FP32 in the Single variants, Sec. 3.5) into src.
+//      lanes of each row once, at the end of the item.  An item spanning
+//      its group's columns finishes z itself: times D_m (Eq. 23), rounded
+//      where Table 1 keeps z in FP32.                               (Eq. 22)
+//  K1b stage-1 reduction of the groups wider than one item: partials in
+//      chunk order, times D_m, rounding of z (Eq. 23).  Not launched when
+//      every group fits one item.
 //  K2  stage 2: one workgroup owns <= 64 rows of y.  The workgroup gathers
-//      the panel's operands (x for dense columns, z for low-rank columns)
-//      into LDS (double-buffered across tiles and chunks when one storage
-//      class is present), then each of its eight waves streams its own 8
-//      interleaved rows over all panel columns (dense leaves + V'_m rows,
-//      Eqs. 21, 24), reduces once and writes its rows of y (Eq. 25).
+//      the panel's operands (x_eff for dense columns, rounded to FP32 in
+//      the Single variants (Sec. 3.5), z for low-rank columns) into LDS
+//      (double-buffered across tiles and chunks when one storage class is
+//      present), then each of its eight waves streams its own 8 interleaved
+//      rows over all panel columns (dense leaves + V'_m rows, Eqs. 21, 24),
+//      reduces once and writes its rows of y (Eq. 25).
+// Work is dealt to the XCDs in contiguous ranges (column groups in stage 1,
+// rows in stage 2): workgroup b serves range b % 8, the order in which
+// workgroups are dispatched to the XCDs, so the operands a range reads stay
+// in one XCD's L2.
 // All products and sums are FP64 after upcasting the stored value.
 #include <hip/hip_runtime.h>
 
@@ -93,7 +100,7 @@ __device__ __forceinline__ double reduce_rows(double (&a)[kRowsPerLane], int lan
 // u*VEC .. u*VEC+VEC-1 of every slab of L*VEC columns.
 template <int CLS>
 __device__ __forceinline__ void s1_item(const S1Item &it, const void *vals, const double *x, int x32,
-                                        double *zpart, int lane) {
+                                        double *zpart, const double *dscale, int z32, double *z, int lane) {
   constexpr int VEC = vec_of(CLS);
   const int L = it.lpr;
   const int RPI = kWave / L;  // rows per load instruction
@@ -147,47 +154,57 @@ __device__ __forceinline__ void s1_item(const S1Item &it, const void *vals, cons
   const int spread = L / kRowsPerLane;
   if (u % spread == 0) {
     const int row = q + RPI * (u / spread);
-    if (row < it.nrows) zpart[it.out_off + row] = sum;
+    if (row < it.nrows) {
+      if (it.z_off >= 0) {  // the whole sum: z = D_m sum (Eq. 23), as the reduction would
+        const double v = sum * dscale[it.z_off + row];
+        z[it.z_off + row] = z32 ? (double)(float)v : v;
+      } else {
+        zpart[it.out_off + row] = sum;
+      }
+    }
   }
 }
 
-// One wave per item, the items in size order (largest first): the
-// hardware's dispatch of the workgroups balances the launch's end, which
-// measured 6-10% faster than persistent waves over a static round-robin.
-// The loop still covers any grid: wave g of G takes items g, g + G, ...
+// One wave per item, the items of each XCD range in size order (largest
+// first): the hardware's dispatch of the workgroups balances the launch's
+// end, which measured 6-10% faster than persistent waves over a static
+// round-robin.  Workgroup b serves range b % 8 with its (b / 8)-th group of
+// four waves; the loop covers any grid that is a multiple of 8.
+constexpr int kS1Waves = 4;  // waves per stage-1 workgroup
 template <int CLS>
-__global__ __launch_bounds__(256) void k_stage1(
-    const S1Item *__restrict__ items, int64_t nitems, const void *__restrict__ vals, const double *__restrict__ x,
-    int64_t ldx, int x32, double *__restrict__ zpart, int64_t zpart_len, const int32_t *__restrict__ skip) {
+__global__ __launch_bounds__(kS1Waves * kWave) void k_stage1(
+    const S1Item *__restrict__ items, XcdSplit sp, const void *__restrict__ vals, const double *__restrict__ x,
+    int64_t ldx, int x32, double *__restrict__ zpart, int64_t zpart_len, const double *__restrict__ dscale, int z32,
+    double *__restrict__ src, int64_t src_len, int64_t n, const int32_t *__restrict__ skip) {
   if (skip && *skip) return;  // the caller's recurrence has stopped: nothing to compute
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t rhs = blockIdx.y;
   const double *xr = x + rhs * ldx;
   double *zp = zpart + rhs * zpart_len;
-  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  double *z = src + rhs * src_len + n;
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t gx = ((int64_t)gridDim.x - xcd + kXcds - 1) / kXcds;  // workgroups serving this range
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  for (int64_t idx = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave; idx < nitems; idx += nwaves) {
+  for (int64_t idx = sp.lo[xcd] + (int64_t)(blockIdx.x / kXcds) * kS1Waves + wave; idx < sp.lo[xcd + 1];
+       idx += gx * kS1Waves) {
     const S1Item it = items[idx];
-    s1_item<CLS>(it, vals, xr, x32, zp, lane);
+    s1_item<CLS>(it, vals, xr, x32, zp, dscale, z32, z, lane);
   }
 }
 
 // ----------------------------------------------------------------- K1b
-__global__ __launch_bounds__(256) void k_stage1b(int64_t n, int64_t zlen, const double *__restrict__ x,
-                                                 int64_t ldx, int x32, int z32, const ZInfo *__restrict__ zi,
-                                                 const double *__restrict__ dscale,
+// z entries [zw0, zlen): the groups wider than one stage-1 item.
+__global__ __launch_bounds__(256) void k_stage1b(int64_t n, int64_t zw0, int64_t zlen, int z32,
+                                                 const ZInfo *__restrict__ zi, const double *__restrict__ dscale,
                                                  const double *__restrict__ zpart, int64_t zpart_len,
                                                  double *__restrict__ src, int64_t src_len,
                                                  const int32_t *__restrict__ skip) {
   if (skip && *skip) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = zw0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t rhs = blockIdx.y;
   double *s = src + rhs * src_len;
-  if (i < n) {
-    const double xv = x[rhs * ldx + i];
-    s[i] = x32 ? (double)(float)xv : xv;
-  } else if (i < n + zlen) {
-    const int64_t j = i - n;
+  if (j < zlen) {
+    const int64_t i = n + j;
     const ZInfo q = zi[j];
     const double d = dscale[j];
     const double *zp = zpart + rhs * zpart_len + q.zp;
@@ -206,9 +223,19 @@ __global__ __launch_bounds__(256) void k_stage1b(int64_t n, int64_t zlen, const 
     }
     acc *= d;
     s[i] = z32 ? (double)(float)acc : acc;
-  } else if (i == n + zlen) {
-    s[i] = 0.0;
   }
+}
+
+// x_eff into the head of src (x rounded to FP32 in the Single variants), for
+// products whose y overlaps x.
+__global__ __launch_bounds__(256) void k_copy_x(int64_t n, const double *__restrict__ x, int64_t ldx, int x32,
+                                                double *__restrict__ src, int64_t src_len,
+                                                const int32_t *__restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = x[blockIdx.y * ldx + i];
+  src[blockIdx.y * src_len + i] = x32 ? (double)(float)v : v;
 }
 
 // ------------------------------------------------------------------ K2
@@ -255,10 +282,23 @@ __device__ __forceinline__ void s2_slabs(int64_t panel_off, int ld, int h, const
   }
 }
 
-// The workgroup gathers g[k] = src[gi[k]], k < kn <= kS2Tile, into LDS.  The
-// index loads are unconditional (indices past kn repeat the last one), so
-// that each thread's loads issue together.
-__device__ __forceinline__ void s2_gather(const int32_t *gi, int kn, const double *src, double *g) {
+// Operands of the panel columns: source index k < n is x_eff[k] (x, rounded
+// to FP32 in the Single variants), k >= n is src[k] (z, or the zero slot).
+struct S2Src {
+  const double *src;  // [unused (n) | z | 0] of this right-hand side
+  const double *x;    // x of this right-hand side
+  int64_t n;
+  int x32;
+};
+__device__ __forceinline__ const double *s2_addr(const S2Src &o, int32_t k) { return k < o.n ? o.x + k : o.src + k; }
+__device__ __forceinline__ double s2_round(const S2Src &o, int32_t k, double v) {
+  return (o.x32 && k < o.n) ? (double)(float)v : v;
+}
+
+// The workgroup gathers the operands of columns gi[k], k < kn <= kS2Tile,
+// into LDS.  The index loads are unconditional (indices past kn repeat the
+// last one), so that each thread's loads issue together.
+__device__ __forceinline__ void s2_gather(const int32_t *gi, int kn, const S2Src &o, double *g) {
   constexpr int PER = kS2Tile / kS2Threads;
   if (kn <= 0) return;  // uniform
   int32_t k[PER];
@@ -266,17 +306,17 @@ __device__ __forceinline__ void s2_gather(const int32_t *gi, int kn, const doubl
 #pragma unroll
   for (int j = 0; j < PER; j++) k[j] = gi[min((int)threadIdx.x + j * kS2Threads, kn - 1)];
 #pragma unroll
-  for (int j = 0; j < PER; j++) v[j] = src[k[j]];
+  for (int j = 0; j < PER; j++) v[j] = *s2_addr(o, k[j]);
 #pragma unroll
   for (int j = 0; j < PER; j++)
-    if ((int)threadIdx.x + j * kS2Threads < kn) g[threadIdx.x + j * kS2Threads] = v[j];
+    if ((int)threadIdx.x + j * kS2Threads < kn) g[threadIdx.x + j * kS2Threads] = s2_round(o, k[j], v[j]);
 }
 
 // One storage class of a chunk (chunks with several classes): each tile of
 // operands is gathered into LDS, then streamed.
 template <int CLS>
 __device__ __forceinline__ void s2_class(const RowChunk &ch, const void *vals, const int32_t *gidx,
-                                         const double *src, double *gbuf, double (&acc)[kRowsPerLane], int wave,
+                                         const S2Src &src, double *gbuf, double (&acc)[kRowsPerLane], int wave,
                                          int lane) {
   const int ld = ch.ld[CLS];
   if (ld == 0) return;  // uniform over the workgroup
@@ -361,18 +401,21 @@ __device__ __forceinline__ S2Cur s2_cur(const RowChunk *chunks, int64_t c) {
 }
 
 template <int CLS>
-__device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, int64_t nchunks,
+__device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, const XcdSplit &sp,
                                           const void *__restrict__ vals, const int32_t *__restrict__ gidx,
-                                          const double *__restrict__ src, double *__restrict__ y,
-                                          const S2Dot &dot) {
+                                          const S2Src &src, double *__restrict__ y, const S2Dot &dot) {
   constexpr int SLAB = kWave * vec_of(CLS);
   constexpr int PER = kS2Tile / kS2Threads;  // gathered operands per thread and tile
   static_assert(kS2Tile % kS2Threads == 0 && kS2Tile % SLAB == 0, "whole slabs, equal shares");
   __shared__ double gbuf[2][kS2Tile];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   double dacc[2] = {0.0, 0.0};
-  int64_t c = blockIdx.x;
-  if (c >= nchunks) {  // uniform over the workgroup
+  // this workgroup's chunks: its XCD range, every gx-th from its own
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t gx = ((int64_t)gridDim.x - xcd + kXcds - 1) / kXcds;
+  const int64_t hi = sp.lo[xcd + 1];
+  int64_t c = sp.lo[xcd] + blockIdx.x / kXcds;
+  if (c >= hi) {  // uniform over the workgroup
     s2_dot_finish(dot, dacc);
     return;
   }
@@ -390,10 +433,10 @@ __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, i
     int64_t nc = c;
     int nkt = kt0 + kS2Tile;
     if (nkt >= ch.ld) {
-      nc = c + gridDim.x;
+      nc = c + gx;
       nkt = 0;
     }
-    const bool more = nc < nchunks;
+    const bool more = nc < hi;
     const bool same = nc == c;
     const S2Cur nx = (more && !same) ? s2_cur<CLS>(chunks, nc) : ch;
     const int nkn = more ? min(kS2Tile, nx.ld - nkt) : 0;
@@ -413,7 +456,7 @@ __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, i
     s2_slabs<CLS>(ch.panel_off, ch.ld, ch.h, vals, gt, kt0, 0, first, acc, wave, lane);
     double pre[PER];
 #pragma unroll
-    for (int j = 0; j < PER; j++) pre[j] = src[gn[j]];
+    for (int j = 0; j < PER; j++) pre[j] = *s2_addr(src, gn[j]);
     s2_slabs<CLS>(ch.panel_off, ch.ld, ch.h, vals, gt, kt0, first, kn, acc, wave, lane);
     if (!same) {  // the chunk is complete
       s2_write(ch.r0, ch.h, acc, y, wave, lane, dot, dacc);
@@ -424,7 +467,7 @@ __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, i
 #pragma unroll
     for (int j = 0; j < PER; j++) {
       const int k = threadIdx.x + j * kS2Threads;
-      if (k < nkn) gw[k] = pre[j];
+      if (k < nkn) gw[k] = s2_round(src, gn[j], pre[j]);
     }
     if (!more) break;  // uniform
     __syncthreads();   // this tile is consumed, the next one is stored
@@ -437,19 +480,18 @@ __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, i
 }
 
 template <int MASK>
-__device__ __forceinline__ void s2_body(const RowChunk *__restrict__ chunks, int64_t nchunks,
+__device__ __forceinline__ void s2_body(const RowChunk *__restrict__ chunks, const XcdSplit &sp,
                                         const double *__restrict__ v64, const float *__restrict__ v32,
                                         const unsigned short *__restrict__ v16, const int32_t *__restrict__ g64,
                                         const int32_t *__restrict__ g32, const int32_t *__restrict__ g16,
-                                        const double *__restrict__ src, int64_t src_len, double *__restrict__ y,
-                                        int64_t ldy, const S2Dot &dot) {
+                                        const S2Src &s, double *__restrict__ y, const S2Dot &dot) {
   __shared__ double gbuf[kS2Tile];
   double dacc[2] = {0.0, 0.0};
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
-  const int64_t rhs = blockIdx.y;
-  const double *s = src + rhs * src_len;
-  // static round-robin over the size-sorted chunks
-  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+  // this workgroup's chunks: its XCD range, every gx-th from its own
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t gx = ((int64_t)gridDim.x - xcd + kXcds - 1) / kXcds;
+  for (int64_t c = sp.lo[xcd] + blockIdx.x / kXcds; c < sp.lo[xcd + 1]; c += gx) {
     const RowChunk ch = chunks[c];
     double acc[kRowsPerLane];
 #pragma unroll
@@ -457,17 +499,19 @@ __device__ __forceinline__ void s2_body(const RowChunk *__restrict__ chunks, int
     if constexpr ((MASK & 1) != 0) s2_class<F64>(ch, v64, g64, s, gbuf, acc, wave, lane);
     if constexpr ((MASK & 2) != 0) s2_class<F32>(ch, v32, g32, s, gbuf, acc, wave, lane);
     if constexpr ((MASK & 4) != 0) s2_class<BF16>(ch, v16, g16, s, gbuf, acc, wave, lane);
-    s2_write(ch.r0, ch.h, acc, y + rhs * ldy, wave, lane, dot, dacc);
+    s2_write(ch.r0, ch.h, acc, y, wave, lane, dot, dacc);
   }
   s2_dot_finish(dot, dacc);
 }
 
 #define HM_S2_ARGS                                                                                              \
-  const RowChunk *__restrict__ chunks, int64_t nchunks, const double *__restrict__ v64,                         \
+  const RowChunk *__restrict__ chunks, XcdSplit sp, const double *__restrict__ v64,                             \
       const float *__restrict__ v32, const unsigned short *__restrict__ v16, const int32_t *__restrict__ g64,   \
       const int32_t *__restrict__ g32, const int32_t *__restrict__ g16, const double *__restrict__ src,         \
-      int64_t src_len, double *__restrict__ y, int64_t ldy, const int32_t *__restrict__ skip, S2Dot dot
-#define HM_S2_PASS chunks, nchunks, v64, v32, v16, g64, g32, g16, src, src_len, y, ldy, dot
+      int64_t src_len, const double *__restrict__ x, int64_t ldx, int x32, int64_t n, double *__restrict__ y,  \
+      int64_t ldy, const int32_t *__restrict__ skip, S2Dot dot
+// this right-hand side's operand sources
+#define HM_S2_SRC S2Src{src + blockIdx.y * src_len, x + blockIdx.y * ldx, n, x32}
 
 // One storage class: double-buffered operand tiles.
 template <int MASK>
@@ -477,20 +521,20 @@ __global__ __launch_bounds__(kS2Threads, 4) void k_stage2(HM_S2_ARGS) {
   constexpr int CLS = MASK == 1 ? F64 : MASK == 2 ? F32 : BF16;
   const void *vals = CLS == F64 ? (const void *)v64 : CLS == F32 ? (const void *)v32 : (const void *)v16;
   const int32_t *gidx = CLS == F64 ? g64 : CLS == F32 ? g32 : g16;
-  s2_single<CLS>(chunks, nchunks, vals, gidx, src + blockIdx.y * src_len, y + blockIdx.y * ldy, dot);
+  s2_single<CLS>(chunks, sp, vals, gidx, HM_S2_SRC, y + blockIdx.y * ldy, dot);
 }
 // Two or three classes: let the compiler size the registers (no spills).
 template <int MASK>
 __global__ __launch_bounds__(kS2Threads) void k_stage2_multi(HM_S2_ARGS) {
   if (skip && *skip) return;
-  s2_body<MASK>(HM_S2_PASS);
+  s2_body<MASK>(chunks, sp, v64, v32, v16, g64, g32, g16, HM_S2_SRC, y + blockIdx.y * ldy, dot);
 }
 
 static_assert(kRowChunk == kS2Waves * kRowsPerLane, "each wave owns 8 rows of a chunk");
 
-typedef void (*Stage2Fn)(const RowChunk *, int64_t, const double *, const float *, const unsigned short *,
-                         const int32_t *, const int32_t *, const int32_t *, const double *, int64_t, double *,
-                         int64_t, const int32_t *, S2Dot);
+typedef void (*Stage2Fn)(const RowChunk *, XcdSplit, const double *, const float *, const unsigned short *,
+                         const int32_t *, const int32_t *, const int32_t *, const double *, int64_t, const double *,
+                         int64_t, int, int64_t, double *, int64_t, const int32_t *, S2Dot);
 static Stage2Fn stage2_fn(int mask) {
   switch (mask) {
     case 1: return k_stage2<1>;
@@ -502,8 +546,8 @@ static Stage2Fn stage2_fn(int mask) {
     default: return k_stage2_multi<7>;
   }
 }
-typedef void (*Stage1Fn)(const S1Item *, int64_t, const void *, const double *, int64_t, int, double *, int64_t,
-                         const int32_t *);
+typedef void (*Stage1Fn)(const S1Item *, XcdSplit, const void *, const double *, int64_t, int, double *, int64_t,
+                         const double *, int, double *, int64_t, int64_t, const int32_t *);
 static Stage1Fn stage1_fn(int cls) { return cls == F64 ? k_stage1<F64> : cls == F32 ? k_stage1<F32> : k_stage1<BF16>; }
 
 // Grid sizes: stage 1 one wave per item (four per workgroup); stage 2 a
@@ -514,13 +558,23 @@ int size_grids(hmat_s *h) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return fail(HMAT_E_HIP, "cannot query the device");
+  // stage 1: one wave per item, so each XCD range gets as many workgroups as
+  // its items need (a multiple of 8 in all)
   for (int c = 0; c < NCLS; c++) {
-    const int64_t cnt = h->item_end[c] - h->item_begin[c];
-    h->grid1[c] = (int32_t)std::max<int64_t>(1, (cnt + 3) / 4);
+    int64_t most = 1;
+    for (int x = 0; x < kXcds; x++)
+      most = std::max<int64_t>(most, (h->s1_split[c].lo[x + 1] - h->s1_split[c].lo[x] + kS1Waves - 1) / kS1Waves);
+    h->grid1[c] = (int32_t)(most * kXcds);
   }
+  // stage 2: persistent, as many workgroups as fit on the device at once (a
+  // multiple of 8, at most 8 per chunk range), whose per-workgroup partials
+  // the fused inner products reduce
   int per = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, stage2_fn(h->cls_mask), kS2Threads, 0) != hipSuccess || per < 1) per = 1;
-  h->grid2 = (int32_t)std::max<int64_t>(1, std::min<int64_t>(h->nchunks, (int64_t)per * cus));
+  int64_t most = 1;
+  for (int x = 0; x < kXcds; x++) most = std::max<int64_t>(most, h->s2_split.lo[x + 1] - h->s2_split.lo[x]);
+  const int64_t slots = std::max<int64_t>(1, (int64_t)per * cus / kXcds);
+  h->grid2 = (int32_t)(std::min<int64_t>(most, slots) * kXcds);
   return HMAT_OK;
 }
 
@@ -540,22 +594,35 @@ int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int
   for (int c = 0; c < NCLS; c++) {
     const int64_t cnt = h->item_end[c] - h->item_begin[c];
     if (cnt <= 0) continue;
-    hipLaunchKernelGGL(stage1_fn(c), dim3((unsigned)h->grid1[c], (unsigned)nrhs), blk, 0, st,
-                       h->items + h->item_begin[c], cnt, (const void *)h->vals[c], x, ld, h->x32, h->zpart,
-                       h->zpart_len, skip);
+    hipLaunchKernelGGL(stage1_fn(c), dim3((unsigned)h->grid1[c], (unsigned)nrhs), dim3(kS1Waves * kWave), 0, st,
+                       h->items + h->item_begin[c], h->s1_split[c], (const void *)h->vals[c], x, ld, h->x32,
+                       h->zpart, h->zpart_len, h->dscale, h->z32, h->src, h->src_len, h->n, skip);
   }
   prof_mark(h, 1, stream);
-  {
-    const int64_t tot = h->n + h->zlen + 1;
-    dim3 grd((unsigned)((tot + 255) / 256), (unsigned)nrhs);
-    hipLaunchKernelGGL(k_stage1b, grd, blk, 0, st, h->n, h->zlen, x, ld, h->x32, h->z32, h->zinfo, h->dscale,
-                       h->zpart, h->zpart_len, h->src, h->src_len, skip);
+  if (h->zlen > h->zw0) {
+    dim3 grd((unsigned)((h->zlen - h->zw0 + 255) / 256), (unsigned)nrhs);
+    hipLaunchKernelGGL(k_stage1b, grd, blk, 0, st, h->n, h->zw0, h->zlen, h->z32, h->zinfo, h->dscale, h->zpart,
+                       h->zpart_len, h->src, h->src_len, skip);
+  }
+  // stage 2 gathers x directly unless y overlaps it (y may alias x): then
+  // x_eff goes to the unused head of src first and is gathered from there
+  const double *xs = x;
+  int64_t ldxs = ld;
+  int x32 = h->x32;
+  const char *xb = (const char *)x, *xe = (const char *)(x + (nrhs - 1) * ld + h->n);
+  const char *yb = (const char *)y, *ye = (const char *)(y + (nrhs - 1) * ld + h->n);
+  if (xb < ye && yb < xe) {
+    dim3 grd((unsigned)((h->n + 255) / 256), (unsigned)nrhs);
+    hipLaunchKernelGGL(k_copy_x, grd, blk, 0, st, h->n, x, ld, h->x32, h->src, h->src_len, skip);
+    xs = h->src;
+    ldxs = h->src_len;
+    x32 = 0;
   }
   prof_mark(h, 2, stream);
-  hipLaunchKernelGGL(stage2_fn(h->cls_mask), dim3((unsigned)h->grid2, (unsigned)nrhs), dim3(kS2Threads), 0, st, h->chunks,
-                     h->nchunks, (const double *)h->vals[F64], (const float *)h->vals[F32],
+  hipLaunchKernelGGL(stage2_fn(h->cls_mask), dim3((unsigned)h->grid2, (unsigned)nrhs), dim3(kS2Threads), 0, st,
+                     h->chunks, h->s2_split, (const double *)h->vals[F64], (const float *)h->vals[F32],
                      (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16], h->src,
-                     h->src_len, y, ld, skip, d);
+                     h->src_len, xs, ldxs, x32, h->n, y, ld, skip, d);
   prof_mark(h, 3, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(HMAT_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
@@ -624,6 +691,15 @@ static int build_planned(Packed *P, const hmat_plan_info &info, void *dev_mem, u
   if (e != hipSuccess) {
     delete h;
     return fail(HMAT_E_HIP, "copy to device failed: %s", hipGetErrorString(e));
+  }
+  if (!h->mr) {  // the zero slot of src that padding columns gather (never written by a product)
+    for (int32_t r = 0; r < h->nrhs_max && e == hipSuccess; r++)
+      e = hipMemsetAsync(h->src + (int64_t)r * h->src_len + h->n + h->zlen, 0, sizeof(double), st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      delete h;
+      return fail(HMAT_E_HIP, "workspace initialisation failed: %s", hipGetErrorString(e));
+    }
   }
   if ((rc = h->mr ? size_grids_mr(h) : size_grids(h)) != HMAT_OK) {
     delete h;

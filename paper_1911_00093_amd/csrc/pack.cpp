@@ -112,6 +112,8 @@ struct Packed {
   std::vector<ZInfo> zinfo;
   std::vector<double> dscale;
   int64_t zlen = 0, zpart_len = 0;
+  int64_t zw0 = 0;  // first z entry of the groups wider than one stage-1 item
+  XcdSplit s1_split[NCLS]{}, s2_split{};
   int64_t vals_elems[NCLS] = {0, 0, 0};
   int64_t gidx_elems[NCLS] = {0, 0, 0};
   DevLayout lay{};
@@ -415,34 +417,60 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
       P->groups[it->second].rows.emplace_back(k, t);
     }
   }
-  int64_t z = 0, zp = 0;
   struct ItemSrc {
     S1Item it;
     int64_t group, k0, c0;
   };
   std::vector<ItemSrc> isrc;
-  for (auto &kv : gmap) {  // key order: class, then column range
+  // column chunks per group; z numbering: the groups one item wide first
+  // (their items finish z themselves), then the wider ones, whose entries
+  // [zw0, zlen) the stage-1 reduction finishes
+  auto chunk_cols = [&](const Group &g) {
+    return P->mr ? (int64_t)kMRCols : std::max<int64_t>((int64_t)s1_lpr(g.cls, g.ncols) * vec_of(g.cls), kS1Cols);
+  };
+  for (auto &kv : gmap) {
+    Group &g = P->groups[kv.second];
+    const int64_t CH = chunk_cols(g);
+    g.nch = (g.ncols + CH - 1) / CH;
+  }
+  int64_t z = 0, zp = 0;
+  for (int pass = 0; pass < 2; pass++)
+    for (auto &kv : gmap) {  // key order: class, then column range
+      Group &g = P->groups[kv.second];
+      if ((g.nch > 1) != (pass == 1)) continue;
+      g.z0 = z;
+      g.zp0 = zp;
+      z += (int64_t)g.rows.size();
+      zp += g.nch * (int64_t)g.rows.size();
+    }
+  {
+    int64_t narrow = 0;
+    for (auto &kv : gmap)
+      if (P->groups[kv.second].nch == 1) narrow += (int64_t)P->groups[kv.second].rows.size();
+    P->zw0 = narrow;
+  }
+  P->zinfo.assign(z, ZInfo{0, 1, 1});
+  P->dscale.assign(z, 0.0);
+  for (auto &kv : gmap) {
     Group &g = P->groups[kv.second];
     const int64_t R = (int64_t)g.rows.size();
     const int cls = g.cls;
     const int lpr = s1_lpr(cls, g.ncols);
-    const int64_t CH = P->mr ? kMRCols : std::max<int64_t>((int64_t)lpr * vec_of(cls), kS1Cols);
+    const int64_t CH = chunk_cols(g);
     const int64_t RB = P->mr ? kRowChunk : (int64_t)kRowsPerLane * (kWave / lpr);  // rows per item
-    g.z0 = z;
-    g.zp0 = zp;
-    g.nch = (g.ncols + CH - 1) / CH;
     for (int64_t k = 0; k < R; k++) {
       auto [blk, t] = g.rows[k];
-      P->terms[blk][t].zidx = z + k;
-      P->zinfo.push_back({zp + k, (int32_t)g.nch, (int32_t)R});
-      P->dscale.push_back(P->terms[blk][t].d);
+      P->terms[blk][t].zidx = g.z0 + k;
+      P->zinfo[g.z0 + k] = {g.zp0 + k, (int32_t)g.nch, (int32_t)R};
+      P->dscale[g.z0 + k] = P->terms[blk][t].d;
     }
     for (int64_t ch = 0; ch < g.nch; ch++) {
       const int64_t c0 = ch * CH, cn = std::min(CH, g.ncols - c0);
       for (int64_t k0 = 0; k0 < R; k0 += RB) {
         S1Item it{};
         it.x0 = g.col0 + c0;
-        it.out_off = zp + ch * R + k0;
+        it.out_off = g.zp0 + ch * R + k0;
+        it.z_off = g.nch == 1 ? g.z0 + k0 : -1;
         it.ncols = (int32_t)cn;
         it.nrows = (int32_t)std::min<int64_t>(RB, R - k0);
         it.cls = cls;
@@ -450,8 +478,6 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
         isrc.push_back({it, kv.second, k0, c0});
       }
     }
-    z += R;
-    zp += g.nch * R;
   }
   P->zlen = z;
   P->zpart_len = zp;
@@ -487,11 +513,36 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
     for (size_t q : ord) sorted.push_back(isrc[q]);
     isrc.swap(sorted);
   } else {
-    std::stable_sort(isrc.begin(), isrc.end(), [&](const ItemSrc &a, const ItemSrc &c) {
-      if (a.it.cls != c.it.cls) return a.it.cls < c.it.cls;  // one launch per class
-      return (int64_t)a.it.ncols * a.it.nrows * bytes_of(a.it.cls) >
-             (int64_t)c.it.ncols * c.it.nrows * bytes_of(c.it.cls);
+    // one launch per class; per class, XCD ranges over the items in
+    // column-group order balanced by bytes (the x columns a range reads stay
+    // in its XCD's L2), and within a range the largest items first so the
+    // tail of the launch is short
+    std::stable_sort(isrc.begin(), isrc.end(), [](const ItemSrc &a, const ItemSrc &c) { return a.it.cls < c.it.cls; });
+    std::vector<int> region(isrc.size(), 0);
+    for (size_t b = 0; b < isrc.size();) {
+      const int c = isrc[b].it.cls;
+      size_t e = b;
+      while (e < isrc.size() && isrc[e].it.cls == c) e++;
+      std::vector<double> cost(e - b);
+      for (size_t q = b; q < e; q++)
+        cost[q - b] = (double)isrc[q].it.ncols * isrc[q].it.nrows * bytes_of(c) + 8.0 * isrc[q].it.ncols;
+      P->s1_split[c] = xcd_split(cost);
+      for (int x = 0; x < kXcds; x++)
+        for (int64_t q = P->s1_split[c].lo[x]; q < P->s1_split[c].lo[x + 1]; q++) region[b + q] = x;
+      b = e;
+    }
+    std::vector<size_t> ord(isrc.size());
+    for (size_t q = 0; q < ord.size(); q++) ord[q] = q;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t c) {
+      const S1Item &A = isrc[a].it, &B = isrc[c].it;
+      if (A.cls != B.cls) return A.cls < B.cls;
+      if (region[a] != region[c]) return region[a] < region[c];
+      return (int64_t)A.ncols * A.nrows > (int64_t)B.ncols * B.nrows;
     });
+    std::vector<ItemSrc> sorted;
+    sorted.reserve(isrc.size());
+    for (size_t q : ord) sorted.push_back(isrc[q]);
+    isrc.swap(sorted);
   }
   for (auto &q : isrc) {
     const int c = q.it.cls;
@@ -569,8 +620,23 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
   // (multi-RHS: row order, so chunks sharing z and x operands are neighbours,
   // within the XCD piece of each chunk's system)
   if (!P->mr) {
-    std::stable_sort(P->chunk_order.begin(), P->chunk_order.end(),
-                     [&](int64_t a, int64_t c) { return cbytes(a) > cbytes(c); });
+    // XCD ranges of chunks in row order balanced by bytes (the rows of a
+    // range gather their x and z operands from one XCD's L2); within a
+    // range, most bytes first
+    std::vector<double> cost(P->chunks.size());
+    for (size_t i = 0; i < P->chunks.size(); i++) {
+      int64_t cols = 0;
+      for (int c = 0; c < NCLS; c++) cols += P->chunks[i].K[c];
+      cost[i] = (double)cbytes((int64_t)i) + 12.0 * cols;
+    }
+    P->s2_split = xcd_split(cost);
+    std::vector<int> region(P->chunks.size(), 0);
+    for (int x = 0; x < kXcds; x++)
+      for (int64_t q = P->s2_split.lo[x]; q < P->s2_split.lo[x + 1]; q++) region[q] = x;
+    std::stable_sort(P->chunk_order.begin(), P->chunk_order.end(), [&](int64_t a, int64_t c) {
+      if (region[a] != region[c]) return region[a] < region[c];
+      return cbytes(a) > cbytes(c);
+    });
   } else {
     std::vector<int32_t> sy(P->chunks.size());
     std::vector<double> co(P->chunks.size());
@@ -1023,6 +1089,9 @@ int pack_into(Packed *P, HostImage &img, hmat_s *h) {
   for (auto &R : P->mrc)
     for (int c = 0; c < NCLS; c++)
       if (R.nkb[c]) h->cls_mask |= 1 << c;
+  h->zw0 = P->zw0;
+  h->s2_split = P->s2_split;
+  for (int c = 0; c < NCLS; c++) h->s1_split[c] = P->s1_split[c];
   h->mr = P->mr;
   h->mr_split2 = P->mr_split2;
   for (int c = 0; c < NCLS; c++) h->mr_split1[c] = P->mr_split1[c];

@@ -119,10 +119,14 @@ def test_multi_rhs_equals_single():
         assert np.array_equal(Y[:, k], yk)
 
 
-def test_deterministic_and_aliasing():
+@pytest.mark.parametrize("variant", [oracle.M1_MIXED, oracle.M1_SINGLE, oracle.M2_SINGLE, oracle.BF16_SCALED])
+def test_deterministic_and_aliasing(variant):
+    """Repeated products are bitwise equal, and an in-place product (y = x,
+    where stage 2 cannot read x while it writes y) equals the out-of-place one
+    bit for bit, the Single variants' rounding of x included."""
     need_gpu()
     m, h = oracle_hmatrix("sphere-L4")
-    H = hmat.HMatrix(blockset(h), oracle.M1_MIXED)
+    H = hmat.HMatrix(blockset(h), variant, c=-1)
     x = to_dev(np.random.default_rng(3).standard_normal(h.n))
     y1 = H.matvec(x).cpu().numpy()
     y2 = H.matvec(x).cpu().numpy()
