@@ -164,6 +164,8 @@ def main():
                     help="Method 3: split the dense leaves by column with the same c (Sec. 4.5)")
     ap.add_argument("--assembly", default="gpu", choices=["gpu", "host"],
                     help="setup builder: entries and ACA on the GPU (default) or on the host threads")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="single-system workloads: keep the untuned launch configuration")
     ap.add_argument("--train-leaves", type=int, default=20000)
     ap.add_argument("--epochs", type=int, default=100)
     args = ap.parse_args()
@@ -206,6 +208,14 @@ def main():
     H64 = hmat.HMatrix(bs, hmat.M1_DOUBLE)
     Hm = hmat.HMatrix(bs, variant, c=args.c, drop=args.drop, dense_split=args.dense_split)
     log(f"[setup] builds {time.time() - t0:.1f}s")
+    tune = {}
+    if not args.no_autotune:  # launch configuration per handle, timed on its own blocks (results unchanged)
+        t0 = time.time()
+        for name, H in (("M1-Double", H64), (args.variant, Hm)):
+            info = H.autotune(reps=10)
+            tune[name] = {k: info[k] for k in ("stage1_grid", "stage2_grid", "stage2_tile")}
+            tune[name].update(ms_fixed=round(info["ms_fixed"], 4), ms_tuned=round(info["ms_tuned"], 4))
+        log(f"[setup] autotune {time.time() - t0:.1f}s: {tune}")
     st64, stm = H64.stats(), Hm.stats()
     B64, Bm = st64.algorithmic_bytes, stm.algorithmic_bytes
     b = torch.as_tensor(mesh.rhs()[bs.perm], device=dev)
@@ -398,6 +408,8 @@ def main():
         "bytes_per_matvec": {"mixed": int(Bm), "fp64": int(B64),
                              "mixed_stage1": int(k1_bytes), "mixed_stage2": int(k2_bytes)},
         "matvec_only": matvec_gbs,
+        "autotune": tune or None,
+        "row_chunks": int(stm.row_chunks),
         "kernel_ms_in_solves": {"stage1": solve_kernel_ms[0], "stage1_reduce": solve_kernel_ms[1],
                                 "stage2": solve_kernel_ms[2], "launched": kcount_p, "executed": executed,
                                 "note": "event time of the replica solves over the products that executed"},

@@ -161,21 +161,31 @@ int hmat_build(const hmat_blocks *blocks, const hmat_build_opts *opts, void *dev
  * order differs. */
 int hmat_matvec(hmat_t h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream);
 
-/* Tuning of a multi-right-hand-side handle (nrhs_max > 1; not from the
- * paper): for each stage-1 storage class and for stage 2, times every
- * choice of column blocks loaded per batch (1, 2, 4) and grid (persistent
- * at full or half occupancy, or one wave per work unit) on this handle's
- * own blocks, and keeps the fastest for later products.  x: device, n x min(16, nrhs_max) FP64
- * column-major (ld = n), the timing input; y (same shape) receives products.
- * reps: timed launches per choice (1 .. 1000).  Results are unchanged by the
- * choice (same arithmetic, same summation order).  Synchronises `stream`. */
+/* Tuning of a handle's launch configuration (not from the paper), timed on
+ * the handle's own blocks; the fastest choice is kept for later products of
+ * that handle.  Results are unchanged by the choice (same arithmetic, same
+ * summation order; the solver's fused inner products are kept per row chunk,
+ * so its iterations do not change either).
+ *  Multi-right-hand-side handles (nrhs_max > 1): for each stage-1 storage
+ *  class and for stage 2, the column blocks loaded per batch (1, 2, 4) and
+ *  the grid (0 persistent at full occupancy, 1 at half occupancy, 2 one wave
+ *  per work unit).
+ *  Single-vector handles (nrhs_max = 1): for each stage-1 storage class the
+ *  grid (0 one wave per item, 1 persistent at full occupancy, 2 at half), and
+ *  for stage 2 the grid (0 persistent at full occupancy, 1 at half, 2 one
+ *  workgroup per row chunk) and the operand tile, the panel columns whose
+ *  operands are staged in LDS per pass (1024, 2048 or 4096).
+ * x: device, n x min(16, nrhs_max) FP64 column-major (ld = n), the timing
+ * input; y (same shape) receives products.  reps: timed launches per choice
+ * (1 .. 1000).  Synchronises `stream`. */
 typedef struct {
-    int32_t stage1_batch[3];  /* per storage class FP64 / FP32 / BF16 (0: no items) */
-    int32_t stage1_grid[3];   /* 0: persistent, 1: persistent at half occupancy, 2: one wave per item */
-    int32_t stage2_batch, stage2_grid;  /* grid as above, per output chunk */
-    double ms_fixed;          /* one product with the default choice (batch 2; stage 1
-                                 persistent, stage 2 one wave per chunk) */
+    int32_t stage1_batch[3];  /* per storage class FP64 / FP32 / BF16 (0: no items; 1 on single-vector handles) */
+    int32_t stage1_grid[3];   /* grid mode per storage class (see above) */
+    int32_t stage2_batch, stage2_grid;  /* batch (0 on single-vector handles) and grid mode of stage 2 */
+    double ms_fixed;          /* one product with the configuration before tuning */
     double ms_tuned;          /* one product with the chosen configuration */
+    int32_t stage2_tile;      /* single-vector handles: operand tile chosen (0 otherwise) */
+    int32_t reserved;
 } hmat_tune_info;
 
 int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps, hmat_tune_info *info, void *stream);

@@ -20,7 +20,7 @@ constexpr int kRowChunk = 64;     // rows owned by one stage-2 workgroup
 constexpr int kS2Waves = 8;       // waves per stage-2 workgroup (rows interleaved)
 constexpr int kRowsPerLane = 8;   // row accumulators per lane (stage 1 and stage 2)
 constexpr int kS2Threads = kS2Waves * kWave;
-constexpr int kS2Tile = 2048;     // gathered operands staged in LDS per pass (FP64)
+constexpr int kS2Tile = 2048;     // gathered operands staged in LDS per pass (FP64), untuned
 constexpr int kS1Cols = 1024;     // stage-1 item width (columns) for wide groups
 
 // elements per 16-byte lane load
@@ -161,7 +161,7 @@ struct DevLayout {
   uint64_t off_vals[NCLS], bytes_vals[NCLS];
   uint64_t off_gidx[NCLS], bytes_gidx[NCLS];
   uint64_t off_chunks, off_items, off_zinfo, off_dscale;
-  uint64_t off_src, off_zpart;
+  uint64_t off_src, off_zpart, off_dpart;
   uint64_t off_mrc, off_mri, off_src64;  // multi-RHS layout
   uint64_t ws_begin;  // everything before this offset is packed at build
   uint64_t total;
@@ -195,6 +195,11 @@ struct hmat_s {
   // XCD ranges: stage-1 items of each class (relative to item_begin) and
   // stage-2 chunks, each range served by the workgroups b with b % 8 == x
   hm::XcdSplit s1_split[hm::NCLS]{}, s2_split{};
+  // launch configuration (hmat_autotune): stage-1 grid per class (0 one wave
+  // per item, 1 persistent, 2 persistent at half occupancy), stage-2 grid
+  // (0 persistent, 1 persistent at half occupancy, 2 one workgroup per
+  // chunk) and operand tile (1024, 2048 or 4096 columns)
+  int32_t s1_mode[hm::NCLS] = {0, 0, 0}, s2_mode = 0, s2_tile = hm::kS2Tile;
   // multi-RHS (MFMA) layout
   bool mr = false;
   int64_t mr_nitems[hm::NCLS] = {0, 0, 0}, mr_item_begin[hm::NCLS] = {0, 0, 0};
@@ -209,6 +214,7 @@ struct hmat_s {
   std::vector<int64_t> sys_off;  // system boundaries of a batched handle
   double *src = nullptr;    // nrhs_max x (n + zlen + 1)
   double *zpart = nullptr;  // nrhs_max x zpart_len
+  double *dpart = nullptr;  // 3 x nchunks: per-chunk partials of the fused inner products (S2Dot)
   // kept for the block-Jacobi preconditioner and diagnostics
   std::vector<int64_t> diag_r0, diag_m;
   hm::Prof *prof = nullptr;  // non-null while kernel timing is enabled
@@ -259,17 +265,17 @@ void packed_free(Packed *p);
 XcdSplit xcd_split(const std::vector<double> &cost);
 
 // Inner products of the product's result y, fused into stage 2 (one
-// right-hand side): every stage-2 workgroup b sums, over the rows it
-// writes, y_i w1_i (mode 1) or y_i y_i and y_i w2_i (mode 2), and writes the
-// sums to part[4 b + slot], slot = slot0 and slot0 + 1; workgroup 0 also
-// zeroes those slots of the workgroups b in [grid2, nparts), so a consumer
-// can always sum nparts partials in index order.
+// right-hand side): for every row chunk c (its position in launch order),
+// the workgroup that writes it sums y_i w1_i over the chunk's rows (mode 1,
+// into part[c]) or y_i y_i and y_i w2_i (mode 2, into part[2c], part[2c+1]),
+// in a fixed order.  The partials depend only on the chunks, not on the
+// launch grid, so a consumer summing them in chunk order gets the same value
+// whatever grid stage 2 ran on.  part holds the handle's dot_partials()
+// (3 x nchunks doubles: mode 1 uses the first nchunks, mode 2 the rest).
 struct S2Dot {
   const double *w1, *w2;
   double *part;
   int32_t mode;   // 0 none, 1 y.w1, 2 y.y and y.w2
-  int32_t slot0;  // first slot of part[4 b + ...]
-  int32_t nparts;
   int32_t pad;
 };
 
@@ -277,11 +283,14 @@ struct S2Dot {
 // skip: optional device flag read by every product kernel at its start; a
 // nonzero value makes the product a no-op (a solver whose recurrence has
 // stopped inside a batch of queued iterations).
-// dot: optional fused inner products (single-vector handles, nrhs == 1,
-// grid2 <= dot->nparts: see matvec_dot_fusable).
+// dot: optional fused inner products (single-vector handles, nrhs == 1: see
+// matvec_dot_fusable); dot->part must be h->dpart (mode 1) or
+// h->dpart + nchunks (mode 2).
 int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream,
                   const int32_t *skip = nullptr, const S2Dot *dot = nullptr);
-bool matvec_dot_fusable(const hmat_s *h, int nparts);
+bool matvec_dot_fusable(const hmat_s *h);
+// hmat_autotune for single-vector handles (matvec.hip)
+int autotune_sv(hmat_s *h, const double *x, double *y, int reps, hmat_tune_info *info, void *stream);
 int size_grids(hmat_s *h);
 // active (multi-RHS only): optional device array, one entry per system of a
 // batched handle; the units (stage-1 items, stage-2 chunks) of a system

@@ -9,7 +9,9 @@
 // One small single-workgroup kernel per iteration ("finalize") owns the
 // status word; the host reads it every `poll_every` iterations.  On
 // single-vector handles the two inner products of the product results are
-// taken by the products' stage 2 itself (one partial per stage-2 workgroup).
+// taken by the products' stage 2 itself (one partial per row chunk, summed
+// in chunk order by the consumers, so the result does not depend on the
+// grid stage 2 runs on).
 //
 // Per iteration (right preconditioning with K; K = I when none):
 //   p <- r (restart) or r + beta (p - omega v);  p^ = K p
@@ -115,6 +117,29 @@ __device__ __forceinline__ void sum_parts(const double *part, const int (&slot)[
   for (int q = 0; q < NV; q++) out[q] = v[q];
 }
 
+// Where the consumers find r~^T v, t^T t and t^T s: the per-workgroup
+// partials of the separate inner-product kernels (kParts entries of `part`,
+// stride 4) or the per-chunk partials of the products' fused stage 2
+// (h_iter->dpart, in chunk order).  Either way a fixed order.
+struct DotSrc {
+  const double *p;
+  int64_t count;
+  int32_t stride, off;
+};
+template <int NV>
+__device__ __forceinline__ void sum_src(const DotSrc &d, double (&out)[NV], double (*lds)[kThreads / 64]) {
+  double v[NV];
+#pragma unroll
+  for (int q = 0; q < NV; q++) {
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < d.count; i += kThreads) a += d.p[i * d.stride + d.off + q];
+    v[q] = a;
+  }
+  block_sum<NV>(v, lds);
+#pragma unroll
+  for (int q = 0; q < NV; q++) out[q] = v[q];
+}
+
 #define GRID_LOOP(i, n) for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < (n); i += (int64_t)kParts * kThreads)
 
 // r = b - Ax (Ax in tmp), r~ = r; partials: slot0 = r~^T r, slot1 = |r|^2, slot2 = |b|^2
@@ -186,12 +211,11 @@ __global__ __launch_bounds__(kThreads) void k_dot_rtv(int64_t n, const SolverSta
 // alpha = rho / r~^T v; s = r - alpha v; partial |s|^2 -> slot 1
 __global__ __launch_bounds__(kThreads) void k_supdate(int64_t n, SolverState *__restrict__ st,
                                                       const double *__restrict__ r, const double *__restrict__ v,
-                                                      double *__restrict__ s, double *__restrict__ part) {
+                                                      double *__restrict__ s, double *__restrict__ part, DotSrc dv) {
   if (st->flag != 0) return;
   __shared__ double lds[4][kThreads / 64];
-  const int sl[1] = {0};
   double rtv[1];
-  sum_parts<1>(part, sl, rtv, lds);
+  sum_src<1>(dv, rtv, lds);
   const double alpha = st->rho / rtv[0];
   double a[1] = {0};
   if (rtv[0] != 0.0) {
@@ -234,12 +258,18 @@ __global__ __launch_bounds__(kThreads) void k_xupdate(int64_t n, SolverState *__
                                                       const double *__restrict__ rt, const double *__restrict__ ph,
                                                       const double *__restrict__ s, const double *__restrict__ sh,
                                                       const double *__restrict__ t, double *__restrict__ part,
-                                                      double *__restrict__ aux) {
+                                                      double *__restrict__ aux, DotSrc dv, DotSrc dt) {
   if (st->flag != 0) return;
   __shared__ double lds[4][kThreads / 64];
-  const int sl[4] = {0, 1, 2, 3};
-  double q[4];
-  sum_parts<4>(part, sl, q, lds);  // rtv, |s|^2, t^T t, t^T s
+  const int sl[1] = {1};
+  double q[4], q0[1], q1[1], q23[2];
+  sum_src<1>(dv, q0, lds);          // r~^T v
+  sum_parts<1>(part, sl, q1, lds);  // |s|^2
+  sum_src<2>(dt, q23, lds);         // t^T t, t^T s
+  q[0] = q0[0];
+  q[1] = q1[0];
+  q[2] = q23[0];
+  q[3] = q23[1];
   const double alpha = st->alpha;
   const double snorm = sqrt(q[1]) / st->bnorm;
   int mode;  // 0 breakdown (no update), 1 s-converged, 2 full step
@@ -718,21 +748,23 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
   // On single-vector handles the inner products r~^T v and t^T t, t^T s are
   // fused into the products' stage 2 (one partial per stage-2 workgroup, in
   // the same partial slots the separate kernels fill).
-  const bool fuse = matvec_dot_fusable(h_iter, kParts);
-  const S2Dot dot_v{w.rt, nullptr, w.part, 1, 0, kParts, 0};  // slot 0: r~^T v
-  const S2Dot dot_t{nullptr, w.s, w.part, 2, 2, kParts, 0};   // slots 2, 3: t^T t, t^T s
+  const bool fuse = matvec_dot_fusable(h_iter);
+  const S2Dot dot_v{w.rt, nullptr, h_iter->dpart, 1, 0};                    // r~^T v per chunk
+  const S2Dot dot_t{nullptr, w.s, h_iter->dpart + h_iter->nchunks, 2, 0};  // t^T t, t^T s per chunk
+  const DotSrc dv = fuse ? DotSrc{h_iter->dpart, h_iter->nchunks, 1, 0} : DotSrc{w.part, kParts, 4, 0};
+  const DotSrc dt = fuse ? DotSrc{h_iter->dpart + h_iter->nchunks, h_iter->nchunks, 2, 0} : DotSrc{w.part, kParts, 4, 2};
   auto iteration = [&](hipStream_t s2) -> int {
     hipLaunchKernelGGL(k_pupdate, G, B, 0, s2, n, w.st, w.r, w.p, w.v);
     if (pre) hmat_precond_apply(o->precond, w.p, w.ph, s2);
     int r2 = fuse ? launch_matvec(h_iter, ph, w.v, 1, n, s2, stopped, &dot_v) : product(h_iter, ph, w.v, s2, stopped);
     if (r2) return r2;
     if (!fuse) hipLaunchKernelGGL(k_dot_rtv, G, B, 0, s2, n, w.st, w.rt, w.v, w.part);
-    hipLaunchKernelGGL(k_supdate, G, B, 0, s2, n, w.st, w.r, w.v, w.s, w.part);
+    hipLaunchKernelGGL(k_supdate, G, B, 0, s2, n, w.st, w.r, w.v, w.s, w.part, dv);
     if (pre) hmat_precond_apply(o->precond, w.s, w.sh, s2);
     r2 = fuse ? launch_matvec(h_iter, sh, w.t, 1, n, s2, stopped, &dot_t) : product(h_iter, sh, w.t, s2, stopped);
     if (r2) return r2;
     if (!fuse) hipLaunchKernelGGL(k_dot_t, G, B, 0, s2, n, w.st, w.t, w.s, w.part);
-    hipLaunchKernelGGL(k_xupdate, G, B, 0, s2, n, w.st, x, w.r, w.rt, ph, w.s, sh, w.t, w.part, bank);
+    hipLaunchKernelGGL(k_xupdate, G, B, 0, s2, n, w.st, x, w.r, w.rt, ph, w.s, sh, w.t, w.part, bank, dv, dt);
     hipLaunchKernelGGL(k_finalize, dim3(1), B, 0, s2, w.st, bank, w.hist);
     return HMAT_OK;
   };

@@ -295,11 +295,12 @@ __device__ __forceinline__ double s2_round(const S2Src &o, int32_t k, double v) 
   return (o.x32 && k < o.n) ? (double)(float)v : v;
 }
 
-// The workgroup gathers the operands of columns gi[k], k < kn <= kS2Tile,
+// The workgroup gathers the operands of columns gi[k], k < kn <= TILE,
 // into LDS.  The index loads are unconditional (indices past kn repeat the
 // last one), so that each thread's loads issue together.
+template <int TILE>
 __device__ __forceinline__ void s2_gather(const int32_t *gi, int kn, const S2Src &o, double *g) {
-  constexpr int PER = kS2Tile / kS2Threads;
+  constexpr int PER = TILE / kS2Threads;
   if (kn <= 0) return;  // uniform
   int32_t k[PER];
   double v[PER];
@@ -314,18 +315,18 @@ __device__ __forceinline__ void s2_gather(const int32_t *gi, int kn, const S2Src
 
 // One storage class of a chunk (chunks with several classes): each tile of
 // operands is gathered into LDS, then streamed.
-template <int CLS>
+template <int CLS, int TILE>
 __device__ __forceinline__ void s2_class(const RowChunk &ch, const void *vals, const int32_t *gidx,
                                          const S2Src &src, double *gbuf, double (&acc)[kRowsPerLane], int wave,
                                          int lane) {
   const int ld = ch.ld[CLS];
   if (ld == 0) return;  // uniform over the workgroup
   const int32_t *gi = gidx + ch.gidx_off[CLS];
-  static_assert(kS2Tile % (kWave * vec_of(CLS)) == 0, "LDS tiles hold whole slabs");
-  for (int kt0 = 0; kt0 < ld; kt0 += kS2Tile) {
-    const int kn = min(kS2Tile, ld - kt0);
+  static_assert(TILE % (kWave * vec_of(CLS)) == 0, "LDS tiles hold whole slabs");
+  for (int kt0 = 0; kt0 < ld; kt0 += TILE) {
+    const int kn = min(TILE, ld - kt0);
     __syncthreads();  // the previous tile's operands are no longer read
-    s2_gather(gi + kt0, kn, src, gbuf);
+    s2_gather<TILE>(gi + kt0, kn, src, gbuf);
     __syncthreads();
     s2_slabs<CLS>(ch.panel_off[CLS], ld, ch.h, vals, gbuf, kt0, 0, kn, acc, wave, lane);
   }
@@ -350,10 +351,10 @@ __device__ __forceinline__ void s2_write(int r0, int h, double (&acc)[kRowsPerLa
   }
 }
 
-// The workgroup's fused inner products: fixed-order reduction over its
-// threads, one partial per workgroup (and zeros for the slots of workgroups
-// beyond the grid).  Called by every thread of the workgroup.
-__device__ __forceinline__ void s2_dot_finish(const S2Dot &dot, double (&dacc)[2]) {
+// The fused inner products of one chunk (at launch position c): fixed-order
+// reduction over the workgroup's threads, written by thread 0; dacc is reset.
+// Called by every thread of the workgroup.
+__device__ __forceinline__ void s2_dot_chunk(const S2Dot &dot, double (&dacc)[2], int64_t c) {
   if (dot.mode == 0) return;  // uniform
   __shared__ double red[2][kS2Waves];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
@@ -365,6 +366,7 @@ __device__ __forceinline__ void s2_dot_finish(const S2Dot &dot, double (&dacc)[2
     red[0][wave] = dacc[0];
     red[1][wave] = dacc[1];
   }
+  dacc[0] = dacc[1] = 0.0;
   __syncthreads();
   if (threadIdx.x == 0) {
     double a = 0.0, b = 0.0;
@@ -372,14 +374,14 @@ __device__ __forceinline__ void s2_dot_finish(const S2Dot &dot, double (&dacc)[2
       a += red[0][w];
       b += red[1][w];
     }
-    dot.part[4 * blockIdx.x + dot.slot0] = a;
-    if (dot.mode == 2) dot.part[4 * blockIdx.x + dot.slot0 + 1] = b;
-    if (blockIdx.x == 0)
-      for (int g = gridDim.x; g < dot.nparts; g++) {
-        dot.part[4 * g + dot.slot0] = 0.0;
-        if (dot.mode == 2) dot.part[4 * g + dot.slot0 + 1] = 0.0;
-      }
+    if (dot.mode == 1) {
+      dot.part[c] = a;
+    } else {
+      dot.part[2 * c] = a;
+      dot.part[2 * c + 1] = b;
+    }
   }
+  // red is rewritten only after the workgroup's next barrier
 }
 
 // One storage class in every chunk: the workgroup walks the tiles of its
@@ -400,14 +402,14 @@ __device__ __forceinline__ S2Cur s2_cur(const RowChunk *chunks, int64_t c) {
   return S2Cur{ch.panel_off[CLS], ch.gidx_off[CLS], ch.ld[CLS], ch.r0, ch.h};
 }
 
-template <int CLS>
+template <int CLS, int TILE>
 __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, const XcdSplit &sp,
                                           const void *__restrict__ vals, const int32_t *__restrict__ gidx,
                                           const S2Src &src, double *__restrict__ y, const S2Dot &dot) {
   constexpr int SLAB = kWave * vec_of(CLS);
-  constexpr int PER = kS2Tile / kS2Threads;  // gathered operands per thread and tile
-  static_assert(kS2Tile % kS2Threads == 0 && kS2Tile % SLAB == 0, "whole slabs, equal shares");
-  __shared__ double gbuf[2][kS2Tile];
+  constexpr int PER = TILE / kS2Threads;  // gathered operands per thread and tile
+  static_assert(TILE % kS2Threads == 0 && TILE % SLAB == 0, "whole slabs, equal shares");
+  __shared__ double gbuf[2][TILE];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   double dacc[2] = {0.0, 0.0};
   // this workgroup's chunks: its XCD range, every gx-th from its own
@@ -415,13 +417,10 @@ __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, c
   const int64_t gx = ((int64_t)gridDim.x - xcd + kXcds - 1) / kXcds;
   const int64_t hi = sp.lo[xcd + 1];
   int64_t c = sp.lo[xcd] + blockIdx.x / kXcds;
-  if (c >= hi) {  // uniform over the workgroup
-    s2_dot_finish(dot, dacc);
-    return;
-  }
+  if (c >= hi) return;  // uniform over the workgroup
   S2Cur ch = s2_cur<CLS>(chunks, c);
   int kt0 = 0;
-  s2_gather(gidx + ch.gidx_off, min(kS2Tile, ch.ld), src, gbuf[0]);
+  s2_gather<TILE>(gidx + ch.gidx_off, min(TILE, ch.ld), src, gbuf[0]);
   __syncthreads();
   double acc[kRowsPerLane];
 #pragma unroll
@@ -431,7 +430,7 @@ __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, c
     // the tile after this one: the next of this chunk, else the first of the
     // workgroup's next chunk
     int64_t nc = c;
-    int nkt = kt0 + kS2Tile;
+    int nkt = kt0 + TILE;
     if (nkt >= ch.ld) {
       nc = c + gx;
       nkt = 0;
@@ -439,7 +438,7 @@ __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, c
     const bool more = nc < hi;
     const bool same = nc == c;
     const S2Cur nx = (more && !same) ? s2_cur<CLS>(chunks, nc) : ch;
-    const int nkn = more ? min(kS2Tile, nx.ld - nkt) : 0;
+    const int nkn = more ? min(TILE, nx.ld - nkt) : 0;
     // indices past the tile repeat its last one (unconditional loads; the
     // operands they fetch are not stored)
     int32_t gn[PER];
@@ -450,7 +449,7 @@ __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, c
       for (int j = 0; j < PER; j++)
         gn[j] = gidx[nx.gidx_off + nkt + min((int)threadIdx.x + j * kS2Threads, nkn - 1)];
     }
-    const int kn = min(kS2Tile, ch.ld - kt0);
+    const int kn = min(TILE, ch.ld - kt0);
     const double *gt = gbuf[buf];
     const int first = min(kn, SLAB);
     s2_slabs<CLS>(ch.panel_off, ch.ld, ch.h, vals, gt, kt0, 0, first, acc, wave, lane);
@@ -460,6 +459,7 @@ __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, c
     s2_slabs<CLS>(ch.panel_off, ch.ld, ch.h, vals, gt, kt0, first, kn, acc, wave, lane);
     if (!same) {  // the chunk is complete
       s2_write(ch.r0, ch.h, acc, y, wave, lane, dot, dacc);
+      s2_dot_chunk(dot, dacc, c);
 #pragma unroll
       for (int i = 0; i < kRowsPerLane; i++) acc[i] = 0.0;
     }
@@ -476,16 +476,15 @@ __device__ __forceinline__ void s2_single(const RowChunk *__restrict__ chunks, c
     kt0 = nkt;
     ch = nx;
   }
-  s2_dot_finish(dot, dacc);
 }
 
-template <int MASK>
+template <int MASK, int TILE>
 __device__ __forceinline__ void s2_body(const RowChunk *__restrict__ chunks, const XcdSplit &sp,
                                         const double *__restrict__ v64, const float *__restrict__ v32,
                                         const unsigned short *__restrict__ v16, const int32_t *__restrict__ g64,
                                         const int32_t *__restrict__ g32, const int32_t *__restrict__ g16,
                                         const S2Src &s, double *__restrict__ y, const S2Dot &dot) {
-  __shared__ double gbuf[kS2Tile];
+  __shared__ double gbuf[TILE];
   double dacc[2] = {0.0, 0.0};
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   // this workgroup's chunks: its XCD range, every gx-th from its own
@@ -496,12 +495,12 @@ __device__ __forceinline__ void s2_body(const RowChunk *__restrict__ chunks, con
     double acc[kRowsPerLane];
 #pragma unroll
     for (int i = 0; i < kRowsPerLane; i++) acc[i] = 0.0;
-    if constexpr ((MASK & 1) != 0) s2_class<F64>(ch, v64, g64, s, gbuf, acc, wave, lane);
-    if constexpr ((MASK & 2) != 0) s2_class<F32>(ch, v32, g32, s, gbuf, acc, wave, lane);
-    if constexpr ((MASK & 4) != 0) s2_class<BF16>(ch, v16, g16, s, gbuf, acc, wave, lane);
+    if constexpr ((MASK & 1) != 0) s2_class<F64, TILE>(ch, v64, g64, s, gbuf, acc, wave, lane);
+    if constexpr ((MASK & 2) != 0) s2_class<F32, TILE>(ch, v32, g32, s, gbuf, acc, wave, lane);
+    if constexpr ((MASK & 4) != 0) s2_class<BF16, TILE>(ch, v16, g16, s, gbuf, acc, wave, lane);
     s2_write(ch.r0, ch.h, acc, y, wave, lane, dot, dacc);
+    s2_dot_chunk(dot, dacc, c);
   }
-  s2_dot_finish(dot, dacc);
 }
 
 #define HM_S2_ARGS                                                                                              \
@@ -513,21 +512,21 @@ __device__ __forceinline__ void s2_body(const RowChunk *__restrict__ chunks, con
 // this right-hand side's operand sources
 #define HM_S2_SRC S2Src{src + blockIdx.y * src_len, x + blockIdx.y * ldx, n, x32}
 
-// One storage class: double-buffered operand tiles.
-template <int MASK>
+// One storage class: double-buffered operand tiles of TILE columns.
+template <int MASK, int TILE>
 __global__ __launch_bounds__(kS2Threads, 4) void k_stage2(HM_S2_ARGS) {
   static_assert(MASK == 1 || MASK == 2 || MASK == 4, "one class");
   if (skip && *skip) return;
   constexpr int CLS = MASK == 1 ? F64 : MASK == 2 ? F32 : BF16;
   const void *vals = CLS == F64 ? (const void *)v64 : CLS == F32 ? (const void *)v32 : (const void *)v16;
   const int32_t *gidx = CLS == F64 ? g64 : CLS == F32 ? g32 : g16;
-  s2_single<CLS>(chunks, sp, vals, gidx, HM_S2_SRC, y + blockIdx.y * ldy, dot);
+  s2_single<CLS, TILE>(chunks, sp, vals, gidx, HM_S2_SRC, y + blockIdx.y * ldy, dot);
 }
 // Two or three classes: let the compiler size the registers (no spills).
-template <int MASK>
+template <int MASK, int TILE>
 __global__ __launch_bounds__(kS2Threads) void k_stage2_multi(HM_S2_ARGS) {
   if (skip && *skip) return;
-  s2_body<MASK>(chunks, sp, v64, v32, v16, g64, g32, g16, HM_S2_SRC, y + blockIdx.y * ldy, dot);
+  s2_body<MASK, TILE>(chunks, sp, v64, v32, v16, g64, g32, g16, HM_S2_SRC, y + blockIdx.y * ldy, dot);
 }
 
 static_assert(kRowChunk == kS2Waves * kRowsPerLane, "each wave owns 8 rows of a chunk");
@@ -535,16 +534,21 @@ static_assert(kRowChunk == kS2Waves * kRowsPerLane, "each wave owns 8 rows of a 
 typedef void (*Stage2Fn)(const RowChunk *, XcdSplit, const double *, const float *, const unsigned short *,
                          const int32_t *, const int32_t *, const int32_t *, const double *, int64_t, const double *,
                          int64_t, int, int64_t, double *, int64_t, const int32_t *, S2Dot);
-static Stage2Fn stage2_fn(int mask) {
+template <int TILE>
+static Stage2Fn stage2_fn_t(int mask) {
   switch (mask) {
-    case 1: return k_stage2<1>;
-    case 2: return k_stage2<2>;
-    case 3: return k_stage2_multi<3>;
-    case 4: return k_stage2<4>;
-    case 5: return k_stage2_multi<5>;
-    case 6: return k_stage2_multi<6>;
-    default: return k_stage2_multi<7>;
+    case 1: return k_stage2<1, TILE>;
+    case 2: return k_stage2<2, TILE>;
+    case 3: return k_stage2_multi<3, TILE>;
+    case 4: return k_stage2<4, TILE>;
+    case 5: return k_stage2_multi<5, TILE>;
+    case 6: return k_stage2_multi<6, TILE>;
+    default: return k_stage2_multi<7, TILE>;
   }
+}
+// operand tiles the tuner chooses from (columns gathered into LDS per pass)
+static Stage2Fn stage2_fn(int mask, int tile) {
+  return tile == 1024 ? stage2_fn_t<1024>(mask) : tile == 4096 ? stage2_fn_t<4096>(mask) : stage2_fn_t<2048>(mask);
 }
 typedef void (*Stage1Fn)(const S1Item *, XcdSplit, const void *, const double *, int64_t, int, double *, int64_t,
                          const double *, int, double *, int64_t, int64_t, const int32_t *);
@@ -558,51 +562,66 @@ int size_grids(hmat_s *h) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return fail(HMAT_E_HIP, "cannot query the device");
-  // stage 1: one wave per item, so each XCD range gets as many workgroups as
-  // its items need (a multiple of 8 in all)
-  for (int c = 0; c < NCLS; c++) {
+  // workgroups per XCD range: what the largest range needs (one per work
+  // unit), or, persistent, what fits on the range's share of the device
+  auto per_range = [&](const XcdSplit &sp, int64_t units_per_group, const void *fn, int threads, int mode,
+                       bool one_per_unit_mode) {
     int64_t most = 1;
     for (int x = 0; x < kXcds; x++)
-      most = std::max<int64_t>(most, (h->s1_split[c].lo[x + 1] - h->s1_split[c].lo[x] + kS1Waves - 1) / kS1Waves);
-    h->grid1[c] = (int32_t)(most * kXcds);
+      most = std::max<int64_t>(most, (sp.lo[x + 1] - sp.lo[x] + units_per_group - 1) / units_per_group);
+    if (one_per_unit_mode) return most;
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, 0) != hipSuccess || per < 1) per = 1;
+    const int64_t slots = std::max<int64_t>(1, (int64_t)per * cus / kXcds / (mode == 1 || mode == 2 ? 2 : 1));
+    return std::min<int64_t>(most, slots);
+  };
+  for (int c = 0; c < NCLS; c++) {
+    const int m = h->s1_mode[c];
+    h->grid1[c] = (int32_t)(kXcds * per_range(h->s1_split[c], kS1Waves, (const void *)stage1_fn(c), kS1Waves * kWave,
+                                               m == 2 ? 1 : 0, m == 0));
   }
-  // stage 2: persistent, as many workgroups as fit on the device at once (a
-  // multiple of 8, at most 8 per chunk range), whose per-workgroup partials
-  // the fused inner products reduce
-  int per = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, stage2_fn(h->cls_mask), kS2Threads, 0) != hipSuccess || per < 1) per = 1;
-  int64_t most = 1;
-  for (int x = 0; x < kXcds; x++) most = std::max<int64_t>(most, h->s2_split.lo[x + 1] - h->s2_split.lo[x]);
-  const int64_t slots = std::max<int64_t>(1, (int64_t)per * cus / kXcds);
-  h->grid2 = (int32_t)(std::min<int64_t>(most, slots) * kXcds);
+  const int m2 = h->s2_mode;
+  h->grid2 = (int32_t)(kXcds * per_range(h->s2_split, 1, (const void *)stage2_fn(h->cls_mask, h->s2_tile), kS2Threads,
+                                          m2, m2 == 2));
   return HMAT_OK;
 }
 
-bool matvec_dot_fusable(const hmat_s *h, int nparts) { return !h->mr && h->grid2 >= 1 && h->grid2 <= nparts; }
+bool matvec_dot_fusable(const hmat_s *h) { return !h->mr && h->nchunks >= 1; }
+
+static void launch_stage1(const hmat_s *h, int c, const double *x, int64_t ld, int64_t nrhs, hipStream_t st,
+                          const int32_t *skip) {
+  const int64_t cnt = h->item_end[c] - h->item_begin[c];
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(stage1_fn(c), dim3((unsigned)h->grid1[c], (unsigned)nrhs), dim3(kS1Waves * kWave), 0, st,
+                     h->items + h->item_begin[c], h->s1_split[c], (const void *)h->vals[c], x, ld, h->x32, h->zpart,
+                     h->zpart_len, h->dscale, h->z32, h->src, h->src_len, h->n, skip);
+}
+
+// stage 2 with x_eff taken from xs (ldxs, rounded to FP32 when x32)
+static void launch_stage2(const hmat_s *h, const double *xs, int64_t ldxs, int x32, double *y, int64_t ld,
+                          int64_t nrhs, hipStream_t st, const int32_t *skip, const S2Dot &d) {
+  hipLaunchKernelGGL(stage2_fn(h->cls_mask, h->s2_tile), dim3((unsigned)h->grid2, (unsigned)nrhs), dim3(kS2Threads),
+                     0, st, h->chunks, h->s2_split, (const double *)h->vals[F64], (const float *)h->vals[F32],
+                     (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16], h->src,
+                     h->src_len, xs, ldxs, x32, h->n, y, ld, skip, d);
+}
 
 int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int64_t ld, void *stream,
                   const int32_t *skip, const S2Dot *dot) {
   S2Dot d{};
   if (dot && dot->mode != 0) {
-    if (nrhs != 1 || !matvec_dot_fusable(h, dot->nparts))
-      return fail(HMAT_E_ARG, "fused inner products need one right-hand side and a stage-2 grid within the partials");
+    if (nrhs != 1 || !matvec_dot_fusable(h))
+      return fail(HMAT_E_ARG, "fused inner products need a single-vector handle and one right-hand side");
     d = *dot;
   }
   hipStream_t st = (hipStream_t)stream;
-  const dim3 blk(256);
   prof_mark(h, 0, stream);
-  for (int c = 0; c < NCLS; c++) {
-    const int64_t cnt = h->item_end[c] - h->item_begin[c];
-    if (cnt <= 0) continue;
-    hipLaunchKernelGGL(stage1_fn(c), dim3((unsigned)h->grid1[c], (unsigned)nrhs), dim3(kS1Waves * kWave), 0, st,
-                       h->items + h->item_begin[c], h->s1_split[c], (const void *)h->vals[c], x, ld, h->x32,
-                       h->zpart, h->zpart_len, h->dscale, h->z32, h->src, h->src_len, h->n, skip);
-  }
+  for (int c = 0; c < NCLS; c++) launch_stage1(h, c, x, ld, nrhs, st, skip);
   prof_mark(h, 1, stream);
   if (h->zlen > h->zw0) {
     dim3 grd((unsigned)((h->zlen - h->zw0 + 255) / 256), (unsigned)nrhs);
-    hipLaunchKernelGGL(k_stage1b, grd, blk, 0, st, h->n, h->zw0, h->zlen, h->z32, h->zinfo, h->dscale, h->zpart,
-                       h->zpart_len, h->src, h->src_len, skip);
+    hipLaunchKernelGGL(k_stage1b, grd, dim3(256), 0, st, h->n, h->zw0, h->zlen, h->z32, h->zinfo, h->dscale,
+                       h->zpart, h->zpart_len, h->src, h->src_len, skip);
   }
   // stage 2 gathers x directly unless y overlaps it (y may alias x): then
   // x_eff goes to the unused head of src first and is gathered from there
@@ -613,19 +632,98 @@ int launch_matvec(const hmat_s *h, const double *x, double *y, int64_t nrhs, int
   const char *yb = (const char *)y, *ye = (const char *)(y + (nrhs - 1) * ld + h->n);
   if (xb < ye && yb < xe) {
     dim3 grd((unsigned)((h->n + 255) / 256), (unsigned)nrhs);
-    hipLaunchKernelGGL(k_copy_x, grd, blk, 0, st, h->n, x, ld, h->x32, h->src, h->src_len, skip);
+    hipLaunchKernelGGL(k_copy_x, grd, dim3(256), 0, st, h->n, x, ld, h->x32, h->src, h->src_len, skip);
     xs = h->src;
     ldxs = h->src_len;
     x32 = 0;
   }
   prof_mark(h, 2, stream);
-  hipLaunchKernelGGL(stage2_fn(h->cls_mask), dim3((unsigned)h->grid2, (unsigned)nrhs), dim3(kS2Threads), 0, st,
-                     h->chunks, h->s2_split, (const double *)h->vals[F64], (const float *)h->vals[F32],
-                     (const unsigned short *)h->vals[BF16], h->gidx[F64], h->gidx[F32], h->gidx[BF16], h->src,
-                     h->src_len, xs, ldxs, x32, h->n, y, ld, skip, d);
+  launch_stage2(h, xs, ldxs, x32, y, ld, nrhs, st, skip, d);
   prof_mark(h, 3, stream);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(HMAT_E_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return HMAT_OK;
+}
+
+// Mean duration in ms of `reps` launches (HIP events on st; -1 on failure).
+template <class F>
+static double sv_time_ms(hipStream_t st, int reps, F launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1.0;
+  launch();  // warm
+  float ms = -1.0f;
+  if (hipEventRecord(a, st) == hipSuccess) {
+    for (int i = 0; i < reps; i++) launch();
+    if (hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess)
+      ms = -1.0f;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return ms < 0 ? -1.0 : (double)ms / reps;
+}
+
+// Tuning of a single-vector handle: per stage-1 storage class the grid, and
+// for stage 2 the grid and the operand tile, each timed on the handle's own
+// blocks with the inputs of a full product in place.  Every choice computes
+// the same values in the same order (the fused inner products are kept per
+// chunk), so results do not depend on it.
+int autotune_sv(hmat_s *h, const double *x, double *y, int reps, hmat_tune_info *info, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = h->n;
+  Prof *saved = h->prof;  // the tuner's own events only
+  h->prof = nullptr;
+  auto product = [&]() { launch_matvec(h, x, y, 1, n, st); };
+  info->ms_fixed = sv_time_ms(st, reps, product);
+  int rc = HMAT_OK;
+  for (int c = 0; c < NCLS && rc == HMAT_OK; c++) {
+    info->stage1_batch[c] = 0;
+    if (h->item_end[c] <= h->item_begin[c]) continue;
+    double best = 1e300;
+    int bmode = 0;
+    for (int mode = 0; mode < 3; mode++) {
+      h->s1_mode[c] = mode;
+      if ((rc = size_grids(h)) != HMAT_OK) break;
+      const double t = sv_time_ms(st, reps, [&]() { launch_stage1(h, c, x, n, 1, st, nullptr); });
+      if (t >= 0 && t < best) {
+        best = t;
+        bmode = mode;
+      }
+    }
+    h->s1_mode[c] = bmode;
+    info->stage1_batch[c] = 1;
+    info->stage1_grid[c] = bmode;
+  }
+  if (rc == HMAT_OK) {
+    product();  // z complete: stage 2 alone reads the inputs of a product
+    const int tiles[3] = {1024, 2048, 4096};
+    double best = 1e300;
+    int bmode = h->s2_mode, btile = h->s2_tile;
+    for (int tile : tiles)
+      for (int mode = 0; mode < 3; mode++) {
+        h->s2_tile = tile;
+        h->s2_mode = mode;
+        if ((rc = size_grids(h)) != HMAT_OK) break;
+        const double t = sv_time_ms(st, reps, [&]() { launch_stage2(h, x, n, h->x32, y, n, 1, st, nullptr, S2Dot{}); });
+        if (t >= 0 && t < best) {
+          best = t;
+          bmode = mode;
+          btile = tile;
+        }
+      }
+    h->s2_mode = bmode;
+    h->s2_tile = btile;
+    info->stage2_batch = 0;
+    info->stage2_grid = bmode;
+    info->stage2_tile = btile;
+  }
+  if (rc == HMAT_OK) rc = size_grids(h);
+  if (rc == HMAT_OK) info->ms_tuned = sv_time_ms(st, reps, product);
+  h->prof = saved;
+  if (rc) return rc;
+  const hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(HMAT_E_HIP, "autotuning failed: %s", hipGetErrorString(e));
+  if (info->ms_fixed < 0 || info->ms_tuned < 0) return fail(HMAT_E_HIP, "event timing failed");
   return HMAT_OK;
 }
 
@@ -685,6 +783,7 @@ static int build_planned(Packed *P, const hmat_plan_info &info, void *dev_mem, u
   h->src = (double *)at(L.off_src);
   h->src64 = (double *)at(L.off_src64);
   h->zpart = (double *)(d + L.off_zpart);
+  h->dpart = (double *)at(L.off_dpart);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipMemcpyAsync(d, img.data(), img.size(), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);

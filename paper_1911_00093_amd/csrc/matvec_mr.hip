@@ -412,10 +412,10 @@ static double time_ms(hipStream_t st, int reps, F launch) {
 extern "C" int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps, hmat_tune_info *info, void *stream) {
   using namespace hm;
   if (!h || !x || !y || !info) return fail(HMAT_E_ARG, "null argument");
-  if (!h->mr) return fail(HMAT_E_ARG, "autotuning applies to multi-right-hand-side handles (nrhs_max > 1)");
   if (reps < 1 || reps > 1000) return fail(HMAT_E_ARG, "reps %d out of range", reps);
   std::memset(info, 0, sizeof *info);
   hipStream_t st = (hipStream_t)stream;
+  if (!h->mr) return autotune_sv(h, x, y, reps, info, stream);
   const int64_t n = h->n, nr = std::min<int64_t>(kMRhs, h->nrhs_max);
   Prof *saved = h->prof;  // the tuner's own events only
   h->prof = nullptr;

@@ -733,6 +733,7 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
     L.off_src = take((uint64_t)P->nrhs_max * (n + P->zlen + 1) * sizeof(double));
     L.off_zpart = take((uint64_t)P->nrhs_max * std::max<int64_t>(P->zpart_len, 1) * sizeof(double));
   }
+  L.off_dpart = P->mr ? ~0ull : take(3 * std::max<uint64_t>(P->chunks.size(), 1) * sizeof(double));
   L.total = at;
 
   // ---- sizes and statistics

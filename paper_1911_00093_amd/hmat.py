@@ -90,7 +90,8 @@ class hmat_solve_info(C.Structure):
 
 class hmat_tune_info(C.Structure):
     _fields_ = [("stage1_batch", C.c_int32 * 3), ("stage1_grid", C.c_int32 * 3), ("stage2_batch", C.c_int32),
-                ("stage2_grid", C.c_int32), ("ms_fixed", C.c_double), ("ms_tuned", C.c_double)]
+                ("stage2_grid", C.c_int32), ("ms_fixed", C.c_double), ("ms_tuned", C.c_double),
+                ("stage2_tile", C.c_int32), ("reserved", C.c_int32)]
 
 
 class hmat_batch_result(C.Structure):
@@ -378,7 +379,7 @@ class HMatrix:
         return hmat_matvec(self, x, y, stream)
 
     def autotune(self, reps=10, stream=None):
-        """Pick the multi-RHS launch configuration (hmat_autotune); returns a dict."""
+        """Pick the launch configuration on this handle's blocks (hmat_autotune); returns a dict."""
         import torch
 
         nr = min(16, self.nrhs_max)
@@ -388,7 +389,7 @@ class HMatrix:
         _check(lib().hmat_autotune(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), int(reps),
                                    C.byref(info), _stream_ptr(stream)))
         return dict(stage1_batch=list(info.stage1_batch), stage1_grid=list(info.stage1_grid),
-                    stage2_batch=info.stage2_batch, stage2_grid=info.stage2_grid,
+                    stage2_batch=info.stage2_batch, stage2_grid=info.stage2_grid, stage2_tile=info.stage2_tile,
                     ms_fixed=info.ms_fixed, ms_tuned=info.ms_tuned)
 
     def set_profiling(self, enable=True):

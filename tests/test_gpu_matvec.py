@@ -227,3 +227,39 @@ def test_permute_roundtrip():
     ex = A @ X[0]
     assert np.linalg.norm(yo - ex) / np.linalg.norm(ex) < 1e-5  # ACA 1e-6 blocks
     assert hmat.lib().hmat_permute(h.n, None, None, None, 1, 0, None) == hmat.HMAT_E_ARG
+
+
+@pytest.mark.parametrize("variant", [oracle.M1_DOUBLE, oracle.M2_MIXED, oracle.M3, oracle.BF16_SCALED])
+def test_autotune_single_vector_keeps_results(variant):
+    """hmat_autotune on a single-vector handle picks, per storage class, the
+    stage-1 grid and the stage-2 grid and operand tile; products before and
+    after are identical bit for bit and equal the oracle's, and a BiCGSTAB
+    solve takes the same iterations to the same x (its fused inner products
+    are summed per row chunk, whatever grid stage 2 runs on)."""
+    need_gpu()
+    m, h = oracle_hmatrix("spheres-mixed")
+    bs = blockset(h)
+    H = hmat.HMatrix(bs, variant, c=1)
+    H64 = hmat.HMatrix(bs, oracle.M1_DOUBLE)
+    x = to_dev(np.random.default_rng(21).standard_normal(h.n))
+    y0 = H.matvec(x).cpu().numpy()
+    b = to_dev(m.rhs()[h.perm])
+    xs0, i0 = hmat.hmat_bicgstab(H, b, h_fp64=H64, tol=1e-10, maxiter=400, history=True)
+    xs0 = xs0.cpu().numpy()
+    seen = set()
+    for _ in range(2):
+        info = H.autotune(reps=3)
+        print(oracle.VARIANT_NAMES[variant], info)
+        assert info["stage2_tile"] in (1024, 2048, 4096) and info["stage2_grid"] in (0, 1, 2)
+        for c in range(3):
+            assert info["stage1_grid"][c] in (0, 1, 2)
+        assert info["ms_fixed"] > 0 and info["ms_tuned"] > 0
+        seen.add((info["stage2_tile"], info["stage2_grid"]))
+        y1 = H.matvec(x).cpu().numpy()
+        assert np.array_equal(y0, y1)
+        xs1, i1 = hmat.hmat_bicgstab(H, b, h_fp64=H64, tol=1e-10, maxiter=400, history=True)
+        assert i1["iterations"] == i0["iterations"] and np.array_equal(i1["history"], i0["history"])
+        assert np.array_equal(xs1.cpu().numpy(), xs0)
+    conv = oracle.Converted(h, variant, 1)
+    xh = x.cpu().numpy()
+    assert np.abs(y0 - conv.matvec(xh)).max() <= tolerance(variant) * abs_scale(h, xh).max()

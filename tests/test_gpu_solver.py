@@ -12,6 +12,51 @@ from tests.gpu_util import blockset, need_gpu, to_dev
 pytestmark = pytest.mark.gpu
 
 
+def _iterations_over_dot_orders(op, b, tol, maxiter):
+    """Iterations Algorithm 1 takes with the oracle's operator when only the
+    summation order of its inner products changes (sequential as in the
+    oracle, numpy's pairwise sum, and sums of chunk sums as the GPU forms
+    them).  The paper fixes no order, and near a residual plateau the step at
+    which |r|/|b| crosses tol moves with it (plates-32 at 1e-10: 42 to 46)."""
+    def seq(a, c):
+        t = 0.0
+        for u in (a * c).tolist():
+            t += u
+        return t
+
+    def chunked(k):
+        return lambda a, c: seq(np.add.reduceat(a * c, np.arange(0, a.size, k)), np.ones((a.size + k - 1) // k))
+
+    counts = []
+    for dot in (seq, np.dot, chunked(64), chunked(256)):
+        x = np.zeros_like(b)
+        r = b - op(x)
+        rt = r.copy()
+        bn = np.sqrt(dot(b, b))
+        rho_prev = alpha = omega = 1.0
+        p = v = None
+        it_done = maxiter
+        for it in range(1, maxiter + 1):
+            rho = dot(rt, r)
+            p = r.copy() if it == 1 else r + (rho / rho_prev) * (alpha / omega) * (p - omega * v)
+            v = op(p)
+            alpha = rho / dot(rt, v)
+            s_ = r - alpha * v
+            if np.sqrt(dot(s_, s_)) / bn < tol:
+                it_done = it
+                break
+            t = op(s_)
+            omega = dot(t, s_) / dot(t, t)
+            x += alpha * p + omega * s_
+            r = s_ - omega * t
+            rho_prev = rho
+            if np.sqrt(dot(r, r)) / bn < tol:
+                it_done = it
+                break
+        counts.append(it_done)
+    return counts
+
+
 @pytest.mark.parametrize("key", ["sphere-L4", "plates-32"])
 def test_bicgstab_fp64_matches_oracle(key):
     need_gpu()
@@ -20,9 +65,15 @@ def test_bicgstab_fp64_matches_oracle(key):
     bs = blockset(h)
     H = hmat.HMatrix(bs, oracle.M1_DOUBLE)
     x, info = hmat.hmat_bicgstab(H, to_dev(b), tol=1e-10, maxiter=300, history=True)
-    xo, io = oracle.bicgstab(oracle.Converted(h, oracle.M1_DOUBLE), b, tol=1e-10, maxiter=300)
+    op = oracle.Converted(h, oracle.M1_DOUBLE)
+    xo, io = oracle.bicgstab(op, b, tol=1e-10, maxiter=300)
     assert info["status"] == 0 and io["status"] == 0
-    assert abs(info["iterations"] - io["iterations"]) <= 1
+    # the iteration count is fixed only up to the inner products' summation
+    # order: the GPU's lies within the range those orders give (+-1)
+    counts = _iterations_over_dot_orders(op.matvec, b, 1e-10, 300)
+    print(f"{key}: iterations gpu {info['iterations']}, oracle {io['iterations']}, over dot orders {counts}")
+    assert io["iterations"] == counts[0]
+    assert min(counts) - 1 <= info["iterations"] <= max(counts) + 1
     x = x.cpu().numpy()
     # both solves stop at |r|/|b| < 1e-10, so each is off the exact solution
     # by up to kappa * 1e-10; compare each with a tight solve instead
