@@ -128,12 +128,28 @@ struct DotSrc {
 };
 template <int NV>
 __device__ __forceinline__ void sum_src(const DotSrc &d, double (&out)[NV], double (*lds)[kThreads / 64]) {
+  // thread t adds entries t, t + 256, t + 512, ... in that order, eight
+  // loads in flight at a time (indices past the end repeat the last entry
+  // and are not added)
+  constexpr int B = 8;
   double v[NV];
 #pragma unroll
-  for (int q = 0; q < NV; q++) {
-    double a = 0.0;
-    for (int64_t i = threadIdx.x; i < d.count; i += kThreads) a += d.p[i * d.stride + d.off + q];
-    v[q] = a;
+  for (int q = 0; q < NV; q++) v[q] = 0.0;
+  for (int64_t i0 = threadIdx.x; i0 < d.count; i0 += (int64_t)B * kThreads) {
+    double t[B][NV];
+#pragma unroll
+    for (int e = 0; e < B; e++) {
+      const int64_t i = min(i0 + (int64_t)e * kThreads, d.count - 1);
+#pragma unroll
+      for (int q = 0; q < NV; q++) t[e][q] = d.p[i * d.stride + d.off + q];
+    }
+#pragma unroll
+    for (int e = 0; e < B; e++)
+#pragma unroll
+      for (int q = 0; q < NV; q++) {
+        const double a = v[q] + t[e][q];
+        v[q] = i0 + (int64_t)e * kThreads < d.count ? a : v[q];
+      }
   }
   block_sum<NV>(v, lds);
 #pragma unroll

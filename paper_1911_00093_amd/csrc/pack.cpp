@@ -425,8 +425,11 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
   // column chunks per group; z numbering: the groups one item wide first
   // (their items finish z themselves), then the wider ones, whose entries
   // [zw0, zlen) the stage-1 reduction finishes
+  // (BF16 items twice as wide: about the same bytes per row as FP32's)
   auto chunk_cols = [&](const Group &g) {
-    return P->mr ? (int64_t)kMRCols : std::max<int64_t>((int64_t)s1_lpr(g.cls, g.ncols) * vec_of(g.cls), kS1Cols);
+    return P->mr ? (int64_t)kMRCols
+                 : std::max<int64_t>((int64_t)s1_lpr(g.cls, g.ncols) * vec_of(g.cls),
+                                     g.cls == BF16 ? 2 * kS1Cols : kS1Cols);
   };
   for (auto &kv : gmap) {
     Group &g = P->groups[kv.second];
