@@ -208,6 +208,29 @@ int hmat_system_offsets(hmat_t h, int64_t *offsets, int64_t capacity, int64_t *c
 /* Release the host-side handle state (not the caller's device buffer). */
 int hmat_destroy(hmat_t h);
 
+/* The packed image hmat_build would upload, written into host memory (pure
+ * host code, no GPU: for inspection and for checking the layout on the CPU).
+ * `image` receives image_bytes bytes (pass NULL to query the sizes; else
+ * HMAT_E_WORKSPACE if `bytes` is smaller); `out` the offsets of its parts.
+ * The layout is the library's internal one (single-vector handles: per
+ * storage class the values in consumption order, 32-bit gather indices,
+ * then the row-chunk and stage-1 item descriptors, the stage-1 reduction
+ * table and the D_m scales); hmat_build copies exactly these bytes to the
+ * start of its device buffer. */
+typedef struct {
+    uint64_t image_bytes;
+    uint64_t off_vals[3], bytes_vals[3];  /* per storage class FP64 / FP32 / BF16 */
+    uint64_t off_gidx[3], bytes_gidx[3];
+    uint64_t off_chunks, off_items, off_zinfo, off_dscale;
+    int64_t n, nchunks, nitems, zlen;
+    int64_t zw0;              /* z entries [zw0, zlen) are finished by the stage-1 reduction */
+    int32_t x32, z32;         /* x rounded to FP32 (Single variants); z rounded to FP32 (M1-Single/Mixed) */
+    int32_t layout;           /* 0 single-vector, 1 multi-right-hand-side */
+    int32_t reserved;
+} hmat_image_info;
+int hmat_pack_host(const hmat_blocks *blocks, const hmat_build_opts *opts, void *image, uint64_t bytes,
+                   hmat_image_info *out);
+
 typedef struct {
     int64_t n, nblocks, nblocks_dense, nblocks_lowrank, max_rank;
     int64_t row_chunks;       /* stage-2 work units (row ownership) */

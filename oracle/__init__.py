@@ -29,16 +29,22 @@ M1_DOUBLE, M1_SINGLE, M1_MIXED, M2_DOUBLE, M2_SINGLE, M2_MIXED, M3, BF16_SCALED 
 VARIANT_NAMES = ["M1-Double", "M1-Single", "M1-Mixed", "M2-Double", "M2-Single", "M2-Mixed", "M3", "BF16-scaled"]
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-             _SRC, "-o", tmp, "-lm"]
-        )
-        os.replace(tmp, _LIB)
-    return _LIB
+_SAN_LIB = os.path.join(_HERE, "libhmat_oracle_san.so")
+
+
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (no fast-math, no FMA contraction);
+    sanitize: a separate copy with AddressSanitizer and UndefinedBehavior-
+    Sanitizer for CPU tests (load it with the ASan runtime preloaded)."""
+    lib = _SAN_LIB if sanitize else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp%d" % os.getpid()
+        flags = (["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"])
+        subprocess.check_call(["gcc"] + flags + ["-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                                                 "-fno-fast-math", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 def _load():
@@ -46,9 +52,12 @@ def _load():
     with _lock:
         if _lib is not None:
             return _lib
-        if not os.path.exists(_LIB):
-            build()
-        L = C.CDLL(_LIB)
+        if os.environ.get("HMAT_ORACLE_SANITIZED") == "1":  # the sanitized copy (CPU tests only)
+            L = C.CDLL(build(sanitize=True))
+        else:
+            if not os.path.exists(_LIB):
+                build()
+            L = C.CDLL(_LIB)
         P, D, I64, I32 = C.c_void_p, C.c_double, C.c_int64, C.c_int32
         dp = C.POINTER(C.c_double)
         L.ora_assemble.restype = P

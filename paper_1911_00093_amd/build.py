@@ -62,5 +62,25 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host-only library with AddressSanitizer and UndefinedBehaviorSanitizer:
+# the packer and the setup builder (pure host C++, no HIP), for CPU tests
+# under the sanitizers (loaded with the ASan runtime preloaded).
+SAN_LIB = os.path.join(OUT, "san", "libhmat_host_san.so")
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=undefined", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+             "-fno-fast-math", "-Wall", "-pthread"]
+
+
+def build_host_sanitized() -> str:
+    os.makedirs(os.path.dirname(SAN_LIB), exist_ok=True)
+    tmp = SAN_LIB + ".tmp%d" % os.getpid()
+    _run(["g++"] + SAN_FLAGS + INC + [os.path.join(CSRC, s) for s in HOST_SOURCES] + ["-o", tmp])
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_host_sanitized())
+    else:
+        print(build(verbose="-v" in sys.argv))

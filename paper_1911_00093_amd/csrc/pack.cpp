@@ -889,24 +889,23 @@ bool HostImage::alloc(uint64_t bytes) {
   return true;
 }
 
-int pack_into(Packed *P, HostImage &img, hmat_s *h) {
+// The packed part of the device image, [0, lay.ws_begin), written into
+// `base` (which must hold that many bytes).
+static void pack_image(Packed *P, unsigned char *base) {
   const hmat_blocks *b = &P->b;
   const DevLayout &L = P->lay;
   const int64_t n = b->n;
   // the packed part of the image starts zeroed (padding, compact tiles); the
   // workspace after it needs no initial contents
-  if (!img.alloc(L.ws_begin))
-    return fail(HMAT_E_NOMEM, "cannot allocate %llu bytes of host staging", (unsigned long long)L.ws_begin);
   {
     constexpr uint64_t kPiece = uint64_t(64) << 20;
-    unsigned char *z = img.data();
+    unsigned char *z = base;
     const uint64_t total = L.ws_begin;
     parallel_for((int64_t)((total + kPiece - 1) / kPiece), [z, total](int64_t q) {
       const uint64_t lo = (uint64_t)q * kPiece, hi = std::min(total, lo + kPiece);
       std::memset(z + lo, 0, hi - lo);
     });
   }
-  unsigned char *base = img.data();
   auto put = [base, &L](int cls, int64_t idx, double v) {
     unsigned char *p = base + L.off_vals[cls];
     if (cls == F64) ((double *)p)[idx] = v;
@@ -1058,12 +1057,24 @@ int pack_into(Packed *P, HostImage &img, hmat_s *h) {
       }
     }
   });
-  std::memcpy(base + L.off_chunks, P->rc.data(), P->rc.size() * sizeof(RowChunk));
-  std::memcpy(base + L.off_mrc, P->mrc.data(), P->mrc.size() * sizeof(MRChunk));
-  std::memcpy(base + L.off_mri, P->mri.data(), P->mri.size() * sizeof(MRItem));
-  std::memcpy(base + L.off_items, P->items.data(), P->items.size() * sizeof(S1Item));
-  std::memcpy(base + L.off_zinfo, P->zinfo.data(), P->zinfo.size() * sizeof(ZInfo));
-  std::memcpy(base + L.off_dscale, P->dscale.data(), P->dscale.size() * sizeof(double));
+  // descriptor tables (an empty table has no storage to copy from)
+  auto put_table = [base](uint64_t off, const auto &v) {
+    if (!v.empty()) std::memcpy(base + off, v.data(), v.size() * sizeof(v[0]));
+  };
+  put_table(L.off_chunks, P->rc);
+  put_table(L.off_mrc, P->mrc);
+  put_table(L.off_mri, P->mri);
+  put_table(L.off_items, P->items);
+  put_table(L.off_zinfo, P->zinfo);
+  put_table(L.off_dscale, P->dscale);
+}
+
+int pack_into(Packed *P, HostImage &img, hmat_s *h) {
+  const DevLayout &L = P->lay;
+  const int64_t n = P->b.n;
+  if (!img.alloc(L.ws_begin))
+    return fail(HMAT_E_NOMEM, "cannot allocate %llu bytes of host staging", (unsigned long long)L.ws_begin);
+  pack_image(P, img.data());
 
   h->n = n;
   h->precision = P->precision;
@@ -1120,3 +1131,44 @@ int pack_into(Packed *P, HostImage &img, hmat_s *h) {
 }  // namespace hm
 
 extern "C" const char *hmat_last_error(void) { return hm::last_error(); }
+
+extern "C" int hmat_pack_host(const hmat_blocks *blocks, const hmat_build_opts *opts, void *image, uint64_t bytes,
+                              hmat_image_info *out) {
+  using namespace hm;
+  if (!out) return fail(HMAT_E_ARG, "null output");
+  std::memset(out, 0, sizeof *out);
+  Packed *P = nullptr;
+  hmat_plan_info info{};
+  int rc = plan_blocks(blocks, opts, &info, &P);
+  if (rc) return rc;
+  rc = host_guarded([&]() -> int {
+    const DevLayout &L = P->lay;
+    out->image_bytes = L.ws_begin;
+    for (int c = 0; c < NCLS; c++) {
+      out->off_vals[c] = L.off_vals[c];
+      out->bytes_vals[c] = L.bytes_vals[c];
+      out->off_gidx[c] = L.off_gidx[c];
+      out->bytes_gidx[c] = L.bytes_gidx[c];
+    }
+    out->off_chunks = L.off_chunks;
+    out->off_items = L.off_items;
+    out->off_zinfo = L.off_zinfo;
+    out->off_dscale = L.off_dscale;
+    out->n = P->b.n;
+    out->nchunks = (int64_t)(P->mr ? P->mrc.size() : P->rc.size());
+    out->nitems = (int64_t)(P->mr ? P->mri.size() : P->items.size());
+    out->zlen = P->zlen;
+    out->zw0 = P->zw0;
+    out->x32 = P->x32;
+    out->z32 = P->z32;
+    out->layout = P->mr ? 1 : 0;
+    if (!image) return HMAT_OK;  // size query
+    if (bytes < L.ws_begin)
+      return fail(HMAT_E_WORKSPACE, "image buffer holds %llu bytes, %llu needed", (unsigned long long)bytes,
+                  (unsigned long long)L.ws_begin);
+    pack_image(P, (unsigned char *)image);
+    return HMAT_OK;
+  });
+  packed_free(P);
+  return rc;
+}

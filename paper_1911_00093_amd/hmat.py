@@ -39,7 +39,7 @@ EXPORTED = [
     "hmat_bicgstab_batched_workspace_bytes", "hmat_bicgstab_batched", "hmat_precond_create_learned",
     "hmat_precond_leaves", "hmat_leaf_features", "hmat_leaf_scales", "hmat_dense_inverse", "hmat_mlp_workspace_bytes",
     "hmat_mlp_forward", "hmat_mlp_loss_grad", "hmat_mlp_adam", "hmat_autotune", "hmat_permute",
-    "hmat_bicgstab_noalloc_max_n", "hmat_bicgstab_noalloc",
+    "hmat_bicgstab_noalloc_max_n", "hmat_bicgstab_noalloc", "hmat_pack_host",
 ]
 
 
@@ -94,6 +94,15 @@ class hmat_tune_info(C.Structure):
                 ("stage2_tile", C.c_int32), ("reserved", C.c_int32)]
 
 
+class hmat_image_info(C.Structure):
+    _fields_ = [("image_bytes", C.c_uint64), ("off_vals", C.c_uint64 * 3), ("bytes_vals", C.c_uint64 * 3),
+                ("off_gidx", C.c_uint64 * 3), ("bytes_gidx", C.c_uint64 * 3), ("off_chunks", C.c_uint64),
+                ("off_items", C.c_uint64), ("off_zinfo", C.c_uint64), ("off_dscale", C.c_uint64),
+                ("n", C.c_int64), ("nchunks", C.c_int64), ("nitems", C.c_int64), ("zlen", C.c_int64),
+                ("zw0", C.c_int64), ("x32", C.c_int32), ("z32", C.c_int32), ("layout", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class hmat_batch_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("restarts", C.c_int32), ("iterations", C.c_int64),
                 ("rel_res", C.c_double), ("true_rel_res", C.c_double), ("products", C.c_int64)]
@@ -130,6 +139,7 @@ def lib():
         "hmat_last_error": (C.c_char_p, []),
         "hmat_version": (C.c_char_p, []),
         "hmat_plan": (C.c_int, [P, P, P]),
+        "hmat_pack_host": (C.c_int, [P, P, P, U64, P]),
         "hmat_build": (C.c_int, [P, P, P, U64, P, P]),
         "hmat_matvec": (C.c_int, [P, P, P, I64, I64, P]),
         "hmat_destroy": (C.c_int, [P]),
@@ -315,6 +325,21 @@ def hmat_plan(blocks: BlockSet, precision: int, c: int = 0, nrhs_max: int = 1, d
     o = hmat_build_opts(int(precision), int(c), int(nrhs_max), int(drop), int(bool(dense_split)), 0)
     _check(lib().hmat_plan(C.byref(s), C.byref(o), C.byref(info)))
     return info
+
+
+def hmat_pack_host(blocks: BlockSet, precision: int, c: int = 0, nrhs_max: int = 1, drop: int = 0,
+                   dense_split: bool = False):
+    """The packed image hmat_build would upload, in host memory (no GPU):
+    (uint8 array, dict of the image_info fields)."""
+    info = hmat_image_info()
+    s = blocks.struct()
+    o = hmat_build_opts(int(precision), int(c), int(nrhs_max), int(drop), int(bool(dense_split)), 0)
+    _check(lib().hmat_pack_host(C.byref(s), C.byref(o), None, 0, C.byref(info)))
+    img = np.zeros(int(info.image_bytes), np.uint8)
+    _check(lib().hmat_pack_host(C.byref(s), C.byref(o), _p(img), img.size, C.byref(info)))
+    d = {f: (list(getattr(info, f)) if f in ("off_vals", "bytes_vals", "off_gidx", "bytes_gidx") else getattr(info, f))
+         for f, _ in hmat_image_info._fields_}
+    return img, d
 
 
 # ----------------------------------------------------------------- device
