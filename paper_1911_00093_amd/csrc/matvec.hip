@@ -185,10 +185,19 @@ __global__ __launch_bounds__(kS1Waves * kWave) void k_stage1(
   const int xcd = blockIdx.x % kXcds;
   const int64_t gx = ((int64_t)gridDim.x - xcd + kXcds - 1) / kXcds;  // workgroups serving this range
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  for (int64_t idx = sp.lo[xcd] + (int64_t)(blockIdx.x / kXcds) * kS1Waves + wave; idx < sp.lo[xcd + 1];
-       idx += gx * kS1Waves) {
-    const S1Item it = items[idx];
+  // a persistent wave loads its next item's descriptor before working on
+  // the current one, so the descriptor's latency overlaps the item
+  const int64_t step = gx * kS1Waves, hi = sp.lo[xcd + 1];
+  int64_t idx = sp.lo[xcd] + (int64_t)(blockIdx.x / kXcds) * kS1Waves + wave;
+  if (idx >= hi) return;
+  S1Item it = items[idx];
+  for (;;) {
+    const int64_t nidx = idx + step;
+    const S1Item nx = items[nidx < hi ? nidx : idx];
     s1_item<CLS>(it, vals, xr, x32, zp, dscale, z32, z, lane);
+    if (nidx >= hi) break;
+    idx = nidx;
+    it = nx;
   }
 }
 
