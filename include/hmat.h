@@ -190,6 +190,15 @@ typedef struct {
 
 int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps, hmat_tune_info *info, void *stream);
 
+/* Apply a launch configuration without timing (a choice hmat_autotune made
+ * for another handle of the same blocks, kept by the caller): the fields
+ * hmat_autotune fills, read as above (ms_fixed / ms_tuned ignored).  Single-
+ * vector handles read stage1_grid, stage2_grid and stage2_tile;
+ * multi-right-hand-side handles stage1_batch (classes with items),
+ * stage1_grid, stage2_batch and stage2_grid.  HMAT_E_ARG for a value out of
+ * range; results are unchanged by any valid choice. */
+int hmat_set_tuning(hmat_t h, const hmat_tune_info *cfg);
+
 /* Independent systems batched into one handle (not from the paper): system
  * k (a full H-matrix of order n_k, blocks as in hmat_blocks) occupies the
  * index range [off_k, off_k + n_k) of a block-diagonal operator, off_0 = 0,

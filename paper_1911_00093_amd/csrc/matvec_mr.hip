@@ -409,6 +409,35 @@ static double time_ms(hipStream_t st, int reps, F launch) {
 
 }  // namespace hm
 
+extern "C" int hmat_set_tuning(hmat_t h, const hmat_tune_info *cfg) {
+  using namespace hm;
+  if (!h || !cfg) return fail(HMAT_E_ARG, "null argument");
+  auto grid_ok = [](int32_t g) { return g >= 0 && g <= 2; };
+  auto batch_ok = [](int32_t b) { return b == 1 || b == 2 || b == 4; };
+  if (!grid_ok(cfg->stage2_grid)) return fail(HMAT_E_ARG, "stage-2 grid mode %d (0..2)", cfg->stage2_grid);
+  for (int c = 0; c < NCLS; c++)
+    if (!grid_ok(cfg->stage1_grid[c])) return fail(HMAT_E_ARG, "stage-1 grid mode %d (0..2)", cfg->stage1_grid[c]);
+  if (h->mr) {
+    if (!batch_ok(cfg->stage2_batch)) return fail(HMAT_E_ARG, "stage-2 batch %d (1, 2 or 4)", cfg->stage2_batch);
+    for (int c = 0; c < NCLS; c++)
+      if (h->mr_nitems[c] > 0 && !batch_ok(cfg->stage1_batch[c]))
+        return fail(HMAT_E_ARG, "stage-1 batch %d (1, 2 or 4)", cfg->stage1_batch[c]);
+    for (int c = 0; c < NCLS; c++) {
+      if (h->mr_nitems[c] > 0) h->mr_nb1[c] = cfg->stage1_batch[c];
+      h->mr_mode1[c] = cfg->stage1_grid[c];
+    }
+    h->mr_nb2 = cfg->stage2_batch;
+    h->mr_mode2 = cfg->stage2_grid;
+    return size_grids_mr(h);
+  }
+  const int32_t t = cfg->stage2_tile;
+  if (t != 1024 && t != 2048 && t != 4096) return fail(HMAT_E_ARG, "stage-2 tile %d (1024, 2048 or 4096)", t);
+  for (int c = 0; c < NCLS; c++) h->s1_mode[c] = cfg->stage1_grid[c];
+  h->s2_mode = cfg->stage2_grid;
+  h->s2_tile = t;
+  return size_grids(h);
+}
+
 extern "C" int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps, hmat_tune_info *info, void *stream) {
   using namespace hm;
   if (!h || !x || !y || !info) return fail(HMAT_E_ARG, "null argument");

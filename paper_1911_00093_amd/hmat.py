@@ -39,7 +39,7 @@ EXPORTED = [
     "hmat_bicgstab_batched_workspace_bytes", "hmat_bicgstab_batched", "hmat_precond_create_learned",
     "hmat_precond_leaves", "hmat_leaf_features", "hmat_leaf_scales", "hmat_dense_inverse", "hmat_mlp_workspace_bytes",
     "hmat_mlp_forward", "hmat_mlp_loss_grad", "hmat_mlp_adam", "hmat_autotune", "hmat_permute",
-    "hmat_bicgstab_noalloc_max_n", "hmat_bicgstab_noalloc", "hmat_pack_host",
+    "hmat_bicgstab_noalloc_max_n", "hmat_bicgstab_noalloc", "hmat_pack_host", "hmat_set_tuning",
 ]
 
 
@@ -180,6 +180,7 @@ def lib():
         "hmat_mlp_loss_grad": (C.c_int, [P, P, P, P, P, P, I64, P, I64, P, P, P, U64, P]),
         "hmat_mlp_adam": (C.c_int, [P, P, P, P, I64, C.c_float, P]),
         "hmat_autotune": (C.c_int, [P, P, P, I32, P, P]),
+        "hmat_set_tuning": (C.c_int, [P, P]),
         "hmat_permute": (C.c_int, [I64, P, P, P, I64, I32, P]),
     }
     for name, (res, args) in sig.items():
@@ -416,6 +417,17 @@ class HMatrix:
         return dict(stage1_batch=list(info.stage1_batch), stage1_grid=list(info.stage1_grid),
                     stage2_batch=info.stage2_batch, stage2_grid=info.stage2_grid, stage2_tile=info.stage2_tile,
                     ms_fixed=info.ms_fixed, ms_tuned=info.ms_tuned)
+
+    def set_tuning(self, stage1_grid=(0, 0, 0), stage2_grid=0, stage2_tile=2048, stage1_batch=(2, 2, 2),
+                   stage2_batch=2):
+        """Apply a launch configuration (hmat_set_tuning), e.g. one autotune() returned."""
+        cfg = hmat_tune_info()
+        for c in range(3):
+            cfg.stage1_grid[c] = int(stage1_grid[c])
+            cfg.stage1_batch[c] = int(stage1_batch[c])
+        cfg.stage2_grid, cfg.stage2_tile = int(stage2_grid), int(stage2_tile)
+        cfg.stage2_batch = int(stage2_batch)
+        _check(lib().hmat_set_tuning(self.h, C.byref(cfg)))
 
     def set_profiling(self, enable=True):
         _check(lib().hmat_set_profiling(self.h, int(bool(enable))))

@@ -263,3 +263,38 @@ def test_autotune_single_vector_keeps_results(variant):
     conv = oracle.Converted(h, variant, 1)
     xh = x.cpu().numpy()
     assert np.abs(y0 - conv.matvec(xh)).max() <= tolerance(variant) * abs_scale(h, xh).max()
+
+
+@pytest.mark.parametrize("variant,c,split", [(oracle.M2_MIXED, -1, False), (oracle.BF16_SCALED, -1, False),
+                                             (oracle.M3, 0, True)])
+def test_every_launch_configuration_same_result(variant, c, split):
+    """Every single-vector launch configuration hmat_set_tuning accepts
+    (stage-1 grid, stage-2 grid, operand tile) gives the same product bit
+    for bit, and the same BiCGSTAB solve; invalid ones are refused."""
+    need_gpu()
+    import itertools
+
+    m, h = oracle_hmatrix("plates-32")
+    bs = blockset(h)
+    H = hmat.HMatrix(bs, variant, c=c, dense_split=split)
+    H64 = hmat.HMatrix(bs, oracle.M1_DOUBLE)
+    x = to_dev(np.random.default_rng(4).standard_normal(h.n))
+    b = to_dev(m.rhs()[h.perm])
+    ref = ref_solve = None
+    for g1, g2, tile in itertools.product((0, 1, 2), (0, 1, 2), (1024, 2048, 4096)):
+        H.set_tuning(stage1_grid=(g1, g1, g1), stage2_grid=g2, stage2_tile=tile)
+        y = H.matvec(x).cpu().numpy()
+        if ref is None:
+            ref = y
+            conv = oracle.Converted(h, variant, c, dense_split=split)
+            xh = x.cpu().numpy()
+            assert np.abs(y - conv.matvec(xh)).max() <= tolerance(variant) * abs_scale(h, xh).max()
+        assert np.array_equal(y, ref), (g1, g2, tile)
+        if g1 == 0 and tile == 2048:
+            xs, info = hmat.hmat_bicgstab(H, b, h_fp64=H64, tol=1e-9, maxiter=300, history=True)
+            if ref_solve is None:
+                ref_solve = (xs.cpu().numpy(), info["history"])
+            assert np.array_equal(xs.cpu().numpy(), ref_solve[0]) and np.array_equal(info["history"], ref_solve[1])
+    for bad in (dict(stage2_tile=3000), dict(stage2_grid=3), dict(stage1_grid=(0, 5, 0))):
+        with pytest.raises(hmat.HmatError):
+            H.set_tuning(**bad)
