@@ -18,7 +18,7 @@ enum Cls : int { F64 = 0, F32 = 1, BF16 = 2, NCLS = 3 };
 constexpr int kWave = 64;         // CDNA wavefront
 constexpr int kRowChunk = 64;     // rows owned by one stage-2 workgroup
 constexpr int kS2Waves = 8;       // waves per stage-2 workgroup (rows interleaved)
-constexpr int kRowsPerLane = 8;   // row accumulators per lane (stage 1 and stage 2)
+constexpr int kRowsPerLane = 8;   // row accumulators per lane (stage 2; stage 1 see s1_slots)
 constexpr int kS2Threads = kS2Waves * kWave;
 constexpr int kS2Tile = 2048;     // gathered operands staged in LDS per pass (FP64), untuned
 constexpr int kS1Cols = 1024;     // stage-1 item width (columns) for wide groups
@@ -26,6 +26,11 @@ constexpr int kS1Cols = 1024;     // stage-1 item width (columns) for wide group
 // elements per 16-byte lane load
 constexpr int vec_of(int cls) { return cls == F64 ? 2 : (cls == F32 ? 4 : 8); }
 constexpr int bytes_of(int cls) { return cls == F64 ? 8 : (cls == F32 ? 4 : 2); }
+// Stage-1 row slots per lane (accumulators, and 16-byte loads in flight per
+// slab): 16 for BF16, whose loads carry half of FP32's bytes per value, so
+// an item keeps the same bytes in flight and reuses its x operands twice as
+// often; 8 otherwise.
+constexpr int s1_slots(int cls) { return cls == BF16 ? 16 : 8; }
 // Stage-1 lanes per W' row: the narrowest of 16 / 32 / 64 lanes whose
 // 16-byte loads span the group's columns, so narrow groups still fill the
 // wave (64 / lpr rows per load instruction).

@@ -69,18 +69,20 @@ __device__ __forceinline__ double dot16(raw16 t, const double (&g)[vec_of(CLS)],
   return acc;
 }
 
-// Butterfly reduce-scatter of R = 8 accumulators over the lowest log2(L)
-// lane bits (L = 16, 32 or 64 lanes per row): the three halving steps (lane
-// bits L/2, L/4, L/8) each exchange the half of the accumulators a lane gives
-// away, the remaining bits are plain xor-adds, so 8 row sums cost 8-10
-// shuffles instead of 8 full reductions.  Afterwards the lane whose in-row
-// index u satisfies u % (L / 8) == 0 holds the complete sum of accumulator
-// u / (L / 8).
-__device__ __forceinline__ double reduce_rows(double (&a)[kRowsPerLane], int lane, int L) {
-  static_assert(kRowsPerLane == 8, "three halving steps");
+// Butterfly reduce-scatter of R = 8 or 16 accumulators over the lowest
+// log2(L) lane bits (L = 16, 32 or 64 lanes per row, L >= R): the log2(R)
+// halving steps (lane bits L/2, L/4, ...) each exchange the half of the
+// accumulators a lane gives away, the remaining bits are plain xor-adds, so
+// R row sums cost about R + log2(L) shuffles instead of R full reductions.
+// Afterwards the lane whose in-row index u satisfies u % (L / R) == 0 holds
+// the complete sum of accumulator u / (L / R).
+template <int R>
+__device__ __forceinline__ double reduce_rows(double (&a)[R], int lane, int L) {
+  static_assert(R == 8 || R == 16, "8 or 16 accumulators");
+  constexpr int S = R == 8 ? 3 : 4;  // halving steps
 #pragma unroll
-  for (int step = 0; step < 3; step++) {
-    const int half = kRowsPerLane >> (step + 1);
+  for (int step = 0; step < S; step++) {
+    const int half = R >> (step + 1);
     const int bit = L >> (step + 1);
     const bool upper = (lane & bit) != 0;
 #pragma unroll
@@ -90,7 +92,7 @@ __device__ __forceinline__ double reduce_rows(double (&a)[kRowsPerLane], int lan
       a[j] = keep + __shfl_xor(give, bit, kWave);
     }
   }
-  for (int bit = L >> 4; bit >= 1; bit >>= 1) a[0] += __shfl_xor(a[0], bit, kWave);
+  for (int bit = L >> (S + 1); bit >= 1; bit >>= 1) a[0] += __shfl_xor(a[0], bit, kWave);
   return a[0];
 }
 
@@ -102,13 +104,14 @@ template <int CLS>
 __device__ __forceinline__ void s1_item(const S1Item &it, const void *vals, const double *x, int x32,
                                         double *zpart, const double *dscale, int z32, double *z, int lane) {
   constexpr int VEC = vec_of(CLS);
+  constexpr int SLOTS = s1_slots(CLS);  // row slots per lane
   const int L = it.lpr;
   const int RPI = kWave / L;  // rows per load instruction
   const int SLAB = L * VEC;   // columns per load instruction
   const int q = lane / L, u = lane % L;
-  double acc[kRowsPerLane];
+  double acc[SLOTS];
 #pragma unroll
-  for (int i = 0; i < kRowsPerLane; i++) acc[i] = 0.0;
+  for (int i = 0; i < SLOTS; i++) acc[i] = 0.0;
   const int cols = (it.ncols + VEC - 1) / VEC * VEC;
   const int nslab = (cols + SLAB - 1) / SLAB;
   const int64_t rows_pad = s1_rows_pad(it.nrows, L);
@@ -133,9 +136,9 @@ __device__ __forceinline__ void s1_item(const S1Item &it, const void *vals, cons
     const char *sbase = (const char *)vals + (it.w_off + (int64_t)s * rows_pad * SLAB) * bytes_of(CLS);
     const uint32_t loff = (uint32_t)((q * ws + uc) * VEC * bytes_of(CLS));
     const uint32_t slot_bytes = (uint32_t)(RPI * ws * VEC * bytes_of(CLS));
-    raw16 t[kRowsPerLane];
+    raw16 t[SLOTS];
 #pragma unroll
-    for (int i = 0; i < kRowsPerLane; i++) {
+    for (int i = 0; i < SLOTS; i++) {
       const int ic = i < nslot ? i : nslot - 1;
       t[i] = ld16(sbase + (int64_t)ic * slot_bytes, loff);
     }
@@ -148,10 +151,10 @@ __device__ __forceinline__ void s1_item(const S1Item &it, const void *vals, cons
       g[e] = __longlong_as_double((long long)((uint64_t)__double_as_longlong(xs) & keep));
     }
 #pragma unroll
-    for (int i = 0; i < kRowsPerLane; i++) acc[i] = dot16<CLS>(t[i], g, acc[i]);
+    for (int i = 0; i < SLOTS; i++) acc[i] = dot16<CLS>(t[i], g, acc[i]);
   }
-  const double sum = reduce_rows(acc, lane, L);
-  const int spread = L / kRowsPerLane;
+  const double sum = reduce_rows<SLOTS>(acc, lane, L);
+  const int spread = L / SLOTS;
   if (u % spread == 0) {
     const int row = q + RPI * (u / spread);
     if (row < it.nrows) {

@@ -460,7 +460,7 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
     const int cls = g.cls;
     const int lpr = s1_lpr(cls, g.ncols);
     const int64_t CH = chunk_cols(g);
-    const int64_t RB = P->mr ? kRowChunk : (int64_t)kRowsPerLane * (kWave / lpr);  // rows per item
+    const int64_t RB = P->mr ? kRowChunk : (int64_t)s1_slots(cls) * (kWave / lpr);  // rows per item
     for (int64_t k = 0; k < R; k++) {
       auto [blk, t] = g.rows[k];
       P->terms[blk][t].zidx = g.z0 + k;
