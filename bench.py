@@ -42,7 +42,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # kernel and layout sources it was measured with (their hash).
 PROFILED_TRAFFIC = {
     ("plates-128", "M2-Mixed"): {"sources_sha256_16": "9be1ab7bc1196c46", "k_stage2_bytes": 899.1e6},
-    ("sphere-L7+8", "M2-Mixed"): {"sources_sha256_16": "9be1ab7bc1196c46", "k_stage2_bytes": 3111.7e6},
+    ("sphere-L7+8", "M2-Mixed"): {"sources_sha256_16": "45420e889469a96b", "k_stage2_bytes": 3000.2e6},
+    ("sphere-L7+8", "BF16-scaled"): {"sources_sha256_16": "45420e889469a96b", "k_stage2_bytes": 1883.0e6},
 }
 PROFILED_SOURCES = ["paper_1911_00093_amd/csrc/matvec.hip", "paper_1911_00093_amd/csrc/hmat_impl.h",
                     "paper_1911_00093_amd/csrc/pack.cpp"]
@@ -100,6 +101,16 @@ def assembly_note(bs):
             f"entries + ACA {st['ms_fill']:.0f} ms" +
             (f" (k_aca {st['ms_aca']:.1f} ms, k_emit {st['ms_emit']:.1f} ms, copy-back {st['ms_copy']:.0f} ms, "
              f"host-filled blocks {st['host_blocks']})" if st["rank_cap"] else ""))
+
+
+def profiled_traffic(args, variant_name):
+    """Stage-2 HBM bytes per launch from the committed rocprofv3 counters, if
+    they were taken for this workload, variant and these sources."""
+    P = PROFILED_TRAFFIC.get((args.workload, variant_name))
+    if (P is not None and sources_hash() == P["sources_sha256_16"] and args.drop == 0 and not args.dense_split
+            and args.eps is None):
+        return P["k_stage2_bytes"]
+    return None
 
 
 def storage_label(variant, c=-1, dense_split=False, drop=0):
@@ -357,11 +368,7 @@ def main():
     copy_gbs = 2 * (1 << 30) / (e0.elapsed_time(e1) / 1e3) / 1e9
     del buf, dst
 
-    P = PROFILED_TRAFFIC.get((args.workload, args.variant))
-    traffic = None
-    if (P is not None and sources_hash() == P["sources_sha256_16"] and args.drop == 0 and not args.dense_split
-            and args.eps is None):
-        traffic = P["k_stage2_bytes"]
+    traffic = profiled_traffic(args, args.variant)
 
     # roofline of the dominant kernel (stage 2): algorithmic bytes of one
     # launch over its average duration in the back-to-back pass
@@ -503,6 +510,7 @@ def bench_extra_variant(args, bs, variant, H64, b, work, x, xref, t_fp64, stream
             "matvec_frac": round(B / ms / 1e6 / HBM_PEAK_GBS, 4),
             "kernel_ms": {"stage1": round(kt[0], 4), "stage1_reduce": round(kt[1], 4), "stage2": round(kt[2], 4)},
             "stage2_frac": round(st.stage2_algorithmic_bytes / (kt[2] / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if kt[2] else None,
+            "stage2_traffic": profiled_traffic(args, hmat.PRECISION_NAMES[variant]),
             "autotune": tune}
 
 
