@@ -263,9 +263,10 @@ int hmat_get_stats(hmat_t h, hmat_stats *out);
 /* ------------------------------------------------------------- solver */
 /* Right preconditioner K for hmat_bicgstab (a fixed linear map; not from the
  * paper).  HMAT_PRECOND_JACOBI inverts every dense diagonal block of the
- * handle's FP64 source blocks (Gauss-Jordan with partial pivoting, FP64) and
- * applies y_tau = A_tautau^{-1} x_tau on each; rows of no diagonal dense
- * block pass through unchanged. */
+ * handle's FP64 source blocks (up to 256 rows; hmat_batched_inverse on the
+ * GPU, inside hmat_precond_create, which fails with HMAT_E_ARG naming the
+ * first singular block) and applies y_tau = A_tautau^{-1} x_tau on each;
+ * rows of no diagonal dense block pass through unchanged. */
 typedef struct hmat_precond_s *hmat_precond_t;
 enum { HMAT_PRECOND_NONE = 0, HMAT_PRECOND_JACOBI = 1, HMAT_PRECOND_LEARNED = 2 };
 
@@ -436,9 +437,30 @@ int hmat_leaf_features(int64_t m, const double *centroids, const double *normals
  * applies in FP64.  HMAT_E_ARG for a zero diagonal entry. */
 int hmat_leaf_scales(int64_t m, const double *a, float *dinv, float *sinv);
 
-/* Exact inverse of a dense m x m block (host, FP64 Gauss-Jordan with
- * partial pivoting; column-major in and out).  HMAT_E_ARG if singular. */
-int hmat_dense_inverse(int64_t m, const double *a, double *out);
+/* Batched exact FP64 inverse of small dense square matrices on the GPU, in
+ * place: the inverses A_tautau^{-1} of the dense diagonal leaves that
+ * block-Jacobi applies and that the learned map is trained against
+ * (Gauss-Jordan elimination with partial pivoting, every operation in FP64;
+ * one workgroup per matrix, orders up to 128 held in LDS).
+ *   count      number of matrices, 0 .. 2^31-1.
+ *   off, dim   device arrays of count entries: matrix q has order dim[q] and
+ *              starts at a + off[q] (elements), stored m x m column-major
+ *              (row-major storage gives the inverse in row-major: the
+ *              inverse of the transpose is the transposed inverse).
+ *              Matrices must not overlap.
+ *   max_dim    (host) the largest order present, 1 .. 256; it sizes the
+ *              launch's LDS.
+ *   a          device FP64, overwritten by the inverses.
+ *   first_bad  device int64 (one word): set to count, then to the smallest q
+ *              whose order lies outside 1 .. max_dim or whose elimination
+ *              meets a pivot that is zero or NaN (such a matrix holds
+ *              unspecified values afterwards; every other matrix is
+ *              inverted).
+ * Asynchronous on `stream`; allocates nothing.  HMAT_E_ARG for null
+ * pointers, count < 0 or max_dim outside 1 .. 256; HMAT_E_HIP if a launch
+ * fails.  The caller owns every buffer. */
+int hmat_batched_inverse(int64_t count, const int64_t *off, const int32_t *dim, int32_t max_dim, double *a,
+                         int64_t *first_bad, void *stream);
 
 /* Device workspace of the MLP calls for `batch` samples. */
 uint64_t hmat_mlp_workspace_bytes(int64_t batch);

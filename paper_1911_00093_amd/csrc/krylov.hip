@@ -22,7 +22,9 @@
 // A failed FP64 true-residual check (Sec. 4.1.3) restarts from the current x.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -467,35 +469,6 @@ int64_t hm::precond_order(const hmat_precond_s *p) { return p->n; }
 
 namespace hm {
 
-// Gauss-Jordan with partial pivoting on [A | I] (FP64); A column-major m x m.
-static bool invert(int64_t m, const double *A, double *out) {
-  std::vector<double> W(m * 2 * m);
-  for (int64_t i = 0; i < m; i++)
-    for (int64_t j = 0; j < m; j++) {
-      W[i * 2 * m + j] = A[i + j * m];
-      W[i * 2 * m + m + j] = i == j;
-    }
-  for (int64_t k = 0; k < m; k++) {
-    int64_t p = k;
-    for (int64_t i = k + 1; i < m; i++)
-      if (std::fabs(W[i * 2 * m + k]) > std::fabs(W[p * 2 * m + k])) p = i;
-    if (W[p * 2 * m + k] == 0.0) return false;
-    if (p != k)
-      for (int64_t j = 0; j < 2 * m; j++) std::swap(W[k * 2 * m + j], W[p * 2 * m + j]);
-    const double piv = W[k * 2 * m + k];
-    for (int64_t j = 0; j < 2 * m; j++) W[k * 2 * m + j] /= piv;
-    for (int64_t i = 0; i < m; i++) {
-      if (i == k) continue;
-      const double f = W[i * 2 * m + k];
-      if (f == 0.0) continue;
-      for (int64_t j = 0; j < 2 * m; j++) W[i * 2 * m + j] -= f * W[k * 2 * m + j];
-    }
-  }
-  for (int64_t i = 0; i < m; i++)
-    for (int64_t j = 0; j < m; j++) out[i + j * m] = W[i * 2 * m + m + j];
-  return true;
-}
-
 static void diag_blocks(const hmat_blocks *b, std::vector<int64_t> &ids) {
   for (int64_t k = 0; k < b->nblocks; k++)
     if (b->kind[k] == HMAT_DENSE && b->row0[k] == b->col0[k] && b->nrows[k] == b->ncols[k] && b->nrows[k] <= kThreads)
@@ -525,7 +498,7 @@ int hmat_precond_plan(const hmat_blocks *b, int32_t kind, uint64_t *device_bytes
   }
   uint64_t vals = 0;
   for (int64_t k : ids) vals += (uint64_t)b->nrows[k] * b->nrows[k];
-  *device_bytes = hm::align256(ids.size() * sizeof(hm::JLeaf)) + hm::align256(vals * 8);
+  *device_bytes = hm::align256(ids.size() * sizeof(hm::JLeaf)) + hm::align256(vals * 8) + 256;  // + status word
   return HMAT_OK;
   });
 }
@@ -547,14 +520,6 @@ int hmat_precond_leaves(const hmat_blocks *b, int32_t kind, int64_t *block, int6
     if (row0) row0[q] = b->row0[ids[q]];
     if (rows) rows[q] = b->nrows[ids[q]];
   }
-  return HMAT_OK;
-  });
-}
-
-int hmat_dense_inverse(int64_t m, const double *a, double *out) {
-  return hm::host_guarded([&]() -> int {
-  if (!a || !out || m < 1) return hm::fail(HMAT_E_ARG, "bad argument");
-  if (!hm::invert(m, a, out)) return hm::fail(HMAT_E_ARG, "singular matrix");
   return HMAT_OK;
   });
 }
@@ -641,16 +606,18 @@ int hmat_precond_create(const hmat_blocks *b, int32_t kind, void *dev_mem, uint6
   hm::diag_blocks(b, ids);
   std::vector<hm::JLeaf> leaves(ids.size());
   uint64_t tot = 0;
+  int max_m = 1;
   for (size_t q = 0; q < ids.size(); q++) {
     const int64_t k = ids[q];
     leaves[q] = {b->row0[k], (int64_t)tot, (int32_t)b->nrows[k], 0};
     tot += (uint64_t)b->nrows[k] * b->nrows[k];
+    max_m = std::max(max_m, (int)b->nrows[k]);
   }
-  std::vector<double> inv(tot);
+  // the diagonal leaves A_tt, packed in leaf order; inverted in place on the GPU
+  std::vector<double> vals(tot);
   for (size_t q = 0; q < ids.size(); q++) {
     const int64_t k = ids[q];
-    if (!hm::invert(b->nrows[k], b->data + b->offset[k], inv.data() + leaves[q].off))
-      return hm::fail(HMAT_E_ARG, "diagonal block %lld is singular", (long long)k);
+    std::memcpy(vals.data() + leaves[q].off, b->data + b->offset[k], (size_t)b->nrows[k] * b->nrows[k] * 8);
   }
   auto *P = new hmat_precond_s();
   P->n = b->n;
@@ -664,13 +631,34 @@ int hmat_precond_create(const hmat_blocks *b, int32_t kind, void *dev_mem, uint6
   unsigned char *d = (unsigned char *)dev_mem;
   P->leaves = (hm::JLeaf *)d;
   P->inv = (double *)(d + hm::align256(ids.size() * sizeof(hm::JLeaf)));
+  int64_t *first_bad = (int64_t *)(d + hm::align256(ids.size() * sizeof(hm::JLeaf)) + hm::align256(tot * 8));
+  static_assert(sizeof(hm::JLeaf) == 24, "descriptor strides below");
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = hipMemcpyAsync(P->leaves, leaves.data(), leaves.size() * sizeof(hm::JLeaf), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(P->inv, inv.data(), tot * 8, hipMemcpyHostToDevice, st);
+  int64_t bad = 0;
+  hipError_t e = hipSuccess;
+  if (!ids.empty()) {
+    e = hipMemcpyAsync(P->leaves, leaves.data(), leaves.size() * sizeof(hm::JLeaf), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(P->inv, vals.data(), tot * 8, hipMemcpyHostToDevice, st);
+  }
+  if (e == hipSuccess) {
+    const unsigned char *desc = (const unsigned char *)P->leaves;
+    rc = hm::batched_inverse(P->nleaf, (const int64_t *)(desc + offsetof(hm::JLeaf, off)), 3,
+                             (const int32_t *)(desc + offsetof(hm::JLeaf, m)), 6, max_m, P->inv, first_bad, stream);
+    if (rc) {
+      delete P;
+      return rc;
+    }
+    e = hipMemcpyAsync(&bad, first_bad, 8, hipMemcpyDeviceToHost, st);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     delete P;
-    return hm::fail(HMAT_E_HIP, "preconditioner upload failed: %s", hipGetErrorString(e));
+    return hm::fail(HMAT_E_HIP, "preconditioner setup failed: %s", hipGetErrorString(e));
+  }
+  if (bad < P->nleaf) {
+    const long long blk = (long long)ids[bad];
+    delete P;
+    return hm::fail(HMAT_E_ARG, "diagonal block %lld is singular", blk);
   }
   *out = P;
   return HMAT_OK;

@@ -37,7 +37,7 @@ EXPORTED = [
     "hmat_assembly_perm", "hmat_assembly_free", "hmat_version", "hmat_set_profiling", "hmat_kernel_times",
     "hmat_stream_read", "hmat_stream_copy", "hmat_plan_batched", "hmat_build_batched", "hmat_system_offsets",
     "hmat_bicgstab_batched_workspace_bytes", "hmat_bicgstab_batched", "hmat_precond_create_learned",
-    "hmat_precond_leaves", "hmat_leaf_features", "hmat_leaf_scales", "hmat_dense_inverse", "hmat_mlp_workspace_bytes",
+    "hmat_precond_leaves", "hmat_leaf_features", "hmat_leaf_scales", "hmat_batched_inverse", "hmat_mlp_workspace_bytes",
     "hmat_mlp_forward", "hmat_mlp_loss_grad", "hmat_mlp_adam", "hmat_autotune", "hmat_permute",
     "hmat_bicgstab_noalloc_max_n", "hmat_bicgstab_noalloc", "hmat_pack_host", "hmat_set_tuning",
 ]
@@ -174,7 +174,7 @@ def lib():
         "hmat_precond_leaves": (C.c_int, [P, I32, P, P, P, I64, P]),
         "hmat_leaf_features": (C.c_int, [I64, P, P, P, P]),
         "hmat_leaf_scales": (C.c_int, [I64, P, P, P]),
-        "hmat_dense_inverse": (C.c_int, [I64, P, P]),
+        "hmat_batched_inverse": (C.c_int, [I64, P, P, C.c_int32, P, P, P]),
         "hmat_mlp_workspace_bytes": (U64, [I64]),
         "hmat_mlp_forward": (C.c_int, [P, P, I64, P, P, U64, P]),
         "hmat_mlp_loss_grad": (C.c_int, [P, P, P, P, P, P, I64, P, I64, P, P, P, U64, P]),
@@ -586,13 +586,44 @@ def hmat_leaf_scales(A):
     return dinv, sinv[0]
 
 
-def hmat_dense_inverse(A) -> np.ndarray:
-    """Exact inverse of a dense block (host FP64 Gauss-Jordan with pivoting)."""
-    A = np.asfortranarray(A, dtype=np.float64)
-    m = A.shape[0]
-    out = np.zeros((m, m), order="F")
-    _check(lib().hmat_dense_inverse(m, C.c_void_p(A.ctypes.data), C.c_void_p(out.ctypes.data)))
-    return out
+def hmat_batched_inverse(a, off, dim, max_dim: int, stream=None) -> int:
+    """In-place FP64 inverses on the GPU (hmat_batched_inverse): `a` float64,
+    `off` int64 and `dim` int32 device tensors (matrix q of order dim[q] at
+    element off[q]); returns the first flagged matrix (== count when all were
+    inverted), read back after the stream has finished."""
+    import torch
+
+    count = int(off.numel())
+    for t, dt, name in ((a, torch.float64, "a"), (off, torch.int64, "off"), (dim, torch.int32, "dim")):
+        if not isinstance(t, torch.Tensor) or t.dtype != dt or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous {dt} tensor")
+        _on_device(t, name)
+    if dim.numel() != count:
+        raise ValueError("off and dim differ in length")
+    bad = torch.empty(1, dtype=torch.int64, device=a.device)
+    _check(lib().hmat_batched_inverse(count, C.c_void_p(off.data_ptr()), C.c_void_p(dim.data_ptr()), int(max_dim),
+                                      C.c_void_p(a.data_ptr()), C.c_void_p(bad.data_ptr()), _stream_ptr(stream)))
+    torch.cuda.synchronize(a.device)
+    return int(bad.cpu()[0])
+
+
+def dense_inverses(mats, device="cuda") -> list:
+    """Exact inverses of host square FP64 matrices (orders 1..256) through
+    hmat_batched_inverse; HmatError names the first singular one."""
+    import torch
+
+    dims = np.array([m.shape[0] for m in mats], np.int32)
+    offs = np.zeros(len(mats), np.int64)
+    if len(mats) > 1:
+        offs[1:] = np.cumsum(dims.astype(np.int64) ** 2)[:-1]
+    flat = np.concatenate([np.asarray(m, np.float64).ravel(order="F") for m in mats]) if mats else np.zeros(1)
+    a = torch.from_numpy(flat).to(device)
+    bad = hmat_batched_inverse(a, torch.from_numpy(offs).to(device), torch.from_numpy(dims).to(device),
+                               int(dims.max()) if len(mats) else 1)
+    if bad < len(mats):
+        raise HmatError(HMAT_E_ARG, f"matrix {bad} is singular")
+    host = a.cpu().numpy()
+    return [host[o:o + d * d].reshape(d, d, order="F") for o, d in zip(offs, dims)]
 
 
 class MLP:

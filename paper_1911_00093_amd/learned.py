@@ -21,7 +21,8 @@ def leaf_inputs(mesh, bs: hmat.BlockSet, with_inverse: bool = False):
     """Per diagonal leaf of an assembled mesh, in the preconditioner's leaf
     order: features (k, 512) float32, 1 / A_ii (k, 64), 1 / s_tau (k,),
     panel count m (k,), and with_inverse the exact inverse (k, 64, 64),
-    row-major with the leaf's inverse in the leading m x m corner."""
+    row-major with the leaf's inverse in the leading m x m corner (all
+    leaves inverted in one batch on the GPU)."""
     blk, r0, m = hmat.precond_leaves(bs, hmat.PRECOND_LEARNED)
     k = blk.size
     cent, nrm, area = mesh.centroids[bs.perm], mesh.normals[bs.perm], mesh.areas[bs.perm]
@@ -29,14 +30,17 @@ def leaf_inputs(mesh, bs: hmat.BlockSet, with_inverse: bool = False):
     dinv = np.zeros((k, LEAF), np.float32)
     sinv = np.zeros(k, np.float32)
     ainv = np.zeros((k, LEAF, LEAF), np.float32) if with_inverse else None
+    leaves = []
     for q in range(k):
         a, mm = int(r0[q]), int(m[q])
         x[q] = hmat.hmat_leaf_features(cent[a:a + mm], nrm[a:a + mm], area[a:a + mm])
         off = int(bs.offset[blk[q]])
         A = bs.data[off:off + mm * mm].reshape(mm, mm, order="F")
         dinv[q], sinv[q] = hmat.hmat_leaf_scales(A)
-        if with_inverse:
-            ainv[q, :mm, :mm] = hmat.hmat_dense_inverse(A)
+        leaves.append(A)
+    if with_inverse:
+        for q, Ai in enumerate(hmat.dense_inverses(leaves)):
+            ainv[q, :Ai.shape[0], :Ai.shape[0]] = Ai
     return dict(x=x, dinv=dinv, sinv=sinv, m=m.astype(np.int32), ainv=ainv)
 
 

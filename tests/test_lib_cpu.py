@@ -7,6 +7,7 @@
   block partition as the oracle, bit for bit, and the same factors.
 """
 
+import ctypes as C
 import os
 import re
 import subprocess
@@ -276,16 +277,20 @@ def test_leaf_features_match_oracle():
         hmat.hmat_leaf_features(np.zeros((65, 3)), np.zeros((65, 3)), np.ones(65))
 
 
-def test_dense_inverse_matches_oracle():
-    m, h = oracle_hmatrix("sphere-L3")
-    b = next(i for i in range(h.nblocks) if h.kind[i] == 0 and h.row0[i] == h.col0[i])
-    k = int(h.nrows[b])
-    A = h.data[h.offset[b]:h.offset[b] + k * k].reshape(k, k, order="F")
-    Ai = hmat.hmat_dense_inverse(A)
-    assert np.abs(Ai @ A - np.eye(k)).max() < 1e-10
-    assert np.allclose(Ai, oracle.invert(A), rtol=1e-10, atol=1e-12 * np.abs(Ai).max())
-    with pytest.raises(hmat.HmatError):
-        hmat.hmat_dense_inverse(np.zeros((3, 3)))
+def test_batched_inverse_argument_errors():
+    """hmat_batched_inverse refuses bad arguments before touching the GPU."""
+    L = hmat.lib()
+    P = C.c_void_p
+    dev = P(256)  # never dereferenced: every call below fails its host checks
+    assert L.hmat_batched_inverse(-1, dev, dev, 64, dev, dev, None) == hmat.HMAT_E_ARG
+    assert L.hmat_batched_inverse(1 << 31, dev, dev, 64, dev, dev, None) == hmat.HMAT_E_ARG
+    assert L.hmat_batched_inverse(4, dev, dev, 0, dev, dev, None) == hmat.HMAT_E_ARG
+    assert L.hmat_batched_inverse(4, dev, dev, 257, dev, dev, None) == hmat.HMAT_E_ARG
+    assert L.hmat_batched_inverse(4, None, dev, 64, dev, dev, None) == hmat.HMAT_E_ARG
+    assert L.hmat_batched_inverse(4, dev, None, 64, dev, dev, None) == hmat.HMAT_E_ARG
+    assert L.hmat_batched_inverse(4, dev, dev, 64, None, dev, None) == hmat.HMAT_E_ARG
+    assert L.hmat_batched_inverse(0, None, None, 1, None, None, None) == hmat.HMAT_E_ARG
+    assert b"null" in L.hmat_last_error()
 
 
 def test_precond_plan_learned():
