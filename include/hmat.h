@@ -571,8 +571,10 @@ int hmat_kernel_times(hmat_t h, double *avg_ms, int64_t *count);
 
 /* Bandwidth calibration kernels (device pointers, 16-byte aligned, bytes a
  * multiple of 16), asynchronous on `stream`.  hmat_stream_read reads
- * `bytes` with the same 16-byte non-temporal loads the product uses (sink:
- * one device double, written only to keep the loads alive);
+ * `bytes` with 16-byte non-temporal loads, one contiguous range per
+ * workgroup and eight loads in flight per thread, the fastest plain read
+ * measured on MI355X (sink: one device double, written only to keep the
+ * loads alive);
  * hmat_stream_copy copies `bytes` from src to dst. */
 int hmat_stream_read(const void *src, uint64_t bytes, double *sink, void *stream);
 int hmat_stream_copy(void *dst, const void *src, uint64_t bytes, void *stream);
