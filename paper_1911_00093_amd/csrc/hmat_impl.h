@@ -305,10 +305,6 @@ int launch_matvec_mr(const hmat_s *h, const double *x, double *y, int64_t nrhs, 
 int size_grids_mr(hmat_s *h);
 // order of a preconditioner (krylov.hip)
 int64_t precond_order(const hmat_precond_s *p);
-// hmat_batched_inverse with strided descriptors (inverse.hip): matrix q has
-// order dim[q * dim_step] and starts at a + off[q * off_step].
-int batched_inverse(int64_t count, const int64_t *off, int off_step, const int32_t *dim, int dim_step, int max_m,
-                    double *a, int64_t *first_bad, void *stream);
 
 // Kernel timing (diag.hip): mark(h, k, stream) records event k (0..3) of the
 // current product when timing is enabled.

@@ -20,6 +20,7 @@
 
 #include "hmat.h"
 #include "hmat_impl.h"
+#include "inverse.h"
 
 namespace hm {
 

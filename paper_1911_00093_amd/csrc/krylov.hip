@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "hmat_impl.h"
+#include "inverse.h"
 
 namespace hm {
 
