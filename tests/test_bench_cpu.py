@@ -1,0 +1,42 @@
+"""bench.py's host side (no GPU): the one-GPU contract, the CPU refusal, and
+the helpers that label the JSON line."""
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+from tests.conftest import ROOT
+
+
+def run_bench(*args):
+    env = dict(os.environ, HIP_VISIBLE_DEVICES="")
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                          env=env, timeout=300, cwd=ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    p = run_bench("--gpus", "2")
+    assert p.returncode == 2 and "exactly one GPU" in p.stderr
+
+
+def test_no_gpu_is_refused_loudly():
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    for extra in ((), ("--sweep-variants", "--workload", "plates-128"), ("--workload", "ellipsoids-64x16")):
+        p = run_bench("--steps", "1", *extra)
+        assert p.returncode == 1 and "needs a GPU" in p.stderr, (extra, p.stderr[-500:])
+
+
+def test_labels():
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1911_00093_amd import hmat
+
+    assert "fp32 dense" in bench.storage_label(hmat.M2_MIXED)
+    assert "bf16" in bench.storage_label(hmat.BF16_SCALED).lower()
+    assert "fp64" in bench.storage_label(hmat.M1_DOUBLE).lower()
+    assert len(bench.sources_hash()) == 16
