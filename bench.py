@@ -179,6 +179,9 @@ def main():
                     help="sphere-L7+8: skip the scaled-BF16 solves reported beside the headline variant")
     ap.add_argument("--no-autotune", action="store_true",
                     help="single-system workloads: keep the untuned launch configuration")
+    ap.add_argument("--accuracy-tol", type=float, default=1e-10,
+                    help="also time mixed and FP64 solves to this tolerance (0: skip), the mixed one with early "
+                         "FP64 true-residual checks, and report both solutions' error against the FP64 1e-12 one")
     ap.add_argument("--sweep-variants", action="store_true",
                     help="every Table 1 variant, Method 3 for c = -1..7 and BF16 on the workload's blocks")
     ap.add_argument("--train-leaves", type=int, default=20000)
@@ -304,6 +307,29 @@ def main():
     err_fp64 = float(torch.linalg.norm(x64 - xref) / torch.linalg.norm(xref))
     err_same_tol = float(torch.linalg.norm(xs - x64) / torch.linalg.norm(x64))
 
+    # a tighter tolerance: what the solution error against the FP64 1e-12
+    # solve becomes when both solvers go further (untimed for the metric)
+    accuracy = None
+    if args.accuracy_tol > 0 and not gm:
+        accuracy = {"tol": args.accuracy_tol, "mixed_refine": 1e-2}
+        reps = max(1, min(args.steps, 3))
+        for key, H, refine in (("mixed", Hm, 1e-2), ("fp64", H64, 0.0)):
+            xa = torch.zeros(n, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+            for _ in range(reps):
+                xa, ia = hmat.hmat_bicgstab(H, b, x=xa.zero_(), h_fp64=H64, tol=args.accuracy_tol, maxiter=4000,
+                                            poll_every=args.poll_every, work=work, refine=refine)
+            torch.cuda.synchronize()
+            assert ia["status"] == 0, (key, ia)
+            accuracy[key] = {"ms": round(1e3 * (time.perf_counter() - t_start) / reps, 3),
+                             "iterations": ia["iterations"], "restarts": ia["restarts"],
+                             "true_rel_res": ia["true_rel_res"],
+                             "solution_rel_err_vs_fp64_1e-12":
+                                 float(torch.linalg.norm(xa - xref) / torch.linalg.norm(xref))}
+        accuracy["speedup_vs_fp64"] = round(accuracy["fp64"]["ms"] / accuracy["mixed"]["ms"], 3)
+        log(f"[accuracy] {accuracy}")
+
     # ---------------- untimed: per-kernel durations with HIP events
     # (a) a replica of the timed mixed solves.  Products queued past the
     # recurrence's stop return at once; the device counts the products that
@@ -413,6 +439,7 @@ def main():
         "solution_rel_err": {"mixed_vs_fp64_1e-12": err_mixed, "fp64_1e-8_vs_fp64_1e-12": err_fp64,
                              "mixed_vs_fp64_same_tol": err_same_tol},
         "true_rel_res": {"mixed": infos[-1]["true_rel_res"], "fp64": infos64[-1]["true_rel_res"]},
+        "accuracy_tighter_tol": accuracy,
         "bytes_per_matvec": {"mixed": int(Bm), "fp64": int(B64),
                              "mixed_stage1": int(k1_bytes), "mixed_stage2": int(k2_bytes)},
         "matvec_only": matvec_gbs,
