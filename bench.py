@@ -529,6 +529,17 @@ def bench_extra_variant(args, bs, variant, H64, b, work, x, xref, t_fp64, stream
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     assert all(i["status"] == 0 for i in infos), infos
+    accuracy = None
+    if args.accuracy_tol > 0:  # reported whatever the outcome (status included), never asserted
+        xa = torch.zeros_like(x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xa, ia = hmat.hmat_bicgstab(H, b, x=xa, h_fp64=H64, tol=args.accuracy_tol, maxiter=4000,
+                                    poll_every=args.poll_every, work=work, refine=1e-2)
+        torch.cuda.synchronize()
+        accuracy = {"tol": args.accuracy_tol, "status": ia["status"], "ms": round(1e3 * (time.perf_counter() - t0), 3),
+                    "iterations": ia["iterations"], "restarts": ia["restarts"], "true_rel_res": ia["true_rel_res"],
+                    "solution_rel_err_vs_fp64_1e-12": float(torch.linalg.norm(xa - xref) / torch.linalg.norm(xref))}
     xv = torch.randn(b.numel(), dtype=torch.float64, device=b.device)
     yv = torch.empty_like(xv)
     ms, ms_best = product_sets(H, xv, yv, args.matvec_reps, stream)
@@ -549,6 +560,7 @@ def bench_extra_variant(args, bs, variant, H64, b, work, x, xref, t_fp64, stream
             "kernel_ms": {"stage1": round(kt[0], 4), "stage1_reduce": round(kt[1], 4), "stage2": round(kt[2], 4)},
             "stage2_frac": round(st.stage2_algorithmic_bytes / (kt[2] / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if kt[2] else None,
             "stage2_traffic": profiled_traffic(args, hmat.PRECISION_NAMES[variant]),
+            "accuracy_tighter_tol": accuracy,
             "autotune": tune}
 
 
