@@ -38,12 +38,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 # HBM traffic of the dominant kernel per launch, from the rocprofv3 --pmc
 # FETCH_SIZE / WRITE_SIZE runs recorded in profiles/ (scaled by the
-# plain-copy calibration), per (workload, variant).  Valid only for the
-# kernel and layout sources it was measured with (their hash).
+# plain-copy calibration): stage-2 bytes per launch per (workload, variant)
+# and operand tile.  Valid only for the kernel and layout sources they were
+# measured with (their hash).
 PROFILED_TRAFFIC = {
-    ("plates-128", "M2-Mixed"): {"sources_sha256_16": "9be1ab7bc1196c46", "k_stage2_bytes": 899.1e6},
-    ("sphere-L7+8", "M2-Mixed"): {"sources_sha256_16": "45420e889469a96b", "k_stage2_bytes": 3000.2e6},
-    ("sphere-L7+8", "BF16-scaled"): {"sources_sha256_16": "45420e889469a96b", "k_stage2_bytes": 1883.0e6},
+    ("sphere-L7+8", "M2-Mixed"): {"sources_sha256_16": "f2b00ff5e01ab288",
+                                  "k_stage2_bytes": {1024: 3008.9e6, 2048: 3001.1e6, 4096: 3003.9e6}},
+    ("sphere-L7+8", "BF16-scaled"): {"sources_sha256_16": "f2b00ff5e01ab288",
+                                     "k_stage2_bytes": {1024: 1876.2e6, 2048: 1883.2e6, 4096: 1884.5e6}},
 }
 PROFILED_SOURCES = ["paper_1911_00093_amd/csrc/matvec.hip", "paper_1911_00093_amd/csrc/hmat_impl.h",
                     "paper_1911_00093_amd/csrc/pack.cpp"]
@@ -78,6 +80,10 @@ WORKLOADS = {
 }
 
 
+def _r4(v):
+    return None if v is None else round(v, 4)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -103,13 +109,14 @@ def assembly_note(bs):
              f"host-filled blocks {st['host_blocks']})" if st["rank_cap"] else ""))
 
 
-def profiled_traffic(args, variant_name):
+def profiled_traffic(args, variant_name, tile):
     """Stage-2 HBM bytes per launch from the committed rocprofv3 counters, if
-    they were taken for this workload, variant and these sources."""
+    they were taken for this workload, variant, operand tile and these
+    sources."""
     P = PROFILED_TRAFFIC.get((args.workload, variant_name))
     if (P is not None and sources_hash() == P["sources_sha256_16"] and args.drop == 0 and not args.dense_split
             and args.eps is None):
-        return P["k_stage2_bytes"]
+        return P["k_stage2_bytes"].get(int(tile))
     return None
 
 
@@ -196,7 +203,7 @@ def main():
 
     import torch
 
-    from paper_1911_00093_amd import hmat, meshes
+    from paper_1911_00093_amd import hmat, meshes, tuning
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -232,9 +239,10 @@ def main():
     if not args.no_autotune:  # launch configuration per handle, timed on its own blocks (results unchanged)
         t0 = time.time()
         for name, H in (("M1-Double", H64), (args.variant, Hm)):
-            info = H.autotune(reps=10)
+            info = tuning.autotune(H, reps=10)
             tune[name] = {k: info[k] for k in ("stage1_grid", "stage2_grid", "stage2_tile")}
-            tune[name].update(ms_fixed=round(info["ms_fixed"], 4), ms_tuned=round(info["ms_tuned"], 4))
+            tune[name].update(ms_fixed=_r4(info.get("ms_fixed")), ms_tuned=_r4(info.get("ms_tuned")),
+                              cached=info["cached"])
         log(f"[setup] autotune {time.time() - t0:.1f}s: {tune}")
     st64, stm = H64.stats(), Hm.stats()
     B64, Bm = st64.algorithmic_bytes, stm.algorithmic_bytes
@@ -393,7 +401,7 @@ def main():
     copy_gbs = 2 * (1 << 30) / (e0.elapsed_time(e1) / 1e3) / 1e9
     del buf, dst
 
-    traffic = profiled_traffic(args, args.variant)
+    traffic = profiled_traffic(args, args.variant, tune.get(args.variant, {}).get("stage2_tile", 2048))
 
     # roofline of the dominant kernel (stage 2): algorithmic bytes of one
     # launch over its average duration in the back-to-back pass
@@ -506,12 +514,12 @@ def bench_extra_variant(args, bs, variant, H64, b, work, x, xref, t_fp64, stream
     runs), back-to-back products with per-kernel events (untimed pass)."""
     import torch
 
-    from paper_1911_00093_amd import hmat
+    from paper_1911_00093_amd import hmat, tuning
 
     H = hmat.HMatrix(bs, variant)
     tune = None
     if not args.no_autotune:
-        info = H.autotune(reps=10)
+        info = tuning.autotune(H, reps=10)
         tune = {k: info[k] for k in ("stage1_grid", "stage2_grid", "stage2_tile")}
     refine = 1e-2 if variant == hmat.BF16_SCALED else 0.0
     B = H.stats().algorithmic_bytes
@@ -559,7 +567,8 @@ def bench_extra_variant(args, bs, variant, H64, b, work, x, xref, t_fp64, stream
             "matvec_frac": round(B / ms / 1e6 / HBM_PEAK_GBS, 4),
             "kernel_ms": {"stage1": round(kt[0], 4), "stage1_reduce": round(kt[1], 4), "stage2": round(kt[2], 4)},
             "stage2_frac": round(st.stage2_algorithmic_bytes / (kt[2] / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if kt[2] else None,
-            "stage2_traffic": profiled_traffic(args, hmat.PRECISION_NAMES[variant]),
+            "stage2_traffic": profiled_traffic(args, hmat.PRECISION_NAMES[variant],
+                                               (tune or {}).get("stage2_tile", 2048)),
             "accuracy_tighter_tol": accuracy,
             "autotune": tune}
 
@@ -573,11 +582,11 @@ def bench_variant_sweep(args, W, mesh, bs, dev, stream):
     residual, with its error against an FP64 solve to 1e-12."""
     import torch
 
-    from paper_1911_00093_amd import hmat
+    from paper_1911_00093_amd import hmat, tuning
 
     n = bs.n
     H64 = hmat.HMatrix(bs, hmat.M1_DOUBLE)
-    H64.autotune(reps=10)
+    tuning.autotune(H64, reps=10)
     b = torch.as_tensor(mesh.rhs()[bs.perm], device=dev)
     work = torch.empty(hmat.hmat_solver_workspace_bytes(n), dtype=torch.uint8, device=dev)
     xref, _ = hmat.hmat_bicgstab(H64, b, tol=1e-12, maxiter=4000, work=work)
@@ -592,7 +601,7 @@ def bench_variant_sweep(args, W, mesh, bs, dev, stream):
         name = hmat.PRECISION_NAMES[v] + (f" c={c}" if v == hmat.M3 else "")
         H = H64 if v == hmat.M1_DOUBLE else hmat.HMatrix(bs, v, c=c)
         if H is not H64:
-            H.autotune(reps=10)
+            tuning.autotune(H, reps=10)
         ms_mean, ms_best = product_sets(H, xv, yv, args.matvec_reps, stream)
         err = {k: float(torch.linalg.norm(H.matvec(p) - y64[k]) / torch.linalg.norm(y64[k]))
                for k, p in probes.items()}
@@ -649,7 +658,7 @@ def bench_batched(args, W, variant, dev, stream):
     persistent launch per stage on the FP64 matrix cores."""
     import torch
 
-    from paper_1911_00093_amd import hmat, meshes
+    from paper_1911_00093_amd import hmat, meshes, tuning
 
     nsys, nrhs = W["nsys"], W["nrhs"]
     t0 = time.time()
@@ -672,9 +681,9 @@ def bench_batched(args, W, variant, dev, stream):
     t0 = time.time()
     tune = {"fixed_ms": {}, "tuned_ms": {}, "choice": {}}
     for name, H in (("M1-Double", H64), (args.variant, Hm)):
-        info = H.autotune(reps=5)
-        tune["fixed_ms"][name] = round(info["ms_fixed"], 4)
-        tune["tuned_ms"][name] = round(info["ms_tuned"], 4)
+        info = tuning.autotune(H, reps=5)
+        tune["fixed_ms"][name] = _r4(info.get("ms_fixed"))
+        tune["tuned_ms"][name] = _r4(info.get("ms_tuned"))
         tune["choice"][name] = {k: info[k] for k in ("stage1_batch", "stage1_grid", "stage2_batch", "stage2_grid")}
     log(f"[setup] autotune {time.time() - t0:.1f}s: {tune}")
     stm, st64 = Hm.stats(), H64.stats()

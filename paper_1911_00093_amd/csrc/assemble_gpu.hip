@@ -32,6 +32,7 @@
 
 #include "assemble_impl.h"
 #include "hmat_impl.h"
+#include "trace.h"
 #include "workers.h"
 
 // Bit-identical to the host builder: no multiply-add contraction.
@@ -646,6 +647,7 @@ static int assemble_gpu(int64_t count, const int64_t *nv, const double *const *c
 extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const double *areas,
                                      const hmat_assemble_opts *opts, int32_t rank_cap, void *stream,
                                      hmat_assembly_t *out) {
+  hm::TraceRange trace_("hmat_assemble_bem_gpu");
   if (!out) return hm::fail(HMAT_E_ARG, "null output");
   *out = nullptr;
   if (n <= 0 || n >= INT_MAX || !centroids || !areas || !opts) return hm::fail(HMAT_E_ARG, "bad arguments");
@@ -661,6 +663,7 @@ extern "C" int hmat_assemble_bem_gpu(int64_t n, const double *centroids, const d
 extern "C" int hmat_assemble_bem_gpu_batched(int64_t count, const int64_t *n, const double *const *centroids,
                                              const double *const *areas, const hmat_assemble_opts *opts,
                                              int32_t rank_cap, void *stream, hmat_assembly_t *out) {
+  hm::TraceRange trace_("hmat_assemble_bem_gpu_batched");
   try {
     return hm::assemble_gpu(count, n, centroids, areas, opts, rank_cap, stream, out);
   } catch (const std::bad_alloc &) {

@@ -18,6 +18,7 @@
 #include <cstring>
 
 #include "hmat_impl.h"
+#include "trace.h"
 
 namespace hm {
 
@@ -357,6 +358,7 @@ uint64_t hmat_gmres_workspace_bytes(int64_t n, int32_t restart) {
 
 int hmat_gmres(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, int32_t restart, const hmat_solve_opts *o,
                hmat_solve_info *info, void *work, uint64_t work_bytes, void *stream) {
+  hm::TraceRange trace_("hmat_gmres");
   using namespace hm;
   if (info) std::memset(info, 0, sizeof *info);
   if (!h_iter || !b || !x || !o || !info || !work) return fail(HMAT_E_ARG, "null argument");

@@ -20,6 +20,7 @@
 
 #include "hmat.h"
 #include "hmat_impl.h"
+#include "trace.h"
 #include "inverse.h"
 
 namespace hm {
@@ -167,5 +168,6 @@ int batched_inverse(int64_t count, const int64_t *off, int off_step, const int32
 
 extern "C" int hmat_batched_inverse(int64_t count, const int64_t *off, const int32_t *dim, int32_t max_dim, double *a,
                                     int64_t *first_bad, void *stream) {
+  hm::TraceRange trace_("hmat_batched_inverse");
   return hm::batched_inverse(count, off, 1, dim, 1, max_dim, a, first_bad, stream);
 }

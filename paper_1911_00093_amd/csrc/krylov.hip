@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "hmat_impl.h"
+#include "trace.h"
 #include "inverse.h"
 
 namespace hm {
@@ -527,6 +528,7 @@ int hmat_precond_leaves(const hmat_blocks *b, int32_t kind, int64_t *block, int6
 
 int hmat_precond_create_learned(const hmat_blocks *b, const float *uv, void *dev_mem, uint64_t dev_bytes,
                                 void *stream, hmat_precond_t *out) {
+  hm::TraceRange trace_("hmat_precond_create_learned");
   return hm::host_guarded([&]() -> int {
   if (!out) return hm::fail(HMAT_E_ARG, "null output");
   *out = nullptr;
@@ -592,6 +594,7 @@ int hmat_precond_create_learned(const hmat_blocks *b, const float *uv, void *dev
 
 int hmat_precond_create(const hmat_blocks *b, int32_t kind, void *dev_mem, uint64_t dev_bytes, void *stream,
                         hmat_precond_t *out) {
+  hm::TraceRange trace_("hmat_precond_create");
   return hm::host_guarded([&]() -> int {
   if (!out) return hm::fail(HMAT_E_ARG, "null output");
   *out = nullptr;
@@ -687,6 +690,7 @@ int hmat_precond_destroy(hmat_precond_t p) {
 
 int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, const hmat_solve_opts *o,
                   hmat_solve_info *info, void *work, uint64_t work_bytes, void *stream) {
+  hm::TraceRange trace_("hmat_bicgstab");
   using namespace hm;
   if (info) std::memset(info, 0, sizeof *info);
   if (!h_iter || !b || !x || !o || !info || !work) return fail(HMAT_E_ARG, "null argument");
@@ -821,6 +825,7 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
     if (hs.flag == 1) {
       // convergence of the recurrence (or an early check, opts->refine):
       // confirm with the FP64 true residual
+      hm::TraceRange trace_check("true residual (FP64)");
       if ((rc = mv(h_fp64, x, w.tmp, true))) return rc;
       hipLaunchKernelGGL(k_residual, G, B, 0, st, n, b, w.tmp, w.t, w.rt, w.part, 0);
       hipLaunchKernelGGL(k_true_norm, dim3(1), B, 0, st, w.st, w.part, true_slot);

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "hmat_impl.h"
+#include "trace.h"
 
 namespace hm {
 
@@ -464,6 +465,7 @@ uint64_t hmat_bicgstab_batched_workspace_bytes(hmat_t h, int64_t nrhs) {
 int hmat_bicgstab_batched(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, int64_t nrhs,
                           const hmat_solve_opts *o, hmat_batch_result *results, hmat_solve_info *summary, void *work,
                           uint64_t work_bytes, void *stream) {
+  hm::TraceRange trace_("hmat_bicgstab_batched");
   return hm::host_guarded([&]() -> int {
   using namespace hm;
   if (summary) std::memset(summary, 0, sizeof *summary);

@@ -33,6 +33,7 @@
 #include <cstring>
 
 #include "hmat_impl.h"
+#include "trace.h"
 
 namespace hm {
 
@@ -825,6 +826,7 @@ extern "C" {
 
 int hmat_build(const hmat_blocks *blocks, const hmat_build_opts *opts, void *dev_mem, uint64_t dev_bytes,
                void *stream, hmat_t *out) {
+  hm::TraceRange trace_("hmat_build");
   if (!out) return hm::fail(HMAT_E_ARG, "null output handle");
   *out = nullptr;
   hm::Packed *P = nullptr;
@@ -841,6 +843,7 @@ int hmat_plan_batched(const hmat_blocks *systems, int64_t count, const hmat_buil
 
 int hmat_build_batched(const hmat_blocks *systems, int64_t count, const hmat_build_opts *opts, void *dev_mem,
                        uint64_t dev_bytes, void *stream, hmat_t *out) {
+  hm::TraceRange trace_("hmat_build_batched");
   if (!out) return hm::fail(HMAT_E_ARG, "null output handle");
   *out = nullptr;
   hm::Packed *P = nullptr;

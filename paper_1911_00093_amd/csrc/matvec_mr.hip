@@ -24,6 +24,7 @@
 #include <cstring>
 
 #include "hmat_impl.h"
+#include "trace.h"
 
 namespace hm {
 
@@ -439,6 +440,7 @@ extern "C" int hmat_set_tuning(hmat_t h, const hmat_tune_info *cfg) {
 }
 
 extern "C" int hmat_autotune(hmat_t h, const double *x, double *y, int32_t reps, hmat_tune_info *info, void *stream) {
+  hm::TraceRange trace_("hmat_autotune");
   using namespace hm;
   if (!h || !x || !y || !info) return fail(HMAT_E_ARG, "null argument");
   if (reps < 1 || reps > 1000) return fail(HMAT_E_ARG, "reps %d out of range", reps);

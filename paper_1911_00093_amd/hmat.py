@@ -236,6 +236,26 @@ class BlockSet:
     def nblocks(self):
         return int(self.row0.size)
 
+    _FIELDS = ("row0", "nrows", "col0", "ncols", "kind", "rank", "offset", "data")
+
+    def save(self, path):
+        """Checkpoint the assembled H-matrix (blocks, factors, permutation) to
+        an uncompressed .npz, so that a later run skips the assembly."""
+        arrays = {f: getattr(self, f) for f in self._FIELDS}
+        arrays["n"] = np.array([self.n], np.int64)
+        if self.perm is not None:
+            arrays["perm"] = self.perm
+        with open(path, "wb") as fh:
+            np.savez(fh, **arrays)
+
+    @classmethod
+    def load(cls, path) -> "BlockSet":
+        """A BlockSet saved by save(); plain arrays only (no pickled objects)."""
+        with np.load(path, allow_pickle=False) as z:
+            a = {f: z[f] for f in cls._FIELDS}
+            return cls.from_arrays(int(z["n"][0]), *(a[f] for f in cls._FIELDS),
+                                   perm=z["perm"] if "perm" in z.files else None)
+
     def struct(self) -> hmat_blocks:
         return hmat_blocks(self.n, self.nblocks, self.row0.ctypes.data, self.nrows.ctypes.data,
                            self.col0.ctypes.data, self.ncols.ctypes.data, self.kind.ctypes.data,
