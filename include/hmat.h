@@ -240,6 +240,7 @@ typedef struct {
 int hmat_pack_host(const hmat_blocks *blocks, const hmat_build_opts *opts, void *image, uint64_t bytes,
                    hmat_image_info *out);
 
+#define HMAT_SIZE_CLASSES 8
 typedef struct {
     int64_t n, nblocks, nblocks_dense, nblocks_lowrank, max_rank;
     int64_t row_chunks;       /* stage-2 work units (row ownership) */
@@ -256,6 +257,13 @@ typedef struct {
     uint64_t stage2_algorithmic_bytes; /* dense + V' values + x/z reads + y writes */
     int32_t precision;
     int32_t c;
+    /* stored values per storage class (FP64, FP32, BF16): dense columns and
+     * low-rank terms of that class, V'_m and W'_m rows together */
+    uint64_t bytes_class[3];
+    /* blocks per size class of their larger side max(#I, #J): class k holds
+     * sides in (2^(k+3), 2^(k+4)] (class 0: <= 16; the last class: > 1024) */
+    int64_t blocks_dense_by_size[HMAT_SIZE_CLASSES];
+    int64_t blocks_lowrank_by_size[HMAT_SIZE_CLASSES];
 } hmat_stats;
 
 int hmat_get_stats(hmat_t h, hmat_stats *out);

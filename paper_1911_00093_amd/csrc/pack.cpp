@@ -740,17 +740,27 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
   L.total = at;
 
   // ---- sizes and statistics
-  uint64_t bd = 0, bv = 0, bw = 0;
+  uint64_t bd = 0, bv = 0, bw = 0, bcls[NCLS] = {0, 0, 0};
+  int64_t by_size[2][HMAT_SIZE_CLASSES] = {};
   for (int64_t k = 0; k < nb; k++) {
+    const int64_t side = std::max(b->nrows[k], b->ncols[k]);
+    int sc = 0;
+    while (sc < HMAT_SIZE_CLASSES - 1 && side > (int64_t(16) << sc)) sc++;
+    by_size[b->kind[k] == HMAT_DENSE ? 0 : 1][sc]++;
     if (b->kind[k] == HMAT_DENSE && !P->dcol_off.empty()) {
-      for (int64_t j = 0; j < b->ncols[k]; j++)
-        bd += (uint64_t)b->nrows[k] * bytes_of(P->dcol_cls[P->dcol_off[k] + j]);
+      for (int64_t j = 0; j < b->ncols[k]; j++) {
+        const int cl = P->dcol_cls[P->dcol_off[k] + j];
+        bd += (uint64_t)b->nrows[k] * bytes_of(cl);
+        bcls[cl] += (uint64_t)b->nrows[k] * bytes_of(cl);
+      }
     } else if (b->kind[k] == HMAT_DENSE) {
       bd += (uint64_t)b->nrows[k] * b->ncols[k] * bytes_of(P->dense_cls);
+      bcls[P->dense_cls] += (uint64_t)b->nrows[k] * b->ncols[k] * bytes_of(P->dense_cls);
     } else {
       for (auto &t : P->terms[k]) {
         bv += (uint64_t)b->nrows[k] * bytes_of(t.cls);
         bw += (uint64_t)b->ncols[k] * bytes_of(t.cls);
+        bcls[t.cls] += (uint64_t)(b->nrows[k] + b->ncols[k]) * bytes_of(t.cls);
       }
     }
   }
@@ -787,6 +797,11 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
   S.stage2_algorithmic_bytes = bd + bv + 8ull * n;
   S.precision = prec;
   S.c = o->c;
+  for (int c = 0; c < NCLS; c++) S.bytes_class[c] = bcls[c];
+  for (int q = 0; q < HMAT_SIZE_CLASSES; q++) {
+    S.blocks_dense_by_size[q] = by_size[0][q];
+    S.blocks_lowrank_by_size[q] = by_size[1][q];
+  }
   if (info) *info = I;
   if (out_keep) *out_keep = own.release();
   return HMAT_OK;

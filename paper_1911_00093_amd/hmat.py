@@ -74,7 +74,8 @@ class hmat_stats(C.Structure):
                 ("bytes_dense", C.c_uint64), ("bytes_v", C.c_uint64), ("bytes_w", C.c_uint64),
                 ("bytes_packed", C.c_uint64), ("bytes_index", C.c_uint64), ("algorithmic_bytes", C.c_uint64),
                 ("stage1_algorithmic_bytes", C.c_uint64), ("stage2_algorithmic_bytes", C.c_uint64),
-                ("precision", C.c_int32), ("c", C.c_int32)]
+                ("precision", C.c_int32), ("c", C.c_int32), ("bytes_class", C.c_uint64 * 3),
+                ("blocks_dense_by_size", C.c_int64 * 8), ("blocks_lowrank_by_size", C.c_int64 * 8)]
 
 
 class hmat_solve_opts(C.Structure):
