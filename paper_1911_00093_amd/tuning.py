@@ -23,9 +23,19 @@ ENV = "HMAT_TUNE_CACHE"
 _CFG = ("stage1_grid", "stage2_grid", "stage2_tile", "stage1_batch", "stage2_batch")
 
 
+_LIB_ID = None
+
+
 def _library_id() -> str:
-    st = os.stat(build.LIB)
-    return f"{st.st_size}-{int(st.st_mtime)}"
+    """sha256 of the loaded library file (first 16 hex digits), once per process."""
+    global _LIB_ID
+    if _LIB_ID is None:
+        h = hashlib.sha256()
+        with open(build.LIB, "rb") as fh:
+            for chunk in iter(lambda: fh.read(1 << 22), b""):
+                h.update(chunk)
+        _LIB_ID = h.hexdigest()[:16]
+    return _LIB_ID
 
 
 def handle_key(H: hmat.HMatrix) -> str:
