@@ -47,6 +47,8 @@ struct SolverState {
   int64_t iter;
   int64_t maxiter;
   int64_t runs;     // iterations that ran (their two products included)
+  int32_t x0zero;   // x_0 is exactly zero: r_0 = b without a product
+  int32_t pad;
 };
 
 // workspace: vectors, two banks of partial sums, residual history, status
@@ -162,15 +164,18 @@ __device__ __forceinline__ void sum_src(const DotSrc &d, double (&out)[NV], doub
 
 #define GRID_LOOP(i, n) for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < (n); i += (int64_t)kParts * kThreads)
 
-// r = b - Ax (Ax in tmp), r~ = r; partials: slot0 = r~^T r, slot1 = |r|^2, slot2 = |b|^2
+// r = b - Ax (Ax in tmp), r~ = r; partials: slot0 = r~^T r, slot1 = |r|^2, slot2 = |b|^2.
+// zero_ax (optional): when it points to a nonzero word, Ax is zero and tmp
+// is not read (the product was skipped).
 __global__ __launch_bounds__(kThreads) void k_residual(int64_t n, const double *__restrict__ b,
                                                        const double *__restrict__ ax, double *__restrict__ r,
                                                        double *__restrict__ rt, double *__restrict__ part,
-                                                       int set_rt) {
+                                                       int set_rt, const int32_t *zero_ax = nullptr) {
   __shared__ double lds[4][kThreads / 64];
   double v[3] = {0, 0, 0};
+  const bool az = zero_ax && *zero_ax;
   GRID_LOOP(i, n) {
-    const double ri = b[i] - ax[i];
+    const double ri = az ? b[i] : b[i] - ax[i];
     r[i] = ri;
     if (set_rt) rt[i] = ri;
     v[0] += ri * ri;
@@ -183,6 +188,15 @@ __global__ __launch_bounds__(kThreads) void k_residual(int64_t n, const double *
     part[blockIdx.x * 4 + 1] = v[1];
     part[blockIdx.x * 4 + 2] = v[2];
   }
+}
+
+// x_0 == 0 (every entry +0.0): then r_0 = b and its product is skipped
+// (the product of zero adds only zeros).  st->x0zero starts at 1 (set by
+// k_init_state); any nonzero entry clears it (every writer stores 0).
+__global__ __launch_bounds__(kThreads) void k_x0_scan(int64_t n, const double *__restrict__ x, SolverState *st) {
+  bool nz = false;
+  GRID_LOOP(i, n) nz |= __double_as_longlong(x[i]) != 0;
+  if (nz) st->x0zero = 0;
 }
 
 // (re)start: rho = r~^T r, relres = |r|/|b|
@@ -370,6 +384,7 @@ __global__ void k_init_state(SolverState *st, double tol, int64_t maxiter, doubl
     st->rho_prev = 1.0;
     st->alpha = 1.0;
     st->omega = 1.0;
+    st->x0zero = 1;
   }
 }
 
@@ -740,11 +755,14 @@ int hmat_bicgstab(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, cons
   };
 
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, st, w.st, o->tol, o->maxiter, o->refine);
-  // r0 = b - A x0 (Algorithm 1)
-  if ((rc = mv(h_iter, x, w.tmp, false))) return rc;
-  hipLaunchKernelGGL(k_residual, G, B, 0, st, n, b, w.tmp, w.r, w.rt, w.part, 1);
+  // r0 = b - A x0 (Algorithm 1); the product is skipped on the device when
+  // x0 is exactly zero
+  hipLaunchKernelGGL(k_x0_scan, G, B, 0, st, n, x, w.st);
+  if ((rc = product(h_iter, x, w.tmp, st, &w.st->x0zero))) return rc;
+  hipLaunchKernelGGL(k_residual, G, B, 0, st, n, b, w.tmp, w.r, w.rt, w.part, 1, &w.st->x0zero);
   hipLaunchKernelGGL(k_start, dim3(1), B, 0, st, w.st, w.part, 1);
   if (poll() != hipSuccess) return fail(HMAT_E_HIP, "solver start failed");
+  if (!hs.x0zero) nmv++;
   if (hs.bnorm == 0.0) {  // b = 0: x = 0
     hipLaunchKernelGGL(k_zero, G, B, 0, st, n, x);
     if (hipStreamSynchronize(st) != hipSuccess) return fail(HMAT_E_HIP, "zero solution failed");

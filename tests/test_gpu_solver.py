@@ -184,7 +184,8 @@ def test_bicgstab_poll_every_same_result(nrhs_max):
     x7, i7 = hmat.hmat_bicgstab(H, b, h_fp64=H64, poll_every=7, use_graph=True)
     print(i1, i5, i7)
     assert i1["status"] == 0 and i1["iterations"] == i5["iterations"] == i7["iterations"]
-    assert i1["matvecs"] == i5["matvecs"] == i7["matvecs"] == 1 + 2 * i1["iterations"]
+    # x_0 = 0: r_0 = b without a product, then two products per iteration
+    assert i1["matvecs"] == i5["matvecs"] == i7["matvecs"] == 2 * i1["iterations"]
     assert i1["matvecs_fp64"] == i5["matvecs_fp64"] == i7["matvecs_fp64"]
     assert np.array_equal(x1.cpu().numpy(), x5.cpu().numpy())
     assert np.array_equal(x1.cpu().numpy(), x7.cpu().numpy())
@@ -254,12 +255,13 @@ def test_bicgstab_graph_replay_identical(pre):
     xb, ib = hmat.hmat_bicgstab(H, b, h_fp64=H64, precond=P, poll_every=3, use_graph=True)
     assert ia["status"] == 0 and ib["status"] == 0
     assert ia["iterations"] == ib["iterations"] and np.array_equal(xa.cpu().numpy(), xb.cpu().numpy())
-    # r_0 plus two per launched iteration (launches past convergence inside a
-    # polling window are no-ops but counted), the same with and without graph
-    assert ib["matvecs"] == ia["matvecs"] and ia["matvecs"] >= 2 * ia["iterations"] + 1
+    # two per launched iteration (launches past convergence inside a polling
+    # window are no-ops but counted; x_0 = 0 needs no product for r_0), the
+    # same with and without graph
+    assert ib["matvecs"] == ia["matvecs"] and ia["matvecs"] >= 2 * ia["iterations"]
     assert ib["matvecs_fp64"] == ia["matvecs_fp64"] >= 1
     x64, i64 = hmat.hmat_bicgstab(H64, b, poll_every=3, use_graph=True)
-    assert i64["status"] == 0 and i64["matvecs_fp64"] >= 1 and i64["matvecs"] >= 2 * i64["iterations"] + 1
+    assert i64["status"] == 0 and i64["matvecs_fp64"] >= 1 and i64["matvecs"] >= 2 * i64["iterations"]
 
 
 @pytest.mark.parametrize("variant", [oracle.M1_DOUBLE, oracle.M2_MIXED, oracle.BF16_SCALED])
@@ -285,7 +287,9 @@ def test_bicgstab_first_iterations_match_oracle(variant, key):
     xo, io = oracle.bicgstab(op, b, op64=op64, tol=1e-30, maxiter=3)
     assert info["status"] == hmat.HMAT_E_NOCONV and io["status"] == hmat.HMAT_E_NOCONV
     assert info["iterations"] == 3 and io["iterations"] == 3
-    assert info["matvecs"] == io["matvecs"] == 7
+    # the oracle forms r_0 = b - A x_0 with a product; the library skips the
+    # product of x_0 = 0 (it adds only zeros)
+    assert io["matvecs"] == 7 and info["matvecs"] == 6
     x = x.cpu().numpy()
     e = np.abs(x - xo).max() / np.abs(xo).max()
     print(f"{key} {oracle.VARIANT_NAMES[variant]}: max |x3 - x3_oracle| / max |x3_oracle| = {e:.2e}")
@@ -294,3 +298,25 @@ def test_bicgstab_first_iterations_match_oracle(variant, key):
     # the true residual the GPU reports for x_3 is the oracle's for x_3
     tr = np.linalg.norm(b - op64.matvec(x)) / np.linalg.norm(b)
     assert abs(info["true_rel_res"] - tr) <= 1e-9 * tr
+
+
+def test_zero_x0_skips_the_initial_product():
+    """x_0 exactly zero: r_0 = b without a product (the device checks x_0 and
+    the product returns at once); any nonzero x_0 takes the product.  With
+    x_0 = 1e-300 in one entry neither r_0 nor the iterates change in FP64, so
+    the two solves agree bit for bit and differ by that one product."""
+    need_gpu()
+    import torch
+
+    m, h = oracle_hmatrix("sphere-L4")
+    b = to_dev(m.rhs()[h.perm])
+    bs = blockset(h)
+    H, H64 = hmat.HMatrix(bs, oracle.M2_MIXED), hmat.HMatrix(bs, oracle.M1_DOUBLE)
+    xa, ia = hmat.hmat_bicgstab(H, b, h_fp64=H64, tol=1e-10)
+    x0 = torch.zeros(h.n, dtype=torch.float64, device="cuda")
+    x0[5] = 1e-300
+    xb, ib = hmat.hmat_bicgstab(H, b, x=x0, h_fp64=H64, tol=1e-10)
+    assert ia["status"] == ib["status"] == 0 and ia["iterations"] == ib["iterations"]
+    assert ia["matvecs"] == 2 * ia["iterations"] and ib["matvecs"] == ia["matvecs"] + 1
+    assert torch.equal(xa, xb) and ia["rel_res"] == ib["rel_res"]
+
