@@ -3,8 +3,8 @@ built with AddressSanitizer and UndefinedBehaviorSanitizer (g++/gcc, no GPU
 code) and exercised in a child process with the ASan runtime preloaded:
 assembly of several meshes (compared with the oracle's, array by array),
 packing of every precision variant into a host image (read back through the
-kernels' layouts and multiplied; the multi-right-hand-side layout packed as
-well), and the oracle's conversion, products,
+kernels' layouts and multiplied, the multi-right-hand-side fragment layout
+included), and the oracle's conversion, products,
 BiCGSTAB and block-Jacobi inverse.  Any out-of-bounds access, use after
 free or undefined behaviour aborts the child, and the test fails with its
 report."""
@@ -24,7 +24,7 @@ CHILD = textwrap.dedent(r"""
     sys.path.insert(0, os.environ["HMAT_ROOT"])
     import oracle
     from paper_1911_00093_amd import hmat, meshes
-    from tests.test_pack_layout import product_from_image
+    from tests.test_pack_layout import product_from_image, product_from_image_mr
     from tests.gpu_util import abs_scale, tolerance
 
     L = C.CDLL(os.environ["HMAT_SAN_LIB"])
@@ -95,7 +95,12 @@ CHILD = textwrap.dedent(r"""
             ok(L.hmat_pack_host(C.byref(s), C.byref(o), None, 0, C.byref(info)))
             img = np.zeros(info.image_bytes, np.uint8)
             ok(L.hmat_pack_host(C.byref(s), C.byref(o), img.ctypes.data, img.size, C.byref(info)))
-            assert info.layout == 1 and img.any()
+            assert info.layout == 1
+            d = {f: (list(getattr(info, f)) if f in ("off_vals", "bytes_vals", "off_gidx", "bytes_gidx")
+                     else getattr(info, f)) for f, _ in hmat.hmat_image_info._fields_}
+            y = product_from_image_mr(img, d, x)
+            err = np.abs(y - oracle.Converted(h, variant, -1).matvec(x)).max() / scale
+            assert err <= tolerance(variant), (key, "multi-rhs", variant, err)
         op64 = oracle.Converted(h, oracle.M1_DOUBLE)
         xs, inf = oracle.bicgstab(oracle.Converted(h, oracle.M2_MIXED, -1), m.rhs()[h.perm], op64=op64, tol=1e-8,
                                   refine=1e-2)
