@@ -3,7 +3,7 @@ paper): the MLP is trained by the library's own GPU kernels on 20,000 leaves
 of random ellipsoids and plate pairs (seed 1), then used as the right
 preconditioner of the mixed BiCGSTAB on a held-out scene it never saw, a
 unit icosphere of level 6 plus two 1 x 1 plates (N = 327,680, leaf 64,
-ACA 1e-5).  The solve without a preconditioner judges the gain, plain
+ACA 1e-5).  The gain is measured against the solve without a preconditioner; plain
 block-Jacobi (exact inverses of the same leaves) is reported beside it.
 Training is deterministic (fixed seeds, fixed summation orders), so the
 iteration counts are reproducible."""
