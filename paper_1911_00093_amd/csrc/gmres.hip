@@ -34,7 +34,8 @@ struct GState {
   int32_t j;     // steps of this cycle
   int64_t it;    // steps in total
   int64_t maxiter;
-  int32_t m, pad;
+  int32_t m;
+  int32_t x0zero;  // x_0 is exactly zero: r_0 = b without a product
 };
 
 struct GWork {
@@ -257,13 +258,15 @@ __global__ __launch_bounds__(kGThreads) void k_gm_scale(int64_t n, const GState 
   }
 }
 
-// r = b - Ax; partials |r|^2 and |b|^2
+// r = b - Ax; partials |r|^2 and |b|^2.  zero_ax (optional): when it points
+// to a nonzero word, Ax is zero and ax is not read (its product was skipped).
 __global__ __launch_bounds__(kGThreads) void k_gm_resid(int64_t n, const double *__restrict__ b,
                                                         const double *__restrict__ ax, double *__restrict__ r,
-                                                        double *__restrict__ pn) {
+                                                        double *__restrict__ pn, const int32_t *zero_ax = nullptr) {
   double a[2] = {0.0, 0.0};
+  const bool az = zero_ax && *zero_ax;
   G_LOOP(e, n) {
-    const double q = b[e] - ax[e];
+    const double q = az ? b[e] : b[e] - ax[e];
     r[e] = q;
     a[0] += q * q;
     a[1] += b[e] * b[e];
@@ -342,7 +345,16 @@ __global__ void k_gm_init(GState *st, double tol, int64_t maxiter, int m) {
     st->tol = tol;
     st->maxiter = maxiter;
     st->m = m;
+    st->x0zero = 1;
   }
+}
+
+// x_0 == 0 (every entry +0.0) leaves st->x0zero set; any nonzero entry
+// clears it (every writer stores 0)
+__global__ __launch_bounds__(kGThreads) void k_gm_x0_scan(int64_t n, const double *__restrict__ x, GState *st) {
+  bool nz = false;
+  G_LOOP(e, n) nz |= __double_as_longlong(x[e]) != 0;
+  if (nz) st->x0zero = 0;
 }
 
 __global__ __launch_bounds__(kGThreads) void k_gm_zero(int64_t n, double *__restrict__ x) { G_LOOP(e, n) x[e] = 0.0; }
@@ -390,13 +402,15 @@ int hmat_gmres(hmat_t h_iter, hmat_t h_fp64, const double *b, double *x, int32_t
   };
   int rc;
   hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(64), 0, st, w.st, o->tol, o->maxiter, m);
-  // first cycle: r_0 = b - A~ x_0 with the iteration operator
-  if ((rc = product(h_iter, x, w.tmp, st, nullptr))) return rc;
-  nmv++;
-  hipLaunchKernelGGL(k_gm_resid, G, B, 0, st, n, b, w.tmp, w.r, w.pn);
+  // first cycle: r_0 = b - A~ x_0 with the iteration operator (the product
+  // is skipped on the device when x_0 is exactly zero)
+  hipLaunchKernelGGL(k_gm_x0_scan, G, B, 0, st, n, x, w.st);
+  if ((rc = product(h_iter, x, w.tmp, st, &w.st->x0zero))) return rc;
+  hipLaunchKernelGGL(k_gm_resid, G, B, 0, st, n, b, w.tmp, w.r, w.pn, &w.st->x0zero);
   hipLaunchKernelGGL(k_gm_cycle, dim3(1), B, 0, st, w.st, w.pn, w.g, 1);
   hipLaunchKernelGGL(k_gm_first, G, B, 0, st, n, w.st, w.r, w.V, w.vcur);
   if (poll() != hipSuccess) return fail(HMAT_E_HIP, "GMRES start failed");
+  if (!hs.x0zero) nmv++;
   if (hs.bnorm == 0.0) {  // b = 0: x = 0
     hipLaunchKernelGGL(k_gm_zero, G, B, 0, st, n, x);
     if (hipStreamSynchronize(st) != hipSuccess) return fail(HMAT_E_HIP, "zero solution failed");
