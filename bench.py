@@ -575,7 +575,8 @@ def bench_extra_variant(args, bs, variant, H64, b, work, x, xref, t_fp64, stream
 
 def bench_variant_sweep(args, W, mesh, bs, dev, stream):
     """Every precision variant on one workload's blocks (Table 1's six, Method 3
-    for c = -1..7, scaled BF16), each handle tuned: product time (10 sets of
+    for c = -1..7, Method 3 with the dense leaves split for c = -1, 0, 1,
+    scaled BF16), each handle tuned: product time (10 sets of
     --matvec-reps back-to-back products, mean and best set), the product's
     difference from the FP64 product on x = 1 and on the FP64 solution, and
     the best of --steps BiCGSTAB solves to --tol confirmed by the FP64 true
@@ -593,13 +594,14 @@ def bench_variant_sweep(args, W, mesh, bs, dev, stream):
     xref = xref.clone()
     probes = {"x=1": torch.ones(n, dtype=torch.float64, device=dev), "x=sigma": xref}
     y64 = {k: H64.matvec(v).clone() for k, v in probes.items()}
-    specs = [(v, -1) for v in range(6)] + [(hmat.M3, c) for c in range(-1, 8)] + [(hmat.BF16_SCALED, -1)]
+    specs = ([(v, -1, False) for v in range(6)] + [(hmat.M3, c, False) for c in range(-1, 8)] +
+             [(hmat.M3, c, True) for c in (-1, 0, 1)] + [(hmat.BF16_SCALED, -1, False)])
     rows, fp64_ms = [], None
     xv = torch.randn(n, dtype=torch.float64, device=dev)
     yv = torch.empty_like(xv)
-    for v, c in specs:
-        name = hmat.PRECISION_NAMES[v] + (f" c={c}" if v == hmat.M3 else "")
-        H = H64 if v == hmat.M1_DOUBLE else hmat.HMatrix(bs, v, c=c)
+    for v, c, split in specs:
+        name = hmat.PRECISION_NAMES[v] + (f" c={c}" if v == hmat.M3 else "") + (", dense split" if split else "")
+        H = H64 if v == hmat.M1_DOUBLE else hmat.HMatrix(bs, v, c=c, dense_split=split)
         if H is not H64:
             tuning.autotune(H, reps=10)
         ms_mean, ms_best = product_sets(H, xv, yv, args.matvec_reps, stream)
@@ -619,8 +621,9 @@ def bench_variant_sweep(args, W, mesh, bs, dev, stream):
                 best = (dt, info)
         if v == hmat.M1_DOUBLE:
             fp64_ms = best[0]
-        B = H.stats().algorithmic_bytes
-        row = dict(variant=name, bytes_per_product=int(B), product_us_mean=round(1e3 * ms_mean, 2),
+        st = H.stats()
+        B = st.algorithmic_bytes
+        row = dict(variant=name, bytes_per_product=int(B), dense_bytes=int(st.bytes_dense), product_us_mean=round(1e3 * ms_mean, 2),
                    product_us_best=round(1e3 * ms_best, 2), gbs=round(B / ms_best / 1e6, 1),
                    err_vs_fp64_x1=err["x=1"], err_vs_fp64_sigma=err["x=sigma"],
                    iterations=best[1]["iterations"], restarts=best[1]["restarts"], solve_ms=round(best[0], 3),
