@@ -8,7 +8,9 @@ oracle's, bit for bit: tests/test_gpu_assembly.py and the largest mesh in
 tests/test_gpu_fullsize.py).  The product runs over all 64 systems; the
 outputs of four sampled systems (the smallest, the median, the largest and
 the last one in the batch) are compared element by element, for every
-right-hand side, with the oracle's product of that system's blocks."""
+right-hand side, with the oracle's product of that system's blocks; and the
+batched solver's x after three iterations of every recurrence, on three of
+them, with the oracle's."""
 
 import numpy as np
 import pytest
@@ -52,3 +54,41 @@ def test_fullsize_batch_multirhs_parity(variant):
             worst = max(worst, err)
         print(f"{oracle.VARIANT_NAMES[variant]} system {s} (n = {b.n}): worst error {worst:.2e} of |A~||x|")
         assert worst <= tolerance(variant), (s, worst)
+
+
+def test_fullsize_batch_solver_first_iterations():
+    """The batched BiCGSTAB over all 1,024 (mesh, right-hand side) pairs of
+    the full workload, exactly three iterations each (tol unreachable), in
+    the benchmark's configuration (M2-Mixed 16-column handle, tuned, FP64
+    handle for the true residuals, graph-replayed iteration): x_3 of every
+    right-hand side of three sampled systems equals the oracle's x_3 for the
+    same operator arithmetic (bound 1e-10: three iterations amplify the
+    products' summation-order differences, as in the small-mesh test)."""
+    need_gpu()
+    import torch
+
+    ms = meshes.random_ellipsoids(64, seed=0)
+    bss = hmat.hmat_assemble_bem_gpu_batched(ms, leaf=32, eta=2.0, eps=1e-6)
+    Hi = hmat.HMatrix(bss, oracle.M2_MIXED, c=-1, nrhs_max=16)
+    H64 = hmat.HMatrix(bss, oracle.M1_DOUBLE, nrhs_max=16)
+    tuning.autotune(Hi, reps=3)
+    off = Hi.system_offsets()
+    B = np.random.default_rng(1).standard_normal((16, Hi.n))
+    X, summ, per = hmat.hmat_bicgstab_batched(Hi, torch.as_tensor(B).cuda().T, h_fp64=H64, tol=1e-30, maxiter=3)
+    X = X.cpu().numpy().T
+    assert np.all(per["iterations"] == 3) and np.all(per["status"] == hmat.HMAT_E_NOCONV)
+    sizes = np.array([b.n for b in bss])
+    order = np.argsort(sizes, kind="stable")
+    worst = 0.0
+    for s in sorted({int(order[0]), int(order[len(order) // 2]), int(order[-1])}):
+        b_ = bss[s]
+        h = oracle.HMatrix.from_blocks(b_.n, b_.row0, b_.nrows, b_.col0, b_.ncols, b_.kind, b_.rank, b_.offset,
+                                       b_.data)
+        op = oracle.Converted(h, oracle.M2_MIXED, -1)
+        for k in range(16):
+            xo, io = oracle.bicgstab(op, B[k, off[s]:off[s + 1]], tol=1e-30, maxiter=3)
+            assert io["iterations"] == 3
+            e = np.linalg.norm(X[k, off[s]:off[s + 1]] - xo) / np.linalg.norm(xo)
+            worst = max(worst, e)
+            assert e <= 1e-10, (s, k, e)
+    print(f"worst |x3 - x3_oracle| / |x3_oracle| = {worst:.2e}")
