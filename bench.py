@@ -60,7 +60,7 @@ def sources_hash():
             h.update(fh.read())
     return h.hexdigest()[:16]
 WORKLOADS = {
-    "plates-128": dict(leaf=64, eta=2.0, eps=1e-5,
+    "plates-128": dict(leaf=64, eta=2.0, eps=1e-5, refine=1e-4,
                        desc="two 1x1 plates, gap 0.1, 128x128 squares x 4 right triangles each, N=131072; "
                             "leaf 64, eta 2, ACA 1e-5; b = +1/-1"),
     "sphere-L7+8": dict(leaf=64, eta=2.0, eps=1e-6,
@@ -73,7 +73,7 @@ WORKLOADS = {
                                   "triangles each, offset 3 along x), N=327,680; leaf 64, eta 2, ACA 1e-5; "
                                   "b = 1 / +1 / -1; preconditioners none, block-Jacobi, learned leaf map "
                                   "(trained on 20,000 leaves of random ellipsoids and plate pairs, seed 1)"),
-    "ellipsoids-64x16": dict(leaf=32, eta=2.0, eps=1e-6, nsys=64, nrhs=16,
+    "ellipsoids-64x16": dict(leaf=32, eta=2.0, eps=1e-6, nsys=64, nrhs=16, refine=1e-4,
                              desc="64 independent geodesic ellipsoids (frequency U{10..44}, N = 20 f^2 in "
                                   "[2000, 38720], semi-axes U[0.5, 2], seed 0), N = 1,089,460 in total; leaf 32, "
                                   "eta 2, ACA 1e-6 per mesh; 16 N(0,1) right-hand sides per mesh (seed 1)"),
@@ -171,7 +171,9 @@ def main():
                     help="oracle BiCGSTAB iterations timed for the CPU solve estimate")
     ap.add_argument("--eps", type=float, default=None, help="ACA tolerance (default: the workload's)")
     ap.add_argument("--refine", type=float, default=None,
-                    help="early FP64 true-residual check ratio (default 1e-2 for BF16-scaled, else 0)")
+                    help="early FP64 true-residual check ratio (default 1e-2 for BF16-scaled, else the "
+                         "workload's: 1e-4 for plates-128 and ellipsoids-64x16, 0 otherwise); the FP64 "
+                         "baseline is timed with none and with the same ratio, the faster kept")
     ap.add_argument("--solver", default="bicgstab", choices=["bicgstab", "gmres"],
                     help="Krylov solver of the single-system workloads (GMRES: restarted, --restart steps)")
     ap.add_argument("--restart", type=int, default=30)
@@ -212,9 +214,9 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     variant = hmat.PRECISION_NAMES.index(args.variant)
-    if args.refine is None:
-        args.refine = 1e-2 if variant == hmat.BF16_SCALED else 0.0
     W = dict(WORKLOADS[args.workload])
+    if args.refine is None:
+        args.refine = 1e-2 if variant == hmat.BF16_SCALED else W.get("refine", 0.0)
     if args.eps is not None:
         W["eps"] = args.eps
         W["desc"] = W["desc"].replace("ACA 1e-6", f"ACA {args.eps:g}").replace("ACA 1e-5", f"ACA {args.eps:g}")
@@ -252,12 +254,14 @@ def main():
     wbytes = (hmat.lib().hmat_gmres_workspace_bytes(n, args.restart) if gm else hmat.hmat_solver_workspace_bytes(n))
     work = torch.empty(int(wbytes), dtype=torch.uint8, device=dev)
 
-    def run(H, tol, x, use_graph=False):
+    def run(H, tol, x, use_graph=False, refine=None):
+        if refine is None:
+            refine = args.refine if H is Hm else 0.0
         if gm:
             return hmat.hmat_gmres(H, b, x=x, h_fp64=H64, tol=tol, maxiter=2000, restart=args.restart,
                                    poll_every=args.poll_every, work=work, use_graph=use_graph)
         return hmat.hmat_bicgstab(H, b, x=x, h_fp64=H64, tol=tol, maxiter=2000, poll_every=args.poll_every,
-                                  work=work, refine=args.refine if H is Hm else 0.0, use_graph=use_graph)
+                                  work=work, refine=refine, use_graph=use_graph)
 
     def solve(H, tol, x=None):
         x = torch.zeros(n, dtype=torch.float64, device=dev) if x is None else x.zero_()
@@ -302,16 +306,31 @@ def main():
     torch.cuda.synchronize()
     t_graph = time.perf_counter() - t_start
 
-    # FP64 solves, same protocol (context for "mixed vs FP64")
-    x64 = torch.zeros(n, dtype=torch.float64, device=dev)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    infos64 = []
-    for _ in range(args.steps):
-        x64, i64 = solve(H64, args.tol, x64)
-        infos64.append(i64)
-    torch.cuda.synchronize()
-    t_fp64 = time.perf_counter() - t_start
+    # FP64 solves, same protocol.  Early checks restart the recurrence, and
+    # a restarted BiCGSTAB can converge in fewer iterations whatever the
+    # precision, so the FP64 baseline is the faster of the FP64 solves with
+    # no early checks and with the mixed solve's threshold.
+    fp64_runs = {}
+
+    def fp64_time(refine):
+        if refine not in fp64_runs:
+            x_ = torch.zeros(n, dtype=torch.float64, device=dev)
+            run(H64, args.tol, x_, refine=refine)  # warm-up at this threshold
+            torch.cuda.synchronize()
+            t0_ = time.perf_counter()
+            inf_ = []
+            for _ in range(args.steps):
+                x_.zero_()
+                x_, i_ = run(H64, args.tol, x_, refine=refine)
+                inf_.append(i_)
+            torch.cuda.synchronize()
+            fp64_runs[refine] = (time.perf_counter() - t0_, inf_, x_)
+        return fp64_runs[refine][0]
+
+    for r_ in sorted({0.0, args.refine if not gm else 0.0}):
+        fp64_time(r_)
+    refine64 = min(fp64_runs, key=lambda r_: fp64_runs[r_][0])
+    t_fp64, infos64, x64 = fp64_runs[refine64]
     err_fp64 = float(torch.linalg.norm(x64 - xref) / torch.linalg.norm(xref))
     err_same_tol = float(torch.linalg.norm(xs - x64) / torch.linalg.norm(x64))
 
@@ -321,7 +340,8 @@ def main():
     if args.accuracy_tol > 0 and not gm:
         accuracy = {"tol": args.accuracy_tol, "mixed_refine": 1e-2}
         reps = max(1, min(args.steps, 3))
-        for key, H, refine in (("mixed", Hm, 1e-2), ("fp64", H64, 0.0)):
+        # FP64: with and without the mixed solve's early checks, the faster kept
+        for key, H, refine in (("mixed", Hm, 1e-2), ("fp64", H64, 0.0), ("fp64_refine", H64, 1e-2)):
             xa = torch.zeros(n, dtype=torch.float64, device=dev)
             torch.cuda.synchronize()
             t_start = time.perf_counter()
@@ -335,6 +355,9 @@ def main():
                              "true_rel_res": ia["true_rel_res"],
                              "solution_rel_err_vs_fp64_1e-12":
                                  float(torch.linalg.norm(xa - xref) / torch.linalg.norm(xref))}
+        if accuracy["fp64_refine"]["ms"] < accuracy["fp64"]["ms"]:
+            accuracy["fp64"] = dict(accuracy["fp64_refine"], refine=1e-2)
+        del accuracy["fp64_refine"]
         accuracy["speedup_vs_fp64"] = round(accuracy["fp64"]["ms"] / accuracy["mixed"]["ms"], 3)
         log(f"[accuracy] {accuracy}")
 
@@ -440,10 +463,12 @@ def main():
             "parallelism": "1 GPU",
         },
         "time_to_tol_ms": {"mixed": round(ms_per_step, 3), "fp64": round(1e3 * t_fp64 / args.steps, 3),
-                           "mixed_graph_replay": round(1e3 * t_graph / args.steps, 3)},
+                           "mixed_graph_replay": round(1e3 * t_graph / args.steps, 3),
+                           "fp64_by_refine": {f"{r_:g}": round(1e3 * v_[0] / args.steps, 3)
+                                              for r_, v_ in sorted(fp64_runs.items())}},
         "speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
         "iterations": {"mixed": infos[-1]["iterations"], "fp64": infos64[-1]["iterations"],
-                       "mixed_restarts": infos[-1]["restarts"]},
+                       "mixed_restarts": infos[-1]["restarts"], "fp64_refine": refine64},
         "solution_rel_err": {"mixed_vs_fp64_1e-12": err_mixed, "fp64_1e-8_vs_fp64_1e-12": err_fp64,
                              "mixed_vs_fp64_same_tol": err_same_tol},
         "true_rel_res": {"mixed": infos[-1]["true_rel_res"], "fp64": infos64[-1]["true_rel_res"]},
@@ -481,7 +506,7 @@ def main():
     # early true-residual checks)
     if args.workload == "sphere-L7+8" and variant != hmat.BF16_SCALED and not gm and not args.no_bf16:
         out["bf16_scaled"] = bench_extra_variant(args, bs, hmat.BF16_SCALED, H64, b, work, x64.new_zeros(n),
-                                                 xref, t_fp64, stream)
+                                                 xref, fp64_time, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, W, variant, args.cpu_matvecs, Bm, args.drop, args.c,
                                            args.dense_split, b.cpu().numpy(), infos[-1], args.cpu_solve_iters,
@@ -508,7 +533,7 @@ def product_sets(H, xv, yv, reps, stream, sets=10):
     return float(np.mean(per)), float(min(per))
 
 
-def bench_extra_variant(args, bs, variant, H64, b, work, x, xref, t_fp64, stream):
+def bench_extra_variant(args, bs, variant, H64, b, work, x, xref, fp64_time, stream):
     """One more precision variant on the same blocks: K solves to tol (timed,
     no per-kernel events; early FP64 checks 1e-2 as for the variant's own
     runs), back-to-back products with per-kernel events (untimed pass)."""
@@ -522,6 +547,7 @@ def bench_extra_variant(args, bs, variant, H64, b, work, x, xref, t_fp64, stream
         info = tuning.autotune(H, reps=10)
         tune = {k: info[k] for k in ("stage1_grid", "stage2_grid", "stage2_tile")}
     refine = 1e-2 if variant == hmat.BF16_SCALED else 0.0
+    t_fp64 = min(fp64_time(0.0), fp64_time(refine))  # FP64 with and without the same early checks
     B = H.stats().algorithmic_bytes
 
     def solve():
@@ -607,18 +633,20 @@ def bench_variant_sweep(args, W, mesh, bs, dev, stream):
         ms_mean, ms_best = product_sets(H, xv, yv, args.matvec_reps, stream)
         err = {k: float(torch.linalg.norm(H.matvec(p) - y64[k]) / torch.linalg.norm(y64[k]))
                for k, p in probes.items()}
-        refine = 1e-2 if v == hmat.BF16_SCALED else 0.0
+        # BF16: early checks 1e-2; the FP64 reference: the faster of none and 1e-2
+        refines = [1e-2] if v == hmat.BF16_SCALED else [0.0, 1e-2] if v == hmat.M1_DOUBLE else [0.0]
         best, x = None, torch.zeros(n, dtype=torch.float64, device=dev)
-        for _ in range(max(args.steps, 1)):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            x, info = hmat.hmat_bicgstab(H, b, x=x.zero_(), h_fp64=H64, tol=args.tol, maxiter=4000,
-                                         poll_every=args.poll_every, work=work, refine=refine)
-            torch.cuda.synchronize()
-            dt = 1e3 * (time.perf_counter() - t0)
-            assert info["status"] == 0, (name, info)
-            if best is None or dt < best[0]:
-                best = (dt, info)
+        for refine in refines:
+            for _ in range(max(args.steps, 1)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, info = hmat.hmat_bicgstab(H, b, x=x.zero_(), h_fp64=H64, tol=args.tol, maxiter=4000,
+                                             poll_every=args.poll_every, work=work, refine=refine)
+                torch.cuda.synchronize()
+                dt = 1e3 * (time.perf_counter() - t0)
+                assert info["status"] == 0, (name, info)
+                if best is None or dt < best[0]:
+                    best = (dt, dict(info, refine=refine), float(torch.linalg.norm(x - xref) / torch.linalg.norm(xref)))
         if v == hmat.M1_DOUBLE:
             fp64_ms = best[0]
         st = H.stats()
@@ -626,9 +654,10 @@ def bench_variant_sweep(args, W, mesh, bs, dev, stream):
         row = dict(variant=name, bytes_per_product=int(B), dense_bytes=int(st.bytes_dense), product_us_mean=round(1e3 * ms_mean, 2),
                    product_us_best=round(1e3 * ms_best, 2), gbs=round(B / ms_best / 1e6, 1),
                    err_vs_fp64_x1=err["x=1"], err_vs_fp64_sigma=err["x=sigma"],
-                   iterations=best[1]["iterations"], restarts=best[1]["restarts"], solve_ms=round(best[0], 3),
+                   iterations=best[1]["iterations"], restarts=best[1]["restarts"], refine=best[1]["refine"],
+                   solve_ms=round(best[0], 3),
                    vs_fp64=round(fp64_ms / best[0], 3),
-                   solution_err=float(torch.linalg.norm(x - xref) / torch.linalg.norm(xref)))
+                   solution_err=best[2])
         rows.append(row)
         log(f"[sweep] {row}")
         if H is not H64:
@@ -712,10 +741,11 @@ def bench_batched(args, W, variant, dev, stream):
     work = torch.empty(hmat.hmat_bicgstab_batched_workspace_bytes(Hm, nrhs), dtype=torch.uint8, device=dev)
     maxiter = 3000
 
-    def solve(H, x):
+    def solve(H, x, refine=None):
         x.zero_()
         return hmat.hmat_bicgstab_batched(H, b, x=x, h_fp64=H64, tol=args.tol, maxiter=maxiter,
-                                          poll_every=args.poll_every, use_graph=True, work=work)
+                                          poll_every=args.poll_every, use_graph=True, work=work,
+                                          refine=args.refine if refine is None else refine)
 
     xm = torch.zeros((nrhs, n), dtype=torch.float64, device=dev).T
     x64 = torch.zeros_like(xm)
@@ -736,14 +766,22 @@ def bench_batched(args, W, variant, dev, stream):
     mv_bytes = sum(float(Bsys @ p["products"][:, 0]) + s["matvecs_fp64"] * B64 for _, s, p in runs)
     value = mv_bytes / t_mixed / 1e9
     per = runs[-1][2]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    runs64 = []
-    for _ in range(args.steps):
-        runs64.append(solve(H64, x64))
-        log(f"[step] FP64 solve: {runs64[-1][1]}")
-    torch.cuda.synchronize()
-    t_fp64 = time.perf_counter() - t_start
+    # FP64 solves with no early checks and with the mixed solve's threshold
+    # (a restarted BiCGSTAB can converge in fewer iterations whatever the
+    # precision): the faster is the baseline
+    fp64_runs = {}
+    for refine in sorted({0.0, args.refine}):
+        solve(H64, x64, refine)  # warm-up at this threshold
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        runs64 = []
+        for _ in range(args.steps):
+            runs64.append(solve(H64, x64, refine))
+            log(f"[step] FP64 solve (early checks {refine:g}): {runs64[-1][1]}")
+        torch.cuda.synchronize()
+        fp64_runs[refine] = (time.perf_counter() - t_start, runs64, x64.clone())
+    refine64 = min(fp64_runs, key=lambda r_: fp64_runs[r_][0])
+    t_fp64, runs64, x64 = fp64_runs[refine64]
     per64 = runs64[-1][2]
     err = float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64))
 
@@ -791,15 +829,19 @@ def bench_batched(args, W, variant, dev, stream):
             "n": n, "systems": nsys, "rhs_per_system": nrhs,
             "step": f"batched BiCGSTAB of all {nsys * nrhs} (mesh, rhs) pairs, x0=0 -> |r|/|b|<{args.tol:g} each, "
                     "confirmed by the FP64 true residual; iteration replayed from a HIP graph",
+            "refine": args.refine,
             "parallelism": "1 GPU",
         },
         "time_all_solves_ms": {"mixed": round(1e3 * t_mixed / args.steps, 3),
-                               "fp64": round(1e3 * t_fp64 / args.steps, 3)},
+                               "fp64": round(1e3 * t_fp64 / args.steps, 3),
+                               "fp64_by_refine": {f"{r_:g}": round(1e3 * v_[0] / args.steps, 3)
+                                                  for r_, v_ in sorted(fp64_runs.items())}},
         "speedup_vs_fp64": round(t_fp64 / t_mixed, 3),
         "iterations": {"mixed_max": int(its.max()), "mixed_median": float(np.median(its)),
                        "fp64_max": int(per64["iterations"].max()),
                        "fp64_median": float(np.median(per64["iterations"])),
-                       "mixed_max_restarts": int(per["restarts"].max())},
+                       "mixed_max_restarts": int(per["restarts"].max()),
+                       "mixed_median_restarts": float(np.median(per["restarts"])), "fp64_refine": refine64},
         "products": {"mixed_launched": runs[-1][1]["matvecs"], "fp64_checks": runs[-1][1]["matvecs_fp64"],
                      "mixed_work_fraction": round(float(Bsys @ per["products"][:, 0]) / (runs[-1][1]["matvecs"] * Bm), 4),
                      "fp64_work_fraction": round(float(Bsys64 @ per64["products"][:, 0]) / (runs64[-1][1]["matvecs"] * B64), 4)},
