@@ -927,36 +927,43 @@ static void pack_image(Packed *P, unsigned char *base) {
     else if (cls == F32) ((float *)p)[idx] = (float)v;
     else ((uint16_t *)p)[idx] = bf16_bits(v);
   };
-  // converted value of a low-rank term's V' entry (row i) / W' entry (column j)
-  auto vval = [b, P](int64_t k, const Term &t, int64_t i) {
-    const double *U = P->bsrc[k];
-    return U[i + (int64_t)t.l * b->nrows[k]] / t.div_v;
+  // Source of one panel column (a column of a dense block or a low-rank
+  // term's V' column), or of one W' row of a stage-1 item: entry e is
+  // p[e - e0] / div.  Dense columns have div = 1 (x / 1 == x exactly); a
+  // padding column has no source and reads 0.
+  struct Src {
+    const double *p = nullptr;
+    int64_t e0 = 0;
+    double div = 1.0;
+    double at(int64_t e) const { return p ? p[e - e0] / div : 0.0; }
   };
-  auto wval = [b, P](int64_t k, const Term &t, int64_t j) {
-    const double *Wt = P->bsrc[k] + b->nrows[k] * (int64_t)b->rank[k];
-    return Wt[j + (int64_t)t.l * b->ncols[k]] / t.div_w;
-  };
-
-  // column sources of a chunk's panel of class c: (block, column of a dense
-  // block / term of a low-rank block), and its gather indices
+  // column sources of a chunk's panel of class c (padded to `padded`
+  // columns) and its gather indices, in panel order
   auto chunk_columns = [&](const ChunkPlan &cp, int c, int64_t padded, int32_t *gi) {
-    std::vector<std::pair<int64_t, int32_t>> col(padded, {-1, 0});
+    std::vector<Src> col(padded);
     int64_t k2 = 0;
     for (const Run &run : cp.runs[c])
       for (int32_t e = 0; e < run.count; e++, k2++) {
-        const int64_t k = run.block;
-        col[k2] = {k, run.first + e};
-        gi[k2] = b->kind[k] == HMAT_DENSE ? (int32_t)(b->col0[k] + run.first + e)
-                                          : (int32_t)(n + P->terms[k][run.first + e].zidx);
+        const int64_t k = run.block, m = b->nrows[k];
+        if (b->kind[k] == HMAT_DENSE) {
+          col[k2] = {P->bsrc[k] + (int64_t)(run.first + e) * m, b->row0[k], 1.0};
+          gi[k2] = (int32_t)(b->col0[k] + run.first + e);
+        } else {
+          const Term &t = P->terms[k][run.first + e];
+          col[k2] = {P->bsrc[k] + (int64_t)t.l * m, b->row0[k], t.div_v};
+          gi[k2] = (int32_t)(n + t.zidx);
+        }
       }
     for (; k2 < padded; k2++) gi[k2] = (int32_t)(n + P->zlen);  // padding reads the zero slot
     return col;
   };
-  auto panel_value = [&](const std::pair<int64_t, int32_t> &src, int64_t row) {
-    if (src.first < 0) return 0.0;
-    const int64_t k = src.first;
-    if (b->kind[k] == HMAT_DENSE) return P->bsrc[k][(row - b->row0[k]) + (int64_t)src.second * b->nrows[k]];
-    return vval(k, P->terms[k][src.second], row - b->row0[k]);
+  // W' row of stage-1 row slot r of a group, from column c0 on (entry j of
+  // the item is column c0 + j of the block)
+  auto w_row = [&](const Group &g, int64_t r, int64_t c0) {
+    auto [k, ti] = g.rows[r];
+    const Term &t = P->terms[k][ti];
+    const double *Wt = P->bsrc[k] + b->nrows[k] * (int64_t)b->rank[k];
+    return Src{Wt + (int64_t)t.l * b->ncols[k] + c0, 0, t.div_w};
   };
   if (P->mr) {
     // multi-RHS panels: (tile, column block, lane, v) -> A[16 t + l % 16][kb CB + 4 v + l / 16]
@@ -967,7 +974,7 @@ static void pack_image(Packed *P, unsigned char *base) {
         if (!R.nkb[c]) continue;
         const int vec = vec_of(c), cb = mr_cb(c), nkb = R.nkb[c];
         int32_t *gi = (int32_t *)(base + L.off_gidx[c]) + R.gidx_off[c];
-        auto col = chunk_columns(cp, c, (int64_t)nkb * cb, gi);
+        const std::vector<Src> col = chunk_columns(cp, c, (int64_t)nkb * cb, gi);
         // lane-group-major order within each column block
         std::vector<int32_t> blk(cb);
         for (int kb = 0; kb < nkb; kb++) {
@@ -976,16 +983,16 @@ static void pack_image(Packed *P, unsigned char *base) {
             for (int v = 0; v < vec; v++) gi[(int64_t)kb * cb + qg * vec + v] = blk[4 * v + qg];
         }
         const int hh = (int)cp.h, tiles = (hh + kMRTile - 1) / kMRTile;
-        for (int t = 0; t < tiles; t++)
+        for (int t = 0; t < tiles; t++) {
+          const int tr = mr_tile_rows(hh, t);
           for (int kb = 0; kb < nkb; kb++)
             for (int l = 0; l < kWave; l++) {
-              if (l % kMRTile >= mr_tile_rows(hh, t)) continue;  // row beyond the chunk: not stored
-              for (int v = 0; v < vec; v++) {
-                const int64_t row = t * kMRTile + l % kMRTile;
-                const int64_t kk = (int64_t)kb * cb + 4 * v + l / kMRTile;
-                put(c, R.panel_off[c] + mr_elem(hh, nkb, vec, t, kb, l, v), panel_value(col[kk], cp.r0 + row));
-              }
+              if (l % kMRTile >= tr) continue;  // row beyond the chunk: not stored
+              const int64_t row = cp.r0 + t * kMRTile + l % kMRTile;
+              const int64_t at = R.panel_off[c] + mr_elem(hh, nkb, vec, t, kb, l, 0);
+              for (int v = 0; v < vec; v++) put(c, at + v, col[(int64_t)kb * cb + 4 * v + l / kMRTile].at(row));
             }
+        }
       }
     });
     parallel_for((int64_t)P->mri.size(), [&](int64_t q) {
@@ -993,82 +1000,67 @@ static void pack_image(Packed *P, unsigned char *base) {
       const Group &g = P->groups[P->mri_group[q]];
       const int c = m.cls, vec = vec_of(c), cb = mr_cb(c);
       const int tiles = (m.nrows + kMRTile - 1) / kMRTile;
-      for (int t = 0; t < tiles; t++)
+      std::vector<Src> rows(m.nrows);
+      for (int r = 0; r < m.nrows; r++) rows[r] = w_row(g, P->mri_k0[q] + r, P->mri_c0[q]);
+      for (int t = 0; t < tiles; t++) {
+        const int tr = mr_tile_rows(m.nrows, t);
         for (int kb = 0; kb < m.nkb; kb++)
           for (int l = 0; l < kWave; l++) {
-            if (l % kMRTile >= mr_tile_rows(m.nrows, t)) continue;  // row beyond the item: not stored
+            if (l % kMRTile >= tr) continue;  // row beyond the item: not stored
+            const Src &w = rows[t * kMRTile + l % kMRTile];
+            const int64_t at = m.w_off + mr_elem(m.nrows, m.nkb, vec, t, kb, l, 0);
             for (int v = 0; v < vec; v++) {
-              const int64_t r = t * kMRTile + l % kMRTile;
               const int64_t jj = (int64_t)kb * cb + 4 * v + l / kMRTile;
-              double val = 0.0;
-              if (jj < m.ncols) {
-                auto [k, ti] = g.rows[P->mri_k0[q] + r];
-                val = wval(k, P->terms[k][ti], P->mri_c0[q] + jj);
-              }
-              put(c, m.w_off + mr_elem(m.nrows, m.nkb, vec, t, kb, l, v), val);
+              put(c, at + v, jj < m.ncols ? w.at(jj) : 0.0);
             }
           }
+      }
     });
   }
-  // stage-2 panels and gather indices, in launch order
+  // stage-2 panels and gather indices, in launch order.  For one wave w,
+  // slab s and row slot i the slab's columns are contiguous in the panel
+  // (s2_elem): the columns of slab s start at element
+  // wave_base(w) + s * rows_of_wave(w) * 64 * VEC + i * lanes(s) * VEC.
   if (!P->mr) parallel_for((int64_t)P->chunk_order.size(), [&](int64_t q) {
     const ChunkPlan &cp = P->chunks[P->chunk_order[q]];
     const RowChunk &R = P->rc[q];
     for (int c = 0; c < NCLS; c++) {
       if (!cp.K[c]) continue;
       const int vec = vec_of(c), ld = R.ld[c], hh = (int)cp.h;
-      // column sources: (block, column of a dense block / term of a low-rank block)
-      std::vector<std::pair<int64_t, int32_t>> col(ld, {-1, 0});
       int32_t *gi = (int32_t *)(base + L.off_gidx[c]) + R.gidx_off[c];
-      int64_t k2 = 0;
-      for (const Run &run : cp.runs[c])
-        for (int32_t e = 0; e < run.count; e++, k2++) {
-          const int64_t k = run.block;
-          col[k2] = {k, run.first + e};
-          gi[k2] = b->kind[k] == HMAT_DENSE ? (int32_t)(b->col0[k] + run.first + e)
-                                            : (int32_t)(n + P->terms[k][run.first + e].zidx);
-        }
-      for (; k2 < ld; k2++) gi[k2] = (int32_t)(n + P->zlen);  // padding reads the zero slot
+      const std::vector<Src> col = chunk_columns(cp, c, ld, gi);
+      const int64_t slab = (int64_t)kWave * vec;
+      const int ns = (int)((ld + slab - 1) / slab);
+      int64_t wbase = R.panel_off[c];
       for (int w = 0; w < kS2Waves; w++) {
         const int nw = s2_rows_of_wave(hh, w);
-        for (int i = 0; i < nw; i++) {
-          const int64_t row = cp.r0 + w + (int64_t)kS2Waves * i;
-          for (int64_t kk = 0; kk < ld; kk++) {
-            const int s = (int)(kk / ((int64_t)kWave * vec)), lane = (int)((kk % ((int64_t)kWave * vec)) / vec);
-            const int64_t at = R.panel_off[c] + s2_elem(hh, ld, vec, w, s, i, lane) + kk % vec;
-            const auto src = col[kk];
-            double v = 0.0;
-            if (src.first >= 0) {
-              const int64_t k = src.first;
-              if (b->kind[k] == HMAT_DENSE)
-                v = P->bsrc[k][(row - b->row0[k]) + (int64_t)src.second * b->nrows[k]];
-              else
-                v = vval(k, P->terms[k][src.second], row - b->row0[k]);
-            }
-            put(c, at, v);
+        for (int s = 0; s < ns; s++) {
+          const int64_t k0 = s * slab, kn = (int64_t)slab_lanes(ld, vec, kWave, s) * vec;
+          for (int i = 0; i < nw; i++) {
+            const int64_t row = cp.r0 + w + (int64_t)kS2Waves * i;
+            const int64_t at = wbase + s * nw * slab + i * kn;
+            for (int64_t e = 0; e < kn; e++) put(c, at + e, col[k0 + e].at(row));
           }
         }
+        wbase += (int64_t)nw * ld;
       }
     }
   });
-  // stage-1 items: W' rows in consumption order
+  // stage-1 items: W' rows in consumption order.  Row r of slab s is
+  // contiguous (s1_elem): it starts at s * rows_pad * lpr * VEC + r * lanes(s) * VEC.
   if (!P->mr) parallel_for((int64_t)P->items.size(), [&](int64_t q) {
     const S1Item &it = P->items[q];
     const Group &g = P->groups[P->item_group[q]];
-    const int c = it.cls, vec = vec_of(c), lpr = it.lpr, rpi = kWave / lpr;
+    const int c = it.cls, vec = vec_of(c), lpr = it.lpr;
     const int cols = (int)pad_to(it.ncols, vec);
-    const int64_t rows = s1_rows_pad(it.nrows, lpr);
+    const int64_t rows = s1_rows_pad(it.nrows, lpr), sw = (int64_t)lpr * vec;
+    const int ns = (int)((cols + sw - 1) / sw);
     for (int64_t r = 0; r < rows; r++) {
-      const int i = (int)(r / rpi), qq = (int)(r % rpi);
-      for (int jj = 0; jj < cols; jj++) {
-        const int s = jj / (lpr * vec), u = (jj % (lpr * vec)) / vec;
-        const int64_t at = it.w_off + s1_elem(it.nrows, cols, vec, lpr, s, i, qq, u) + jj % vec;
-        double v = 0.0;
-        if (r < it.nrows && jj < it.ncols) {
-          auto [k, ti] = g.rows[P->item_k0[q] + r];
-          v = wval(k, P->terms[k][ti], P->item_c0[q] + jj);
-        }
-        put(c, at, v);
+      const Src w = r < it.nrows ? w_row(g, P->item_k0[q] + r, P->item_c0[q]) : Src{};
+      for (int s = 0; s < ns; s++) {
+        const int64_t j0 = s * sw, kn = (int64_t)slab_lanes(cols, vec, lpr, s) * vec;
+        const int64_t at = it.w_off + s * rows * sw + r * kn;
+        for (int64_t e = 0; e < kn; e++) put(c, at + e, j0 + e < it.ncols ? w.at(j0 + e) : 0.0);
       }
     }
   });
