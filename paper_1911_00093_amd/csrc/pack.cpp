@@ -403,18 +403,24 @@ static int plan_blocks_src(const hmat_blocks *b, const hmat_build_opts *o, hmat_
   std::map<std::tuple<int, int64_t, int64_t>, int64_t> gmap;
   for (int64_t k = 0; k < nb; k++) {
     auto &T = P->terms[k];
+    int cur_cls = -1;  // a block's terms of one class share a group (Method 3: FP64 terms first)
+    int64_t cur = -1;
     for (int32_t t = 0; t < (int32_t)T.size(); t++) {
-      auto key = std::make_tuple(T[t].cls, b->col0[k], b->ncols[k]);
-      auto it = gmap.find(key);
-      if (it == gmap.end()) {
-        Group g;
-        g.cls = T[t].cls;
-        g.col0 = b->col0[k];
-        g.ncols = b->ncols[k];
-        it = gmap.emplace(key, (int64_t)P->groups.size()).first;
-        P->groups.push_back(std::move(g));
+      if (T[t].cls != cur_cls) {
+        auto key = std::make_tuple(T[t].cls, b->col0[k], b->ncols[k]);
+        auto it = gmap.find(key);
+        if (it == gmap.end()) {
+          Group g;
+          g.cls = T[t].cls;
+          g.col0 = b->col0[k];
+          g.ncols = b->ncols[k];
+          it = gmap.emplace(key, (int64_t)P->groups.size()).first;
+          P->groups.push_back(std::move(g));
+        }
+        cur_cls = T[t].cls;
+        cur = it->second;
       }
-      P->groups[it->second].rows.emplace_back(k, t);
+      P->groups[cur].rows.emplace_back(k, t);
     }
   }
   struct ItemSrc {
