@@ -80,6 +80,17 @@ WORKLOADS = {
 }
 
 
+def default_refine(variant, workload):
+    """Threshold of the early FP64 true-residual checks when --refine is not
+    given: 1e-2 for scaled BF16 (its operator error needs them), else the
+    workload's measured best (none on the sphere scene, where every restart
+    costs iterations; 1e-4 on plates-128 and the 64-mesh batch, where a
+    restarted recurrence converges in fewer iterations)."""
+    from paper_1911_00093_amd import hmat
+
+    return 1e-2 if variant == hmat.BF16_SCALED else WORKLOADS[workload].get("refine", 0.0)
+
+
 def _r4(v):
     return None if v is None else round(v, 4)
 
@@ -216,7 +227,7 @@ def main():
     variant = hmat.PRECISION_NAMES.index(args.variant)
     W = dict(WORKLOADS[args.workload])
     if args.refine is None:
-        args.refine = 1e-2 if variant == hmat.BF16_SCALED else W.get("refine", 0.0)
+        args.refine = default_refine(variant, args.workload)
     if args.eps is not None:
         W["eps"] = args.eps
         W["desc"] = W["desc"].replace("ACA 1e-6", f"ACA {args.eps:g}").replace("ACA 1e-5", f"ACA {args.eps:g}")

@@ -40,3 +40,17 @@ def test_labels():
     assert "bf16" in bench.storage_label(hmat.BF16_SCALED).lower()
     assert "fp64" in bench.storage_label(hmat.M1_DOUBLE).lower()
     assert len(bench.sources_hash()) == 16
+
+
+def test_default_early_checks():
+    """Early FP64 checks by default: BF16 always (1e-2), M2-Mixed only where
+    restarts were measured to pay (plates-128 and the batch, 1e-4)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_1911_00093_amd import hmat
+
+    assert bench.default_refine(hmat.M2_MIXED, "sphere-L7+8") == 0.0
+    assert bench.default_refine(hmat.M2_MIXED, "plates-128") == 1e-4
+    assert bench.default_refine(hmat.M2_MIXED, "ellipsoids-64x16") == 1e-4
+    for w in ("sphere-L7+8", "plates-128"):
+        assert bench.default_refine(hmat.BF16_SCALED, w) == 1e-2
