@@ -210,6 +210,28 @@ int hmat_set_tuning(hmat_t h, const hmat_tune_info *cfg);
 int hmat_plan_batched(const hmat_blocks *systems, int64_t count, const hmat_build_opts *opts, hmat_plan_info *out);
 int hmat_build_batched(const hmat_blocks *systems, int64_t count, const hmat_build_opts *opts, void *dev_mem,
                        uint64_t dev_bytes, void *stream, hmat_t *out);
+/* Plan once, build from the kept plan (not from the paper; setup only).
+ * hmat_plan_keep and hmat_plan_keep_batched check and size exactly as
+ * hmat_plan and hmat_plan_batched do (same errors, same `out`, which may be
+ * NULL) and also keep the plan, returned in *plan (NULL on error);
+ * hmat_build_kept then does what hmat_build / hmat_build_batched do with
+ * that plan (same buffer rules, errors and result) without planning again:
+ * a plan scans every low-rank factor for the Method 2 scales (Eqs. 13-16),
+ * which otherwise runs once for the caller's sizing and again in the build.
+ * A kept plan points into the caller's block arrays and values (for a
+ * batch, into each system's arrays; the `systems` array itself is only read
+ * during the call): they must stay alive and unchanged until the last
+ * build from it.  A plan is only read by a build and may serve several,
+ * each into its own buffer.  hmat_plan_release frees a plan (NULL is
+ * ignored); handles built from it stay valid. */
+typedef struct hmat_kept_plan_s *hmat_kept_plan_t;
+int hmat_plan_keep(const hmat_blocks *blocks, const hmat_build_opts *opts, hmat_plan_info *out,
+                   hmat_kept_plan_t *plan);
+int hmat_plan_keep_batched(const hmat_blocks *systems, int64_t count, const hmat_build_opts *opts,
+                           hmat_plan_info *out, hmat_kept_plan_t *plan);
+int hmat_build_kept(hmat_kept_plan_t plan, void *dev_mem, uint64_t dev_bytes, void *stream, hmat_t *out);
+int hmat_plan_release(hmat_kept_plan_t plan);
+
 /* System boundaries of a handle: *count systems, offsets[0..count] (host,
  * capacity >= count + 1; offsets may be NULL to query the count). */
 int hmat_system_offsets(hmat_t h, int64_t *offsets, int64_t capacity, int64_t *count);

@@ -755,26 +755,19 @@ int hmat_plan(const hmat_blocks *blocks, const hmat_build_opts *opts, hmat_plan_
 }  // extern "C"
 
 namespace hm {
-// Pack a planned H-matrix into the caller's device buffer and create the handle.
-static int build_planned(Packed *P, const hmat_plan_info &info, void *dev_mem, uint64_t dev_bytes, void *stream,
-                         hmat_t *out) {
-  if (!dev_mem || ((uintptr_t)dev_mem & 255u)) {
-    packed_free(P);
+// Pack a planned H-matrix into the caller's device buffer and create the
+// handle.  P is only read: a kept plan may serve several builds.
+static int build_kept(Packed *P, const hmat_plan_info &info, void *dev_mem, uint64_t dev_bytes, void *stream,
+                      hmat_t *out) {
+  if (!dev_mem || ((uintptr_t)dev_mem & 255u))
     return fail(HMAT_E_WORKSPACE, "device buffer missing or not 256-byte aligned");
-  }
-  if (dev_bytes < info.device_bytes) {
-    packed_free(P);
+  if (dev_bytes < info.device_bytes)
     return fail(HMAT_E_WORKSPACE, "device buffer holds %llu bytes, %llu needed", (unsigned long long)dev_bytes,
                 (unsigned long long)info.device_bytes);
-  }
   hmat_s *h = new (std::nothrow) hmat_s();
-  if (!h) {
-    packed_free(P);
-    return fail(HMAT_E_NOMEM, "handle allocation failed");
-  }
+  if (!h) return fail(HMAT_E_NOMEM, "handle allocation failed");
   HostImage img;
   int rc = host_guarded([&]() { return pack_into(P, img, h); });
-  packed_free(P);
   if (rc) {
     delete h;
     return rc;
@@ -820,7 +813,21 @@ static int build_planned(Packed *P, const hmat_plan_info &info, void *dev_mem, u
   *out = h;
   return HMAT_OK;
 }
+
+// The same, for a plan made for this one build (freed here).
+static int build_planned(Packed *P, const hmat_plan_info &info, void *dev_mem, uint64_t dev_bytes, void *stream,
+                         hmat_t *out) {
+  const int rc = build_kept(P, info, dev_mem, dev_bytes, stream, out);
+  packed_free(P);
+  return rc;
+}
 }  // namespace hm
+
+// A plan kept for later builds: the library's plan and its sizes.
+struct hmat_kept_plan_s {
+  hm::Packed *P;
+  hmat_plan_info info;
+};
 
 extern "C" {
 
@@ -851,6 +858,55 @@ int hmat_build_batched(const hmat_blocks *systems, int64_t count, const hmat_bui
   int rc = hm::plan_batched(systems, count, opts, &info, &P);
   if (rc) return rc;
   return hm::build_planned(P, info, dev_mem, dev_bytes, stream, out);
+}
+
+static int keep_plan(int rc, hm::Packed *P, const hmat_plan_info &info, hmat_plan_info *out,
+                     hmat_kept_plan_t *plan) {
+  if (rc) return rc;
+  hmat_kept_plan_s *k = new (std::nothrow) hmat_kept_plan_s{P, info};
+  if (!k) {
+    hm::packed_free(P);
+    return hm::fail(HMAT_E_NOMEM, "plan allocation failed");
+  }
+  if (out) *out = info;
+  *plan = k;
+  return HMAT_OK;
+}
+
+int hmat_plan_keep(const hmat_blocks *blocks, const hmat_build_opts *opts, hmat_plan_info *out,
+                   hmat_kept_plan_t *plan) {
+  if (!plan) return hm::fail(HMAT_E_ARG, "null plan output");
+  *plan = nullptr;
+  hm::Packed *P = nullptr;
+  hmat_plan_info info{};
+  const int rc = hm::plan_blocks(blocks, opts, &info, &P);
+  return keep_plan(rc, P, info, out, plan);
+}
+
+int hmat_plan_keep_batched(const hmat_blocks *systems, int64_t count, const hmat_build_opts *opts,
+                           hmat_plan_info *out, hmat_kept_plan_t *plan) {
+  if (!plan) return hm::fail(HMAT_E_ARG, "null plan output");
+  *plan = nullptr;
+  hm::Packed *P = nullptr;
+  hmat_plan_info info{};
+  const int rc = hm::plan_batched(systems, count, opts, &info, &P);
+  return keep_plan(rc, P, info, out, plan);
+}
+
+int hmat_build_kept(hmat_kept_plan_t plan, void *dev_mem, uint64_t dev_bytes, void *stream, hmat_t *out) {
+  hm::TraceRange trace_("hmat_build");
+  if (!out) return hm::fail(HMAT_E_ARG, "null output handle");
+  *out = nullptr;
+  if (!plan) return hm::fail(HMAT_E_ARG, "null plan");
+  return hm::build_kept(plan->P, plan->info, dev_mem, dev_bytes, stream, out);
+}
+
+int hmat_plan_release(hmat_kept_plan_t plan) {
+  if (plan) {
+    hm::packed_free(plan->P);
+    delete plan;
+  }
+  return HMAT_OK;
 }
 
 int hmat_system_offsets(hmat_t h, int64_t *offsets, int64_t capacity, int64_t *count) {

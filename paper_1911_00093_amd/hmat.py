@@ -40,6 +40,7 @@ EXPORTED = [
     "hmat_precond_leaves", "hmat_leaf_features", "hmat_leaf_scales", "hmat_batched_inverse", "hmat_mlp_workspace_bytes",
     "hmat_mlp_forward", "hmat_mlp_loss_grad", "hmat_mlp_adam", "hmat_autotune", "hmat_permute",
     "hmat_bicgstab_noalloc_max_n", "hmat_bicgstab_noalloc", "hmat_pack_host", "hmat_set_tuning",
+    "hmat_plan_keep", "hmat_plan_keep_batched", "hmat_build_kept", "hmat_plan_release",
 ]
 
 
@@ -167,6 +168,10 @@ def lib():
         "hmat_stream_read": (C.c_int, [P, U64, P, P]),
         "hmat_stream_copy": (C.c_int, [P, P, U64, P]),
         "hmat_plan_batched": (C.c_int, [P, I64, P, P]),
+        "hmat_plan_keep": (C.c_int, [P, P, P, P]),
+        "hmat_plan_keep_batched": (C.c_int, [P, I64, P, P, P]),
+        "hmat_build_kept": (C.c_int, [P, P, U64, P, P]),
+        "hmat_plan_release": (C.c_int, [P]),
         "hmat_build_batched": (C.c_int, [P, I64, P, P, U64, P, P]),
         "hmat_system_offsets": (C.c_int, [P, P, I64, P]),
         "hmat_bicgstab_batched_workspace_bytes": (U64, [P, I64]),
@@ -387,20 +392,24 @@ class HMatrix:
         batched = isinstance(blocks, (list, tuple))
         o = hmat_build_opts(self.precision, self.c, self.nrhs_max, self.drop, int(self.dense_split), 0)
         h = C.c_void_p()
+        # plan once (sizes for the buffer), then build from the kept plan;
+        # `blocks` (whose arrays the plan points into) is alive throughout
+        self.plan = hmat_plan_info()
+        keep = C.c_void_p()
         if batched:
-            self.plan = hmat_plan_batched(blocks, precision, c, nrhs_max, drop, dense_split)
             self.n = sum(b.n for b in blocks)
-            self.buf = torch.empty(int(self.plan.device_bytes), dtype=torch.uint8, device=device)
             arr = (hmat_blocks * len(blocks))(*[b.struct() for b in blocks])
-            _check(lib().hmat_build_batched(arr, len(blocks), C.byref(o), C.c_void_p(self.buf.data_ptr()),
-                                            self.buf.numel(), _stream_ptr(stream), C.byref(h)))
+            _check(lib().hmat_plan_keep_batched(arr, len(blocks), C.byref(o), C.byref(self.plan), C.byref(keep)))
         else:
-            self.plan = hmat_plan(blocks, precision, c, nrhs_max, drop, dense_split)
             self.n = blocks.n
-            self.buf = torch.empty(int(self.plan.device_bytes), dtype=torch.uint8, device=device)
             s = blocks.struct()
-            _check(lib().hmat_build(C.byref(s), C.byref(o), C.c_void_p(self.buf.data_ptr()), self.buf.numel(),
-                                    _stream_ptr(stream), C.byref(h)))
+            _check(lib().hmat_plan_keep(C.byref(s), C.byref(o), C.byref(self.plan), C.byref(keep)))
+        try:
+            self.buf = torch.empty(int(self.plan.device_bytes), dtype=torch.uint8, device=device)
+            _check(lib().hmat_build_kept(keep, C.c_void_p(self.buf.data_ptr()), self.buf.numel(),
+                                         _stream_ptr(stream), C.byref(h)))
+        finally:
+            lib().hmat_plan_release(keep)
         self.h = h
         self._destroy = lib().hmat_destroy  # kept: module globals may be gone at exit
 

@@ -395,3 +395,44 @@ def test_binding_refuses_bad_vectors():
         hmat.Precond.apply(P, ok)
     with pytest.raises(ValueError, match="rows"):
         hmat.hmat_bicgstab_batched(h, torch.zeros((2, n + 1), dtype=torch.float64).T)
+
+
+def _info_tuple(i):
+    return tuple(getattr(i, f) for f, _ in hmat.hmat_plan_info._fields_)
+
+
+@pytest.mark.parametrize("prec,nrhs", [(hmat.M2_MIXED, 1), (hmat.BF16_SCALED, 1), (hmat.M1_DOUBLE, 16)])
+def test_kept_plan_sizes_and_errors(prec, nrhs):
+    """hmat_plan_keep sizes exactly as hmat_plan (single and batched); a
+    bad partition is refused with the same code and no plan; a kept plan
+    builds only into a large enough, aligned buffer (refused before any
+    device work, so this runs without a GPU); release takes NULL."""
+    L = hmat.lib()
+    m, h = oracle_hmatrix("sphere-L3")
+    bs = blockset_from_oracle(h)
+    o = hmat.hmat_build_opts(prec, -1, nrhs, 0, 0, 0)
+    s = bs.struct()
+    info, keep = hmat.hmat_plan_info(), C.c_void_p()
+    assert L.hmat_plan_keep(C.byref(s), C.byref(o), C.byref(info), C.byref(keep)) == hmat.HMAT_OK and keep.value
+    assert _info_tuple(info) == _info_tuple(hmat.hmat_plan(bs, prec, -1, nrhs))
+    out = C.c_void_p()
+    assert L.hmat_build_kept(keep, None, 0, None, C.byref(out)) == hmat.HMAT_E_WORKSPACE and not out.value
+    assert L.hmat_build_kept(keep, C.c_void_p(256), info.device_bytes - 1, None, C.byref(out)) == hmat.HMAT_E_WORKSPACE
+    assert L.hmat_build_kept(keep, C.c_void_p(256), info.device_bytes, None, None) == hmat.HMAT_E_ARG
+    assert L.hmat_plan_release(keep) == hmat.HMAT_OK
+    assert L.hmat_build_kept(None, C.c_void_p(256), 1 << 40, None, C.byref(out)) == hmat.HMAT_E_ARG
+    assert L.hmat_plan_release(None) == hmat.HMAT_OK
+    assert L.hmat_plan_keep(C.byref(s), C.byref(o), C.byref(info), None) == hmat.HMAT_E_ARG
+    # batched
+    bss = [bs, blockset_from_oracle(oracle_hmatrix("plates-16")[1])]
+    arr = (hmat.hmat_blocks * 2)(*[b.struct() for b in bss])
+    keep = C.c_void_p()
+    assert L.hmat_plan_keep_batched(arr, 2, C.byref(o), None, C.byref(keep)) == hmat.HMAT_OK and keep.value
+    L.hmat_plan_release(keep)
+    # a bad partition: the code hmat_plan gives, and no plan
+    bad = hmat.BlockSet.from_arrays(**dict(_tiny_partition(), ncols=[2, 1, 2, 2]))
+    sb = bad.struct()
+    keep = C.c_void_p(123)
+    o1 = hmat.hmat_build_opts(hmat.M1_DOUBLE, 0, 1, 0, 0, 0)
+    assert L.hmat_plan_keep(C.byref(sb), C.byref(o1), None, C.byref(keep)) == hmat.HMAT_E_LAYOUT
+    assert not keep.value
