@@ -436,3 +436,16 @@ def test_kept_plan_sizes_and_errors(prec, nrhs):
     o1 = hmat.hmat_build_opts(hmat.M1_DOUBLE, 0, 1, 0, 0, 0)
     assert L.hmat_plan_keep(C.byref(sb), C.byref(o1), None, C.byref(keep)) == hmat.HMAT_E_LAYOUT
     assert not keep.value
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/hmat.h is a C ABI: a C99 translation unit that includes it and
+    names every declared call compiles with -pedantic -Werror."""
+    names = header_functions()
+    src = tmp_path / "use_header.c"
+    src.write_text('#include "hmat.h"\ntypedef void (*fn)(void);\nfn table[] = {\n' +
+                   ",\n".join(f"  (fn)&{n}" for n in names) + "\n};\n")
+    p = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-Wno-cast-function-type",
+                        "-I", os.path.join(ROOT, "include"), "-c", str(src), "-o", str(tmp_path / "use_header.o")],
+                       capture_output=True, text=True)
+    assert p.returncode == 0, p.stderr
