@@ -24,8 +24,17 @@ def _build(L, fn, args, info, torch):
     return buf, h
 
 
+CASES = {  # precision, c, drop, dense_split
+    "M2-Mixed": (hmat.M2_MIXED, -1, 0, 0),
+    "BF16-scaled": (hmat.BF16_SCALED, -1, 0, 0),
+    "M3-c0-dense-split": (hmat.M3, 0, 0, 1),
+    "M2-Mixed-drop3": (hmat.M2_MIXED, -1, 3, 0),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
 @pytest.mark.parametrize("batched", [False, True], ids=["single", "batched16"])
-def test_kept_plan_builds_equal_one_shot_build(batched):
+def test_kept_plan_builds_equal_one_shot_build(batched, case):
     need_gpu()
     import torch
 
@@ -33,7 +42,8 @@ def test_kept_plan_builds_equal_one_shot_build(batched):
     keys = ("sphere-L4", "plates-32") if batched else ("spheres-mixed",)
     bss = [blockset(oracle_hmatrix(k)[1]) for k in keys]
     nrhs = 16 if batched else 1
-    o = hmat.hmat_build_opts(hmat.M2_MIXED, -1, nrhs, 0, 0, 0)
+    prec, c, drop, split = CASES[case]
+    o = hmat.hmat_build_opts(prec, c, nrhs, drop, split, 0)
     info, keep = hmat.hmat_plan_info(), C.c_void_p()
     if batched:
         arr = (hmat.hmat_blocks * len(bss))(*[b.struct() for b in bss])
