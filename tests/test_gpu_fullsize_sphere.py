@@ -10,7 +10,7 @@ blocks element by element (Eqs. 21-25).  The FP64 handle holds about 10 GB,
 so its value offsets pass 2^32 bytes: the 64-bit offset paths of the
 kernels are compared here.  The solver, in the benchmark's configuration,
 is compared with the oracle's Algorithm 1 after one, two and three
-iterations.
+iterations, and restarted GMRES with the oracle's after one cycle.
 """
 
 import numpy as np
@@ -133,3 +133,48 @@ def test_sphere_bicgstab_first_iterations(variant):
               f"residual norms {eh:.2e} (spread {sh:.2e}, bound {bh:.2e})", flush=True)
         assert ex <= bx
         assert eh <= bh
+
+
+def test_sphere_gmres_first_cycle():
+    """Restarted GMRES at full size in the benchmark's configuration (tuned
+    M2-Mixed handle, FP64 handle for the true residual), exactly one cycle of
+    8 steps (tol unreachable): the solution after the cycle's update,
+    x = x_0 + V y, and the residual estimates of the 8 steps equal the
+    oracle's GMRES for the same operator arithmetic.  Bounds as for
+    BiCGSTAB above: 1000 times the largest spread that a one-ulp perturbation
+    of every element of b gives the oracle's own x and estimates over three
+    seeded draws (at least 1e-12 for x, 1e-9 for the estimates)."""
+    need_gpu()
+    from oracle import gmres as OG
+    from paper_1911_00093_amd import tuning
+
+    d = c3()
+    h, m = d["h"], d["m"]
+    bs = blockset(h)
+    H, H64 = hmat.HMatrix(bs, oracle.M2_MIXED, c=-1), hmat.HMatrix(bs, oracle.M1_DOUBLE)
+    tuning.autotune(H, reps=3)
+    b = m.rhs()[h.perm]
+    steps = 8
+    x, info = hmat.hmat_gmres(H, to_dev(b), h_fp64=H64, tol=1e-30, restart=steps, maxiter=steps, history=True)
+    del H, H64
+    assert info["iterations"] == steps and info["restarts"] == 0
+    x = x.cpu().numpy()
+    est = info["history"][1:steps + 1]
+    op = oracle.Converted(h, oracle.M2_MIXED, -1)
+    xo, io = OG.gmres(op.matvec, b, tol=1e-30, restart=steps, maxiter=steps)
+    assert io["iterations"] == steps and io["cycles"] == 1
+    ho = np.asarray(io["history"][:steps])
+    rng = np.random.default_rng(5)
+    sx = sh = 0.0
+    for _ in range(3):
+        bp = b * (1 + np.ldexp(rng.choice([-1.0, 1.0], b.size), -52))
+        xp, ip = OG.gmres(op.matvec, bp, tol=1e-30, restart=steps, maxiter=steps)
+        sx = max(sx, np.abs(xp - xo).max() / np.abs(xo).max())
+        sh = max(sh, (np.abs(np.asarray(ip["history"][:steps]) - ho) / ho).max())
+    ex = np.abs(x - xo).max() / np.abs(xo).max()
+    eh = (np.abs(est - ho) / ho).max()
+    bx, bh = max(1e-12, 1000 * sx), max(1e-9, 1000 * sh)
+    print(f"GMRES({steps}) one cycle: x {ex:.2e} (one-ulp spread {sx:.2e}, bound {bx:.2e}); "
+          f"estimates {eh:.2e} (spread {sh:.2e}, bound {bh:.2e})", flush=True)
+    assert ex <= bx
+    assert eh <= bh
